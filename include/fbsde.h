@@ -1,0 +1,179 @@
+/*
+ * fbsde.h — C ABI of the MI355X (gfx950) deep-FBSDE library.
+ *
+ * The library trains the Deep-BSDE form of the paper's method
+ * (Güler, Laignelet, Parpas, arXiv 1910.11623):
+ *   - forward SDE   dX = mu dt + sigma(X) dW, X_0 = x0        (Sec. 2.1, eq. coupled; mu = 0)
+ *   - Euler–Maruyama X_{n+1} = X_n + sigma(X_n) dW_n,
+ *                    Y_{n+1} = Y_n + phi(t_n,X_n,Y_n,Z_n) dt + Z_n . sigma(X_n) dW_n
+ *                                                             (Sec. 2.2, eq. disc equations)
+ *   - Z_n from a network per time step (Y_0 and Z_0 are trainable parameters),
+ *     or from one shared network of (t, x)                     (Sec. 2.2, related-work paragraph;
+ *                                                              Sec. 3.1 for the residual form)
+ *   - loss (1/M) sum_m (Y_N - g(X_N))^2                        (Sec. 2.2, eq. loss, terminal term)
+ *   - Adam                                                     (Sec. 4.1)
+ *   - multilevel warm start from N to 2N steps                 (Sec. 3.2)
+ *
+ * Conventions for every call:
+ *   - Pointers named *_dev are device pointers (hipMalloc'd or torch tensors'
+ *     data_ptr) owned by the caller; the library never frees them.  Pointers
+ *     named *_host are host memory.  `stream` is a hipStream_t (NULL = the
+ *     null stream); hot calls are asynchronous on it.
+ *   - Hot calls (fbsde_forward, fbsde_forward_backward, fbsde_adam_step,
+ *     fbsde_prolong, fbsde_sample_normals, fbsde_terminal_mean) allocate
+ *     nothing: all scratch lives in the caller's workspace of
+ *     fbsde_workspace_size bytes (256-byte aligned).  One workspace must not
+ *     be used by two calls that overlap in time.
+ *   - Every call returns a status and never aborts; argument errors are
+ *     detected on the host before any launch and leave device memory
+ *     untouched.  fbsde_last_error() returns a thread-local message.
+ *   - Float parameters are one flat fp32 buffer (layout below); Y_0 is a
+ *     separate fp64 scalar on the device.
+ *
+ * Flat parameter layout (row-major W[out][in], each W followed by its b):
+ *   per-step MLP (depth L hidden tanh layers of width w):
+ *     z0[d]; then for n = 1 .. N-1:
+ *       W1[w][d] b1[w], (W_l[w][w] b_l[w]) for l = 2..L, Wo[d][w] bo[d]
+ *   shared residual net (depth B blocks, Sec. 3.1 with h = 1):
+ *       Win[w][d+1] bin[w]  (column d multiplies t_n),
+ *       (W_k[w][w] b_k[w]) for k = 1..B, Wo[d][w] bo[d]
+ */
+#ifndef FBSDE_H
+#define FBSDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FBSDE_OK = 0,
+  FBSDE_ERR_INVALID = 1,      /* bad argument (null pointer, size, enum)       */
+  FBSDE_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement   */
+  FBSDE_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed     */
+  FBSDE_ERR_NOMEM = 4,        /* plan creation could not allocate              */
+  FBSDE_ERR_NONFINITE = 5     /* loss or gradient not finite (status check)    */
+} fbsde_status;
+
+/* Forward SDE families (mu = 0 in every problem of Sec. 4). */
+typedef enum {
+  FBSDE_SDE_GBM_DIAG = 0,     /* sigma(x) dW = s * x (.) dW   (Black–Scholes–Barenblatt) */
+  FBSDE_SDE_SCALED_BM = 1     /* sigma(x) dW = s * dW         (HJB, Allen–Cahn)          */
+} fbsde_sde;
+
+/* Drivers phi in the convention dY = phi dt + Z^T sigma dW, Z = grad u. */
+typedef enum {
+  FBSDE_DRV_BSB = 0,          /* r (y - z.x)      p[0] = r    */
+  FBSDE_DRV_HJB = 1,          /* lam |z|^2        p[0] = lam  */
+  FBSDE_DRV_AC = 2,           /* y^3 - y                      */
+  FBSDE_DRV_LINEAR = 3        /* a y + b          p[0] = a, p[1] = b */
+} fbsde_driver;
+
+/* Terminal conditions g. */
+typedef enum {
+  FBSDE_G_NORM2 = 0,          /* |x|^2                         */
+  FBSDE_G_LOGHALF = 1,        /* ln((1 + |x|^2) / 2)           */
+  FBSDE_G_INV = 2,            /* 1 / (a + b |x|^2)  p = {a, b} */
+  FBSDE_G_LINEAR = 3          /* a sum_i x_i + c    p = {a, c} */
+} fbsde_terminal;
+
+typedef struct {
+  int32_t d;                  /* state dimension, >= 1                      */
+  double T;                   /* horizon, > 0                               */
+  const double *x0_host;      /* [d] initial state, copied at plan creation */
+  int32_t sde;   double sde_p[2];  /* fbsde_sde, sde_p[0] = s              */
+  int32_t drv;   double drv_p[2];  /* fbsde_driver and its parameters       */
+  int32_t g;     double g_p[2];    /* fbsde_terminal and its parameters     */
+} fbsde_problem;
+
+typedef enum { FBSDE_NET_PER_STEP_MLP = 0, FBSDE_NET_SHARED_RESNET = 1 } fbsde_net_kind;
+
+/* Arithmetic of the network GEMMs.  Path state (X, Y, Z, lambda) is fp32
+ * in both; the loss and dL/dY0 are reduced in fp64.
+ *   FP32     : fp32 MFMA (v_mfma_f32_16x16x4f32), fp32 activations
+ *   BF16_MFMA: bf16 operands (RNE) on v_mfma_f32_16x16x32_bf16, fp32
+ *              accumulation; every GEMM operand (weights, X, hidden
+ *              activations, back-propagated deltas) is rounded to bf16 once. */
+typedef enum { FBSDE_FP32 = 0, FBSDE_BF16_MFMA = 1 } fbsde_precision;
+
+typedef struct {
+  int32_t kind;               /* fbsde_net_kind                              */
+  int32_t width;              /* hidden width w                              */
+  int32_t depth;              /* MLP: hidden layers; ResNet: residual blocks */
+  int32_t prec;               /* fbsde_precision                             */
+} fbsde_net;
+
+typedef struct fbsde_plan fbsde_plan;
+
+/* Create a plan for N time steps (dt = T/N, t_n = n dt) and M paths on the
+ * current HIP device.  Validates everything, copies x0 to the device (the
+ * only allocation the library makes, owned by the plan).  Limits of this
+ * build: per-step MLP with d <= 256, w <= 256, 1 <= depth <= 8.
+ * Errors: INVALID, UNSUPPORTED, NOMEM, HIP. */
+fbsde_status fbsde_plan_create(const fbsde_problem *problem, const fbsde_net *net, int32_t N,
+                               int64_t M, fbsde_plan **out);
+void fbsde_plan_destroy(fbsde_plan *plan);
+
+/* Number of fp32 parameters in the flat layout above. */
+fbsde_status fbsde_param_count(const fbsde_plan *plan, int64_t *n_params_host);
+
+/* Bytes of device workspace the hot calls of this plan need. */
+fbsde_status fbsde_workspace_size(const fbsde_plan *plan, size_t *bytes_host);
+
+/* Loss of one iteration: draws the Brownian increments of iteration `iter`
+ * (Philox4x32-10 keyed by `seed`, counter (i/4, n, m, iter); Box–Muller),
+ * runs the Euler scheme with the networks and writes
+ * L = (1/M) sum_m (Y_N - g(X_N))^2 to *loss_dev (fp64).
+ * params_dev: [n_params] fp32; y0_dev: fp64 scalar. */
+fbsde_status fbsde_forward(fbsde_plan *plan, const float *params_dev, const double *y0_dev,
+                           uint64_t seed, uint64_t iter, double *loss_dev, void *ws_dev,
+                           void *stream);
+
+/* Loss and its exact gradient through the unrolled chain (reverse sweep of
+ * the Euler scheme and of every network): grad_dev [n_params] fp32 and
+ * grad_y0_dev (fp64) are overwritten.  Deterministic: no atomics; every
+ * reduction has a fixed order. */
+fbsde_status fbsde_forward_backward(fbsde_plan *plan, const float *params_dev,
+                                    const double *y0_dev, float *grad_dev, double *grad_y0_dev,
+                                    double *loss_dev, uint64_t seed, uint64_t iter, void *ws_dev,
+                                    void *stream);
+
+/* One Adam step (Kingma & Ba) with step count t >= 1 on the fp32 parameters
+ * (learning rate lr) and on y0 (fp64 state, learning rate lr_y0).
+ * m/v have the parameter layout; m_y0/v_y0 are fp64 scalars. */
+fbsde_status fbsde_adam_step(fbsde_plan *plan, float *params_dev, double *y0_dev,
+                             const float *grad_dev, const double *grad_y0_dev, float *m_dev,
+                             float *v_dev, double *m_y0_dev, double *v_y0_dev, int64_t t, double lr,
+                             double lr_y0, double beta1, double beta2, double eps, void *stream);
+
+/* Multilevel warm start (Sec. 3.2): copy the parameters of a plan with Nc
+ * steps into a plan with Nf = 2 Nc steps of the same problem and network.
+ * Fine net j takes coarse net clamp(floor(j/2), 1, Nc-1); z0 is copied; a
+ * shared network is copied unchanged.  Requires Nc >= 2 for per-step nets. */
+fbsde_status fbsde_prolong(const fbsde_plan *coarse, const fbsde_plan *fine,
+                           const float *params_coarse_dev, float *params_fine_dev, void *stream);
+
+/* Test hook: the standard normals xi[n][m][i] (fp32, [N][M][d]) that the
+ * forward call of iteration `iter` uses. */
+fbsde_status fbsde_sample_normals(fbsde_plan *plan, uint64_t seed, uint64_t iter, float *xi_dev,
+                                  void *stream);
+
+/* Mean of g(X_N) over the M paths of iteration `iter` (fp64), a pilot value
+ * to initialise Y_0.  Uses the workspace. */
+fbsde_status fbsde_terminal_mean(fbsde_plan *plan, uint64_t seed, uint64_t iter,
+                                 double *mean_dev, void *ws_dev, void *stream);
+
+/* Test hook: after a forward call on `ws_dev`, copy X_N ([M][d] fp32) and
+ * Y_N ([M] fp32) out of the workspace (either pointer may be NULL). */
+fbsde_status fbsde_terminal_states(fbsde_plan *plan, const void *ws_dev, float *xN_dev,
+                                   float *yN_dev, void *stream);
+
+const char *fbsde_status_str(fbsde_status s);
+const char *fbsde_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -59,6 +59,9 @@ def lib():
         L.orc_loss_grad.argtypes = [C.POINTER(_Problem), C.POINTER(_Net), C.c_int, C.c_int64,
                                     dp, C.c_double, dp, C.c_uint64, C.c_uint64,
                                     dp, dp, dp, dp, dp, dp]
+        L.orc_paths.restype = C.c_int
+        L.orc_paths.argtypes = [C.POINTER(_Problem), C.POINTER(_Net), C.c_int, dp, C.c_double,
+                                C.c_uint64, C.c_uint64, C.POINTER(C.c_int64), C.c_int64, dp, dp]
         L.orc_loss_exact_bsb.restype = C.c_int
         L.orc_loss_exact_bsb.argtypes = [C.POINTER(_Problem), C.c_int, C.c_int64, C.c_double, dp,
                                          C.c_uint64, C.c_uint64, C.c_int, dp]
@@ -156,6 +159,23 @@ def loss_grad(problem: dict, net: dict, N: int, M: int, params, y0: float, *, xi
     if want_paths:
         out.update(XN=XN, YN=YN, Ypath=Yp)
     return out
+
+
+def paths(problem: dict, net: dict, N: int, params, y0: float, idx, *, seed: int = 0, it: int = 0):
+    """Terminal (Y_N, X_N) of the selected path indices of a full batch."""
+    ps, _keep = _problem(problem)
+    ns = _net(net)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    d = int(problem["d"])
+    YN = np.zeros(idx.size)
+    XN = np.zeros((idx.size, d))
+    rc = lib().orc_paths(C.byref(ps), C.byref(ns), int(N), _ptr(params), float(y0), C.c_uint64(seed),
+                         C.c_uint64(it), idx.ctypes.data_as(C.POINTER(C.c_int64)), idx.size,
+                         _ptr(YN), _ptr(XN))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return YN, XN
 
 
 def loss_exact_bsb(problem: dict, N: int, M: int, y0: float, *, xi=None, seed=0, it=0, flip=False):

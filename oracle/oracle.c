@@ -281,6 +281,39 @@ static void resnet_backward(const orc_problem *p, const orc_net *net, const doub
   outer_acc(net, w, d + 1, dpre, u, G + offin, G + offbin);
 }
 
+/* Forward Euler–Maruyama sweep of one path m, eq. (disc equations) with
+ * mu = 0; stores X_n, Z_n, s_n = sigma(X_n) dW_n, Y_n and the network
+ * activations of every step.  xi: [N][Mx][d] normals or NULL for Philox. */
+static void path_forward(const orc_problem *p, const orc_net *net, int N, const double *params,
+                         double y0, const double *xi, int64_t Mx, uint64_t seed, uint64_t iter,
+                         int64_t m, double *X, double *Zs, double *S, double *Y, double *A,
+                         double *xim, double *dw) {
+  const int d = p->d, w = net->width;
+  const int mlp = (net->kind == ORC_NET_PER_STEP_MLP);
+  const int64_t nacts = mlp ? (int64_t)net->depth * w : (int64_t)(2 * net->depth + 1) * w;
+  const int64_t pstep = mlp ? mlp_step_count(d, w, net->depth) : 0;
+  const double dt = p->T / N, sdt = sqrt(dt);
+  memcpy(X, p->x0, sizeof(double) * d);
+  Y[0] = y0;
+  for (int n = 0; n < N; ++n) {
+    const double *xn = X + (int64_t)n * d;
+    double *zn = Zs + (int64_t)n * d, *sn = S + (int64_t)n * d;
+    if (mlp && n == 0) {
+      memcpy(zn, params, sizeof(double) * d);                 /* Z_0 = z0 */
+    } else if (mlp) {
+      mlp_forward(p, net, params + d + (int64_t)(n - 1) * pstep, xn, A + (int64_t)n * nacts, zn);
+    } else {
+      resnet_forward(p, net, params, xn, n * dt, A + (int64_t)n * nacts, zn);
+    }
+    if (xi) memcpy(xim, xi + ((int64_t)n * Mx + m) * d, sizeof(double) * d);
+    else normals_one(seed, iter, n, m, d, xim);
+    for (int i = 0; i < d; ++i) dw[i] = sdt * xim[i];
+    diffusion(p, xn, dw, sn);
+    Y[n + 1] = Y[n] + driver(p, xn, Y[n], zn) * dt + dot(d, zn, sn);
+    for (int i = 0; i < d; ++i) X[(int64_t)(n + 1) * d + i] = xn[i] + sn[i];
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Loss and gradient                                                         */
 /* ------------------------------------------------------------------------ */
@@ -302,7 +335,7 @@ int orc_loss_grad(const orc_problem *p, const orc_net *net, int N, int64_t M,
   const int64_t nacts = mlp ? (int64_t)net->depth * w : (int64_t)(2 * net->depth + 1) * w;
   const int64_t pstep = mlp ? mlp_step_count(d, w, net->depth) : 0;
   const int64_t npar = orc_param_count(p, net, N);
-  const double dt = p->T / N, sdt = sqrt(dt);
+  const double dt = p->T / N;
 
   double *X = (double *)calloc((size_t)(N + 1) * d, sizeof(double));
   double *Zs = (double *)calloc((size_t)N * d, sizeof(double));
@@ -318,26 +351,7 @@ int orc_loss_grad(const orc_problem *p, const orc_net *net, int N, int64_t M,
   double gy0 = 0.0, lsum = 0.0;
 
   for (int64_t m = 0; m < M; ++m) {
-    /* forward: Euler–Maruyama for X and Y, eq. (disc equations) with mu = 0 */
-    memcpy(X, p->x0, sizeof(double) * d);
-    Y[0] = y0;
-    for (int n = 0; n < N; ++n) {
-      const double *xn = X + (int64_t)n * d;
-      double *zn = Zs + (int64_t)n * d, *sn = S + (int64_t)n * d;
-      if (mlp && n == 0) {
-        memcpy(zn, params, sizeof(double) * d);                 /* Z_0 = z0 */
-      } else if (mlp) {
-        mlp_forward(p, net, params + d + (int64_t)(n - 1) * pstep, xn, A + (int64_t)n * nacts, zn);
-      } else {
-        resnet_forward(p, net, params, xn, n * dt, A + (int64_t)n * nacts, zn);
-      }
-      if (xi) memcpy(xim, xi + ((int64_t)n * M + m) * d, sizeof(double) * d);
-      else normals_one(seed, iter, n, m, d, xim);
-      for (int i = 0; i < d; ++i) dw[i] = sdt * xim[i];
-      diffusion(p, xn, dw, sn);
-      Y[n + 1] = Y[n] + driver(p, xn, Y[n], zn) * dt + dot(d, zn, sn);
-      for (int i = 0; i < d; ++i) X[(int64_t)(n + 1) * d + i] = xn[i] + sn[i];
-    }
+    path_forward(p, net, N, params, y0, xi ? xi : NULL, M, seed, iter, m, X, Zs, S, Y, A, xim, dw);
     const double *xN = X + (int64_t)N * d;
     double e = Y[N] - terminal(p, xN);
     lsum += e * e;
@@ -438,5 +452,27 @@ int orc_prolong(const orc_problem *p, const orc_net *net, int Nc, int Nf,
     if (c > Nc - 1) c = Nc - 1;
     memcpy(pf + d + (int64_t)(j - 1) * ps, pc + d + (int64_t)(c - 1) * ps, sizeof(double) * (size_t)ps);
   }
+  return 0;
+}
+
+int orc_paths(const orc_problem *p, const orc_net *net, int N, const double *params, double y0,
+              uint64_t seed, uint64_t iter, const int64_t *idx, int64_t k, double *YN, double *XN) {
+  if (check_args(p, net, N, 1) || !params || !idx || k < 0) return 1;
+  const int d = p->d, w = net->width;
+  const int mlp = (net->kind == ORC_NET_PER_STEP_MLP);
+  const int64_t nacts = mlp ? (int64_t)net->depth * w : (int64_t)(2 * net->depth + 1) * w;
+  double *X = (double *)calloc((size_t)(N + 1) * d, sizeof(double));
+  double *Zs = (double *)calloc((size_t)N * d, sizeof(double));
+  double *S = (double *)calloc((size_t)N * d, sizeof(double));
+  double *Y = (double *)calloc((size_t)(N + 1), sizeof(double));
+  double *A = (double *)calloc((size_t)N * nacts + 1, sizeof(double));
+  double *xim = (double *)calloc((size_t)d, sizeof(double));
+  double *dw = (double *)calloc((size_t)d, sizeof(double));
+  for (int64_t i = 0; i < k; ++i) {
+    path_forward(p, net, N, params, y0, NULL, 0, seed, iter, idx[i], X, Zs, S, Y, A, xim, dw);
+    if (YN) YN[i] = Y[N];
+    if (XN) memcpy(XN + i * d, X + (int64_t)N * d, sizeof(double) * d);
+  }
+  free(X); free(Zs); free(S); free(Y); free(A); free(xim); free(dw);
   return 0;
 }

@@ -92,6 +92,12 @@ int orc_loss_grad(const orc_problem *p, const orc_net *net, int N, int64_t M,
                   double *loss, double *grad, double *grad_y0,
                   double *XN, double *YN, double *Ypath);
 
+/* Forward sweep of the selected paths idx[0..k) only (same normals as path
+ * idx[i] of a full batch): terminal Y_N (YN[k]) and X_N (XN[k][d]), either
+ * may be NULL.  Lets a full-size GPU run be checked on sampled paths. */
+int orc_paths(const orc_problem *p, const orc_net *net, int N, const double *params, double y0,
+              uint64_t seed, uint64_t iter, const int64_t *idx, int64_t k, double *YN, double *XN);
+
 /* Loss of the Euler scheme driven by the exact solution instead of a
  * network: Y_0 = y0 and Z_n = grad u(t_n, X_n) of the Black–Scholes–
  * Barenblatt closed form u = exp((r + s^2)(T - t)) |x|^2 (Sec. 4).  With

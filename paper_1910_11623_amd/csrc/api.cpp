@@ -1,0 +1,355 @@
+// C ABI of the gfx950 deep-FBSDE library: validation, plan, workspace
+// layout and the launch sequence of each hot call (declared in fbsde.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/fbsde.h"
+#include "fbsde_internal.h"
+
+using fbsde::Geo;
+using fbsde::WsLayout;
+
+struct fbsde_plan {
+  fbsde_problem prob;
+  fbsde_net net;
+  int32_t N;
+  int64_t M;
+  Geo geo;
+  WsLayout ws;
+  float* x0_dev;  // [dp] zero-padded, owned
+  int device;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fbsde_status fail(fbsde_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+fbsde_status hip_fail(hipError_t e, const char* where) {
+  return fail(FBSDE_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int tiles(int n, bool bf16) {
+  // 16-wide tiles; bf16 K-blocks are 32 wide, so bf16 tile counts are even
+  return bf16 ? 2 * ((n + 31) / 32) : (n + 15) / 16;
+}
+
+void make_layout(fbsde_plan* P) {
+  const Geo& g = P->geo;
+  WsLayout& w = P->ws;
+  const size_t M = (size_t)g.M, N = (size_t)g.N, esz = g.bf16 ? 2 : 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  w.X = take((N + 1) * M * g.dp * 4);
+  w.V = take(N * M * g.dp * 4);
+  w.C = take(N * M * 4);
+  w.Y = take((N + 1) * M * 4);
+  w.LAM = take(N * M * 4);
+  w.QN = take(M * 4);
+  w.LN = take(M * 4);
+  w.H = take(N * g.L * M * g.wp * esz);
+  w.DZ = take(N * M * g.zp * esz);
+  w.DH = take(N * g.L * M * g.wp * esz);
+  w.PF = take((N > 1 ? N - 1 : 0) * (size_t)g.packf_step * esz);
+  w.PB = take((N > 1 ? N - 1 : 0) * (size_t)g.packb_step * esz);
+  // wgrad splits over paths: about 512 paths each, multiples of 32
+  int splits = (int)((M + 511) / 512);
+  if (splits < 1) splits = 1;
+  if (splits > 16) splits = 16;
+  long long chunk = ((long long)M + splits - 1) / splits;
+  chunk = (chunk + 31) / 32 * 32;
+  splits = (int)(((long long)M + chunk - 1) / chunk);
+  w.splits = splits;
+  w.chunk = chunk;
+  w.PART = take((size_t)splits * (size_t)g.nparams * 4);
+  w.scan_blocks = (int)((M + 255) / 256);
+  w.RED = take((size_t)w.scan_blocks * 2 * 8 + 64);
+  w.total = off;
+}
+
+bool finite_all(const double* v, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
+}
+template <class T>
+const T* at(const void* ws, size_t off) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(ws) + off);
+}
+
+fbsde_status check_hot(const fbsde_plan* P, const void* ws) {
+  if (!P) return fail(FBSDE_ERR_INVALID, "plan is NULL");
+  if (!ws) return fail(FBSDE_ERR_INVALID, "workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+    return fail(FBSDE_ERR_INVALID, "workspace must be 256-byte aligned");
+  return FBSDE_OK;
+}
+
+fbsde_status run_forward(fbsde_plan* P, const float* params, const double* y0, uint64_t seed,
+                         uint64_t iter, void* ws, hipStream_t s) {
+  const Geo& g = P->geo;
+  const WsLayout& L = P->ws;
+  hipError_t e;
+  if ((e = fbsde::launch_pack(g, params, at<void>(ws, L.PF), at<void>(ws, L.PB), s)) != hipSuccess)
+    return hip_fail(e, "pack");
+  if ((e = fbsde::launch_sde(g, P->x0_dev, seed, iter, at<float>(ws, L.X), at<float>(ws, L.V),
+                             at<float>(ws, L.QN), at<float>(ws, L.LN), s)) != hipSuccess)
+    return hip_fail(e, "sde");
+  if ((e = fbsde::launch_forward(g, params, at<void>(ws, L.PF), at<float>(ws, L.X), at<float>(ws, L.V),
+                                 at<float>(ws, L.C), at<void>(ws, L.H), s)) != hipSuccess)
+    return hip_fail(e, "forward");
+  if ((e = fbsde::launch_scan(g, y0, at<float>(ws, L.C), at<float>(ws, L.QN), at<float>(ws, L.LN),
+                              at<float>(ws, L.Y), at<float>(ws, L.LAM), at<double>(ws, L.RED),
+                              L.scan_blocks, s)) != hipSuccess)
+    return hip_fail(e, "scan");
+  return FBSDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fbsde_status_str(fbsde_status s) {
+  switch (s) {
+    case FBSDE_OK: return "ok";
+    case FBSDE_ERR_INVALID: return "invalid argument";
+    case FBSDE_ERR_UNSUPPORTED: return "unsupported";
+    case FBSDE_ERR_HIP: return "HIP error";
+    case FBSDE_ERR_NOMEM: return "out of memory";
+    case FBSDE_ERR_NONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+const char* fbsde_last_error(void) { return g_last_error.c_str(); }
+
+fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* net, int32_t N, int64_t M,
+                               fbsde_plan** out) {
+  if (!out) return fail(FBSDE_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!problem || !net) return fail(FBSDE_ERR_INVALID, "problem or net is NULL");
+  const fbsde_problem& p = *problem;
+  if (p.d < 1) return fail(FBSDE_ERR_INVALID, "d must be >= 1");
+  if (!(p.T > 0.0) || !std::isfinite(p.T)) return fail(FBSDE_ERR_INVALID, "T must be finite and > 0");
+  if (!p.x0_host) return fail(FBSDE_ERR_INVALID, "x0_host is NULL");
+  if (!finite_all(p.x0_host, p.d)) return fail(FBSDE_ERR_INVALID, "x0 is not finite");
+  if (p.sde < 0 || p.sde > 1) return fail(FBSDE_ERR_INVALID, "unknown sde");
+  if (p.drv < 0 || p.drv > 3) return fail(FBSDE_ERR_INVALID, "unknown driver");
+  if (p.g < 0 || p.g > 3) return fail(FBSDE_ERR_INVALID, "unknown terminal condition");
+  if (!finite_all(p.sde_p, 2) || !finite_all(p.drv_p, 2) || !finite_all(p.g_p, 2))
+    return fail(FBSDE_ERR_INVALID, "problem parameters are not finite");
+  if (N < 1) return fail(FBSDE_ERR_INVALID, "N must be >= 1");
+  if (M < 1 || M > 0x7fffffffLL) return fail(FBSDE_ERR_INVALID, "M must be in [1, 2^31)");
+  if (net->kind != FBSDE_NET_PER_STEP_MLP && net->kind != FBSDE_NET_SHARED_RESNET)
+    return fail(FBSDE_ERR_INVALID, "unknown network kind");
+  if (net->prec != FBSDE_FP32 && net->prec != FBSDE_BF16_MFMA) return fail(FBSDE_ERR_INVALID, "unknown precision");
+  if (net->width < 1 || net->depth < 1) return fail(FBSDE_ERR_INVALID, "width and depth must be >= 1");
+  if (net->kind == FBSDE_NET_SHARED_RESNET)
+    return fail(FBSDE_ERR_UNSUPPORTED, "shared residual network is not implemented in this build");
+  if (p.d > 256 || net->width > 256 || net->depth > 8)
+    return fail(FBSDE_ERR_UNSUPPORTED, "per-step MLP kernels support d <= 256, width <= 256, depth <= 8");
+
+  fbsde_plan* P = new (std::nothrow) fbsde_plan();
+  if (!P) return fail(FBSDE_ERR_NOMEM, "host allocation failed");
+  P->prob = p;
+  P->prob.x0_host = nullptr;
+  P->net = *net;
+  P->N = N;
+  P->M = M;
+  Geo& g = P->geo;
+  const bool bf = net->prec == FBSDE_BF16_MFMA;
+  g.d = p.d;
+  g.dp = (p.d + 3) / 4 * 4;
+  g.w = net->width;
+  g.L = net->depth;
+  g.N = N;
+  g.M = (int)M;
+  if (!fbsde::choose_tiles(bf ? 1 : 0, tiles(p.d, bf), tiles(net->width, bf), &g.ti, &g.tw)) {
+    delete P;
+    return fail(FBSDE_ERR_UNSUPPORTED, "no fused-MLP tile shape covers this d and width");
+  }
+  g.zp = 16 * g.ti;
+  g.wp = 16 * g.tw;
+  g.bf16 = bf ? 1 : 0;
+  g.sde = p.sde;
+  g.sde_s = (float)p.sde_p[0];
+  g.drv = p.drv;
+  g.drv_p0 = (float)p.drv_p[0];
+  g.drv_p1 = (float)p.drv_p[1];
+  g.g = p.g;
+  g.g_p0 = (float)p.g_p[0];
+  g.g_p1 = (float)p.g_p[1];
+  g.dt = (float)(p.T / N);
+  g.sqdt = (float)std::sqrt(p.T / N);
+  const long long d = p.d, w = net->width, L = net->depth;
+  g.pstep = w * d + w + (L - 1) * (w * w + w) + d * w + d;
+  g.nparams = d + (long long)(N - 1) * g.pstep;
+  g.packf_step = 256LL * (g.tw * g.ti + (L - 1) * g.tw * g.tw + g.ti * g.tw);
+  g.packb_step = 256LL * (g.tw * g.ti + (L - 1) * g.tw * g.tw);
+  make_layout(P);
+
+  hipError_t e = hipGetDevice(&P->device);
+  if (e != hipSuccess) {
+    delete P;
+    return hip_fail(e, "hipGetDevice");
+  }
+  e = hipMalloc(&P->x0_dev, (size_t)g.dp * sizeof(float));
+  if (e != hipSuccess) {
+    delete P;
+    return fail(FBSDE_ERR_NOMEM, std::string("hipMalloc x0: ") + hipGetErrorString(e));
+  }
+  float* tmp = new float[g.dp];
+  for (int i = 0; i < g.dp; ++i) tmp[i] = i < p.d ? (float)problem->x0_host[i] : 0.f;
+  e = hipMemcpy(P->x0_dev, tmp, (size_t)g.dp * sizeof(float), hipMemcpyHostToDevice);
+  delete[] tmp;
+  if (e != hipSuccess) {
+    (void)hipFree(P->x0_dev);
+    delete P;
+    return hip_fail(e, "hipMemcpy x0");
+  }
+  *out = P;
+  return FBSDE_OK;
+}
+
+void fbsde_plan_destroy(fbsde_plan* plan) {
+  if (!plan) return;
+  if (plan->x0_dev) (void)hipFree(plan->x0_dev);
+  delete plan;
+}
+
+fbsde_status fbsde_param_count(const fbsde_plan* plan, int64_t* n) {
+  if (!plan || !n) return fail(FBSDE_ERR_INVALID, "plan or output is NULL");
+  *n = plan->geo.nparams;
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_workspace_size(const fbsde_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(FBSDE_ERR_INVALID, "plan or output is NULL");
+  *bytes = plan->ws.total;
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_forward(fbsde_plan* plan, const float* params, const double* y0, uint64_t seed,
+                           uint64_t iter, double* loss, void* ws, void* stream) {
+  fbsde_status st = check_hot(plan, ws);
+  if (st != FBSDE_OK) return st;
+  if (!params || !y0 || !loss) return fail(FBSDE_ERR_INVALID, "params, y0 and loss must be non-NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  st = run_forward(plan, params, y0, seed, iter, ws, s);
+  if (st != FBSDE_OK) return st;
+  hipError_t e = fbsde::launch_loss_only(plan->geo, at<double>(ws, plan->ws.RED), plan->ws.scan_blocks, loss, s);
+  if (e != hipSuccess) return hip_fail(e, "finalize");
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_forward_backward(fbsde_plan* plan, const float* params, const double* y0, float* grad,
+                                    double* grad_y0, double* loss, uint64_t seed, uint64_t iter, void* ws,
+                                    void* stream) {
+  fbsde_status st = check_hot(plan, ws);
+  if (st != FBSDE_OK) return st;
+  if (!params || !y0 || !grad || !grad_y0 || !loss)
+    return fail(FBSDE_ERR_INVALID, "params, y0, grad, grad_y0 and loss must be non-NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  st = run_forward(plan, params, y0, seed, iter, ws, s);
+  if (st != FBSDE_OK) return st;
+  const Geo& g = plan->geo;
+  const WsLayout& L = plan->ws;
+  hipError_t e;
+  if ((e = fbsde::launch_backward(g, at<void>(ws, L.PB), at<float>(ws, L.V), at<float>(ws, L.LAM),
+                                  at<void>(ws, L.H), at<void>(ws, L.DZ), at<void>(ws, L.DH), s)) != hipSuccess)
+    return hip_fail(e, "backward");
+  if ((e = fbsde::launch_wgrad(g, at<float>(ws, L.X), at<void>(ws, L.H), at<void>(ws, L.DZ),
+                               at<void>(ws, L.DH), at<float>(ws, L.PART), L.splits, L.chunk, s)) != hipSuccess)
+    return hip_fail(e, "wgrad");
+  if ((e = fbsde::launch_reduce(g, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
+                                L.scan_blocks, loss, grad_y0, s)) != hipSuccess)
+    return hip_fail(e, "reduce");
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_adam_step(fbsde_plan* plan, float* params, double* y0, const float* grad,
+                             const double* grad_y0, float* m, float* v, double* m_y0, double* v_y0, int64_t t,
+                             double lr, double lr_y0, double b1, double b2, double eps, void* stream) {
+  if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
+  if (!params || !grad || !m || !v) return fail(FBSDE_ERR_INVALID, "params, grad, m, v must be non-NULL");
+  const bool with_y0 = y0 != nullptr;
+  if (with_y0 && (!grad_y0 || !m_y0 || !v_y0))
+    return fail(FBSDE_ERR_INVALID, "y0 given without grad_y0, m_y0, v_y0");
+  if (t < 1) return fail(FBSDE_ERR_INVALID, "Adam step count must be >= 1");
+  if (!(lr >= 0) || !(lr_y0 >= 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+    return fail(FBSDE_ERR_INVALID, "Adam hyper-parameters out of range");
+  const double c1 = 1.0 - std::pow(b1, (double)t), c2 = 1.0 - std::pow(b2, (double)t);
+  hipError_t e = fbsde::launch_adam(plan->geo.nparams, params, grad, m, v, y0, grad_y0, m_y0, v_y0, (float)lr,
+                                    (float)c1, (float)c2, lr_y0, c1, c2, b1, b2, eps,
+                                    reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "adam");
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_prolong(const fbsde_plan* coarse, const fbsde_plan* fine, const float* pc, float* pf,
+                           void* stream) {
+  if (!coarse || !fine || !pc || !pf) return fail(FBSDE_ERR_INVALID, "NULL argument");
+  const Geo &a = coarse->geo, &b = fine->geo;
+  if (b.N != 2 * a.N) return fail(FBSDE_ERR_INVALID, "fine plan must have twice the steps of the coarse plan");
+  if (a.d != b.d || a.w != b.w || a.L != b.L || coarse->net.kind != fine->net.kind)
+    return fail(FBSDE_ERR_INVALID, "coarse and fine plans must share the problem dimension and network");
+  if (a.N < 2) return fail(FBSDE_ERR_INVALID, "coarse grid needs at least 2 steps to hold a network");
+  hipError_t e = fbsde::launch_prolong(a, b, pc, pf, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "prolong");
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_sample_normals(fbsde_plan* plan, uint64_t seed, uint64_t iter, float* xi, void* stream) {
+  if (!plan || !xi) return fail(FBSDE_ERR_INVALID, "plan or xi is NULL");
+  hipError_t e = fbsde::launch_normals(plan->geo, seed, iter, xi, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "normals");
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_terminal_mean(fbsde_plan* plan, uint64_t seed, uint64_t iter, double* mean, void* ws,
+                                 void* stream) {
+  fbsde_status st = check_hot(plan, ws);
+  if (st != FBSDE_OK) return st;
+  if (!mean) return fail(FBSDE_ERR_INVALID, "mean is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const Geo& g = plan->geo;
+  const WsLayout& L = plan->ws;
+  hipError_t e = fbsde::launch_sde(g, plan->x0_dev, seed, iter, at<float>(ws, L.X), at<float>(ws, L.V),
+                                   at<float>(ws, L.QN), at<float>(ws, L.LN), s);
+  if (e != hipSuccess) return hip_fail(e, "sde");
+  e = fbsde::launch_gmean(g, at<float>(ws, L.QN), at<float>(ws, L.LN), mean, s);
+  if (e != hipSuccess) return hip_fail(e, "gmean");
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_terminal_states(fbsde_plan* plan, const void* ws, float* xN, float* yN, void* stream) {
+  fbsde_status st = check_hot(plan, ws);
+  if (st != FBSDE_OK) return st;
+  if (!xN && !yN) return FBSDE_OK;
+  hipError_t e = fbsde::launch_terminal_copy(plan->geo, at<float>(ws, plan->ws.X), at<float>(ws, plan->ws.Y), xN,
+                                             yN, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "terminal copy");
+  return FBSDE_OK;
+}
+
+}  // extern "C"

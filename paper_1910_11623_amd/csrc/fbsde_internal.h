@@ -1,0 +1,70 @@
+// Internal declarations of the gfx950 deep-FBSDE library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fbsde {
+
+// Plan geometry, passed to every kernel by value.
+struct Geo {
+  int d;      // state dimension
+  int dp;     // row stride of X and V buffers: d rounded up to 4
+  int w;      // hidden width
+  int L;      // hidden layers (MLP)
+  int N;      // time steps
+  int M;      // paths
+  int ti;     // 16-wide register tiles over d (kernel instantiation; even in bf16 mode)
+  int tw;     // 16-wide register tiles over w (kernel instantiation; even in bf16 mode)
+  int zp;     // row stride of zeta buffer  = 16 * ti
+  int wp;     // row stride of hidden buffers = 16 * tw
+  int bf16;   // 1: bf16 MFMA operands
+  int sde;    float sde_s;
+  int drv;    float drv_p0, drv_p1;
+  int g;      float g_p0, g_p1;
+  float dt, sqdt;
+  long long pstep;        // fp32 parameters per time step (per-step MLP)
+  long long nparams;      // total fp32 parameters
+  long long packf_step;   // packed forward fragments per step (elements)
+  long long packb_step;   // packed backward fragments per step (elements)
+};
+
+// Offsets (bytes) of the sub-buffers of one workspace.
+struct WsLayout {
+  size_t X, V, C, Y, LAM, QN, LN, H, DZ, DH, PF, PB, PART, RED, total;
+  int scan_blocks;
+  int splits;
+  long long chunk;
+};
+
+// launchers (kernels.hip); all return hipError_t of the launch
+hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* packB, hipStream_t s);
+hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t iter, float* X, float* V,
+                      float* QN, float* LN, hipStream_t s);
+hipError_t launch_forward(const Geo& g, const float* params, const void* packF, const float* X, float* V,
+                          float* C, void* H, hipStream_t s);
+hipError_t launch_scan(const Geo& g, const double* y0, const float* C, const float* QN, const float* LN,
+                       float* Y, float* LAM, double* part, int blocks, hipStream_t s);
+hipError_t launch_backward(const Geo& g, const void* packB, const float* V, const float* LAM,
+                           const void* H, void* DZ, void* DH, hipStream_t s);
+hipError_t launch_wgrad(const Geo& g, const float* X, const void* H, const void* DZ, const void* DH,
+                        float* part, int splits, long long chunk, hipStream_t s);
+hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* grad, const double* scan_part,
+                         int scan_blocks, double* loss, double* grad_y0, hipStream_t s);
+hipError_t launch_loss_only(const Geo& g, const double* scan_part, int scan_blocks, double* loss,
+                            hipStream_t s);
+hipError_t launch_adam(long long n, float* p, const float* gr, float* m, float* v, double* y0,
+                       const double* gy0, double* my0, double* vy0, float lr, float c1, float c2,
+                       double lr_y0, double c1d, double c2d, double b1, double b2, double eps,
+                       hipStream_t s);
+hipError_t launch_prolong(const Geo& coarse, const Geo& fine, const float* pc, float* pf, hipStream_t s);
+hipError_t launch_normals(const Geo& g, uint64_t seed, uint64_t iter, float* xi, hipStream_t s);
+hipError_t launch_gmean(const Geo& g, const float* QN, const float* LN, double* out, hipStream_t s);
+hipError_t launch_terminal_copy(const Geo& g, const float* X, const float* Y, float* xN, float* yN,
+                                hipStream_t s);
+
+// Register-tile shape of the fused MLP kernels: the smallest instantiated
+// (ti, tw) with ti >= ti_min, tw >= tw_min.  Returns false if none exists.
+bool choose_tiles(int bf16, int ti_min, int tw_min, int* ti, int* tw);
+
+}  // namespace fbsde

@@ -1,0 +1,904 @@
+// gfx950 kernels of the deep-FBSDE hot path.
+//
+// One training iteration (Deep-BSDE form of Sec. 2.2 of Güler, Laignelet,
+// Parpas, arXiv 1910.11623) is, in launch order:
+//   pack      flat fp32 parameters -> MFMA A-fragments (forward W, backward W^T)
+//   sde       Philox + Box–Muller increments, Euler–Maruyama X_n, s_n = sigma(X_n) dW_n
+//             (eq. disc equations; mu = 0), and |X_N|^2, sum X_N per path
+//   forward   per (step n, 64 paths): Z_n = NN_n(X_n) on MFMA, the Z-dependent part
+//             c_n of the Y update and v_n = phi_z dt + s_n
+//   scan      per path: Y_{n+1} = Y_n + dt phi_y(Y_n) + c_n, terminal mismatch,
+//             fp64 loss partials, lambda_n = dL/dY_n, fp64 dL/dY0 partials
+//   backward  per (step n, 64 paths): zeta_n = lambda_{n+1} v_n, deltas through NN_n on MFMA
+//   wgrad     dW = sum over paths of delta (x) activation, split over path ranges
+//   reduce    fixed-order sum of the split partials into the flat gradient
+//
+// Because mu and sigma never depend on (Y, Z), X_n does not depend on the
+// network parameters: every network evaluation of every step runs in
+// parallel; only the scalar Y and lambda recursions are sequential.
+//
+// MFMA operand layouts (16x16 output tiles, wave64): lane l holds
+//   A[row l%16][k-slot l/16], B[k-slot l/16][col l%16], D[4*(l/16)+r][l%16].
+// Activations are kept feature-major ("transposed"): output rows are
+// features, columns are 16 paths, so a layer's D registers serve directly as
+// the next layer's B operand once the K order of the next weight matrix is
+// permuted to match (done once per iteration by the pack kernel).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#include "fbsde_internal.h"
+
+namespace fbsde {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+enum { SDE_GBM = 0, SDE_BM = 1 };
+enum { DRV_BSB = 0, DRV_HJB = 1, DRV_AC = 2, DRV_LIN = 3 };
+enum { G_NORM2 = 0, G_LOGHALF = 1, G_INV = 2, G_LIN = 3 };
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ uint32_t bf16_bits(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ float rbf(float f) { return __uint_as_float(bf16_bits(f) << 16); }
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 pack8(f32x4 lo, f32x4 hi) {
+  u32x4 u;
+  u[0] = bf16_bits(lo[0]) | (bf16_bits(lo[1]) << 16);
+  u[1] = bf16_bits(lo[2]) | (bf16_bits(lo[3]) << 16);
+  u[2] = bf16_bits(hi[0]) | (bf16_bits(hi[1]) << 16);
+  u[3] = bf16_bits(hi[2]) | (bf16_bits(hi[3]) << 16);
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
+
+__device__ __forceinline__ f32x4 ld4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
+__device__ __forceinline__ void st4(float* p, f32x4 v) { *reinterpret_cast<f32x4*>(p) = v; }
+
+// 4 activations of one lane, fp32 or bf16 storage
+__device__ __forceinline__ f32x4 ld_act(const void* base, size_t idx, bool bf) {
+  if (!bf) return ld4(reinterpret_cast<const float*>(base) + idx);
+  uint2 u = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(base) + idx);
+  return f32x4{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+               __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u)};
+}
+__device__ __forceinline__ void st_act(void* base, size_t idx, f32x4 v, bool bf) {
+  if (!bf) { st4(reinterpret_cast<float*>(base) + idx, v); return; }
+  uint2 u;
+  u.x = bf16_bits(v[0]) | (bf16_bits(v[1]) << 16);
+  u.y = bf16_bits(v[2]) | (bf16_bits(v[3]) << 16);
+  *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(base) + idx) = u;
+}
+__device__ __forceinline__ f32x4 round4(f32x4 v, bool bf) {
+  if (!bf) return v;
+  return f32x4{rbf(v[0]), rbf(v[1]), rbf(v[2]), rbf(v[3])};
+}
+
+// ------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw (SC'11): 10 rounds, multipliers 0xD2511F53 and
+// 0xCD9E8D57, Weyl key increments 0x9E3779B9 and 0xBB67AE85.
+__device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+}
+
+// Box–Muller: U = ((a >> 8) + 1) 2^-24 in (0,1], V = (b >> 8) 2^-24 in [0,1).
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
+  const float U = (float)((a >> 8) + 1u) * 5.9604644775390625e-8f;
+  const float V = (float)(b >> 8) * 5.9604644775390625e-8f;
+  const float r = sqrtf(-2.0f * logf(U));
+  float sn, cs;
+  sincospif(2.0f * V, &sn, &cs);
+  z0 = r * cs;
+  z1 = r * sn;
+}
+
+// four normals for dims 4j..4j+3 of path m at step n
+__device__ __forceinline__ f32x4 normals4(uint64_t seed, uint64_t iter, int j, int n, int m) {
+  uint32_t c0 = (uint32_t)j, c1 = (uint32_t)n, c2 = (uint32_t)m, c3 = (uint32_t)iter;
+  philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+  float a0, a1, a2, a3;
+  box_muller(c0, c1, a0, a1);
+  box_muller(c2, c3, a2, a3);
+  return f32x4{a0, a1, a2, a3};
+}
+
+// -------------------------------------------------------------- pack kernel
+// Packed A-fragment of a (R x K) matrix A with 16-row tiles T and K tiles t:
+//   fp32: elem ((T*Ti + t)*64 + lane)*4 + r   <- A[16T + lane%16][16t + 4(lane/16) + r]
+//   bf16: elem ((T*Ti/2 + kb)*64 + lane)*8 + j <- A[16T + lane%16][32kb + 16(j/4) + 4(lane/16) + j%4]
+// (A = W for the forward, A = W^T for the backward.)
+__device__ __forceinline__ float packed_value(const float* W, int rows, int cols, bool trans, int To,
+                                              int Ti, long long e, bool bf) {
+  int row, col;
+  if (!bf) {
+    const int r = (int)(e & 3);
+    const long long q = e >> 2;
+    const int lane = (int)(q & 63);
+    const long long tt = q >> 6;
+    const int t = (int)(tt % Ti), T = (int)(tt / Ti);
+    row = 16 * T + (lane & 15);
+    col = 16 * t + 4 * (lane >> 4) + r;
+  } else {
+    const int j = (int)(e & 7);
+    const long long q = e >> 3;
+    const int lane = (int)(q & 63);
+    const long long tt = q >> 6;
+    const int nkb = Ti / 2;
+    const int kb = (int)(tt % nkb), T = (int)(tt / nkb);
+    row = 16 * T + (lane & 15);
+    col = 32 * kb + 16 * (j >> 2) + 4 * (lane >> 4) + (j & 3);
+  }
+  (void)To;
+  const int R = trans ? cols : rows, K = trans ? rows : cols;
+  if (row >= R || col >= K) return 0.f;
+  return trans ? W[(long long)col * cols + row] : W[(long long)row * cols + col];
+}
+
+__global__ __launch_bounds__(256) void k_pack(Geo g, const float* __restrict__ params,
+                                              void* __restrict__ packF, void* __restrict__ packB) {
+  const long long per = g.packf_step + g.packb_step;
+  const long long total = (long long)(g.N - 1) * per;
+  const bool bf = g.bf16;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+    const int n = 1 + (int)(e / per);
+    long long q = e % per;
+    const float* base = params + g.d + (long long)(n - 1) * g.pstep;
+    const long long lw1 = (long long)g.w * g.d + g.w, lwh = (long long)g.w * g.w + g.w;
+    const long long sz_in = 256LL * g.tw * g.ti, sz_h = 256LL * g.tw * g.tw, sz_o = 256LL * g.ti * g.tw;
+    float val;
+    long long out_idx;
+    if (q < g.packf_step) {  // forward: W1, W2..WL, Wo
+      out_idx = (long long)(n - 1) * g.packf_step + q;
+      if (q < sz_in) {
+        val = packed_value(base, g.w, g.d, false, g.tw, g.ti, q, bf);
+      } else if (q < sz_in + (long long)(g.L - 1) * sz_h) {
+        const long long qq = q - sz_in;
+        const int l = 2 + (int)(qq / sz_h);
+        val = packed_value(base + lw1 + (long long)(l - 2) * lwh, g.w, g.w, false, g.tw, g.tw, qq % sz_h, bf);
+      } else {
+        const long long qq = q - sz_in - (long long)(g.L - 1) * sz_h;
+        val = packed_value(base + lw1 + (long long)(g.L - 1) * lwh, g.d, g.w, false, g.ti, g.tw, qq, bf);
+      }
+      if (bf) reinterpret_cast<uint16_t*>(packF)[out_idx] = (uint16_t)bf16_bits(val);
+      else reinterpret_cast<float*>(packF)[out_idx] = val;
+    } else {  // backward: Wo^T (for delta_L), then W_{l+1}^T for delta_l, l = 1..L-1
+      q -= g.packf_step;
+      out_idx = (long long)(n - 1) * g.packb_step + q;
+      if (q < sz_o) {
+        val = packed_value(base + lw1 + (long long)(g.L - 1) * lwh, g.d, g.w, true, g.tw, g.ti, q, bf);
+      } else {
+        const long long qq = q - sz_o;
+        const int l = 1 + (int)(qq / sz_h);  // delta_l uses W_{l+1}
+        val = packed_value(base + lw1 + (long long)(l - 1) * lwh, g.w, g.w, true, g.tw, g.tw, qq % sz_h, bf);
+      }
+      if (bf) reinterpret_cast<uint16_t*>(packB)[out_idx] = (uint16_t)bf16_bits(val);
+      else reinterpret_cast<float*>(packB)[out_idx] = val;
+    }
+  }
+}
+
+// --------------------------------------------------------------- SDE kernel
+// Thread = (path m, dims 4j..4j+3); a block holds whole paths so that
+// |X_N|^2 and sum X_N reduce in LDS in a fixed order.
+__global__ __launch_bounds__(256) void k_sde(Geo g, const float* __restrict__ x0, uint64_t seed,
+                                             uint64_t iter, float* __restrict__ X, float* __restrict__ V,
+                                             float* __restrict__ QN, float* __restrict__ LN) {
+  __shared__ float sq[256], sl[256];
+  const int G = g.dp / 4;
+  const int ppb = max(1, 256 / G);
+  const int lp = threadIdx.x / G, j = threadIdx.x % G;
+  const int m = blockIdx.x * ppb + lp;
+  const bool active = lp < ppb && m < g.M;
+  float q = 0.f, lin = 0.f;
+  if (active) {
+    f32x4 x = ld4(x0 + 4 * j);
+    const size_t rowM = (size_t)g.M * g.dp;
+    const size_t off = (size_t)m * g.dp + 4 * j;
+    for (int n = 0; n < g.N; ++n) {
+      const f32x4 z = normals4(seed, iter, j, n, m);
+      f32x4 s;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float dw = g.sqdt * z[r];
+        s[r] = (4 * j + r < g.d) ? (g.sde == SDE_GBM ? g.sde_s * x[r] * dw : g.sde_s * dw) : 0.f;
+      }
+      st4(X + n * rowM + off, x);
+      st4(V + n * rowM + off, s);
+      x += s;
+    }
+    st4(X + (size_t)g.N * rowM + off, x);
+    q = x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3];
+    lin = x[0] + x[1] + x[2] + x[3];
+  }
+  sq[threadIdx.x] = q;
+  sl[threadIdx.x] = lin;
+  __syncthreads();
+  if (active && j == 0) {
+    float a = 0.f, b = 0.f;
+    for (int k = 0; k < G; ++k) { a += sq[threadIdx.x + k]; b += sl[threadIdx.x + k]; }
+    QN[m] = a;
+    LN[m] = b;
+  }
+}
+
+// -------------------------------------------------------- MFMA layer product
+// acc[T] = sum_k A_T,k * in_k over all TIN K tiles of `in` (registers, D
+// layout).  Tile counts are compile-time: padded tiles carry zero weights,
+// so there is no runtime guard inside the unrolled MFMA chains.
+template <bool BF, int TO, int TIN>
+__device__ __forceinline__ void layer_mm(f32x4 (&acc)[TO], const f32x4 (&in)[TIN], const void* pack,
+                                         int lane) {
+#pragma unroll
+  for (int T = 0; T < TO; ++T) acc[T] = zero4();
+  if constexpr (!BF) {
+    const f32x4* A = reinterpret_cast<const f32x4*>(pack);
+#pragma unroll
+    for (int t = 0; t < TIN; ++t) {
+      f32x4 a[TO];
+#pragma unroll
+      for (int T = 0; T < TO; ++T) a[T] = A[((size_t)T * TIN + t) * 64 + lane];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int T = 0; T < TO; ++T) acc[T] = mfma_f32(a[T][r], in[t][r], acc[T]);
+    }
+  } else {
+    static_assert(TIN % 2 == 0, "bf16 K blocks span two tiles");
+    const bf16x8* A = reinterpret_cast<const bf16x8*>(pack);
+#pragma unroll
+    for (int kb = 0; kb < TIN / 2; ++kb) {
+      const bf16x8 b = pack8(in[2 * kb], in[2 * kb + 1]);
+#pragma unroll
+      for (int T = 0; T < TO; ++T) acc[T] = mfma_bf16(A[((size_t)T * (TIN / 2) + kb) * 64 + lane], b, acc[T]);
+    }
+  }
+}
+
+__device__ __forceinline__ f32x4 bias4(const float* b, int base, int n) {
+  f32x4 v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = (base + r < n) ? b[base + r] : 0.f;
+  return v;
+}
+
+// ----------------------------------------------------------- forward kernel
+template <bool BF, int TI, int TW>
+__global__ __launch_bounds__(256) void k_forward(Geo g, const float* __restrict__ params,
+                                                 const void* __restrict__ packF,
+                                                 const float* __restrict__ X, float* __restrict__ V,
+                                                 float* __restrict__ C, void* __restrict__ H) {
+  const int n = blockIdx.y;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int p = (blockIdx.x * 4 + wv) * 16 + col;
+  const bool valid = p < g.M;
+  const size_t rowM = (size_t)g.M * g.dp;
+  f32x4 Z[TI];
+  if (n == 0) {
+#pragma unroll
+    for (int t = 0; t < TI; ++t) Z[t] = bias4(params, 16 * t + 4 * grp, g.d);  // Z_0 = z0
+  } else {
+    const float* P = params + g.d + (size_t)(n - 1) * g.pstep;
+    const size_t esz = BF ? 2 : 4;
+    const char* pk = reinterpret_cast<const char*>(packF) + (size_t)(n - 1) * g.packf_step * esz;
+    f32x4 xin[TI];
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      xin[t] = (valid && c0 < g.dp) ? ld4(X + n * rowM + (size_t)p * g.dp + c0) : zero4();
+      xin[t] = round4(xin[t], BF);
+    }
+    f32x4 h[TW], acc[TW];
+    layer_mm<BF, TW, TI>(acc, xin, pk, lane);
+    const float* b = P + (size_t)g.w * g.d;
+    const size_t hM = (size_t)g.M * g.wp;
+#pragma unroll
+    for (int T = 0; T < TW; ++T) {
+      const f32x4 bb = bias4(b, 16 * T + 4 * grp, g.w);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[T][r] = tanhf(acc[T][r] + bb[r]);
+      h[T] = round4(h[T], BF);
+      if (valid)
+        st_act(H, ((size_t)n * g.L) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h[T], BF);
+    }
+    const char* pkl = pk + 256ULL * TW * TI * esz;
+    const float* Pl = b + g.w;
+    for (int l = 2; l <= g.L; ++l) {
+      layer_mm<BF, TW, TW>(acc, h, pkl, lane);
+      const float* bl = Pl + (size_t)g.w * g.w;
+#pragma unroll
+      for (int T = 0; T < TW; ++T) {
+        const f32x4 bb = bias4(bl, 16 * T + 4 * grp, g.w);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[T][r] = tanhf(acc[T][r] + bb[r]);
+        h[T] = round4(h[T], BF);
+        if (valid)
+          st_act(H, ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h[T], BF);
+      }
+      pkl += 256ULL * TW * TW * esz;
+      Pl = bl + g.w;
+    }
+    layer_mm<BF, TI, TW>(Z, h, pkl, lane);
+    const float* bo = Pl + (size_t)g.d * g.w;
+#pragma unroll
+    for (int t = 0; t < TI; ++t) Z[t] += bias4(bo, 16 * t + 4 * grp, g.d);
+  }
+  // epilogue: c_n = Z.s + dt * (Z-part of phi), v_n = s + dt * phi_z
+  float cz = 0.f, cx = 0.f;
+#pragma unroll
+  for (int t = 0; t < TI; ++t) {
+    const int c0 = 16 * t + 4 * grp;
+    if (valid && c0 < g.dp) {
+      float* vp = V + n * rowM + (size_t)p * g.dp + c0;
+      const f32x4 s = ld4(vp);
+      f32x4 v = s;
+      if (g.drv == DRV_BSB) {
+        const f32x4 x = ld4(X + n * rowM + (size_t)p * g.dp + c0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          cz += Z[t][r] * s[r];
+          cx += Z[t][r] * x[r];
+          v[r] = s[r] - g.drv_p0 * g.dt * x[r];
+        }
+      } else if (g.drv == DRV_HJB) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          cz += Z[t][r] * s[r];
+          cx += Z[t][r] * Z[t][r];
+          v[r] = s[r] + 2.f * g.drv_p0 * g.dt * Z[t][r];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cz += Z[t][r] * s[r];
+      }
+      st4(vp, v);
+    }
+  }
+  float c = cz;
+  if (g.drv == DRV_BSB) c -= g.dt * g.drv_p0 * cx;
+  else if (g.drv == DRV_HJB) c += g.dt * g.drv_p0 * cx;
+  c += __shfl_xor(c, 16);
+  c += __shfl_xor(c, 32);
+  if (valid && grp == 0) C[(size_t)n * g.M + p] = c;
+}
+
+// -------------------------------------------------------------- scan kernel
+__device__ __forceinline__ float phi_y(const Geo& g, float y) {
+  switch (g.drv) {
+    case DRV_BSB: return g.drv_p0 * y;
+    case DRV_HJB: return 0.f;
+    case DRV_AC: return y * y * y - y;
+    default: return g.drv_p0 * y + g.drv_p1;
+  }
+}
+__device__ __forceinline__ float phi_yy(const Geo& g, float y) {
+  switch (g.drv) {
+    case DRV_BSB: return g.drv_p0;
+    case DRV_HJB: return 0.f;
+    case DRV_AC: return 3.f * y * y - 1.f;
+    default: return g.drv_p0;
+  }
+}
+__device__ __forceinline__ float terminal_g(const Geo& g, float q, float lin) {
+  switch (g.g) {
+    case G_NORM2: return q;
+    case G_LOGHALF: return logf(0.5f * (1.f + q));
+    case G_INV: return 1.f / (g.g_p0 + g.g_p1 * q);
+    default: return g.g_p0 * lin + g.g_p1;
+  }
+}
+
+// fixed-order fp64 block sum of 256 values (result valid in thread 0)
+__device__ __forceinline__ double block_sum_256(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_scan(Geo g, const double* __restrict__ y0,
+                                              const float* __restrict__ C, const float* __restrict__ QN,
+                                              const float* __restrict__ LN, float* __restrict__ Y,
+                                              float* __restrict__ LAM, double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  double l2 = 0.0, lam0 = 0.0;
+  if (m < g.M) {
+    float y = (float)y0[0];
+    Y[m] = y;
+    for (int n = 0; n < g.N; ++n) {
+      y = y + g.dt * phi_y(g, y) + C[(size_t)n * g.M + m];
+      Y[(size_t)(n + 1) * g.M + m] = y;
+    }
+    const float e = y - terminal_g(g, QN[m], LN[m]);
+    l2 = (double)e * (double)e;
+    float lam = 2.f * e / (float)g.M;
+    for (int n = g.N - 1; n >= 0; --n) {
+      LAM[(size_t)n * g.M + m] = lam;
+      lam = lam * (1.f + g.dt * phi_yy(g, Y[(size_t)n * g.M + m]));
+    }
+    lam0 = (double)lam;
+  }
+  const double a = block_sum_256(l2, sh);
+  __syncthreads();
+  const double b = block_sum_256(lam0, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
+  }
+}
+
+// ---------------------------------------------------------- backward kernel
+template <bool BF, int TI, int TW>
+__global__ __launch_bounds__(256) void k_backward(Geo g, const void* __restrict__ packB,
+                                                  const float* __restrict__ V,
+                                                  const float* __restrict__ LAM,
+                                                  const void* __restrict__ H, void* __restrict__ DZ,
+                                                  void* __restrict__ DH) {
+  const int n = blockIdx.y;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int p = (blockIdx.x * 4 + wv) * 16 + col;
+  const bool valid = p < g.M;
+  const size_t rowM = (size_t)g.M * g.dp;
+  const float lam = valid ? LAM[(size_t)n * g.M + p] : 0.f;
+  f32x4 zeta[TI];
+#pragma unroll
+  for (int t = 0; t < TI; ++t) {
+    const int c0 = 16 * t + 4 * grp;
+    f32x4 v = (valid && c0 < g.dp) ? ld4(V + n * rowM + (size_t)p * g.dp + c0) : zero4();
+    zeta[t] = round4(lam * v, BF);
+    if (valid) st_act(DZ, ((size_t)n * g.M + p) * g.zp + c0, zeta[t], BF);
+  }
+  if (n == 0) return;
+  const size_t esz = BF ? 2 : 4;
+  const char* pk = reinterpret_cast<const char*>(packB) + (size_t)(n - 1) * g.packb_step * esz;
+  const size_t hM = (size_t)g.M * g.wp;
+  f32x4 dl[TW], acc[TW];
+  layer_mm<BF, TW, TI>(acc, zeta, pk, lane);
+  {
+    const int l = g.L;
+#pragma unroll
+    for (int T = 0; T < TW; ++T) {
+      const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
+      const f32x4 h = valid ? ld_act(H, idx, BF) : zero4();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dl[T][r] = acc[T][r] * (1.f - h[r] * h[r]);
+      dl[T] = round4(dl[T], BF);
+      if (valid) st_act(DH, idx, dl[T], BF);
+    }
+  }
+  const char* pkl = pk + 256ULL * TW * TI * esz;
+  for (int l = g.L - 1; l >= 1; --l) {
+    layer_mm<BF, TW, TW>(acc, dl, pkl + (size_t)(l - 1) * 256ULL * TW * TW * esz, lane);
+#pragma unroll
+    for (int T = 0; T < TW; ++T) {
+      const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
+      const f32x4 h = valid ? ld_act(H, idx, BF) : zero4();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dl[T][r] = acc[T][r] * (1.f - h[r] * h[r]);
+      dl[T] = round4(dl[T], BF);
+      if (valid) st_act(DH, idx, dl[T], BF);
+    }
+  }
+}
+
+// ------------------------------------------------------------- wgrad kernel
+// Job 0: dz0 = sum_m zeta_0 (a d x 0 "matrix" with only its bias column).
+// Job 1 + (n-1)(L+1) + (l-1), l = 1..L+1: dW_l of step n (bias as column cols).
+struct Job {
+  int rows, cols;
+  long long base;          // flat offset of W_l (b_l follows at base + rows*cols)
+  const void* A; int sA;   // deltas, row stride (per path)
+  const void* B; int sB;   // activations (nullptr: none)
+  bool Bf32;               // B is fp32 path state (X) rather than an activation
+};
+
+__device__ __forceinline__ Job job_info(const Geo& g, int job, const float* X, const void* H,
+                                        const void* DZ, const void* DH) {
+  Job J;
+  const size_t esz = g.bf16 ? 2 : 4;
+  if (job == 0) {
+    J.rows = g.d; J.cols = 0; J.base = 0;
+    J.A = DZ; J.sA = g.zp; J.B = nullptr; J.sB = 0; J.Bf32 = false;
+    return J;
+  }
+  const int jj = job - 1;
+  const int n = 1 + jj / (g.L + 1), l = 1 + jj % (g.L + 1);
+  const size_t hM = (size_t)g.M * g.wp;
+  const long long step = g.d + (long long)(n - 1) * g.pstep;
+  const long long lw1 = (long long)g.w * g.d + g.w, lwh = (long long)g.w * g.w + g.w;
+  J.rows = (l == g.L + 1) ? g.d : g.w;
+  J.cols = (l == 1) ? g.d : g.w;
+  J.base = step + (l == 1 ? 0 : lw1 + (long long)(l - 2) * lwh);
+  if (l == g.L + 1) {
+    J.A = reinterpret_cast<const char*>(DZ) + (size_t)n * g.M * g.zp * esz; J.sA = g.zp;
+  } else {
+    J.A = reinterpret_cast<const char*>(DH) + ((size_t)n * g.L + (l - 1)) * hM * esz; J.sA = g.wp;
+  }
+  if (l == 1) {
+    J.B = X + (size_t)n * g.M * g.dp; J.sB = g.dp; J.Bf32 = true;
+  } else {
+    J.B = reinterpret_cast<const char*>(H) + ((size_t)n * g.L + (l - 2)) * hM * esz; J.sB = g.wp;
+    J.Bf32 = false;
+  }
+  return J;
+}
+
+template <bool BF>
+__device__ __forceinline__ float ldA(const Job& J, int p, int row) {
+  if (BF) return bf2f(reinterpret_cast<const uint16_t*>(J.A)[(size_t)p * J.sA + row]);
+  return reinterpret_cast<const float*>(J.A)[(size_t)p * J.sA + row];
+}
+template <bool BF>
+__device__ __forceinline__ float ldB(const Job& J, int p, int c) {
+  if (c == J.cols) return 1.f;
+  if (c > J.cols) return 0.f;
+  if (J.Bf32) {
+    const float x = reinterpret_cast<const float*>(J.B)[(size_t)p * J.sB + c];
+    return BF ? rbf(x) : x;
+  }
+  if (BF) return bf2f(reinterpret_cast<const uint16_t*>(J.B)[(size_t)p * J.sB + c]);
+  return reinterpret_cast<const float*>(J.B)[(size_t)p * J.sB + c];
+}
+
+template <bool BF>
+__global__ __launch_bounds__(256) void k_wgrad(Geo g, const float* __restrict__ X,
+                                               const void* __restrict__ H, const void* __restrict__ DZ,
+                                               const void* __restrict__ DH, float* __restrict__ part,
+                                               long long chunk) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c16 = lane & 15, grp = lane >> 4;
+  const Job J = job_info(g, blockIdx.y, X, H, DZ, DH);
+  const int ncb = (J.cols + 1 + 63) / 64, nrb = (J.rows + 63) / 64;
+  const int bx = blockIdx.x;
+  if (bx >= ncb * nrb) return;
+  const int R0 = (bx / ncb) * 64 + (wv >> 1) * 32;
+  const int C0 = (bx % ncb) * 64 + (wv & 1) * 32;
+  if (R0 >= J.rows || C0 >= J.cols + 1) return;
+  const long long p0 = (long long)blockIdx.z * chunk;
+  const long long p1 = min((long long)g.M, p0 + chunk);
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = zero4();
+  if constexpr (!BF) {
+    for (long long pb = p0; pb < p1; pb += 4) {
+      const long long pp = pb + grp;
+      const bool ok = pp < p1;
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = R0 + 16 * i + c16;
+        a[i] = (ok && row < J.rows) ? ldA<false>(J, (int)pp, row) : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = ok ? ldB<false>(J, (int)pp, C0 + 16 * j + c16) : 0.f;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
+    }
+  } else {
+    for (long long pb = p0; pb < p1; pb += 32) {
+      f32x4 a[2][2], b[2][2];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const long long pp = pb + 8 * grp + k;
+        const bool ok = pp < p1;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int row = R0 + 16 * i + c16;
+          a[i][k >> 2][k & 3] = (ok && row < J.rows) ? ldA<true>(J, (int)pp, row) : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j][k >> 2][k & 3] = ok ? ldB<true>(J, (int)pp, C0 + 16 * j + c16) : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = mfma_bf16(pack8(a[i][0], a[i][1]), pack8(b[j][0], b[j][1]), acc[i][j]);
+    }
+  }
+  float* out = part + (size_t)blockIdx.z * g.nparams;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = R0 + 16 * i + 4 * grp + r, c = C0 + 16 * j + c16;
+        if (row < J.rows && c <= J.cols) {
+          const long long off = (c < J.cols) ? J.base + (long long)row * J.cols + c
+                                             : J.base + (long long)J.rows * J.cols + row;
+          out[off] = acc[i][j][r];
+        }
+      }
+}
+
+// ------------------------------------------------------------ reduce kernel
+__global__ __launch_bounds__(256) void k_reduce(long long P, const float* __restrict__ part, int splits,
+                                                float* __restrict__ grad) {
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < P; e += (long long)gridDim.x * 256) {
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part[(size_t)k * P + e];
+    grad[e] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(int M, const double* __restrict__ sp, int nb,
+                                                  double* __restrict__ loss, double* __restrict__ gy0) {
+  __shared__ double sh[256];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) { a += sp[2 * k]; b += sp[2 * k + 1]; }
+  const double A = block_sum_256(a, sh);
+  __syncthreads();
+  const double B = block_sum_256(b, sh);
+  if (threadIdx.x == 0) {
+    if (loss) loss[0] = A / (double)M;
+    if (gy0) gy0[0] = B;
+  }
+}
+
+// -------------------------------------------------------------- Adam kernel
+__global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p, const float* __restrict__ gr,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              double* __restrict__ y0, const double* __restrict__ gy0,
+                                              double* __restrict__ my0, double* __restrict__ vy0, float lr,
+                                              float c1, float c2, double lr_y0, double c1d, double c2d,
+                                              double b1d, double b2d, double epsd) {
+  const float b1 = (float)b1d, b2 = (float)b2d, eps = (float)epsd;
+  const long long i0 = blockIdx.x * 256LL + threadIdx.x;
+  for (long long i = i0; i < n; i += (long long)gridDim.x * 256) {
+    const float gi = gr[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+  if (i0 == 0 && y0) {
+    const double gi = gy0[0];
+    const double mi = b1d * my0[0] + (1.0 - b1d) * gi;
+    const double vi = b2d * vy0[0] + (1.0 - b2d) * gi * gi;
+    my0[0] = mi;
+    vy0[0] = vi;
+    y0[0] -= lr_y0 * (mi / c1d) / (sqrt(vi / c2d) + epsd);
+  }
+}
+
+// --------------------------------------------------------- prolong kernel
+__global__ __launch_bounds__(256) void k_prolong(int d, long long pstep, int Nc, long long Pf,
+                                                 const float* __restrict__ pc, float* __restrict__ pf) {
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < Pf; e += (long long)gridDim.x * 256) {
+    if (e < d) { pf[e] = pc[e]; continue; }
+    const long long q = e - d;
+    const int j = 1 + (int)(q / pstep);
+    int c = j / 2;
+    c = c < 1 ? 1 : (c > Nc - 1 ? Nc - 1 : c);
+    pf[e] = pc[d + (long long)(c - 1) * pstep + q % pstep];
+  }
+}
+
+// ---------------------------------------------------------- test hooks
+__global__ __launch_bounds__(256) void k_normals(Geo g, uint64_t seed, uint64_t iter, float* __restrict__ xi) {
+  const int G = g.dp / 4;
+  const long long total = (long long)g.N * g.M * G;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+    const int j = (int)(e % G);
+    const long long q = e / G;
+    const int m = (int)(q % g.M), n = (int)(q / g.M);
+    const f32x4 z = normals4(seed, iter, j, n, m);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (4 * j + r < g.d) xi[((size_t)n * g.M + m) * g.d + 4 * j + r] = z[r];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gmean(Geo g, const float* __restrict__ QN, const float* __restrict__ LN,
+                                               double* __restrict__ out) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int m = threadIdx.x; m < g.M; m += 256) a += (double)terminal_g(g, QN[m], LN[m]);
+  const double A = block_sum_256(a, sh);
+  if (threadIdx.x == 0) out[0] = A / (double)g.M;
+}
+
+__global__ __launch_bounds__(256) void k_terminal_copy(Geo g, const float* __restrict__ X,
+                                                       const float* __restrict__ Y, float* __restrict__ xN,
+                                                       float* __restrict__ yN) {
+  const long long total = (long long)g.M * g.d;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+    const int m = (int)(e / g.d), i = (int)(e % g.d);
+    if (xN) xN[e] = X[((size_t)g.N * g.M + m) * g.dp + i];
+    if (yN && i == 0) yN[m] = Y[(size_t)g.N * g.M + m];
+  }
+}
+
+// ================================================================ launchers
+static inline unsigned grid1(long long n, long long cap = 65536) {
+  long long b = (n + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+
+hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* packB, hipStream_t s) {
+  if (g.N < 2) return hipSuccess;
+  const long long total = (long long)(g.N - 1) * (g.packf_step + g.packb_step);
+  k_pack<<<grid1(total), 256, 0, s>>>(g, params, packF, packB);
+  return hipGetLastError();
+}
+
+hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t iter, float* X, float* V,
+                      float* QN, float* LN, hipStream_t s) {
+  const int G = g.dp / 4;
+  const int ppb = G >= 256 ? 1 : 256 / G;
+  const unsigned blocks = (unsigned)((g.M + ppb - 1) / ppb);
+  k_sde<<<blocks, 256, 0, s>>>(g, x0, seed, iter, X, V, QN, LN);
+  return hipGetLastError();
+}
+
+template <bool BF, int TI, int TW>
+static void fwd_inst(const Geo& g, const float* params, const void* packF, const float* X, float* V, float* C,
+                     void* H, hipStream_t s) {
+  dim3 grid((g.M + 63) / 64, g.N);
+  k_forward<BF, TI, TW><<<grid, 256, 0, s>>>(g, params, packF, X, V, C, H);
+}
+template <bool BF, int TI, int TW>
+static void bwd_inst(const Geo& g, const void* packB, const float* V, const float* LAM, const void* H,
+                     void* DZ, void* DH, hipStream_t s) {
+  dim3 grid((g.M + 63) / 64, g.N);
+  k_backward<BF, TI, TW><<<grid, 256, 0, s>>>(g, packB, V, LAM, H, DZ, DH);
+}
+
+// Instantiated register-tile shapes (TI tiles over d, TW tiles over w).
+// The plan picks the one with the least padded MFMA work that covers the
+// problem; FBSDE_MIN_TILES=k forces both counts to at least k (tests of the
+// padded path).
+struct TileShape { int bf, ti, tw; };
+static const TileShape kShapes[] = {
+    {0, 1, 2}, {0, 2, 2}, {0, 4, 4}, {0, 7, 7}, {0, 8, 8}, {0, 16, 16},
+    {1, 2, 2}, {1, 4, 4}, {1, 8, 8}, {1, 16, 16},
+};
+
+bool choose_tiles(int bf16, int ti_min, int tw_min, int* ti, int* tw) {
+  static const int forced = [] {
+    const char* e = getenv("FBSDE_MIN_TILES");
+    return e ? atoi(e) : 0;
+  }();
+  if (forced > ti_min) ti_min = forced;
+  if (forced > tw_min) tw_min = forced;
+  long long best = -1;
+  for (const TileShape& s : kShapes) {
+    if (s.bf != bf16 || s.ti < ti_min || s.tw < tw_min) continue;
+    const long long cost = (long long)s.ti * s.tw;
+    if (best < 0 || cost < best) { best = cost; *ti = s.ti; *tw = s.tw; }
+  }
+  return best >= 0;
+}
+
+#define FBSDE_DISPATCH(FN, ...)                                                   \
+  do {                                                                            \
+    if (g.bf16) {                                                                 \
+      if (g.ti == 2 && g.tw == 2) FN<true, 2, 2>(__VA_ARGS__);                    \
+      else if (g.ti == 4 && g.tw == 4) FN<true, 4, 4>(__VA_ARGS__);               \
+      else if (g.ti == 8 && g.tw == 8) FN<true, 8, 8>(__VA_ARGS__);               \
+      else if (g.ti == 16 && g.tw == 16) FN<true, 16, 16>(__VA_ARGS__);           \
+      else return hipErrorInvalidValue;                                           \
+    } else {                                                                      \
+      if (g.ti == 1 && g.tw == 2) FN<false, 1, 2>(__VA_ARGS__);                   \
+      else if (g.ti == 2 && g.tw == 2) FN<false, 2, 2>(__VA_ARGS__);              \
+      else if (g.ti == 4 && g.tw == 4) FN<false, 4, 4>(__VA_ARGS__);              \
+      else if (g.ti == 7 && g.tw == 7) FN<false, 7, 7>(__VA_ARGS__);              \
+      else if (g.ti == 8 && g.tw == 8) FN<false, 8, 8>(__VA_ARGS__);              \
+      else if (g.ti == 16 && g.tw == 16) FN<false, 16, 16>(__VA_ARGS__);          \
+      else return hipErrorInvalidValue;                                           \
+    }                                                                             \
+  } while (0)
+
+hipError_t launch_forward(const Geo& g, const float* params, const void* packF, const float* X, float* V,
+                          float* C, void* H, hipStream_t s) {
+  FBSDE_DISPATCH(fwd_inst, g, params, packF, X, V, C, H, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const Geo& g, const double* y0, const float* C, const float* QN, const float* LN,
+                       float* Y, float* LAM, double* part, int blocks, hipStream_t s) {
+  k_scan<<<blocks, 256, 0, s>>>(g, y0, C, QN, LN, Y, LAM, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const Geo& g, const void* packB, const float* V, const float* LAM,
+                           const void* H, void* DZ, void* DH, hipStream_t s) {
+  FBSDE_DISPATCH(bwd_inst, g, packB, V, LAM, H, DZ, DH, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad(const Geo& g, const float* X, const void* H, const void* DZ, const void* DH,
+                        float* part, int splits, long long chunk, hipStream_t s) {
+  const int maxr = g.d > g.w ? g.d : g.w;
+  const int maxc = (g.d > g.w ? g.d : g.w) + 1;
+  const unsigned bx = (unsigned)(((maxr + 63) / 64) * ((maxc + 63) / 64));
+  const unsigned jobs = 1u + (unsigned)(g.N - 1) * (unsigned)(g.L + 1);
+  dim3 grid(bx, jobs, splits);
+  if (g.bf16) k_wgrad<true><<<grid, 256, 0, s>>>(g, X, H, DZ, DH, part, chunk);
+  else k_wgrad<false><<<grid, 256, 0, s>>>(g, X, H, DZ, DH, part, chunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* grad, const double* scan_part,
+                         int scan_blocks, double* loss, double* grad_y0, hipStream_t s) {
+  k_reduce<<<grid1(g.nparams, 4096), 256, 0, s>>>(g.nparams, part, splits, grad);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_finalize<<<1, 256, 0, s>>>(g.M, scan_part, scan_blocks, loss, grad_y0);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_only(const Geo& g, const double* scan_part, int scan_blocks, double* loss,
+                            hipStream_t s) {
+  k_finalize<<<1, 256, 0, s>>>(g.M, scan_part, scan_blocks, loss, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(long long n, float* p, const float* gr, float* m, float* v, double* y0,
+                       const double* gy0, double* my0, double* vy0, float lr, float c1, float c2,
+                       double lr_y0, double c1d, double c2d, double b1, double b2, double eps,
+                       hipStream_t s) {
+  k_adam<<<grid1(n, 8192), 256, 0, s>>>(n, p, gr, m, v, y0, gy0, my0, vy0, lr, c1, c2, lr_y0, c1d, c2d, b1, b2,
+                                        eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const Geo& coarse, const Geo& fine, const float* pc, float* pf, hipStream_t s) {
+  k_prolong<<<grid1(fine.nparams, 8192), 256, 0, s>>>(fine.d, fine.pstep, coarse.N, fine.nparams, pc, pf);
+  return hipGetLastError();
+}
+
+hipError_t launch_normals(const Geo& g, uint64_t seed, uint64_t iter, float* xi, hipStream_t s) {
+  const long long total = (long long)g.N * g.M * (g.dp / 4);
+  k_normals<<<grid1(total), 256, 0, s>>>(g, seed, iter, xi);
+  return hipGetLastError();
+}
+
+hipError_t launch_gmean(const Geo& g, const float* QN, const float* LN, double* out, hipStream_t s) {
+  k_gmean<<<1, 256, 0, s>>>(g, QN, LN, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_terminal_copy(const Geo& g, const float* X, const float* Y, float* xN, float* yN,
+                                hipStream_t s) {
+  k_terminal_copy<<<grid1((long long)g.M * g.d), 256, 0, s>>>(g, X, Y, xN, yN);
+  return hipGetLastError();
+}
+
+}  // namespace fbsde

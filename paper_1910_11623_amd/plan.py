@@ -1,0 +1,138 @@
+"""Plan objects over the C ABI, with torch tensors as device memory.
+
+``Plan`` owns one fbsde_plan and one workspace tensor; every method is one
+call into libfbsde.so on torch's current HIP stream.  ``FBSDELoss`` exposes
+the fused forward + hand-written reverse sweep as a torch.autograd.Function.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import binding as B
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """One (problem, network, N, M) configuration of the hot path."""
+
+    def __init__(self, problem: dict, net: dict, N: int, M: int, device: str | torch.device = "cuda"):
+        self.lib = B.load()
+        self.problem, self.net, self.N, self.M = problem, dict(net), int(N), int(M)
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        with torch.cuda.device(self.device):
+            ps, keep = B.make_problem(problem)
+            ns = B.make_net(self.net)
+            h = C.c_void_p()
+            B.check(self.lib.fbsde_plan_create(C.byref(ps), C.byref(ns), self.N, self.M, C.byref(h)))
+            self._h = h
+            del keep
+            n = C.c_int64()
+            B.check(self.lib.fbsde_param_count(self._h, C.byref(n)))
+            self.n_params = int(n.value)
+            sz = C.c_size_t()
+            B.check(self.lib.fbsde_workspace_size(self._h, C.byref(sz)))
+            self.ws_bytes = int(sz.value)
+            # +256 so that the workspace can be aligned to 256 bytes
+            self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self._ws_raw.data_ptr()) % 256
+            self.ws = self._ws_raw[off:off + self.ws_bytes]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                self.lib.fbsde_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # ---------------------------------------------------------------- calls
+    def _check_params(self, params: torch.Tensor):
+        if params.dtype != torch.float32 or params.numel() != self.n_params or not params.is_contiguous():
+            raise ValueError(f"params must be a contiguous fp32 tensor of {self.n_params} elements")
+        if params.device != self.device:
+            raise ValueError("params must live on the plan's device")
+
+    def forward(self, params: torch.Tensor, y0: torch.Tensor, seed: int, it: int,
+                loss: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_params(params)
+        if loss is None:
+            loss = torch.empty((), dtype=torch.float64, device=self.device)
+        B.check(self.lib.fbsde_forward(self._h, _ptr(params), _ptr(y0), seed, it, _ptr(loss),
+                                       _ptr(self.ws), _stream()))
+        return loss
+
+    def forward_backward(self, params: torch.Tensor, y0: torch.Tensor, seed: int, it: int,
+                         out: tuple | None = None):
+        """Returns (loss fp64 scalar, grad fp32 [n_params], grad_y0 fp64 scalar)."""
+        self._check_params(params)
+        if out is None:
+            loss = torch.empty((), dtype=torch.float64, device=self.device)
+            grad = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+            gy0 = torch.empty((), dtype=torch.float64, device=self.device)
+        else:
+            loss, grad, gy0 = out
+        B.check(self.lib.fbsde_forward_backward(self._h, _ptr(params), _ptr(y0), _ptr(grad), _ptr(gy0),
+                                                _ptr(loss), seed, it, _ptr(self.ws), _stream()))
+        return loss, grad, gy0
+
+    def adam_step(self, params, y0, grad, gy0, m, v, my0, vy0, t: int, lr: float = 1e-3,
+                  lr_y0: float | None = None, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+        B.check(self.lib.fbsde_adam_step(self._h, _ptr(params), _ptr(y0), _ptr(grad), _ptr(gy0), _ptr(m),
+                                         _ptr(v), _ptr(my0), _ptr(vy0), int(t), float(lr),
+                                         float(lr if lr_y0 is None else lr_y0), float(b1), float(b2),
+                                         float(eps), _stream()))
+
+    def prolong_to(self, fine: "Plan", params: torch.Tensor) -> torch.Tensor:
+        self._check_params(params)
+        out = torch.empty(fine.n_params, dtype=torch.float32, device=self.device)
+        B.check(self.lib.fbsde_prolong(self._h, fine._h, _ptr(params), _ptr(out), _stream()))
+        return out
+
+    def sample_normals(self, seed: int, it: int) -> torch.Tensor:
+        xi = torch.empty((self.N, self.M, int(self.problem["d"])), dtype=torch.float32, device=self.device)
+        B.check(self.lib.fbsde_sample_normals(self._h, seed, it, _ptr(xi), _stream()))
+        return xi
+
+    def terminal_mean(self, seed: int, it: int) -> torch.Tensor:
+        out = torch.empty((), dtype=torch.float64, device=self.device)
+        B.check(self.lib.fbsde_terminal_mean(self._h, seed, it, _ptr(out), _ptr(self.ws), _stream()))
+        return out
+
+    def terminal_states(self):
+        d = int(self.problem["d"])
+        xN = torch.empty((self.M, d), dtype=torch.float32, device=self.device)
+        yN = torch.empty(self.M, dtype=torch.float32, device=self.device)
+        B.check(self.lib.fbsde_terminal_states(self._h, _ptr(self.ws), _ptr(xN), _ptr(yN), _stream()))
+        return xN, yN
+
+
+class FBSDELoss(torch.autograd.Function):
+    """loss = FBSDELoss.apply(params, y0, plan, seed, it).
+
+    The forward call runs the fused forward and the hand-written reverse
+    sweep at once (the loss and its gradient come from one pass over the
+    paths); backward only scales the stored gradient."""
+
+    @staticmethod
+    def forward(ctx, params, y0, plan: Plan, seed: int, it: int):
+        loss, grad, gy0 = plan.forward_backward(params.detach(), y0.detach(), seed, it)
+        ctx.save_for_backward(grad, gy0)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gout):
+        grad, gy0 = ctx.saved_tensors
+        return grad * gout.to(grad.dtype), gy0 * gout, None, None, None
