@@ -1,0 +1,335 @@
+#!/usr/bin/env python3
+"""Throughput and time-to-accuracy of the deep-FBSDE hot path on one GPU.
+
+Workload (the throughput configuration): Black–Scholes–Barenblatt, d = 100,
+T = 1, r = 0.05, sigma = 0.4, x0 = (1, 0.5, ...), M = 4096 paths, N = 32
+steps, one MLP per step (2 hidden tanh layers of width 110), fp32.  A step is
+one training iteration: Philox increments, Euler–Maruyama paths, every
+network, the Y recursion, the loss, the reverse sweep and Adam.
+
+Printed: one JSON line with path-steps/s, the dominant kernel against its
+roofline (HIP events on the launch stream), the FP64 CPU oracle timed on a
+bounded sample of the same workload, and the time until Y0 is within 1% of
+the closed form exp((r + sigma^2) T) |x0|^2 = 77.1049, single level and
+multilevel (4 -> 8 -> 16 -> 32 steps), for the library and for a plain FP32
+PyTorch-eager implementation of the same method.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "train path-steps/s (fwd+bwd) at d=100; time to Y0 within 1% vs plain FP32"
+D, W, DEPTH, N, M = 100, 110, 2, 32, 4096
+PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense fp32 matrix
+PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense bf16 matrix
+PEAK_HBM = 8000.0        # GB/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_flops(net_prec: str, d: int, w: int, L: int, n_steps: int, paths: int) -> dict:
+    """Algorithmic flops per launch of the MFMA kernels (useful work only:
+    no padding, 2 flops per multiply-add, 1 per bias add)."""
+    rows = paths * (n_steps - 1)
+    fwd = 2 * (w * d + (L - 1) * w * w + d * w) * rows
+    bwd = 2 * (w * d + (L - 1) * w * w) * rows
+    wgrad = (2 * (w * d + (L - 1) * w * w + d * w) + (L * w + d)) * rows + d * paths
+    return {"forward": fwd, "backward": bwd, "wgrad": wgrad}
+
+
+def time_library(prec: str, steps: int, warmup: int):
+    import torch
+    from paper_1910_11623_amd import inputs as I
+    from paper_1910_11623_amd.plan import Plan
+
+    prob = I.bsb(D)
+    net = dict(kind="mlp", width=W, depth=DEPTH, prec=prec)
+    plan = Plan(prob, net, N, M)
+    params = torch.from_numpy(I.init_params(prob, net, N, seed=0).astype(np.float32)).cuda()
+    y0 = torch.tensor(73.0, dtype=torch.float64, device="cuda")
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    my, vy = torch.zeros_like(y0), torch.zeros_like(y0)
+    out = (torch.empty((), dtype=torch.float64, device="cuda"), torch.empty_like(params),
+           torch.empty((), dtype=torch.float64, device="cuda"))
+
+    def step(k):
+        plan.forward_backward(params, y0, 1, k, out=out)
+        plan.adam_step(params, y0, out[1], out[2], m, v, my, vy, k + 1, lr=1e-3, lr_y0=1e-2)
+
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        step(warmup + k)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+
+    # per-kernel durations, HIP events recorded by the library around each launch
+    plan.profile(True)
+    nprof = max(20, min(steps, 200))
+    for k in range(nprof):
+        step(warmup + steps + k)
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    kern = {k: (t / c if c else 0.0) for k, (t, c) in prof.items()}
+    finite = bool(torch.isfinite(out[0]).item())
+    return ms, kern, finite
+
+
+def roofline_entry(prec: str, kern_ms: dict):
+    flops = kernel_flops(prec, D, W, DEPTH, N, M)
+    dom = max(flops, key=lambda k: kern_ms.get(k, 0.0))
+    t = kern_ms[dom] * 1e-3
+    achieved = flops[dom] / t / 1e12
+    peak = PEAK_FP32_MFMA if prec == "fp32" else PEAK_BF16_MFMA
+    return dom, {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                 "frac": round(achieved / peak, 4), "traffic": None}
+
+
+def cpu_baseline(target_s: float = 12.0):
+    """The FP64 C oracle, single-threaded, on a bounded sample of the same
+    workload: one forward + reverse sweep over a subset of the paths."""
+    from oracle import core as O
+    from paper_1910_11623_amd import inputs as I
+
+    prob = I.bsb(D)
+    net = dict(kind="mlp", width=W, depth=DEPTH)
+    p = I.init_params(prob, net, N, seed=0)
+    t0 = time.perf_counter()
+    O.loss_grad(prob, net, N, 16, p, 73.0, seed=1, it=0)
+    t16 = time.perf_counter() - t0
+    ms = int(max(16, min(M, round(target_s / max(t16 / 16, 1e-6)))))
+    t0 = time.perf_counter()
+    O.loss_grad(prob, net, N, ms, p, 73.0, seed=1, it=0)
+    dt = time.perf_counter() - t0
+    return {"value": round(ms * N / dt, 2), "unit": "path-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{ms} of {M} paths, one forward + reverse sweep at N={N}, d={D}, width {W}x{DEPTH} "
+                      f"({dt:.1f} s)"}
+
+
+# ------------------------------------------------------- plain FP32 eager
+def eager_model(prob, N_, params_flat, y0, device):
+    import torch
+    import torch.nn as nn
+
+    d = prob["d"]
+
+    class DeepBSDE(nn.Module):
+        def __init__(self):
+            super().__init__()
+            self.y0 = nn.Parameter(torch.tensor(float(y0), dtype=torch.float32))
+            self.z0 = nn.Parameter(torch.tensor(params_flat[:d], dtype=torch.float32))
+            self.nets = nn.ModuleList()
+            off = d
+            for _ in range(1, N_):
+                layers = []
+                for k, (o, i) in enumerate([(W, d)] + [(W, W)] * (DEPTH - 1) + [(d, W)]):
+                    lin = nn.Linear(i, o)
+                    lin.weight.data = torch.tensor(params_flat[off:off + o * i].reshape(o, i), dtype=torch.float32)
+                    off += o * i
+                    lin.bias.data = torch.tensor(params_flat[off:off + o], dtype=torch.float32)
+                    off += o
+                    layers.append(lin)
+                    if k < DEPTH:
+                        layers.append(nn.Tanh())
+                self.nets.append(nn.Sequential(*layers))
+            self.register_buffer("x0", torch.tensor(prob["x0"], dtype=torch.float32))
+
+        def forward(self, paths):
+            r, s = prob["drv_p"][0], prob["sde_s"]
+            dt = prob["T"] / N_
+            X = self.x0.expand(paths, d)
+            Y = self.y0.expand(paths)
+            for n in range(N_):
+                Z = self.z0.expand(paths, d) if n == 0 else self.nets[n - 1](X)
+                dW = torch.randn(paths, d, device=X.device) * math.sqrt(dt)
+                sdw = s * X * dW
+                Y = Y + r * (Y - (Z * X).sum(1)) * dt + (Z * sdw).sum(1)
+                X = X + sdw
+            return ((Y - (X * X).sum(1)) ** 2).mean()
+
+    return DeepBSDE().to(device)
+
+
+def eager_prolong(model_c, prob, Nf, device):
+    import torch
+    params = [model_c.z0.detach().cpu().numpy()]
+    Nc = len(model_c.nets) + 1
+    for j in range(1, Nf):
+        c = min(max(j // 2, 1), Nc - 1)
+        for lyr in model_c.nets[c - 1]:
+            if hasattr(lyr, "weight"):
+                params.append(lyr.weight.detach().cpu().numpy().ravel())
+                params.append(lyr.bias.detach().cpu().numpy())
+    flat = np.concatenate(params)
+    return eager_model(prob, Nf, flat, float(model_c.y0.item()), device)
+
+
+def eager_run(levels, iters, y0_init, check_every=100, target=None, max_seconds=90.0):
+    """Plain FP32 eager training; returns (ms/step at the finest level, time to 1%)."""
+    import torch
+    from paper_1910_11623_amd import inputs as I
+
+    torch.backends.cuda.matmul.allow_tf32 = False
+    torch.backends.cudnn.allow_tf32 = False
+    prob = I.bsb(D)
+    p0 = I.init_params(prob, dict(kind="mlp", width=W, depth=DEPTH), levels[0], seed=0)
+    torch.manual_seed(1)
+    model = eager_model(prob, levels[0], p0, y0_init, "cuda")
+    # untimed warmup on a copy
+    wm = eager_model(prob, levels[0], p0, y0_init, "cuda")
+    wopt = torch.optim.Adam(wm.parameters(), lr=1e-3)
+    for _ in range(3):
+        wopt.zero_grad(set_to_none=True)
+        wm(M).backward()
+        wopt.step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ys, ts, Ns = [], [], []
+    ms_fine = None
+    for li, Nl in enumerate(levels):
+        if li > 0:
+            model = eager_prolong(model, prob, Nl, "cuda")
+        opt = torch.optim.Adam([{"params": [model.y0], "lr": 1e-2},
+                                {"params": [p for n_, p in model.named_parameters() if n_ != "y0"], "lr": 1e-3}])
+        ylog = torch.empty(iters[li], device="cuda")
+        lv_t0 = time.perf_counter()
+        done = 0
+        for k in range(iters[li]):
+            opt.zero_grad(set_to_none=True)
+            model(M).backward()
+            opt.step()
+            ylog[k] = model.y0.detach()
+            done = k + 1
+            if (k + 1) % check_every == 0:
+                torch.cuda.synchronize()
+                if time.perf_counter() - t_start > max_seconds:
+                    break
+        torch.cuda.synchronize()
+        lv_dt = time.perf_counter() - lv_t0
+        t_prev = ts[-1][-1] if ts else 0.0
+        ys.append(ylog[:done].cpu().numpy())
+        ts.append(t_prev + lv_dt * np.arange(1, done + 1) / done)
+        Ns.append(np.full(done, Nl))
+        if Nl == levels[-1]:
+            ms_fine = lv_dt / done * 1e3
+        if time.perf_counter() - t_start > max_seconds:
+            break
+    y, t, Nn = np.concatenate(ys), np.concatenate(ts), np.concatenate(Ns)
+    tta = _tta(y, t, Nn, target, levels[-1])
+    return ms_fine, tta, float(y[-1]) if len(y) else None
+
+
+def _tta(y, t, Nn, target, finest, rel=0.01, hold=100):
+    ok = (np.abs(y / target - 1.0) <= rel) & (Nn == finest)
+    for i in range(len(ok) - hold + 1):
+        if ok[i:i + hold].all():
+            return float(t[i])
+    return None
+
+
+def tta_library(levels, iters, y0_init, target):
+    from paper_1910_11623_amd import inputs as I
+    from paper_1910_11623_amd.train import multilevel_schedule, time_to_accuracy, train
+
+    prob = I.bsb(D)
+    net = dict(kind="mlp", width=W, depth=DEPTH, prec="fp32")
+    h = train(prob, net, M, multilevel_schedule(levels, iters), lr=1e-3, lr_y0=1e-2, seed=1, init_seed=0,
+              y0_init=y0_init, warmup=5)
+    return time_to_accuracy(h, target), h.y0_final, float(h.t[-1])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy legs")
+    ap.add_argument("--no-eager", action="store_true", help="skip the PyTorch-eager comparator")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only; there is no multi-GPU path in this library.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from oracle import refvalues as RV
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"device {torch.cuda.get_device_name(0)}")
+    ms, kern, finite = time_library("fp32", args.steps, args.warmup)
+    value = M * N / (ms * 1e-3)
+    log(f"fp32: {ms:.4f} ms/step, {value:.4e} path-steps/s; kernels (ms/launch) "
+        + ", ".join(f"{k}={v:.4f}" for k, v in kern.items()))
+    dom, roof = roofline_entry("fp32", kern)
+    log(f"dominant kernel {dom}: {roof['achieved']} TFLOP/s of {roof['peak']}")
+    ms_bf, kern_bf, _ = time_library("bf16", args.steps, args.warmup)
+    dom_bf, roof_bf = roofline_entry("bf16", kern_bf)
+    log(f"bf16: {ms_bf:.4f} ms/step; dominant {dom_bf} {roof_bf['achieved']} TFLOP/s")
+
+    target = RV.bsb_y0(D)
+    tta = {}
+    if not args.no_tta:
+        y0_init = 73.0
+        single = tta_library([32], [3000], y0_init, target)
+        multi = tta_library([4, 8, 16, 32], [600, 600, 600, 1500], y0_init, target)
+        tta["library_fp32_single_level_s"] = single[0]
+        tta["library_fp32_multilevel_s"] = multi[0]
+        tta["library_final_y0"] = [single[1], multi[1]]
+        log(f"time to 1%: single {single[0]} s, multilevel {multi[0]} s (Y0 {single[1]:.4f}, {multi[1]:.4f})")
+        if not args.no_eager:
+            e_single = eager_run([32], [3000], y0_init, target=target)
+            e_multi = eager_run([4, 8, 16, 32], [600, 600, 600, 1500], y0_init, target=target)
+            tta["eager_fp32_single_level_s"] = e_single[1]
+            tta["eager_fp32_multilevel_s"] = e_multi[1]
+            tta["eager_fp32_ms_per_step"] = round(e_single[0], 4) if e_single[0] else None
+            tta["eager_final_y0"] = [e_single[2], e_multi[2]]
+            log(f"eager: {e_single[0]} ms/step, time to 1% single {e_single[1]} s, multilevel {e_multi[1]} s")
+        tta["target_y0"] = target
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline()
+        log(f"cpu oracle: {cpu['value']} path-steps/s ({cpu['sample']})")
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "path-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"Black-Scholes-Barenblatt d={D} T=1 N={N} M={M}, per-step MLP "
+                               f"{W}x{DEPTH} tanh, fp32, Adam; one step = fwd + reverse sweep + Adam",
+                   "global_batch": M, "seq_len": N, "parallelism": "none"},
+        "roofline": roof,
+        "roofline_kernel": f"k_{dom}<fp32>",
+        "cpu_baseline": cpu,
+        "kernels_ms_per_launch": {k: round(v, 5) for k, v in kern.items()},
+        "finite": finite,
+        "bf16": {"ms_per_step": round(ms_bf, 5), "value": round(M * N / (ms_bf * 1e-3), 1),
+                 "roofline": roof_bf, "roofline_kernel": f"k_{dom_bf}<bf16>",
+                 "kernels_ms_per_launch": {k: round(v, 5) for k, v in kern_bf.items()}},
+        "time_to_1pct": tta or None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -170,6 +170,20 @@ fbsde_status fbsde_terminal_mean(fbsde_plan *plan, uint64_t seed, uint64_t iter,
 fbsde_status fbsde_terminal_states(fbsde_plan *plan, const void *ws_dev, float *xN_dev,
                                    float *yN_dev, void *stream);
 
+/* Per-kernel timing with HIP events recorded on the launch stream around
+ * every kernel of the hot calls of one plan.  fbsde_profile_enable(plan, 1)
+ * creates the event pool (host/driver allocation; not a hot call), 0
+ * destroys it.  fbsde_profile_read waits for the recorded events and returns,
+ * per kernel id (FBSDE_PROF_*), the summed milliseconds and launch counts
+ * since the last read (n entries are written; n <= FBSDE_PROF_NUM). */
+enum {
+  FBSDE_PROF_PACK = 0, FBSDE_PROF_SDE = 1, FBSDE_PROF_FORWARD = 2, FBSDE_PROF_SCAN = 3,
+  FBSDE_PROF_BACKWARD = 4, FBSDE_PROF_WGRAD = 5, FBSDE_PROF_REDUCE = 6, FBSDE_PROF_ADAM = 7,
+  FBSDE_PROF_NUM = 8
+};
+fbsde_status fbsde_profile_enable(fbsde_plan *plan, int32_t enable);
+fbsde_status fbsde_profile_read(fbsde_plan *plan, double *ms_host, int64_t *count_host, int32_t n);
+
 const char *fbsde_status_str(fbsde_status s);
 const char *fbsde_last_error(void);
 

@@ -24,8 +24,9 @@ EXPORTS = [
     "fbsde_plan_create", "fbsde_plan_destroy", "fbsde_param_count", "fbsde_workspace_size",
     "fbsde_forward", "fbsde_forward_backward", "fbsde_adam_step", "fbsde_prolong",
     "fbsde_sample_normals", "fbsde_terminal_mean", "fbsde_terminal_states",
-    "fbsde_status_str", "fbsde_last_error",
+    "fbsde_profile_enable", "fbsde_profile_read", "fbsde_status_str", "fbsde_last_error",
 ]
+PROF_NAMES = ["pack", "sde", "forward", "scan", "backward", "wgrad", "reduce", "adam"]
 
 
 class FbsdeError(RuntimeError):
@@ -70,6 +71,8 @@ def load(path: str = LIB_PATH):
     L.fbsde_sample_normals.argtypes = [vp, u64, u64, vp, vp]
     L.fbsde_terminal_mean.argtypes = [vp, u64, u64, vp, vp, vp]
     L.fbsde_terminal_states.argtypes = [vp, vp, vp, vp, vp]
+    L.fbsde_profile_enable.argtypes = [vp, C.c_int32]
+    L.fbsde_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), C.c_int32]
     L.fbsde_status_str.argtypes = [C.c_int]
     L.fbsde_status_str.restype = C.c_char_p
     L.fbsde_last_error.argtypes = []

@@ -7,12 +7,23 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/fbsde.h"
 #include "fbsde_internal.h"
 
 using fbsde::Geo;
 using fbsde::WsLayout;
+
+// Ring of event pairs per kernel id for live per-kernel timing.
+struct ProfRing {
+  static constexpr int R = 64;
+  std::vector<hipEvent_t> start, stop;
+  std::vector<char> used;
+  int head = 0;
+  double ms = 0.0;
+  long long count = 0;
+};
 
 struct fbsde_plan {
   fbsde_problem prob;
@@ -23,6 +34,8 @@ struct fbsde_plan {
   WsLayout ws;
   float* x0_dev;  // [dp] zero-padded, owned
   int device;
+  bool prof = false;
+  ProfRing ring[FBSDE_PROF_NUM];
 };
 
 namespace {
@@ -105,23 +118,66 @@ fbsde_status check_hot(const fbsde_plan* P, const void* ws) {
   return FBSDE_OK;
 }
 
+// Event pair around one launch (no-op unless profiling is enabled).  A ring
+// slot is reused only after its previous pair has completed.
+struct ProfScope {
+  fbsde_plan* P;
+  int id;
+  hipStream_t s;
+  int slot = -1;
+  ProfScope(fbsde_plan* p, int i, hipStream_t st) : P(p), id(i), s(st) {
+    if (!P->prof) return;
+    ProfRing& r = P->ring[id];
+    slot = r.head;
+    r.head = (r.head + 1) % ProfRing::R;
+    if (r.used[slot]) {
+      float ms = 0.f;
+      if (hipEventSynchronize(r.stop[slot]) == hipSuccess &&
+          hipEventElapsedTime(&ms, r.start[slot], r.stop[slot]) == hipSuccess) {
+        r.ms += ms;
+        r.count += 1;
+      }
+      r.used[slot] = 0;
+    }
+    (void)hipEventRecord(r.start[slot], s);
+  }
+  ~ProfScope() {
+    if (slot < 0) return;
+    ProfRing& r = P->ring[id];
+    (void)hipEventRecord(r.stop[slot], s);
+    r.used[slot] = 1;
+  }
+};
+
 fbsde_status run_forward(fbsde_plan* P, const float* params, const double* y0, uint64_t seed,
                          uint64_t iter, void* ws, hipStream_t s) {
   const Geo& g = P->geo;
   const WsLayout& L = P->ws;
   hipError_t e;
-  if ((e = fbsde::launch_pack(g, params, at<void>(ws, L.PF), at<void>(ws, L.PB), s)) != hipSuccess)
-    return hip_fail(e, "pack");
-  if ((e = fbsde::launch_sde(g, P->x0_dev, seed, iter, at<float>(ws, L.X), at<float>(ws, L.V),
-                             at<float>(ws, L.QN), at<float>(ws, L.LN), s)) != hipSuccess)
-    return hip_fail(e, "sde");
-  if ((e = fbsde::launch_forward(g, params, at<void>(ws, L.PF), at<float>(ws, L.X), at<float>(ws, L.V),
-                                 at<float>(ws, L.C), at<void>(ws, L.H), s)) != hipSuccess)
-    return hip_fail(e, "forward");
-  if ((e = fbsde::launch_scan(g, y0, at<float>(ws, L.C), at<float>(ws, L.QN), at<float>(ws, L.LN),
-                              at<float>(ws, L.Y), at<float>(ws, L.LAM), at<double>(ws, L.RED),
-                              L.scan_blocks, s)) != hipSuccess)
-    return hip_fail(e, "scan");
+  {
+    ProfScope ps(P, FBSDE_PROF_PACK, s);
+    if ((e = fbsde::launch_pack(g, params, at<void>(ws, L.PF), at<void>(ws, L.PB), s)) != hipSuccess)
+      return hip_fail(e, "pack");
+  }
+  {
+    ProfScope ps(P, FBSDE_PROF_SDE, s);
+    if ((e = fbsde::launch_sde(g, P->x0_dev, seed, iter, at<float>(ws, L.X), at<float>(ws, L.V),
+                               at<float>(ws, L.QN), at<float>(ws, L.LN), s)) != hipSuccess)
+      return hip_fail(e, "sde");
+  }
+  {
+    ProfScope ps(P, FBSDE_PROF_FORWARD, s);
+    if ((e = fbsde::launch_forward(g, params, at<void>(ws, L.PF), at<float>(ws, L.X), at<float>(ws, L.V),
+                                   at<float>(ws, L.C), at<void>(ws, L.H), s)) != hipSuccess)
+      return hip_fail(e, "forward");
+  }
+  {
+    ProfScope ps(P, FBSDE_PROF_SCAN, s);
+    if ((e = fbsde::launch_scan(g, y0, at<float>(ws, L.C), at<float>(ws, L.QN), at<float>(ws, L.LN),
+                                at<float>(ws, L.Y), at<float>(ws, L.LAM), at<double>(ws, L.RED),
+                                L.scan_blocks, s)) != hipSuccess)
+      return hip_fail(e, "scan");
+  }
   return FBSDE_OK;
 }
 
@@ -233,6 +289,7 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
 
 void fbsde_plan_destroy(fbsde_plan* plan) {
   if (!plan) return;
+  (void)fbsde_profile_enable(plan, 0);
   if (plan->x0_dev) (void)hipFree(plan->x0_dev);
   delete plan;
 }
@@ -275,15 +332,24 @@ fbsde_status fbsde_forward_backward(fbsde_plan* plan, const float* params, const
   const Geo& g = plan->geo;
   const WsLayout& L = plan->ws;
   hipError_t e;
-  if ((e = fbsde::launch_backward(g, at<void>(ws, L.PB), at<float>(ws, L.V), at<float>(ws, L.LAM),
-                                  at<void>(ws, L.H), at<void>(ws, L.DZ), at<void>(ws, L.DH), s)) != hipSuccess)
-    return hip_fail(e, "backward");
-  if ((e = fbsde::launch_wgrad(g, at<float>(ws, L.X), at<void>(ws, L.H), at<void>(ws, L.DZ),
-                               at<void>(ws, L.DH), at<float>(ws, L.PART), L.splits, L.chunk, s)) != hipSuccess)
-    return hip_fail(e, "wgrad");
-  if ((e = fbsde::launch_reduce(g, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
-                                L.scan_blocks, loss, grad_y0, s)) != hipSuccess)
-    return hip_fail(e, "reduce");
+  {
+    ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
+    if ((e = fbsde::launch_backward(g, at<void>(ws, L.PB), at<float>(ws, L.V), at<float>(ws, L.LAM),
+                                    at<void>(ws, L.H), at<void>(ws, L.DZ), at<void>(ws, L.DH), s)) != hipSuccess)
+      return hip_fail(e, "backward");
+  }
+  {
+    ProfScope ps(plan, FBSDE_PROF_WGRAD, s);
+    if ((e = fbsde::launch_wgrad(g, at<float>(ws, L.X), at<void>(ws, L.H), at<void>(ws, L.DZ),
+                                 at<void>(ws, L.DH), at<float>(ws, L.PART), L.splits, L.chunk, s)) != hipSuccess)
+      return hip_fail(e, "wgrad");
+  }
+  {
+    ProfScope ps(plan, FBSDE_PROF_REDUCE, s);
+    if ((e = fbsde::launch_reduce(g, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
+                                  L.scan_blocks, loss, grad_y0, s)) != hipSuccess)
+      return hip_fail(e, "reduce");
+  }
   return FBSDE_OK;
 }
 
@@ -299,6 +365,7 @@ fbsde_status fbsde_adam_step(fbsde_plan* plan, float* params, double* y0, const 
   if (!(lr >= 0) || !(lr_y0 >= 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
     return fail(FBSDE_ERR_INVALID, "Adam hyper-parameters out of range");
   const double c1 = 1.0 - std::pow(b1, (double)t), c2 = 1.0 - std::pow(b2, (double)t);
+  ProfScope ps(plan, FBSDE_PROF_ADAM, reinterpret_cast<hipStream_t>(stream));
   hipError_t e = fbsde::launch_adam(plan->geo.nparams, params, grad, m, v, y0, grad_y0, m_y0, v_y0, (float)lr,
                                     (float)c1, (float)c2, lr_y0, c1, c2, b1, b2, eps,
                                     reinterpret_cast<hipStream_t>(stream));
@@ -349,6 +416,68 @@ fbsde_status fbsde_terminal_states(fbsde_plan* plan, const void* ws, float* xN, 
   hipError_t e = fbsde::launch_terminal_copy(plan->geo, at<float>(ws, plan->ws.X), at<float>(ws, plan->ws.Y), xN,
                                              yN, reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "terminal copy");
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_profile_enable(fbsde_plan* plan, int32_t enable) {
+  if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
+  if (enable && !plan->prof) {
+    for (int k = 0; k < FBSDE_PROF_NUM; ++k) {
+      ProfRing& r = plan->ring[k];
+      r.start.assign(ProfRing::R, nullptr);
+      r.stop.assign(ProfRing::R, nullptr);
+      r.used.assign(ProfRing::R, 0);
+      r.head = 0;
+      r.ms = 0.0;
+      r.count = 0;
+      for (int i = 0; i < ProfRing::R; ++i) {
+        hipError_t e1 = hipEventCreate(&r.start[i]);
+        hipError_t e2 = hipEventCreate(&r.stop[i]);
+        if (e1 != hipSuccess || e2 != hipSuccess) return hip_fail(e1 != hipSuccess ? e1 : e2, "hipEventCreate");
+      }
+    }
+    plan->prof = true;
+  } else if (!enable && plan->prof) {
+    for (int k = 0; k < FBSDE_PROF_NUM; ++k) {
+      ProfRing& r = plan->ring[k];
+      for (int i = 0; i < ProfRing::R; ++i) {
+        if (r.used[i]) (void)hipEventSynchronize(r.stop[i]);
+        if (r.start[i]) (void)hipEventDestroy(r.start[i]);
+        if (r.stop[i]) (void)hipEventDestroy(r.stop[i]);
+      }
+      r.start.clear();
+      r.stop.clear();
+      r.used.clear();
+    }
+    plan->prof = false;
+  }
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_profile_read(fbsde_plan* plan, double* ms, int64_t* count, int32_t n) {
+  if (!plan || !ms || !count) return fail(FBSDE_ERR_INVALID, "NULL argument");
+  if (n < 0 || n > FBSDE_PROF_NUM) return fail(FBSDE_ERR_INVALID, "n out of range");
+  if (!plan->prof) return fail(FBSDE_ERR_INVALID, "profiling is not enabled on this plan");
+  for (int k = 0; k < FBSDE_PROF_NUM; ++k) {
+    ProfRing& r = plan->ring[k];
+    for (int i = 0; i < ProfRing::R; ++i) {
+      if (!r.used[i]) continue;
+      float t = 0.f;
+      hipError_t e = hipEventSynchronize(r.stop[i]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+      e = hipEventElapsedTime(&t, r.start[i], r.stop[i]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      r.ms += t;
+      r.count += 1;
+      r.used[i] = 0;
+    }
+    if (k < n) {
+      ms[k] = r.ms;
+      count[k] = r.count;
+    }
+    r.ms = 0.0;
+    r.count = 0;
+  }
   return FBSDE_OK;
 }
 

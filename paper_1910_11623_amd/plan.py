@@ -119,6 +119,18 @@ class Plan:
         return xN, yN
 
 
+    def profile(self, enable: bool = True):
+        B.check(self.lib.fbsde_profile_enable(self._h, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total ms, launches)} since the previous read."""
+        n = len(B.PROF_NAMES)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        B.check(self.lib.fbsde_profile_read(self._h, ms, cnt, n))
+        return {B.PROF_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
 class FBSDELoss(torch.autograd.Function):
     """loss = FBSDELoss.apply(params, y0, plan, seed, it).
 
