@@ -550,97 +550,162 @@ __device__ __forceinline__ Job job_info(const Geo& g, int job, const float* X, c
   return J;
 }
 
-template <bool BF>
-__device__ __forceinline__ float ldA(const Job& J, int p, int row) {
-  if (BF) return bf2f(reinterpret_cast<const uint16_t*>(J.A)[(size_t)p * J.sA + row]);
-  return reinterpret_cast<const float*>(J.A)[(size_t)p * J.sA + row];
-}
-template <bool BF>
-__device__ __forceinline__ float ldB(const Job& J, int p, int c) {
-  if (c == J.cols) return 1.f;
-  if (c > J.cols) return 0.f;
-  if (J.Bf32) {
-    const float x = reinterpret_cast<const float*>(J.B)[(size_t)p * J.sB + c];
-    return BF ? rbf(x) : x;
+// LDS-staged weight-gradient GEMM.  Workgroup = (job, 128x128 output block
+// group, path split); it owns a T x T block of 16x16 output tiles and walks
+// its path range in chunks of 32 paths staged in LDS with 16-byte loads.
+// Wave w accumulates tile columns 2w and 2w+1 (the last wave may own one)
+// over all T tile rows.  Bias gradients ride along as an extra input column
+// of ones (column `cols`).
+constexpr int WG_KC = 32;  // paths per LDS chunk
+
+template <int T>
+struct WgradLds {
+  static constexpr int LDA = 16 * T + ((T % 2 == 0) ? 16 : 0);  // fp32 row stride (floats), == 16 mod 32
+  static constexpr int LDT = WG_KC + 4;                          // bf16 transposed row stride (elements)
+  static constexpr size_t F32_BYTES = 2ull * WG_KC * LDA * 4;
+  static constexpr size_t BF_BYTES = 2ull * 16 * T * LDT * 2;
+  static constexpr size_t BYTES = F32_BYTES > BF_BYTES ? F32_BYTES : BF_BYTES;
+};
+
+// 4 consecutive input columns c..c+3 of one path, with the bias column of
+// ones at `cols` and zeros beyond (src row holds `stride` valid entries)
+__device__ __forceinline__ f32x4 load_cols4(const void* base, bool f32src, bool bfsrc, size_t rowoff, int c,
+                                            int cols, int stride) {
+  f32x4 v = zero4();
+  if (c < stride) {
+    if (f32src) v = ld4(reinterpret_cast<const float*>(base) + rowoff + c);
+    else if (bfsrc) v = ld_act(base, rowoff + c, true);
+    else v = ld4(reinterpret_cast<const float*>(base) + rowoff + c);
   }
-  if (BF) return bf2f(reinterpret_cast<const uint16_t*>(J.B)[(size_t)p * J.sB + c]);
-  return reinterpret_cast<const float*>(J.B)[(size_t)p * J.sB + c];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (c + e == cols) v[e] = 1.f;
+    else if (c + e > cols) v[e] = 0.f;
+  }
+  return v;
 }
 
-template <bool BF>
-__global__ __launch_bounds__(256) void k_wgrad(Geo g, const float* __restrict__ X,
-                                               const void* __restrict__ H, const void* __restrict__ DZ,
-                                               const void* __restrict__ DH, float* __restrict__ part,
-                                               long long chunk) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+template <bool BF, int T, int CW>
+__device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, int C0, long long p0,
+                                            long long p1, unsigned char* smem, float* out_split) {
+  using L = WgradLds<T>;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int c16 = lane & 15, grp = lane >> 4;
-  const Job J = job_info(g, blockIdx.y, X, H, DZ, DH);
-  const int ncb = (J.cols + 1 + 63) / 64, nrb = (J.rows + 63) / 64;
-  const int bx = blockIdx.x;
-  if (bx >= ncb * nrb) return;
-  const int R0 = (bx / ncb) * 64 + (wv >> 1) * 32;
-  const int C0 = (bx % ncb) * 64 + (wv & 1) * 32;
-  if (R0 >= J.rows || C0 >= J.cols + 1) return;
-  const long long p0 = (long long)blockIdx.z * chunk;
-  const long long p1 = min((long long)g.M, p0 + chunk);
-  f32x4 acc[2][2];
+  const bool bfA = BF;               // deltas are stored in the GEMM precision
+  const bool bfB = BF && !J.Bf32;    // activations too; X is fp32 state
+  constexpr int CWA = CW > 0 ? CW : 1;  // storage size (a wave with no tiles only stages)
+  f32x4 acc[T][CWA];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < T; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = zero4();
-  if constexpr (!BF) {
-    for (long long pb = p0; pb < p1; pb += 4) {
-      const long long pp = pb + grp;
-      const bool ok = pp < p1;
-      float a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int row = R0 + 16 * i + c16;
-        a[i] = (ok && row < J.rows) ? ldA<false>(J, (int)pp, row) : 0.f;
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = ok ? ldB<false>(J, (int)pp, C0 + 16 * j + c16) : 0.f;
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
-    }
-  } else {
-    for (long long pb = p0; pb < p1; pb += 32) {
-      f32x4 a[2][2], b[2][2];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const long long pp = pb + 8 * grp + k;
-        const bool ok = pp < p1;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int row = R0 + 16 * i + c16;
-          a[i][k >> 2][k & 3] = (ok && row < J.rows) ? ldA<true>(J, (int)pp, row) : 0.f;
+    for (int j = 0; j < CWA; ++j) acc[i][j] = zero4();
+
+  for (long long pc = p0; pc < p1; pc += WG_KC) {
+    __syncthreads();
+    // ---- stage A (deltas, rows R0..) and B (activations, cols C0..) chunks
+    constexpr int NV = WG_KC * 4 * T;  // float4 slots per operand chunk
+    for (int s = tid; s < 2 * NV; s += 256) {
+      const bool isA = s < NV;
+      const int q = isA ? s : s - NV;
+      const int kp = q / (4 * T), c4 = q % (4 * T);
+      const long long p = pc + kp;
+      f32x4 v = zero4();
+      if (p < p1) {
+        if (isA) {
+          const int r = R0 + 4 * c4;
+          if (r < J.rows) {
+            v = bfA ? ld_act(J.A, (size_t)p * J.sA + r, true)
+                    : ld4(reinterpret_cast<const float*>(J.A) + (size_t)p * J.sA + r);
+          }
+        } else {
+          v = load_cols4(J.B, J.Bf32, bfB, (size_t)p * J.sB, C0 + 4 * c4, J.cols, J.B ? J.sB : 0);
+          if (BF && J.Bf32) v = round4(v, true);
         }
+      }
+      if constexpr (!BF) {
+        float* dst = reinterpret_cast<float*>(smem) + (isA ? 0 : WG_KC * L::LDA) + kp * L::LDA + 4 * c4;
+        st4(dst, v);
+      } else {
+        uint16_t* dst = reinterpret_cast<uint16_t*>(smem) + (isA ? 0 : 16 * T * L::LDT);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j][k >> 2][k & 3] = ok ? ldB<true>(J, (int)pp, C0 + 16 * j + c16) : 0.f;
+        for (int e = 0; e < 4; ++e) dst[(4 * c4 + e) * L::LDT + kp] = (uint16_t)bf16_bits(v[e]);
+      }
+    }
+    __syncthreads();
+    // ---- MFMA over the chunk
+    if constexpr (!BF) {
+      const float* As = reinterpret_cast<const float*>(smem);
+      const float* Bs = As + WG_KC * L::LDA;
+#pragma unroll
+      for (int kb = 0; kb < (CW > 0 ? WG_KC / 4 : 0); ++kb) {
+        const int kr = 4 * kb + grp;
+        float a[T], b[CWA];
+#pragma unroll
+        for (int i = 0; i < T; ++i) a[i] = As[kr * L::LDA + 16 * i + c16];
+#pragma unroll
+        for (int j = 0; j < CW; ++j) b[j] = Bs[kr * L::LDA + 16 * (2 * wv + j) + c16];
+#pragma unroll
+        for (int i = 0; i < T; ++i)
+#pragma unroll
+          for (int j = 0; j < CW; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
+      }
+    } else {
+      const uint16_t* As = reinterpret_cast<const uint16_t*>(smem);
+      const uint16_t* Bs = As + 16 * T * L::LDT;
+      if (CW == 0) continue;
+      bf16x8 a[T], b[CWA];
+#pragma unroll
+      for (int i = 0; i < T; ++i) {
+        const uint16_t* src = As + (16 * i + c16) * L::LDT + 8 * grp;
+        const uint2 lo = *reinterpret_cast<const uint2*>(src), hi = *reinterpret_cast<const uint2*>(src + 4);
+        a[i] = __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y});
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < CW; ++j) {
+        const uint16_t* src = Bs + (16 * (2 * wv + j) + c16) * L::LDT + 8 * grp;
+        const uint2 lo = *reinterpret_cast<const uint2*>(src), hi = *reinterpret_cast<const uint2*>(src + 4);
+        b[j] = __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y});
+      }
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = mfma_bf16(pack8(a[i][0], a[i][1]), pack8(b[j][0], b[j][1]), acc[i][j]);
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int j = 0; j < CW; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
     }
   }
-  float* out = part + (size_t)blockIdx.z * g.nparams;
+  // ---- partial sums of this path split, scattered to the flat layout
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < T; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < CW; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = R0 + 16 * i + 4 * grp + r, c = C0 + 16 * j + c16;
+        const int row = R0 + 16 * i + 4 * grp + r, c = C0 + 16 * (2 * wv + j) + c16;
         if (row < J.rows && c <= J.cols) {
           const long long off = (c < J.cols) ? J.base + (long long)row * J.cols + c
                                              : J.base + (long long)J.rows * J.cols + row;
-          out[off] = acc[i][j][r];
+          out_split[off] = acc[i][j][r];
         }
       }
+}
+
+template <bool BF, int T>
+__global__ __launch_bounds__(256) void k_wgrad(Geo g, const float* __restrict__ X, const void* __restrict__ H,
+                                               const void* __restrict__ DZ, const void* __restrict__ DH,
+                                               float* __restrict__ part, long long chunk) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[WgradLds<T>::BYTES];
+  const Job J = job_info(g, blockIdx.x, X, H, DZ, DH);
+  const int ngc = (J.cols + 1 + 16 * T - 1) / (16 * T), ngr = (J.rows + 16 * T - 1) / (16 * T);
+  if ((int)blockIdx.y >= ngc * ngr) return;  // uniform over the workgroup
+  const int R0 = (blockIdx.y / ngc) * 16 * T, C0 = (blockIdx.y % ngc) * 16 * T;
+  const long long p0 = (long long)blockIdx.z * chunk;
+  const long long p1 = min((long long)g.M, p0 + chunk);
+  float* out = part + (size_t)blockIdx.z * g.nparams;
+  const int wv = threadIdx.x >> 6;
+  // tile columns of this wave inside the block: 2wv, 2wv+1 (fewer at the edge)
+  const int ncol = min(2, max(0, T - 2 * wv));
+  if (ncol == 2) wgrad_tiles<BF, T, 2>(g, J, R0, C0, p0, p1, smem, out);
+  else if (ncol == 1) wgrad_tiles<BF, T, 1>(g, J, R0, C0, p0, p1, smem, out);
+  else wgrad_tiles<BF, T, 0>(g, J, R0, C0, p0, p1, smem, out);
 }
 
 // ------------------------------------------------------------ reduce kernel
@@ -843,16 +908,35 @@ hipError_t launch_backward(const Geo& g, const void* packB, const float* V, cons
   return hipGetLastError();
 }
 
+int wgrad_block_tiles(const Geo& g) {
+  const int rmax = g.d > g.w ? g.d : g.w;
+  const int cmax = (g.d > g.w ? g.d : g.w) + 1;
+  const int t = ((rmax > cmax ? rmax : cmax) + 15) / 16;
+  return t <= 1 ? 1 : (t <= 2 ? 2 : (t <= 4 ? 4 : (t <= 7 ? 7 : 8)));
+}
+
+template <bool BF, int T>
+static void wgrad_inst(const Geo& g, const float* X, const void* H, const void* DZ, const void* DH, float* part,
+                       int splits, long long chunk, hipStream_t s) {
+  const int rmax = g.d > g.w ? g.d : g.w, cmax = rmax + 1;
+  const unsigned groups = (unsigned)(((rmax + 16 * T - 1) / (16 * T)) * ((cmax + 16 * T - 1) / (16 * T)));
+  const unsigned jobs = 1u + (unsigned)(g.N - 1) * (unsigned)(g.L + 1);
+  dim3 grid(jobs, groups, splits);
+  k_wgrad<BF, T><<<grid, 256, 0, s>>>(g, X, H, DZ, DH, part, chunk);
+}
+
 hipError_t launch_wgrad(const Geo& g, const float* X, const void* H, const void* DZ, const void* DH,
                         float* part, int splits, long long chunk, hipStream_t s) {
-  const int maxr = g.d > g.w ? g.d : g.w;
-  const int maxc = (g.d > g.w ? g.d : g.w) + 1;
-  const unsigned bx = (unsigned)(((maxr + 63) / 64) * ((maxc + 63) / 64));
-  const unsigned jobs = 1u + (unsigned)(g.N - 1) * (unsigned)(g.L + 1);
-  dim3 grid(bx, jobs, splits);
-  if (g.bf16) k_wgrad<true><<<grid, 256, 0, s>>>(g, X, H, DZ, DH, part, chunk);
-  else k_wgrad<false><<<grid, 256, 0, s>>>(g, X, H, DZ, DH, part, chunk);
-  return hipGetLastError();
+  const int T = wgrad_block_tiles(g);
+#define WG_CASE(TT)                                                                  \
+  if (T == TT) {                                                                     \
+    if (g.bf16) wgrad_inst<true, TT>(g, X, H, DZ, DH, part, splits, chunk, s);       \
+    else wgrad_inst<false, TT>(g, X, H, DZ, DH, part, splits, chunk, s);             \
+    return hipGetLastError();                                                        \
+  }
+  WG_CASE(1) WG_CASE(2) WG_CASE(4) WG_CASE(7) WG_CASE(8)
+#undef WG_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* grad, const double* scan_part,
