@@ -264,6 +264,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy legs")
     ap.add_argument("--no-eager", action="store_true", help="skip the PyTorch-eager comparator")
+    ap.add_argument("--prec", choices=["fp32", "bf16", "both"], default="both",
+                    help="which library precision(s) to time")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -275,12 +279,29 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log(f"device {torch.cuda.get_device_name(0)}")
+    if args.copy_calibration:
+        n = (1 << 30) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
+        return
+    if args.prec == "bf16":
+        ms_bf, kern_bf, _ = time_library("bf16", args.steps, args.warmup)
+        log(f"bf16 only: {ms_bf:.4f} ms/step; kernels " + ", ".join(f"{k}={v:.4f}" for k, v in kern_bf.items()))
+        return
     ms, kern, finite = time_library("fp32", args.steps, args.warmup)
     value = M * N / (ms * 1e-3)
     log(f"fp32: {ms:.4f} ms/step, {value:.4e} path-steps/s; kernels (ms/launch) "
         + ", ".join(f"{k}={v:.4f}" for k, v in kern.items()))
     dom, roof = roofline_entry("fp32", kern)
     log(f"dominant kernel {dom}: {roof['achieved']} TFLOP/s of {roof['peak']}")
+    if args.prec == "fp32":
+        print(json.dumps({"ms_per_step": ms, "kernels_ms_per_launch": kern, "roofline": roof,
+                          "roofline_kernel": dom}), flush=True)
+        return
     ms_bf, kern_bf, _ = time_library("bf16", args.steps, args.warmup)
     dom_bf, roof_bf = roofline_entry("bf16", kern_bf)
     log(f"bf16: {ms_bf:.4f} ms/step; dominant {dom_bf} {roof_bf['achieved']} TFLOP/s")

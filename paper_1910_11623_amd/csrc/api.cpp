@@ -80,6 +80,7 @@ void make_layout(fbsde_plan* P) {
   w.DH = take(N * g.L * M * g.wp * esz);
   w.PF = take((N > 1 ? N - 1 : 0) * (size_t)g.packf_step * esz);
   w.PB = take((N > 1 ? N - 1 : 0) * (size_t)g.packb_step * esz);
+  w.PBIAS = take((N > 1 ? N - 1 : 0) * (size_t)g.pbias_step * 4);
   // wgrad splits over paths: about 512 paths each, multiples of 32
   int splits = (int)((M + 511) / 512);
   if (splits < 1) splits = 1;
@@ -156,7 +157,7 @@ fbsde_status run_forward(fbsde_plan* P, const float* params, const double* y0, u
   hipError_t e;
   {
     ProfScope ps(P, FBSDE_PROF_PACK, s);
-    if ((e = fbsde::launch_pack(g, params, at<void>(ws, L.PF), at<void>(ws, L.PB), s)) != hipSuccess)
+    if ((e = fbsde::launch_pack(g, params, at<void>(ws, L.PF), at<void>(ws, L.PB), at<float>(ws, L.PBIAS), s)) != hipSuccess)
       return hip_fail(e, "pack");
   }
   {
@@ -167,7 +168,8 @@ fbsde_status run_forward(fbsde_plan* P, const float* params, const double* y0, u
   }
   {
     ProfScope ps(P, FBSDE_PROF_FORWARD, s);
-    if ((e = fbsde::launch_forward(g, params, at<void>(ws, L.PF), at<float>(ws, L.X), at<float>(ws, L.V),
+    if ((e = fbsde::launch_forward(g, params, at<void>(ws, L.PF), at<float>(ws, L.PBIAS), at<float>(ws, L.X),
+                                   at<float>(ws, L.V),
                                    at<float>(ws, L.C), at<void>(ws, L.H), s)) != hipSuccess)
       return hip_fail(e, "forward");
   }
@@ -262,6 +264,7 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   g.nparams = d + (long long)(N - 1) * g.pstep;
   g.packf_step = 256LL * (g.tw * g.ti + (L - 1) * g.tw * g.tw + g.ti * g.tw);
   g.packb_step = 256LL * (g.tw * g.ti + (L - 1) * g.tw * g.tw);
+  g.pbias_step = 16LL * (L * g.tw + g.ti);
   make_layout(P);
 
   hipError_t e = hipGetDevice(&P->device);

@@ -27,22 +27,24 @@ struct Geo {
   long long nparams;      // total fp32 parameters
   long long packf_step;   // packed forward fragments per step (elements)
   long long packb_step;   // packed backward fragments per step (elements)
+  long long pbias_step;   // padded fp32 biases per step: L * 16 tw + 16 ti
 };
 
 // Offsets (bytes) of the sub-buffers of one workspace.
 struct WsLayout {
-  size_t X, V, C, Y, LAM, QN, LN, H, DZ, DH, PF, PB, PART, RED, total;
+  size_t X, V, C, Y, LAM, QN, LN, H, DZ, DH, PF, PB, PBIAS, PART, RED, total;
   int scan_blocks;
   int splits;
   long long chunk;
 };
 
 // launchers (kernels.hip); all return hipError_t of the launch
-hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* packB, hipStream_t s);
+hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* packB, float* pbias,
+                       hipStream_t s);
 hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t iter, float* X, float* V,
                       float* QN, float* LN, hipStream_t s);
-hipError_t launch_forward(const Geo& g, const float* params, const void* packF, const float* X, float* V,
-                          float* C, void* H, hipStream_t s);
+hipError_t launch_forward(const Geo& g, const float* params, const void* packF, const float* pbias,
+                          const float* X, float* V, float* C, void* H, hipStream_t s);
 hipError_t launch_scan(const Geo& g, const double* y0, const float* C, const float* QN, const float* LN,
                        float* Y, float* LAM, double* part, int blocks, hipStream_t s);
 hipError_t launch_backward(const Geo& g, const void* packB, const float* V, const float* LAM,

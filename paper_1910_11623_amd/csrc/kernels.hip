@@ -64,6 +64,25 @@ __device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// tanh without a division: for |x| >= 0.4, sign(x) (1 - 2 / (exp(2|x|) + 1))
+// with the hardware base-2 exponential and reciprocal (saturates to +-1);
+// below 0.4 the odd Taylor series through x^13 (truncation < 4e-9
+// relative), which keeps the relative error at a few ulp near zero.
+__device__ __forceinline__ float fast_tanh(float x) {
+  const float ax = fabsf(x);
+  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * ax);  // exp(2|x|)
+  const float big = fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+  const float x2 = ax * ax;
+  float q = 21844.0f / 6081075.0f;
+  q = fmaf(q, x2, -1382.0f / 155925.0f);
+  q = fmaf(q, x2, 62.0f / 2835.0f);
+  q = fmaf(q, x2, -17.0f / 315.0f);
+  q = fmaf(q, x2, 2.0f / 15.0f);
+  q = fmaf(q, x2, -1.0f / 3.0f);
+  const float small = fmaf(ax * x2, q, ax);
+  return copysignf(ax < 0.4f ? small : big, x);
+}
+
 __device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
 
 __device__ __forceinline__ f32x4 ld4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
@@ -157,8 +176,9 @@ __device__ __forceinline__ float packed_value(const float* W, int rows, int cols
 }
 
 __global__ __launch_bounds__(256) void k_pack(Geo g, const float* __restrict__ params,
-                                              void* __restrict__ packF, void* __restrict__ packB) {
-  const long long per = g.packf_step + g.packb_step;
+                                              void* __restrict__ packF, void* __restrict__ packB,
+                                              float* __restrict__ pbias) {
+  const long long per = g.packf_step + g.packb_step + g.pbias_step;
   const long long total = (long long)(g.N - 1) * per;
   const bool bf = g.bf16;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
@@ -166,6 +186,21 @@ __global__ __launch_bounds__(256) void k_pack(Geo g, const float* __restrict__ p
     long long q = e % per;
     const float* base = params + g.d + (long long)(n - 1) * g.pstep;
     const long long lw1 = (long long)g.w * g.d + g.w, lwh = (long long)g.w * g.w + g.w;
+    if (q >= g.packf_step + g.packb_step) {  // biases, zero padded: b_1..b_L (16 tw each), b_o (16 ti)
+      const long long qb = q - g.packf_step - g.packb_step;
+      const long long hb = 16LL * g.tw;
+      float val = 0.f;
+      if (qb < (long long)g.L * hb) {
+        const int l = 1 + (int)(qb / hb), i = (int)(qb % hb);
+        const float* bl = base + (l == 1 ? (long long)g.w * g.d : lw1 + (long long)(l - 2) * lwh + (long long)g.w * g.w);
+        if (i < g.w) val = bl[i];
+      } else {
+        const int i = (int)(qb - (long long)g.L * hb);
+        if (i < g.d) val = base[lw1 + (long long)(g.L - 1) * lwh + (long long)g.d * g.w + i];
+      }
+      pbias[(long long)(n - 1) * g.pbias_step + qb] = val;
+      continue;
+    }
     const long long sz_in = 256LL * g.tw * g.ti, sz_h = 256LL * g.tw * g.tw, sz_o = 256LL * g.ti * g.tw;
     float val;
     long long out_idx;
@@ -284,25 +319,56 @@ __device__ __forceinline__ f32x4 bias4(const float* b, int base, int n) {
 }
 
 // ----------------------------------------------------------- forward kernel
-template <bool BF, int TI, int TW>
-__global__ __launch_bounds__(256) void k_forward(Geo g, const float* __restrict__ params,
-                                                 const void* __restrict__ packF,
-                                                 const float* __restrict__ X, float* __restrict__ V,
-                                                 float* __restrict__ C, void* __restrict__ H) {
+// Copy one step's packed fragments (bytes, multiple of 16) into LDS.
+__device__ __forceinline__ void stage_weights(unsigned char* dst, const void* src, size_t bytes) {
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+  __syncthreads();
+}
+
+// LDSW = false: one 16-path tile per wave, fragments read from global memory.
+// LDSW = true : the workgroup stages step n's fragments in LDS once, then each
+//               of its waves streams `tpw` tiles of 16 paths through them.
+template <bool BF, int TI, int TW, bool LDSW>
+__global__ __launch_bounds__(LDSW ? 512 : 256) void k_forward(Geo g, const float* __restrict__ params,
+                                                               const void* __restrict__ packF,
+                                                               const float* __restrict__ pbias,
+                                                               const float* __restrict__ X,
+                                                               float* __restrict__ V, float* __restrict__ C,
+                                                               void* __restrict__ H, int tpw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
   const int n = blockIdx.y;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  const int p = (blockIdx.x * 4 + wv) * 16 + col;
-  const bool valid = p < g.M;
   const size_t rowM = (size_t)g.M * g.dp;
+  const size_t esz = BF ? 2 : 4;
+  const char* pk;
+  const float* bp;
+  if constexpr (LDSW) {
+    if (n > 0) {
+      const size_t wbytes = (size_t)g.packf_step * esz;
+      const uint4* sb = reinterpret_cast<const uint4*>(pbias + (size_t)(n - 1) * g.pbias_step);
+      uint4* db = reinterpret_cast<uint4*>(wsm + wbytes);
+      for (int i = threadIdx.x; i < g.pbias_step / 4; i += blockDim.x) db[i] = sb[i];
+      stage_weights(wsm, reinterpret_cast<const char*>(packF) + (size_t)(n - 1) * wbytes, wbytes);
+    }
+    pk = reinterpret_cast<const char*>(wsm);
+    bp = reinterpret_cast<const float*>(wsm + (size_t)g.packf_step * esz);
+  } else {
+    pk = reinterpret_cast<const char*>(packF) + (size_t)(n > 0 ? n - 1 : 0) * g.packf_step * esz;
+    bp = pbias + (size_t)(n > 0 ? n - 1 : 0) * g.pbias_step;
+  }
+  for (int it = 0; it < tpw; ++it) {
+  const int tile = (blockIdx.x * tpw + it) * nwv + wv;
+  if (tile * 16 >= g.M) break;
+  const int p = tile * 16 + col;
+  const bool valid = p < g.M;
   f32x4 Z[TI];
   if (n == 0) {
 #pragma unroll
     for (int t = 0; t < TI; ++t) Z[t] = bias4(params, 16 * t + 4 * grp, g.d);  // Z_0 = z0
   } else {
-    const float* P = params + g.d + (size_t)(n - 1) * g.pstep;
-    const size_t esz = BF ? 2 : 4;
-    const char* pk = reinterpret_cast<const char*>(packF) + (size_t)(n - 1) * g.packf_step * esz;
     f32x4 xin[TI];
 #pragma unroll
     for (int t = 0; t < TI; ++t) {
@@ -312,38 +378,35 @@ __global__ __launch_bounds__(256) void k_forward(Geo g, const float* __restrict_
     }
     f32x4 h[TW], acc[TW];
     layer_mm<BF, TW, TI>(acc, xin, pk, lane);
-    const float* b = P + (size_t)g.w * g.d;
     const size_t hM = (size_t)g.M * g.wp;
 #pragma unroll
     for (int T = 0; T < TW; ++T) {
-      const f32x4 bb = bias4(b, 16 * T + 4 * grp, g.w);
+      const f32x4 bb = ld4(bp + 16 * T + 4 * grp);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) h[T][r] = tanhf(acc[T][r] + bb[r]);
+      for (int r = 0; r < 4; ++r) h[T][r] = fast_tanh(acc[T][r] + bb[r]);
       h[T] = round4(h[T], BF);
       if (valid)
         st_act(H, ((size_t)n * g.L) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h[T], BF);
     }
     const char* pkl = pk + 256ULL * TW * TI * esz;
-    const float* Pl = b + g.w;
     for (int l = 2; l <= g.L; ++l) {
       layer_mm<BF, TW, TW>(acc, h, pkl, lane);
-      const float* bl = Pl + (size_t)g.w * g.w;
+      const float* bl = bp + (size_t)(l - 1) * 16 * TW;
 #pragma unroll
       for (int T = 0; T < TW; ++T) {
-        const f32x4 bb = bias4(bl, 16 * T + 4 * grp, g.w);
+        const f32x4 bb = ld4(bl + 16 * T + 4 * grp);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) h[T][r] = tanhf(acc[T][r] + bb[r]);
+        for (int r = 0; r < 4; ++r) h[T][r] = fast_tanh(acc[T][r] + bb[r]);
         h[T] = round4(h[T], BF);
         if (valid)
           st_act(H, ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h[T], BF);
       }
       pkl += 256ULL * TW * TW * esz;
-      Pl = bl + g.w;
     }
     layer_mm<BF, TI, TW>(Z, h, pkl, lane);
-    const float* bo = Pl + (size_t)g.d * g.w;
+    const float* bo = bp + (size_t)g.L * 16 * TW;
 #pragma unroll
-    for (int t = 0; t < TI; ++t) Z[t] += bias4(bo, 16 * t + 4 * grp, g.d);
+    for (int t = 0; t < TI; ++t) Z[t] += ld4(bo + 16 * t + 4 * grp);
   }
   // epilogue: c_n = Z.s + dt * (Z-part of phi), v_n = s + dt * phi_z
   float cz = 0.f, cx = 0.f;
@@ -382,6 +445,7 @@ __global__ __launch_bounds__(256) void k_forward(Geo g, const float* __restrict_
   c += __shfl_xor(c, 16);
   c += __shfl_xor(c, 32);
   if (valid && grp == 0) C[(size_t)n * g.M + p] = c;
+  }
 }
 
 // -------------------------------------------------------------- scan kernel
@@ -454,18 +518,33 @@ __global__ __launch_bounds__(256) void k_scan(Geo g, const double* __restrict__ 
 }
 
 // ---------------------------------------------------------- backward kernel
-template <bool BF, int TI, int TW>
-__global__ __launch_bounds__(256) void k_backward(Geo g, const void* __restrict__ packB,
-                                                  const float* __restrict__ V,
-                                                  const float* __restrict__ LAM,
-                                                  const void* __restrict__ H, void* __restrict__ DZ,
-                                                  void* __restrict__ DH) {
+template <bool BF, int TI, int TW, bool LDSW>
+__global__ __launch_bounds__(LDSW ? 512 : 256) void k_backward(Geo g, const void* __restrict__ packB,
+                                                                const float* __restrict__ V,
+                                                                const float* __restrict__ LAM,
+                                                                const void* __restrict__ H,
+                                                                void* __restrict__ DZ, void* __restrict__ DH,
+                                                                int tpw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
   const int n = blockIdx.y;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  const int p = (blockIdx.x * 4 + wv) * 16 + col;
-  const bool valid = p < g.M;
   const size_t rowM = (size_t)g.M * g.dp;
+  const size_t esz = BF ? 2 : 4;
+  const char* pk;
+  if constexpr (LDSW) {
+    if (n > 0)
+      stage_weights(wsm, reinterpret_cast<const char*>(packB) + (size_t)(n - 1) * g.packb_step * esz,
+                    (size_t)g.packb_step * esz);
+    pk = reinterpret_cast<const char*>(wsm);
+  } else {
+    pk = reinterpret_cast<const char*>(packB) + (size_t)(n > 0 ? n - 1 : 0) * g.packb_step * esz;
+  }
+  for (int it = 0; it < tpw; ++it) {
+  const int tile = (blockIdx.x * tpw + it) * nwv + wv;
+  if (tile * 16 >= g.M) break;
+  const int p = tile * 16 + col;
+  const bool valid = p < g.M;
   const float lam = valid ? LAM[(size_t)n * g.M + p] : 0.f;
   f32x4 zeta[TI];
 #pragma unroll
@@ -475,9 +554,7 @@ __global__ __launch_bounds__(256) void k_backward(Geo g, const void* __restrict_
     zeta[t] = round4(lam * v, BF);
     if (valid) st_act(DZ, ((size_t)n * g.M + p) * g.zp + c0, zeta[t], BF);
   }
-  if (n == 0) return;
-  const size_t esz = BF ? 2 : 4;
-  const char* pk = reinterpret_cast<const char*>(packB) + (size_t)(n - 1) * g.packb_step * esz;
+  if (n == 0) continue;
   const size_t hM = (size_t)g.M * g.wp;
   f32x4 dl[TW], acc[TW];
   layer_mm<BF, TW, TI>(acc, zeta, pk, lane);
@@ -505,6 +582,7 @@ __global__ __launch_bounds__(256) void k_backward(Geo g, const void* __restrict_
       dl[T] = round4(dl[T], BF);
       if (valid) st_act(DH, idx, dl[T], BF);
     }
+  }
   }
 }
 
@@ -816,10 +894,11 @@ static inline unsigned grid1(long long n, long long cap = 65536) {
 }
 
 
-hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* packB, hipStream_t s) {
+hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* packB, float* pbias,
+                       hipStream_t s) {
   if (g.N < 2) return hipSuccess;
-  const long long total = (long long)(g.N - 1) * (g.packf_step + g.packb_step);
-  k_pack<<<grid1(total), 256, 0, s>>>(g, params, packF, packB);
+  const long long total = (long long)(g.N - 1) * (g.packf_step + g.packb_step + g.pbias_step);
+  k_pack<<<grid1(total), 256, 0, s>>>(g, params, packF, packB, pbias);
   return hipGetLastError();
 }
 
@@ -832,17 +911,70 @@ hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t ite
   return hipGetLastError();
 }
 
+// Tiles of 16 paths per wave for the LDS-resident kernels: the count that
+// minimises the makespan ceil(workgroups / CUs) * tiles, one workgroup per CU.
+static int tiles_per_wave(const Geo& g, int waves, int cus) {
+  const long long tiles = (g.M + 15) / 16;
+  int best = 1;
+  long long best_span = -1;
+  for (int t = 1; t <= 64; ++t) {
+    const long long gx = (tiles + (long long)waves * t - 1) / ((long long)waves * t);
+    const long long wgs = gx * g.N;
+    const long long span = ((wgs + cus - 1) / cus) * t;
+    if (best_span < 0 || span < best_span) { best_span = span; best = t; }
+  }
+  return best;
+}
+
+static int num_cus() {
+  static int cus = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+      n = 256;
+    return n;
+  }();
+  return cus;
+}
+
+static const size_t kLdsLimit = 160 * 1024;
+
 template <bool BF, int TI, int TW>
-static void fwd_inst(const Geo& g, const float* params, const void* packF, const float* X, float* V, float* C,
-                     void* H, hipStream_t s) {
-  dim3 grid((g.M + 63) / 64, g.N);
-  k_forward<BF, TI, TW><<<grid, 256, 0, s>>>(g, params, packF, X, V, C, H);
+static void fwd_inst(const Geo& g, const float* params, const void* packF, const float* pbias, const float* X,
+                     float* V, float* C, void* H, hipStream_t s) {
+  const size_t bytes = (size_t)g.packf_step * (BF ? 2 : 4) + (size_t)g.pbias_step * 4;
+  if (bytes <= kLdsLimit && g.N > 1) {
+    static bool attr = [bytes] {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_forward<BF, TI, TW, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+      return true;
+    }();
+    (void)attr;
+    const int tpw = tiles_per_wave(g, 8, num_cus());
+    dim3 grid((unsigned)(((g.M + 15) / 16 + 8 * tpw - 1) / (8 * tpw)), g.N);
+    k_forward<BF, TI, TW, true><<<grid, 512, bytes, s>>>(g, params, packF, pbias, X, V, C, H, tpw);
+  } else {
+    dim3 grid((g.M + 63) / 64, g.N);
+    k_forward<BF, TI, TW, false><<<grid, 256, 0, s>>>(g, params, packF, pbias, X, V, C, H, 1);
+  }
 }
 template <bool BF, int TI, int TW>
 static void bwd_inst(const Geo& g, const void* packB, const float* V, const float* LAM, const void* H,
                      void* DZ, void* DH, hipStream_t s) {
-  dim3 grid((g.M + 63) / 64, g.N);
-  k_backward<BF, TI, TW><<<grid, 256, 0, s>>>(g, packB, V, LAM, H, DZ, DH);
+  const size_t bytes = (size_t)g.packb_step * (BF ? 2 : 4);
+  if (bytes <= kLdsLimit && g.N > 1) {
+    static bool attr = [bytes] {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_backward<BF, TI, TW, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+      return true;
+    }();
+    (void)attr;
+    const int tpw = tiles_per_wave(g, 8, num_cus());
+    dim3 grid((unsigned)(((g.M + 15) / 16 + 8 * tpw - 1) / (8 * tpw)), g.N);
+    k_backward<BF, TI, TW, true><<<grid, 512, bytes, s>>>(g, packB, V, LAM, H, DZ, DH, tpw);
+  } else {
+    dim3 grid((g.M + 63) / 64, g.N);
+    k_backward<BF, TI, TW, false><<<grid, 256, 0, s>>>(g, packB, V, LAM, H, DZ, DH, 1);
+  }
 }
 
 // Instantiated register-tile shapes (TI tiles over d, TW tiles over w).
@@ -890,9 +1022,9 @@ bool choose_tiles(int bf16, int ti_min, int tw_min, int* ti, int* tw) {
     }                                                                             \
   } while (0)
 
-hipError_t launch_forward(const Geo& g, const float* params, const void* packF, const float* X, float* V,
-                          float* C, void* H, hipStream_t s) {
-  FBSDE_DISPATCH(fwd_inst, g, params, packF, X, V, C, H, s);
+hipError_t launch_forward(const Geo& g, const float* params, const void* packF, const float* pbias,
+                          const float* X, float* V, float* C, void* H, hipStream_t s) {
+  FBSDE_DISPATCH(fwd_inst, g, params, packF, pbias, X, V, C, H, s);
   return hipGetLastError();
 }
 
