@@ -359,25 +359,59 @@ __global__ __launch_bounds__(LDSW ? 512 : 256) void k_forward(Geo g, const float
     pk = reinterpret_cast<const char*>(packF) + (size_t)(n > 0 ? n - 1 : 0) * g.packf_step * esz;
     bp = pbias + (size_t)(n > 0 ? n - 1 : 0) * g.pbias_step;
   }
+  // X_n rows of the next tile are fetched while the current tile computes;
+  // s_n rows are fetched at the start of their tile (used in the epilogue).
+  const float* Xn = X + n * rowM;
+  float* Vn = V + n * rowM;
+  f32x4 xin[TI];
+  if constexpr (TI <= 8) {
+    const int p0 = ((blockIdx.x * tpw) * nwv + wv) * 16 + col;
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      xin[t] = (n > 0 && p0 < g.M && c0 < g.dp) ? ld4(Xn + (size_t)p0 * g.dp + c0) : zero4();
+    }
+  }
   for (int it = 0; it < tpw; ++it) {
   const int tile = (blockIdx.x * tpw + it) * nwv + wv;
   if (tile * 16 >= g.M) break;
   const int p = tile * 16 + col;
   const bool valid = p < g.M;
+  // Prefetching keeps two extra tiles of rows in registers; the 16-tile
+  // shapes load just in time instead.
+  constexpr bool PF = TI <= 8;
+  f32x4 sv[TI], xv[TI];
+  if constexpr (PF) {
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      sv[t] = (valid && c0 < g.dp) ? ld4(Vn + (size_t)p * g.dp + c0) : zero4();
+    }
+  }
+  if (n == 0 || !PF) {
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      xv[t] = (valid && c0 < g.dp) ? ld4(Xn + (size_t)p * g.dp + c0) : zero4();
+    }
+  } else if constexpr (PF) {
+#pragma unroll
+    for (int t = 0; t < TI; ++t) xv[t] = xin[t];
+    const int pn = p + 16 * nwv;
+    const bool nxt = it + 1 < tpw && pn - col < g.M;
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      xin[t] = (nxt && pn < g.M && c0 < g.dp) ? ld4(Xn + (size_t)pn * g.dp + c0) : zero4();
+    }
+  }
   f32x4 Z[TI];
   if (n == 0) {
 #pragma unroll
     for (int t = 0; t < TI; ++t) Z[t] = bias4(params, 16 * t + 4 * grp, g.d);  // Z_0 = z0
   } else {
-    f32x4 xin[TI];
-#pragma unroll
-    for (int t = 0; t < TI; ++t) {
-      const int c0 = 16 * t + 4 * grp;
-      xin[t] = (valid && c0 < g.dp) ? ld4(X + n * rowM + (size_t)p * g.dp + c0) : zero4();
-      xin[t] = round4(xin[t], BF);
-    }
     f32x4 h[TW], acc[TW];
-    layer_mm<BF, TW, TI>(acc, xin, pk, lane);
+    layer_mm<BF, TW, TI>(acc, xv, pk, lane);  // bf16: pack8 rounds X to nearest even
     const size_t hM = (size_t)g.M * g.wp;
 #pragma unroll
     for (int T = 0; T < TW; ++T) {
@@ -414,11 +448,11 @@ __global__ __launch_bounds__(LDSW ? 512 : 256) void k_forward(Geo g, const float
   for (int t = 0; t < TI; ++t) {
     const int c0 = 16 * t + 4 * grp;
     if (valid && c0 < g.dp) {
-      float* vp = V + n * rowM + (size_t)p * g.dp + c0;
-      const f32x4 s = ld4(vp);
+      float* vp = Vn + (size_t)p * g.dp + c0;
+      const f32x4 s = PF ? sv[t] : ld4(vp);
       f32x4 v = s;
       if (g.drv == DRV_BSB) {
-        const f32x4 x = ld4(X + n * rowM + (size_t)p * g.dp + c0);
+        const f32x4 x = PF ? xv[t] : ld4(Xn + (size_t)p * g.dp + c0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           cz += Z[t][r] * s[r];
@@ -540,45 +574,88 @@ __global__ __launch_bounds__(LDSW ? 512 : 256) void k_backward(Geo g, const void
   } else {
     pk = reinterpret_cast<const char*>(packB) + (size_t)(n > 0 ? n - 1 : 0) * g.packb_step * esz;
   }
+  const float* Vn = V + n * rowM;
+  const size_t hM = (size_t)g.M * g.wp;
+  // v_n rows and lambda_{n+1} of the next tile are fetched one tile ahead
+  f32x4 vnx[TI];
+  float lnx = 0.f;
+  if constexpr (TI <= 8 && TW <= 8) {
+    const int p0 = ((blockIdx.x * tpw) * nwv + wv) * 16 + col;
+    lnx = p0 < g.M ? LAM[(size_t)n * g.M + p0] : 0.f;
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      vnx[t] = (p0 < g.M && c0 < g.dp) ? ld4(Vn + (size_t)p0 * g.dp + c0) : zero4();
+    }
+  }
   for (int it = 0; it < tpw; ++it) {
   const int tile = (blockIdx.x * tpw + it) * nwv + wv;
   if (tile * 16 >= g.M) break;
   const int p = tile * 16 + col;
   const bool valid = p < g.M;
-  const float lam = valid ? LAM[(size_t)n * g.M + p] : 0.f;
+  constexpr bool PF = TI <= 8 && TW <= 8;
+  const float lam = PF ? lnx : (valid ? LAM[(size_t)n * g.M + p] : 0.f);
   f32x4 zeta[TI];
+  if constexpr (!PF) {
 #pragma unroll
-  for (int t = 0; t < TI; ++t) {
-    const int c0 = 16 * t + 4 * grp;
-    f32x4 v = (valid && c0 < g.dp) ? ld4(V + n * rowM + (size_t)p * g.dp + c0) : zero4();
-    zeta[t] = round4(lam * v, BF);
-    if (valid) st_act(DZ, ((size_t)n * g.M + p) * g.zp + c0, zeta[t], BF);
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      vnx[t] = (valid && c0 < g.dp) ? ld4(Vn + (size_t)p * g.dp + c0) : zero4();
+    }
   }
+#pragma unroll
+  for (int t = 0; t < TI; ++t) zeta[t] = round4(lam * vnx[t], BF);
+  if constexpr (PF) {
+    const int pn = p + 16 * nwv;
+    const bool nxt = it + 1 < tpw && pn - col < g.M;
+    lnx = (nxt && pn < g.M) ? LAM[(size_t)n * g.M + pn] : 0.f;
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      vnx[t] = (nxt && pn < g.M && c0 < g.dp) ? ld4(Vn + (size_t)pn * g.dp + c0) : zero4();
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TI; ++t)
+    if (valid) st_act(DZ, ((size_t)n * g.M + p) * g.zp + 16 * t + 4 * grp, zeta[t], BF);
   if (n == 0) continue;
-  const size_t hM = (size_t)g.M * g.wp;
-  f32x4 dl[TW], acc[TW];
-  layer_mm<BF, TW, TI>(acc, zeta, pk, lane);
+  f32x4 dl[TW], acc[TW], hv[TW];
   {
     const int l = g.L;
+    if constexpr (PF) {
+#pragma unroll
+      for (int T = 0; T < TW; ++T) {
+        const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
+        hv[T] = valid ? ld_act(H, idx, BF) : zero4();
+      }
+    }
+    layer_mm<BF, TW, TI>(acc, zeta, pk, lane);
 #pragma unroll
     for (int T = 0; T < TW; ++T) {
       const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
-      const f32x4 h = valid ? ld_act(H, idx, BF) : zero4();
+      if constexpr (!PF) hv[T] = valid ? ld_act(H, idx, BF) : zero4();
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dl[T][r] = acc[T][r] * (1.f - h[r] * h[r]);
+      for (int r = 0; r < 4; ++r) dl[T][r] = acc[T][r] * (1.f - hv[T][r] * hv[T][r]);
       dl[T] = round4(dl[T], BF);
       if (valid) st_act(DH, idx, dl[T], BF);
     }
   }
   const char* pkl = pk + 256ULL * TW * TI * esz;
   for (int l = g.L - 1; l >= 1; --l) {
+    if constexpr (PF) {
+#pragma unroll
+      for (int T = 0; T < TW; ++T) {
+        const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
+        hv[T] = valid ? ld_act(H, idx, BF) : zero4();
+      }
+    }
     layer_mm<BF, TW, TW>(acc, dl, pkl + (size_t)(l - 1) * 256ULL * TW * TW * esz, lane);
 #pragma unroll
     for (int T = 0; T < TW; ++T) {
       const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
-      const f32x4 h = valid ? ld_act(H, idx, BF) : zero4();
+      if constexpr (!PF) hv[T] = valid ? ld_act(H, idx, BF) : zero4();
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dl[T][r] = acc[T][r] * (1.f - h[r] * h[r]);
+      for (int r = 0; r < 4; ++r) dl[T][r] = acc[T][r] * (1.f - hv[T][r] * hv[T][r]);
       dl[T] = round4(dl[T], BF);
       if (valid) st_act(DH, idx, dl[T], BF);
     }
