@@ -93,6 +93,23 @@ def time_library(prec: str, steps: int, warmup: int):
     return ms, kern, finite
 
 
+def measured_traffic(kernel: str, prec: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration),
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "bsb_d100_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    t = rec.get("per_launch", {}).get(f"{kernel}_{prec}")
+    return None if t is None else int(round(t["read_bytes"] + t["write_bytes"]))
+
+
 def roofline_entry(prec: str, kern_ms: dict):
     flops = kernel_flops(prec, D, W, DEPTH, N, M)
     dom = max(flops, key=lambda k: kern_ms.get(k, 0.0))
@@ -100,7 +117,7 @@ def roofline_entry(prec: str, kern_ms: dict):
     achieved = flops[dom] / t / 1e12
     peak = PEAK_FP32_MFMA if prec == "fp32" else PEAK_BF16_MFMA
     return dom, {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                 "frac": round(achieved / peak, 4), "traffic": None}
+                 "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom, prec)}
 
 
 def cpu_baseline(target_s: float = 12.0):

@@ -54,6 +54,9 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime: load it first so that this library
+    # binds to the same runtime instead of a second copy
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise FbsdeError(ERR_HIP, f"{path} is not built; run __graft_entry__.build()")
     L = C.CDLL(path)

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -82,11 +83,13 @@ void make_layout(fbsde_plan* P) {
   w.PB = take((N > 1 ? N - 1 : 0) * (size_t)g.packb_step * esz);
   w.PBIAS = take((N > 1 ? N - 1 : 0) * (size_t)g.pbias_step * 4);
   // wgrad splits over paths: about 512 paths each, multiples of 32
+  // (FBSDE_WGRAD_SPLITS overrides, for tuning)
   int splits = (int)((M + 511) / 512);
+  if (const char* e = getenv("FBSDE_WGRAD_SPLITS")) splits = atoi(e);
   if (splits < 1) splits = 1;
-  if (splits > 16) splits = 16;
+  if (splits > 64) splits = 64;
   long long chunk = ((long long)M + splits - 1) / splits;
-  chunk = (chunk + 31) / 32 * 32;
+  chunk = (chunk + 63) / 64 * 64;
   splits = (int)(((long long)M + chunk - 1) / chunk);
   w.splits = splits;
   w.chunk = chunk;

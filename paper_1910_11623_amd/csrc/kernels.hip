@@ -711,7 +711,10 @@ __device__ __forceinline__ Job job_info(const Geo& g, int job, const float* X, c
 // Wave w accumulates tile columns 2w and 2w+1 (the last wave may own one)
 // over all T tile rows.  Bias gradients ride along as an extra input column
 // of ones (column `cols`).
-constexpr int WG_KC = 32;  // paths per LDS chunk
+#ifndef FBSDE_WG_KC
+#define FBSDE_WG_KC 32
+#endif
+constexpr int WG_KC = FBSDE_WG_KC;  // paths per LDS chunk
 
 template <int T>
 struct WgradLds {
@@ -1020,7 +1023,7 @@ static void fwd_inst(const Geo& g, const float* params, const void* packF, const
                      float* V, float* C, void* H, hipStream_t s) {
   const size_t bytes = (size_t)g.packf_step * (BF ? 2 : 4) + (size_t)g.pbias_step * 4;
   if (bytes <= kLdsLimit && g.N > 1) {
-    static bool attr = [bytes] {
+    static bool attr = [] {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_forward<BF, TI, TW, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
       return true;
@@ -1039,7 +1042,7 @@ static void bwd_inst(const Geo& g, const void* packB, const float* V, const floa
                      void* DZ, void* DH, hipStream_t s) {
   const size_t bytes = (size_t)g.packb_step * (BF ? 2 : 4);
   if (bytes <= kLdsLimit && g.N > 1) {
-    static bool attr = [bytes] {
+    static bool attr = [] {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_backward<BF, TI, TW, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
       return true;
