@@ -184,6 +184,52 @@ enum {
 fbsde_status fbsde_profile_enable(fbsde_plan *plan, int32_t enable);
 fbsde_status fbsde_profile_read(fbsde_plan *plan, double *ms_host, int64_t *count_host, int32_t n);
 
+/* ---- tuning ---------------------------------------------------------------
+ * A plan keeps up to two candidate register-tile shapes (the cheapest
+ * instantiated kernels that cover d and width); fbsde_workspace_size covers
+ * every configuration below, so tuning never needs a larger workspace.
+ * fbsde_plan_config selects: shape index, LDS staging of the step weights
+ * (lds != 0), 16-path tiles per wave of the LDS kernels (tpw, 0 = automatic),
+ * and the path splits of the weight-gradient reduction (0 = automatic, <= 32).
+ * Results are identical across shapes, LDS modes and tpw; the split count
+ * changes the fp32 summation order of the weight gradient only. */
+fbsde_status fbsde_plan_config(fbsde_plan *plan, int32_t shape, int32_t lds, int32_t tpw, int32_t splits);
+/* cfg_host[6] = {shape, ti, tw, lds, tpw (resolved), splits} of the current configuration */
+fbsde_status fbsde_plan_get_config(const fbsde_plan *plan, int32_t *cfg_host);
+/* Autotuner: times fbsde_forward_backward (reps timed calls per candidate,
+ * HIP events on `stream`) over shapes x LDS mode, then tiles per wave, then
+ * splits, and keeps the fastest configuration.  Writes grad/loss buffers;
+ * params and y0 are only read.  Synchronises the stream. */
+fbsde_status fbsde_plan_autotune(fbsde_plan *plan, const float *params_dev, const double *y0_dev,
+                                 float *grad_dev, double *grad_y0_dev, double *loss_dev, void *ws_dev,
+                                 void *stream, int32_t reps);
+
+/* ---- batches of independent instances in one graph ------------------------
+ * Many problems (uneven d, N, widths) trained together.  fbsde_batch_create
+ * (optionally autotunes every plan, then) captures, for every item, one full
+ * training step -- forward, reverse sweep and Adam -- into a hipGraph whose
+ * independent items run on parallel branches; the iteration index is read
+ * from the device counter *iter_dev (uint64, incremented by the graph at the
+ * end of each step; Adam uses t = *iter_dev + 1), so every replay is the next
+ * iteration.  fbsde_batch_step launches the graph on `stream`.  The batch
+ * keeps the item pointers: buffers must stay allocated, and the plans must
+ * not be reconfigured, until fbsde_batch_destroy.  Not a hot call: creation
+ * creates streams, events and the graph. */
+typedef struct {
+  fbsde_plan *plan;
+  float *params_dev; double *y0_dev;            /* trained in place                  */
+  float *grad_dev; double *grad_y0_dev; double *loss_dev;
+  float *m_dev; float *v_dev; double *m_y0_dev; double *v_y0_dev;  /* Adam state     */
+  void *ws_dev;                                 /* this plan's workspace             */
+  uint64_t seed;                                /* Philox key of this instance       */
+} fbsde_batch_item;
+typedef struct fbsde_batch fbsde_batch;
+fbsde_status fbsde_batch_create(const fbsde_batch_item *items, int32_t n, double lr, double lr_y0,
+                                double beta1, double beta2, double eps, uint64_t *iter_dev,
+                                int32_t autotune, void *stream, fbsde_batch **out);
+fbsde_status fbsde_batch_step(fbsde_batch *batch, void *stream);
+void fbsde_batch_destroy(fbsde_batch *batch);
+
 const char *fbsde_status_str(fbsde_status s);
 const char *fbsde_last_error(void);
 

@@ -24,7 +24,9 @@ EXPORTS = [
     "fbsde_plan_create", "fbsde_plan_destroy", "fbsde_param_count", "fbsde_workspace_size",
     "fbsde_forward", "fbsde_forward_backward", "fbsde_adam_step", "fbsde_prolong",
     "fbsde_sample_normals", "fbsde_terminal_mean", "fbsde_terminal_states",
-    "fbsde_profile_enable", "fbsde_profile_read", "fbsde_status_str", "fbsde_last_error",
+    "fbsde_profile_enable", "fbsde_profile_read", "fbsde_plan_config", "fbsde_plan_get_config",
+    "fbsde_plan_autotune", "fbsde_batch_create", "fbsde_batch_step", "fbsde_batch_destroy",
+    "fbsde_status_str", "fbsde_last_error",
 ]
 PROF_NAMES = ["pack", "sde", "forward", "scan", "backward", "wgrad", "reduce", "adam"]
 
@@ -40,6 +42,13 @@ class Problem(C.Structure):
                 ("sde", C.c_int32), ("sde_p", C.c_double * 2),
                 ("drv", C.c_int32), ("drv_p", C.c_double * 2),
                 ("g", C.c_int32), ("g_p", C.c_double * 2)]
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("params_dev", C.c_void_p), ("y0_dev", C.c_void_p),
+                ("grad_dev", C.c_void_p), ("grad_y0_dev", C.c_void_p), ("loss_dev", C.c_void_p),
+                ("m_dev", C.c_void_p), ("v_dev", C.c_void_p), ("m_y0_dev", C.c_void_p),
+                ("v_y0_dev", C.c_void_p), ("ws_dev", C.c_void_p), ("seed", C.c_uint64)]
 
 
 class Net(C.Structure):
@@ -76,12 +85,20 @@ def load(path: str = LIB_PATH):
     L.fbsde_terminal_states.argtypes = [vp, vp, vp, vp, vp]
     L.fbsde_profile_enable.argtypes = [vp, C.c_int32]
     L.fbsde_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), C.c_int32]
+    L.fbsde_plan_config.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    L.fbsde_plan_get_config.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.fbsde_plan_autotune.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32]
+    L.fbsde_batch_create.argtypes = [C.POINTER(BatchItem), C.c_int32, C.c_double, C.c_double, C.c_double,
+                                     C.c_double, C.c_double, vp, C.c_int32, vp, C.POINTER(vp)]
+    L.fbsde_batch_step.argtypes = [vp, vp]
+    L.fbsde_batch_destroy.argtypes = [vp]
+    L.fbsde_batch_destroy.restype = None
     L.fbsde_status_str.argtypes = [C.c_int]
     L.fbsde_status_str.restype = C.c_char_p
     L.fbsde_last_error.argtypes = []
     L.fbsde_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("fbsde_plan_destroy", "fbsde_status_str", "fbsde_last_error"):
+        if name not in ("fbsde_plan_destroy", "fbsde_batch_destroy", "fbsde_status_str", "fbsde_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L

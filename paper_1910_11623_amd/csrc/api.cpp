@@ -37,6 +37,10 @@ struct fbsde_plan {
   int device;
   bool prof = false;
   ProfRing ring[FBSDE_PROF_NUM];
+  // tuning: candidate register-tile shapes and the workspace reserved for all of them
+  int ncand = 0;
+  int cand_ti[4], cand_tw[4];
+  size_t reserve = 0;
 };
 
 namespace {
@@ -53,6 +57,8 @@ fbsde_status hip_fail(hipError_t e, const char* where) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int kMaxTuneSplits = 32;
 
 int tiles(int n, bool bf16) {
   // 16-wide tiles; bf16 K-blocks are 32 wide, so bf16 tile counts are even
@@ -82,14 +88,14 @@ void make_layout(fbsde_plan* P) {
   w.PF = take((N > 1 ? N - 1 : 0) * (size_t)g.packf_step * esz);
   w.PB = take((N > 1 ? N - 1 : 0) * (size_t)g.packb_step * esz);
   w.PBIAS = take((N > 1 ? N - 1 : 0) * (size_t)g.pbias_step * 4);
-  // wgrad splits over paths: about 512 paths each, multiples of 32
-  // (FBSDE_WGRAD_SPLITS overrides, for tuning)
-  int splits = (int)((M + 511) / 512);
-  if (const char* e = getenv("FBSDE_WGRAD_SPLITS")) splits = atoi(e);
+  // wgrad splits over paths: preset by the caller (0: about 512 paths each)
+  int splits = w.splits > 0 ? w.splits : (int)((M + 511) / 512);
+  if (w.splits <= 0)
+    if (const char* e = getenv("FBSDE_WGRAD_SPLITS")) splits = atoi(e);
   if (splits < 1) splits = 1;
   if (splits > 64) splits = 64;
   long long chunk = ((long long)M + splits - 1) / splits;
-  chunk = (chunk + 63) / 64 * 64;
+  chunk = (chunk + 31) / 32 * 32;
   splits = (int)(((long long)M + chunk - 1) / chunk);
   w.splits = splits;
   w.chunk = chunk;
@@ -97,6 +103,34 @@ void make_layout(fbsde_plan* P) {
   w.scan_blocks = (int)((M + 255) / 256);
   w.RED = take((size_t)w.scan_blocks * 2 * 8 + 64);
   w.total = off;
+}
+
+void set_tiles(Geo& g, int ti, int tw) {
+  g.ti = ti;
+  g.tw = tw;
+  g.zp = 16 * ti;
+  g.wp = 16 * tw;
+  const long long L = g.L;
+  g.packf_step = 256LL * (g.tw * g.ti + (L - 1) * g.tw * g.tw + g.ti * g.tw);
+  g.packb_step = 256LL * (g.tw * g.ti + (L - 1) * g.tw * g.tw);
+  g.pbias_step = 16LL * (L * g.tw + g.ti);
+}
+
+// Largest workspace over the candidate tile shapes and the largest split count
+// the tuner may pick, so that any tuned configuration fits the caller's buffer.
+size_t reserve_bytes(fbsde_plan* P) {
+  const Geo keep_g = P->geo;
+  const WsLayout keep_w = P->ws;
+  size_t mx = 0;
+  for (int c = 0; c < P->ncand; ++c) {
+    set_tiles(P->geo, P->cand_ti[c], P->cand_tw[c]);
+    P->ws.splits = kMaxTuneSplits;
+    make_layout(P);
+    mx = P->ws.total > mx ? P->ws.total : mx;
+  }
+  P->geo = keep_g;
+  P->ws = keep_w;
+  return mx;
 }
 
 bool finite_all(const double* v, int n) {
@@ -154,7 +188,7 @@ struct ProfScope {
 };
 
 fbsde_status run_forward(fbsde_plan* P, const float* params, const double* y0, uint64_t seed,
-                         uint64_t iter, void* ws, hipStream_t s) {
+                         uint64_t iter, const uint64_t* iter_dev, void* ws, hipStream_t s) {
   const Geo& g = P->geo;
   const WsLayout& L = P->ws;
   hipError_t e;
@@ -165,7 +199,7 @@ fbsde_status run_forward(fbsde_plan* P, const float* params, const double* y0, u
   }
   {
     ProfScope ps(P, FBSDE_PROF_SDE, s);
-    if ((e = fbsde::launch_sde(g, P->x0_dev, seed, iter, at<float>(ws, L.X), at<float>(ws, L.V),
+    if ((e = fbsde::launch_sde(g, P->x0_dev, seed, iter, iter_dev, at<float>(ws, L.X), at<float>(ws, L.V),
                                at<float>(ws, L.QN), at<float>(ws, L.LN), s)) != hipSuccess)
       return hip_fail(e, "sde");
   }
@@ -182,6 +216,31 @@ fbsde_status run_forward(fbsde_plan* P, const float* params, const double* y0, u
                                 at<float>(ws, L.Y), at<float>(ws, L.LAM), at<double>(ws, L.RED),
                                 L.scan_blocks, s)) != hipSuccess)
       return hip_fail(e, "scan");
+  }
+  return FBSDE_OK;
+}
+
+fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double* loss, void* ws, hipStream_t s) {
+  const Geo& g = plan->geo;
+  const WsLayout& L = plan->ws;
+  hipError_t e;
+  {
+    ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
+    if ((e = fbsde::launch_backward(g, at<void>(ws, L.PB), at<float>(ws, L.V), at<float>(ws, L.LAM),
+                                    at<void>(ws, L.H), at<void>(ws, L.DZ), at<void>(ws, L.DH), s)) != hipSuccess)
+      return hip_fail(e, "backward");
+  }
+  {
+    ProfScope ps(plan, FBSDE_PROF_WGRAD, s);
+    if ((e = fbsde::launch_wgrad(g, at<float>(ws, L.X), at<void>(ws, L.H), at<void>(ws, L.DZ),
+                                 at<void>(ws, L.DH), at<float>(ws, L.PART), L.splits, L.chunk, s)) != hipSuccess)
+      return hip_fail(e, "wgrad");
+  }
+  {
+    ProfScope ps(plan, FBSDE_PROF_REDUCE, s);
+    if ((e = fbsde::launch_reduce(g, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
+                                  L.scan_blocks, loss, grad_y0, s)) != hipSuccess)
+      return hip_fail(e, "reduce");
   }
   return FBSDE_OK;
 }
@@ -245,12 +304,16 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   g.L = net->depth;
   g.N = N;
   g.M = (int)M;
-  if (!fbsde::choose_tiles(bf ? 1 : 0, tiles(p.d, bf), tiles(net->width, bf), &g.ti, &g.tw)) {
+  int ti0 = 0, tw0 = 0;
+  if (!fbsde::choose_tiles(bf ? 1 : 0, tiles(p.d, bf), tiles(net->width, bf), &ti0, &tw0)) {
     delete P;
     return fail(FBSDE_ERR_UNSUPPORTED, "no fused-MLP tile shape covers this d and width");
   }
-  g.zp = 16 * g.ti;
-  g.wp = 16 * g.tw;
+  P->ncand = fbsde::tile_candidates(bf ? 1 : 0, ti0, tw0, P->cand_ti, P->cand_tw, 2);
+  g.L = net->depth;
+  set_tiles(g, ti0, tw0);
+  g.lds = 1;
+  g.tpw = 0;
   g.bf16 = bf ? 1 : 0;
   g.sde = p.sde;
   g.sde_s = (float)p.sde_p[0];
@@ -265,10 +328,10 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   const long long d = p.d, w = net->width, L = net->depth;
   g.pstep = w * d + w + (L - 1) * (w * w + w) + d * w + d;
   g.nparams = d + (long long)(N - 1) * g.pstep;
-  g.packf_step = 256LL * (g.tw * g.ti + (L - 1) * g.tw * g.tw + g.ti * g.tw);
-  g.packb_step = 256LL * (g.tw * g.ti + (L - 1) * g.tw * g.tw);
-  g.pbias_step = 16LL * (L * g.tw + g.ti);
+  P->ws.splits = 0;
   make_layout(P);
+  P->reserve = reserve_bytes(P);
+  if (P->reserve < P->ws.total) P->reserve = P->ws.total;
 
   hipError_t e = hipGetDevice(&P->device);
   if (e != hipSuccess) {
@@ -308,7 +371,7 @@ fbsde_status fbsde_param_count(const fbsde_plan* plan, int64_t* n) {
 
 fbsde_status fbsde_workspace_size(const fbsde_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return fail(FBSDE_ERR_INVALID, "plan or output is NULL");
-  *bytes = plan->ws.total;
+  *bytes = plan->reserve;
   return FBSDE_OK;
 }
 
@@ -318,7 +381,7 @@ fbsde_status fbsde_forward(fbsde_plan* plan, const float* params, const double* 
   if (st != FBSDE_OK) return st;
   if (!params || !y0 || !loss) return fail(FBSDE_ERR_INVALID, "params, y0 and loss must be non-NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  st = run_forward(plan, params, y0, seed, iter, ws, s);
+  st = run_forward(plan, params, y0, seed, iter, nullptr, ws, s);
   if (st != FBSDE_OK) return st;
   hipError_t e = fbsde::launch_loss_only(plan->geo, at<double>(ws, plan->ws.RED), plan->ws.scan_blocks, loss, s);
   if (e != hipSuccess) return hip_fail(e, "finalize");
@@ -333,30 +396,9 @@ fbsde_status fbsde_forward_backward(fbsde_plan* plan, const float* params, const
   if (!params || !y0 || !grad || !grad_y0 || !loss)
     return fail(FBSDE_ERR_INVALID, "params, y0, grad, grad_y0 and loss must be non-NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  st = run_forward(plan, params, y0, seed, iter, ws, s);
+  st = run_forward(plan, params, y0, seed, iter, nullptr, ws, s);
   if (st != FBSDE_OK) return st;
-  const Geo& g = plan->geo;
-  const WsLayout& L = plan->ws;
-  hipError_t e;
-  {
-    ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
-    if ((e = fbsde::launch_backward(g, at<void>(ws, L.PB), at<float>(ws, L.V), at<float>(ws, L.LAM),
-                                    at<void>(ws, L.H), at<void>(ws, L.DZ), at<void>(ws, L.DH), s)) != hipSuccess)
-      return hip_fail(e, "backward");
-  }
-  {
-    ProfScope ps(plan, FBSDE_PROF_WGRAD, s);
-    if ((e = fbsde::launch_wgrad(g, at<float>(ws, L.X), at<void>(ws, L.H), at<void>(ws, L.DZ),
-                                 at<void>(ws, L.DH), at<float>(ws, L.PART), L.splits, L.chunk, s)) != hipSuccess)
-      return hip_fail(e, "wgrad");
-  }
-  {
-    ProfScope ps(plan, FBSDE_PROF_REDUCE, s);
-    if ((e = fbsde::launch_reduce(g, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
-                                  L.scan_blocks, loss, grad_y0, s)) != hipSuccess)
-      return hip_fail(e, "reduce");
-  }
-  return FBSDE_OK;
+  return run_backward(plan, grad, grad_y0, loss, ws, s);
 }
 
 fbsde_status fbsde_adam_step(fbsde_plan* plan, float* params, double* y0, const float* grad,
@@ -370,11 +412,9 @@ fbsde_status fbsde_adam_step(fbsde_plan* plan, float* params, double* y0, const 
   if (t < 1) return fail(FBSDE_ERR_INVALID, "Adam step count must be >= 1");
   if (!(lr >= 0) || !(lr_y0 >= 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
     return fail(FBSDE_ERR_INVALID, "Adam hyper-parameters out of range");
-  const double c1 = 1.0 - std::pow(b1, (double)t), c2 = 1.0 - std::pow(b2, (double)t);
   ProfScope ps(plan, FBSDE_PROF_ADAM, reinterpret_cast<hipStream_t>(stream));
   hipError_t e = fbsde::launch_adam(plan->geo.nparams, params, grad, m, v, y0, grad_y0, m_y0, v_y0, (float)lr,
-                                    (float)c1, (float)c2, lr_y0, c1, c2, b1, b2, eps,
-                                    reinterpret_cast<hipStream_t>(stream));
+                                    (double)t, nullptr, lr_y0, b1, b2, eps, reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "adam");
   return FBSDE_OK;
 }
@@ -407,7 +447,7 @@ fbsde_status fbsde_terminal_mean(fbsde_plan* plan, uint64_t seed, uint64_t iter,
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const Geo& g = plan->geo;
   const WsLayout& L = plan->ws;
-  hipError_t e = fbsde::launch_sde(g, plan->x0_dev, seed, iter, at<float>(ws, L.X), at<float>(ws, L.V),
+  hipError_t e = fbsde::launch_sde(g, plan->x0_dev, seed, iter, nullptr, at<float>(ws, L.X), at<float>(ws, L.V),
                                    at<float>(ws, L.QN), at<float>(ws, L.LN), s);
   if (e != hipSuccess) return hip_fail(e, "sde");
   e = fbsde::launch_gmean(g, at<float>(ws, L.QN), at<float>(ws, L.LN), mean, s);
@@ -486,5 +526,253 @@ fbsde_status fbsde_profile_read(fbsde_plan* plan, double* ms, int64_t* count, in
   }
   return FBSDE_OK;
 }
+
+// ------------------------------------------------------------------ tuning
+fbsde_status fbsde_plan_config(fbsde_plan* plan, int32_t shape, int32_t lds, int32_t tpw, int32_t splits) {
+  if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
+  if (shape < 0 || shape >= plan->ncand) return fail(FBSDE_ERR_INVALID, "shape index out of range");
+  if (tpw < 0 || tpw > 64 || splits < 0 || splits > kMaxTuneSplits)
+    return fail(FBSDE_ERR_INVALID, "tiles per wave must be in [0, 64] and splits in [0, 32]");
+  const Geo keep_g = plan->geo;
+  const WsLayout keep_w = plan->ws;
+  set_tiles(plan->geo, plan->cand_ti[shape], plan->cand_tw[shape]);
+  plan->geo.lds = lds ? 1 : 0;
+  plan->geo.tpw = tpw;
+  plan->ws.splits = splits;
+  make_layout(plan);
+  if (plan->ws.total > plan->reserve) {
+    plan->geo = keep_g;
+    plan->ws = keep_w;
+    return fail(FBSDE_ERR_INVALID, "configuration does not fit the reserved workspace");
+  }
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_plan_get_config(const fbsde_plan* plan, int32_t* cfg_host /* [6] */) {
+  if (!plan || !cfg_host) return fail(FBSDE_ERR_INVALID, "NULL argument");
+  int shape = 0;
+  for (int c = 0; c < plan->ncand; ++c)
+    if (plan->cand_ti[c] == plan->geo.ti && plan->cand_tw[c] == plan->geo.tw) shape = c;
+  cfg_host[0] = shape;
+  cfg_host[1] = plan->geo.ti;
+  cfg_host[2] = plan->geo.tw;
+  cfg_host[3] = plan->geo.lds;
+  cfg_host[4] = plan->geo.tpw > 0 ? plan->geo.tpw : fbsde::auto_tiles_per_wave(plan->geo);
+  cfg_host[5] = plan->ws.splits;
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_plan_autotune(fbsde_plan* plan, const float* params, const double* y0, float* grad,
+                                 double* grad_y0, double* loss, void* ws, void* stream, int32_t reps) {
+  fbsde_status st = check_hot(plan, ws);
+  if (st != FBSDE_OK) return st;
+  if (!params || !y0 || !grad || !grad_y0 || !loss) return fail(FBSDE_ERR_INVALID, "NULL buffer");
+  if (reps < 1) reps = 1;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool prof = plan->prof;
+  plan->prof = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    plan->prof = prof;
+    return fail(FBSDE_ERR_HIP, "hipEventCreate");
+  }
+  auto timed = [&](float* ms) -> fbsde_status {
+    fbsde_status r = fbsde_forward_backward(plan, params, y0, grad, grad_y0, loss, 0, 0, ws, stream);  // warm
+    if (r != FBSDE_OK) return r;
+    (void)hipEventRecord(e0, s);
+    for (int k = 0; k < reps; ++k) {
+      r = fbsde_forward_backward(plan, params, y0, grad, grad_y0, loss, 0, (uint64_t)k, ws, stream);
+      if (r != FBSDE_OK) return r;
+    }
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) return fail(FBSDE_ERR_HIP, "hipEventSynchronize");
+    (void)hipEventElapsedTime(ms, e0, e1);
+    return FBSDE_OK;
+  };
+  int best[4] = {0, 1, 0, 0};  // shape, lds, tpw, splits
+  float best_ms = 1e30f;
+  auto trial = [&](int sh, int l, int tp, int sp) -> fbsde_status {
+    if (fbsde_plan_config(plan, sh, l, tp, sp) != FBSDE_OK) return FBSDE_OK;  // skip what does not fit
+    float ms = 0.f;
+    fbsde_status r = timed(&ms);
+    if (r != FBSDE_OK) return r;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best[0] = sh; best[1] = l; best[2] = tp; best[3] = sp;
+    }
+    return FBSDE_OK;
+  };
+  fbsde_status r = FBSDE_OK;
+  // 1. register-tile shape and LDS staging
+  for (int sh = 0; sh < plan->ncand && r == FBSDE_OK; ++sh)
+    for (int l = 1; l >= 0 && r == FBSDE_OK; --l) r = trial(sh, l, 0, 0);
+  // 2. tiles per wave of the LDS kernels
+  if (r == FBSDE_OK && best[1]) {
+    Geo g = plan->geo;
+    fbsde_plan_config(plan, best[0], 1, 0, 0);
+    const int a = fbsde::auto_tiles_per_wave(plan->geo);
+    (void)g;
+    const int cand[3] = {a > 1 ? a / 2 : 0, a * 2 <= 64 ? a * 2 : 0, a > 2 ? a - 1 : 0};
+    for (int c = 0; c < 3 && r == FBSDE_OK; ++c)
+      if (cand[c] > 0) r = trial(best[0], 1, cand[c], 0);
+  }
+  // 3. weight-gradient path splits
+  for (int sp : {4, 8, 16, 32}) {
+    if (r != FBSDE_OK) break;
+    if ((long long)sp * 64 > plan->M) continue;
+    r = trial(best[0], best[1], best[2], sp);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  plan->prof = prof;
+  if (r != FBSDE_OK) return r;
+  return fbsde_plan_config(plan, best[0], best[1], best[2], best[3]);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+struct fbsde_batch {
+  std::vector<fbsde_batch_item> items;
+  double lr, lr_y0, b1, b2, eps;
+  uint64_t* iter_dev;
+  hipStream_t cap = nullptr;
+  std::vector<hipStream_t> branch;
+  std::vector<hipEvent_t> events;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void batch_free(fbsde_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  for (hipStream_t s : b->branch) (void)hipStreamDestroy(s);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+}
+
+// One training step of instance `it` on stream s, with the iteration read
+// from the device counter.
+fbsde_status batch_item_step(fbsde_batch* b, const fbsde_batch_item& it, hipStream_t s) {
+  fbsde_status st = run_forward(it.plan, it.params_dev, it.y0_dev, it.seed, 0, b->iter_dev, it.ws_dev, s);
+  if (st != FBSDE_OK) return st;
+  st = run_backward(it.plan, it.grad_dev, it.grad_y0_dev, it.loss_dev, it.ws_dev, s);
+  if (st != FBSDE_OK) return st;
+  hipError_t e = fbsde::launch_adam(it.plan->geo.nparams, it.params_dev, it.grad_dev, it.m_dev, it.v_dev,
+                                    it.y0_dev, it.grad_y0_dev, it.m_y0_dev, it.v_y0_dev, (float)b->lr, 1.0,
+                                    b->iter_dev, b->lr_y0, b->b1, b->b2, b->eps, s);
+  if (e != hipSuccess) return hip_fail(e, "adam");
+  return FBSDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fbsde_status fbsde_batch_create(const fbsde_batch_item* items, int32_t n, double lr, double lr_y0, double b1,
+                                double b2, double eps, uint64_t* iter_dev, int32_t autotune, void* stream,
+                                fbsde_batch** out) {
+  if (!out) return fail(FBSDE_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!items || n < 1) return fail(FBSDE_ERR_INVALID, "need at least one item");
+  if (!iter_dev) return fail(FBSDE_ERR_INVALID, "iter_dev is NULL");
+  if (!(lr >= 0) || !(lr_y0 >= 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+    return fail(FBSDE_ERR_INVALID, "Adam hyper-parameters out of range");
+  for (int i = 0; i < n; ++i) {
+    const fbsde_batch_item& it = items[i];
+    fbsde_status st = check_hot(it.plan, it.ws_dev);
+    if (st != FBSDE_OK) return st;
+    if (!it.params_dev || !it.y0_dev || !it.grad_dev || !it.grad_y0_dev || !it.loss_dev || !it.m_dev ||
+        !it.v_dev || !it.m_y0_dev || !it.v_y0_dev)
+      return fail(FBSDE_ERR_INVALID, "batch item " + std::to_string(i) + " has a NULL buffer");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int i = 0; i < n && autotune; ++i) {
+    const fbsde_batch_item& it = items[i];
+    fbsde_status st = fbsde_plan_autotune(it.plan, it.params_dev, it.y0_dev, it.grad_dev, it.grad_y0_dev,
+                                          it.loss_dev, it.ws_dev, stream, 3);
+    if (st != FBSDE_OK) return st;
+  }
+  // eager pass: first launches of every kernel happen outside the capture
+  for (int i = 0; i < n; ++i) {
+    const fbsde_batch_item& it = items[i];
+    fbsde_status st = fbsde_forward_backward(it.plan, it.params_dev, it.y0_dev, it.grad_dev, it.grad_y0_dev,
+                                             it.loss_dev, it.seed, 0, it.ws_dev, stream);
+    if (st != FBSDE_OK) return st;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(FBSDE_ERR_HIP, "hipStreamSynchronize");
+
+  fbsde_batch* b = new (std::nothrow) fbsde_batch();
+  if (!b) return fail(FBSDE_ERR_NOMEM, "host allocation failed");
+  b->items.assign(items, items + n);
+  b->lr = lr; b->lr_y0 = lr_y0; b->b1 = b1; b->b2 = b2; b->eps = eps;
+  b->iter_dev = iter_dev;
+  const int nb = n < 4 ? n : 4;  // independent instances run on parallel graph branches
+  hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  for (int k = 0; k < nb && e == hipSuccess; ++k) {
+    hipStream_t bs = nullptr;
+    e = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking);
+    if (e == hipSuccess) b->branch.push_back(bs);
+  }
+  for (int k = 0; k < nb + 1 && e == hipSuccess; ++k) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->events.push_back(ev);
+  }
+  if (e != hipSuccess) {
+    batch_free(b);
+    return hip_fail(e, "batch streams/events");
+  }
+  std::vector<char> prof(n);
+  for (int i = 0; i < n; ++i) {
+    prof[i] = items[i].plan->prof;
+    items[i].plan->prof = false;
+  }
+  fbsde_status st = FBSDE_OK;
+  e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    // fork: every branch waits for the start of the capture stream
+    (void)hipEventRecord(b->events[nb], b->cap);
+    for (int k = 0; k < nb; ++k) (void)hipStreamWaitEvent(b->branch[k], b->events[nb], 0);
+    for (int i = 0; i < n && st == FBSDE_OK; ++i) st = batch_item_step(b, b->items[i], b->branch[i % nb]);
+    // join, then advance the device iteration counter
+    for (int k = 0; k < nb; ++k) {
+      (void)hipEventRecord(b->events[k], b->branch[k]);
+      (void)hipStreamWaitEvent(b->cap, b->events[k], 0);
+    }
+    if (st == FBSDE_OK) {
+      hipError_t ec = fbsde::launch_count(iter_dev, b->cap);
+      if (ec != hipSuccess) st = hip_fail(ec, "count");
+    }
+    hipError_t ee = hipStreamEndCapture(b->cap, &b->graph);
+    if (ee != hipSuccess && st == FBSDE_OK) st = hip_fail(ee, "hipStreamEndCapture");
+  } else {
+    st = hip_fail(e, "hipStreamBeginCapture");
+  }
+  for (int i = 0; i < n; ++i) items[i].plan->prof = prof[i];
+  if (st == FBSDE_OK) {
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) st = hip_fail(e, "hipGraphInstantiate");
+  }
+  if (st != FBSDE_OK) {
+    batch_free(b);
+    return st;
+  }
+  *out = b;
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_batch_step(fbsde_batch* b, void* stream) {
+  if (!b || !b->exec) return fail(FBSDE_ERR_INVALID, "batch is NULL");
+  hipError_t e = hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return FBSDE_OK;
+}
+
+void fbsde_batch_destroy(fbsde_batch* b) { batch_free(b); }
 
 }  // extern "C"

@@ -28,6 +28,8 @@ struct Geo {
   long long packf_step;   // packed forward fragments per step (elements)
   long long packb_step;   // packed backward fragments per step (elements)
   long long pbias_step;   // padded fp32 biases per step: L * 16 tw + 16 ti
+  int lds;                // 1: step weights may be staged in LDS (when they fit)
+  int tpw;                // 16-path tiles per wave of the LDS kernels (0: automatic)
 };
 
 // Offsets (bytes) of the sub-buffers of one workspace.
@@ -41,8 +43,8 @@ struct WsLayout {
 // launchers (kernels.hip); all return hipError_t of the launch
 hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* packB, float* pbias,
                        hipStream_t s);
-hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t iter, float* X, float* V,
-                      float* QN, float* LN, hipStream_t s);
+hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t iter, const uint64_t* iter_dev,
+                      float* X, float* V, float* QN, float* LN, hipStream_t s);
 hipError_t launch_forward(const Geo& g, const float* params, const void* packF, const float* pbias,
                           const float* X, float* V, float* C, void* H, hipStream_t s);
 hipError_t launch_scan(const Geo& g, const double* y0, const float* C, const float* QN, const float* LN,
@@ -56,9 +58,9 @@ hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* gra
 hipError_t launch_loss_only(const Geo& g, const double* scan_part, int scan_blocks, double* loss,
                             hipStream_t s);
 hipError_t launch_adam(long long n, float* p, const float* gr, float* m, float* v, double* y0,
-                       const double* gy0, double* my0, double* vy0, float lr, float c1, float c2,
-                       double lr_y0, double c1d, double c2d, double b1, double b2, double eps,
-                       hipStream_t s);
+                       const double* gy0, double* my0, double* vy0, float lr, double t, const uint64_t* t_dev,
+                       double lr_y0, double b1, double b2, double eps, hipStream_t s);
+hipError_t launch_count(uint64_t* c, hipStream_t s);
 hipError_t launch_prolong(const Geo& coarse, const Geo& fine, const float* pc, float* pf, hipStream_t s);
 hipError_t launch_normals(const Geo& g, uint64_t seed, uint64_t iter, float* xi, hipStream_t s);
 hipError_t launch_gmean(const Geo& g, const float* QN, const float* LN, double* out, hipStream_t s);
@@ -68,5 +70,10 @@ hipError_t launch_terminal_copy(const Geo& g, const float* X, const float* Y, fl
 // Register-tile shape of the fused MLP kernels: the smallest instantiated
 // (ti, tw) with ti >= ti_min, tw >= tw_min.  Returns false if none exists.
 bool choose_tiles(int bf16, int ti_min, int tw_min, int* ti, int* tw);
+// All instantiated shapes covering (ti_min, tw_min), cheapest first; returns the count (<= cap).
+int tile_candidates(int bf16, int ti_min, int tw_min, int* ti, int* tw, int cap);
+// Whether the forward / backward step weights of this geometry fit in LDS.
+bool lds_fits(const Geo& g);
+int auto_tiles_per_wave(const Geo& g);
 
 }  // namespace fbsde

@@ -238,8 +238,10 @@ __global__ __launch_bounds__(256) void k_pack(Geo g, const float* __restrict__ p
 // Thread = (path m, dims 4j..4j+3); a block holds whole paths so that
 // |X_N|^2 and sum X_N reduce in LDS in a fixed order.
 __global__ __launch_bounds__(256) void k_sde(Geo g, const float* __restrict__ x0, uint64_t seed,
-                                             uint64_t iter, float* __restrict__ X, float* __restrict__ V,
+                                             uint64_t iter_imm, const uint64_t* __restrict__ iter_dev,
+                                             float* __restrict__ X, float* __restrict__ V,
                                              float* __restrict__ QN, float* __restrict__ LN) {
+  const uint64_t iter = iter_dev ? iter_dev[0] : iter_imm;
   __shared__ float sq[256], sl[256];
   const int G = g.dp / 4;
   const int ppb = max(1, 256 / G);
@@ -891,13 +893,18 @@ __global__ __launch_bounds__(256) void k_finalize(int M, const double* __restric
 }
 
 // -------------------------------------------------------------- Adam kernel
+// Adam step t (bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t).  With t_dev
+// non-null, t = t_dev[0] + 1 is read on the device (graph replays).
 __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p, const float* __restrict__ gr,
                                               float* __restrict__ m, float* __restrict__ v,
                                               double* __restrict__ y0, const double* __restrict__ gy0,
                                               double* __restrict__ my0, double* __restrict__ vy0, float lr,
-                                              float c1, float c2, double lr_y0, double c1d, double c2d,
+                                              double t_imm, const uint64_t* __restrict__ t_dev, double lr_y0,
                                               double b1d, double b2d, double epsd) {
   const float b1 = (float)b1d, b2 = (float)b2d, eps = (float)epsd;
+  const double t = t_dev ? (double)(t_dev[0] + 1) : t_imm;
+  const double c1d = 1.0 - pow(b1d, t), c2d = 1.0 - pow(b2d, t);
+  const float c1 = (float)c1d, c2 = (float)c2d;
   const long long i0 = blockIdx.x * 256LL + threadIdx.x;
   for (long long i = i0; i < n; i += (long long)gridDim.x * 256) {
     const float gi = gr[i];
@@ -915,6 +922,10 @@ __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p
     vy0[0] = vi;
     y0[0] -= lr_y0 * (mi / c1d) / (sqrt(vi / c2d) + epsd);
   }
+}
+
+__global__ void k_count(uint64_t* __restrict__ c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c[0] += 1;
 }
 
 // --------------------------------------------------------- prolong kernel
@@ -982,12 +993,12 @@ hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* pac
   return hipGetLastError();
 }
 
-hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t iter, float* X, float* V,
-                      float* QN, float* LN, hipStream_t s) {
+hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t iter, const uint64_t* iter_dev,
+                      float* X, float* V, float* QN, float* LN, hipStream_t s) {
   const int G = g.dp / 4;
   const int ppb = G >= 256 ? 1 : 256 / G;
   const unsigned blocks = (unsigned)((g.M + ppb - 1) / ppb);
-  k_sde<<<blocks, 256, 0, s>>>(g, x0, seed, iter, X, V, QN, LN);
+  k_sde<<<blocks, 256, 0, s>>>(g, x0, seed, iter, iter_dev, X, V, QN, LN);
   return hipGetLastError();
 }
 
@@ -1018,18 +1029,26 @@ static int num_cus() {
 
 static const size_t kLdsLimit = 160 * 1024;
 
+bool lds_fits(const Geo& g) {
+  const size_t esz = g.bf16 ? 2 : 4;
+  return (size_t)g.packf_step * esz + (size_t)g.pbias_step * 4 <= kLdsLimit &&
+         (size_t)g.packb_step * esz <= kLdsLimit;
+}
+
+int auto_tiles_per_wave(const Geo& g) { return tiles_per_wave(g, 8, num_cus()); }
+
 template <bool BF, int TI, int TW>
 static void fwd_inst(const Geo& g, const float* params, const void* packF, const float* pbias, const float* X,
                      float* V, float* C, void* H, hipStream_t s) {
   const size_t bytes = (size_t)g.packf_step * (BF ? 2 : 4) + (size_t)g.pbias_step * 4;
-  if (bytes <= kLdsLimit && g.N > 1) {
+  if (g.lds && bytes <= kLdsLimit && g.N > 1) {
     static bool attr = [] {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_forward<BF, TI, TW, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
       return true;
     }();
     (void)attr;
-    const int tpw = tiles_per_wave(g, 8, num_cus());
+    const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, 8, num_cus());
     dim3 grid((unsigned)(((g.M + 15) / 16 + 8 * tpw - 1) / (8 * tpw)), g.N);
     k_forward<BF, TI, TW, true><<<grid, 512, bytes, s>>>(g, params, packF, pbias, X, V, C, H, tpw);
   } else {
@@ -1041,14 +1060,14 @@ template <bool BF, int TI, int TW>
 static void bwd_inst(const Geo& g, const void* packB, const float* V, const float* LAM, const void* H,
                      void* DZ, void* DH, hipStream_t s) {
   const size_t bytes = (size_t)g.packb_step * (BF ? 2 : 4);
-  if (bytes <= kLdsLimit && g.N > 1) {
+  if (g.lds && bytes <= kLdsLimit && g.N > 1) {
     static bool attr = [] {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_backward<BF, TI, TW, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
       return true;
     }();
     (void)attr;
-    const int tpw = tiles_per_wave(g, 8, num_cus());
+    const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, 8, num_cus());
     dim3 grid((unsigned)(((g.M + 15) / 16 + 8 * tpw - 1) / (8 * tpw)), g.N);
     k_backward<BF, TI, TW, true><<<grid, 512, bytes, s>>>(g, packB, V, LAM, H, DZ, DH, tpw);
   } else {
@@ -1066,6 +1085,22 @@ static const TileShape kShapes[] = {
     {0, 1, 2}, {0, 2, 2}, {0, 4, 4}, {0, 7, 7}, {0, 8, 8}, {0, 16, 16},
     {1, 2, 2}, {1, 4, 4}, {1, 8, 8}, {1, 16, 16},
 };
+
+int tile_candidates(int bf16, int ti_min, int tw_min, int* ti, int* tw, int cap) {
+  int n = 0;
+  // insertion by cost (ti * tw), ties by order of kShapes
+  for (const TileShape& s : kShapes) {
+    if (s.bf != bf16 || s.ti < ti_min || s.tw < tw_min) continue;
+    int pos = n;
+    while (pos > 0 && (long long)ti[pos - 1] * tw[pos - 1] > (long long)s.ti * s.tw) --pos;
+    if (pos >= cap) continue;
+    for (int q = (n < cap ? n : cap - 1); q > pos; --q) { ti[q] = ti[q - 1]; tw[q] = tw[q - 1]; }
+    ti[pos] = s.ti;
+    tw[pos] = s.tw;
+    if (n < cap) ++n;
+  }
+  return n;
+}
 
 bool choose_tiles(int bf16, int ti_min, int tw_min, int* ti, int* tw) {
   static const int forced = [] {
@@ -1167,11 +1202,14 @@ hipError_t launch_loss_only(const Geo& g, const double* scan_part, int scan_bloc
 }
 
 hipError_t launch_adam(long long n, float* p, const float* gr, float* m, float* v, double* y0,
-                       const double* gy0, double* my0, double* vy0, float lr, float c1, float c2,
-                       double lr_y0, double c1d, double c2d, double b1, double b2, double eps,
-                       hipStream_t s) {
-  k_adam<<<grid1(n, 8192), 256, 0, s>>>(n, p, gr, m, v, y0, gy0, my0, vy0, lr, c1, c2, lr_y0, c1d, c2d, b1, b2,
-                                        eps);
+                       const double* gy0, double* my0, double* vy0, float lr, double t, const uint64_t* t_dev,
+                       double lr_y0, double b1, double b2, double eps, hipStream_t s) {
+  k_adam<<<grid1(n, 8192), 256, 0, s>>>(n, p, gr, m, v, y0, gy0, my0, vy0, lr, t, t_dev, lr_y0, b1, b2, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(uint64_t* c, hipStream_t s) {
+  k_count<<<1, 64, 0, s>>>(c);
   return hipGetLastError();
 }
 

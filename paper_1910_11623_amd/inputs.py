@@ -86,3 +86,12 @@ def param_count(problem: dict, net: dict, N: int) -> int:
     if net.get("kind", "mlp") == "mlp":
         return d + (N - 1) * per
     return per
+
+
+def allen_cahn_batch(n: int = 32, seed: int = 2019):
+    """(d, N) of n Allen–Cahn instances: d uniform on the integers 20..200,
+    N uniform on {10, 20, 40}; width w = d + 10 (two hidden layers)."""
+    rng = np.random.default_rng(seed)
+    ds = rng.integers(20, 201, size=n)
+    Ns = rng.choice([10, 20, 40], size=n)
+    return [(int(d), int(N)) for d, N in zip(ds, Ns)]

@@ -131,6 +131,87 @@ class Plan:
         return {B.PROF_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
 
 
+    # -------------------------------------------------------------- tuning
+    def config(self, shape: int = 0, lds: bool = True, tpw: int = 0, splits: int = 0):
+        B.check(self.lib.fbsde_plan_config(self._h, int(shape), int(bool(lds)), int(tpw), int(splits)))
+
+    def get_config(self) -> dict:
+        c = (C.c_int32 * 6)()
+        B.check(self.lib.fbsde_plan_get_config(self._h, c))
+        return dict(shape=c[0], ti=c[1], tw=c[2], lds=bool(c[3]), tpw=c[4], splits=c[5])
+
+    def autotune(self, params: torch.Tensor, y0: torch.Tensor, reps: int = 3) -> dict:
+        self._check_params(params)
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        gy0 = torch.empty((), dtype=torch.float64, device=self.device)
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        B.check(self.lib.fbsde_plan_autotune(self._h, _ptr(params), _ptr(y0), _ptr(grad), _ptr(gy0),
+                                             _ptr(loss), _ptr(self.ws), _stream(), int(reps)))
+        return self.get_config()
+
+
+class TrainState:
+    """Parameters, y0 and Adam state of one instance, as device tensors."""
+
+    def __init__(self, plan: Plan, params, y0: float):
+        dev = plan.device
+        self.plan = plan
+        self.params = torch.as_tensor(params, dtype=torch.float32).to(dev).contiguous()
+        self.y0 = torch.tensor(float(y0), dtype=torch.float64, device=dev)
+        self.grad = torch.zeros_like(self.params)
+        self.gy0 = torch.zeros((), dtype=torch.float64, device=dev)
+        self.loss = torch.zeros((), dtype=torch.float64, device=dev)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.my0 = torch.zeros((), dtype=torch.float64, device=dev)
+        self.vy0 = torch.zeros((), dtype=torch.float64, device=dev)
+
+    def eager_step(self, seed: int, it: int, lr=1e-3, lr_y0=1e-2, b1=0.9, b2=0.999, eps=1e-8):
+        """The same training step the batch graph runs, as separate calls."""
+        self.plan.forward_backward(self.params, self.y0, seed, it, out=(self.loss, self.grad, self.gy0))
+        self.plan.adam_step(self.params, self.y0, self.grad, self.gy0, self.m, self.v, self.my0, self.vy0,
+                            it + 1, lr=lr, lr_y0=lr_y0, b1=b1, b2=b2, eps=eps)
+
+
+class Batch:
+    """Independent instances advanced by one hipGraph launch per step (the
+    iteration index lives in a device counter, starting at `it0`)."""
+
+    def __init__(self, states: list, seeds: list, lr=1e-3, lr_y0=1e-2, b1=0.9, b2=0.999, eps=1e-8,
+                 autotune: bool = False, it0: int = 0):
+        self.lib = B.load()
+        self.states = states
+        dev = states[0].plan.device
+        self.iter = torch.tensor([it0], dtype=torch.int64, device=dev)
+        items = (B.BatchItem * len(states))()
+        for i, (s, seed) in enumerate(zip(states, seeds)):
+            it = items[i]
+            it.plan = s.plan._h.value
+            it.params_dev, it.y0_dev = s.params.data_ptr(), s.y0.data_ptr()
+            it.grad_dev, it.grad_y0_dev, it.loss_dev = s.grad.data_ptr(), s.gy0.data_ptr(), s.loss.data_ptr()
+            it.m_dev, it.v_dev = s.m.data_ptr(), s.v.data_ptr()
+            it.m_y0_dev, it.v_y0_dev = s.my0.data_ptr(), s.vy0.data_ptr()
+            it.ws_dev = s.plan.ws.data_ptr()
+            it.seed = int(seed)
+        self._items = items
+        h = C.c_void_p()
+        B.check(self.lib.fbsde_batch_create(items, len(states), lr, lr_y0, b1, b2, eps, self.iter.data_ptr(),
+                                            int(bool(autotune)), _stream(), C.byref(h)))
+        self._h = h
+
+    def step(self):
+        B.check(self.lib.fbsde_batch_step(self._h, _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                self.lib.fbsde_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
 class FBSDELoss(torch.autograd.Function):
     """loss = FBSDELoss.apply(params, y0, plan, seed, it).
 

@@ -1,0 +1,122 @@
+"""GPU: tuning configurations, the autotuner, and graph-captured batches of
+uneven instances against eager execution and against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import core as O
+from paper_1910_11623_amd import inputs as I
+
+from gpu_common import blockwise_rel, inputs, oracle_net, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1910_11623_amd.plan import Batch, Plan, TrainState
+
+
+def _fb(plan, p32, y0, seed=3, it=1):
+    loss, g, gy = run_gpu(plan, p32, y0, seed, it)
+    return loss, g, gy
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_tile_shapes_lds_and_tpw_are_bitwise_identical(prec):
+    prob = I.bsb(100)
+    net = dict(width=110, depth=2, prec=prec)
+    p32, _, y0 = inputs(prob, net, 4, seed=2, y0=75.0)
+    plan = Plan(prob, net, 4, 1000)
+    ref = _fb(plan, p32, y0)
+    ncand = 2
+    for shape in range(ncand):
+        for lds in (True, False):
+            for tpw in (0, 1, 3):
+                try:
+                    plan.config(shape=shape, lds=lds, tpw=tpw, splits=0)
+                except Exception:
+                    continue  # shape not available for this problem
+                got = _fb(plan, p32, y0)
+                assert got[0] == ref[0] and got[2] == ref[2], (shape, lds, tpw)
+                assert np.array_equal(got[1], ref[1]), (shape, lds, tpw)
+
+
+def test_split_count_changes_only_summation_order():
+    prob = I.hjb(40)
+    net = dict(width=50, depth=2, prec="fp32")
+    p32, _, y0 = inputs(prob, net, 6, seed=4)
+    plan = Plan(prob, net, 6, 2048)
+    plan.config(splits=4)
+    a = _fb(plan, p32, y0)
+    plan.config(splits=32)
+    b = _fb(plan, p32, y0)
+    assert a[0] == b[0] and a[2] == b[2]
+    assert np.linalg.norm(a[1] - b[1]) <= 1e-6 * np.linalg.norm(a[1])
+
+
+def test_autotune_keeps_parity():
+    prob = I.allen_cahn(60)
+    net = dict(width=70, depth=2, prec="bf16")
+    N, M = 5, 512
+    p32, p64, y0 = inputs(prob, net, N, seed=6)
+    plan = Plan(prob, net, N, M)
+    cfg = plan.autotune(torch.from_numpy(p32).cuda(), torch.tensor(y0, dtype=torch.float64, device="cuda"))
+    assert cfg["splits"] >= 1 and cfg["tpw"] >= 1
+    lg, gg, gy = _fb(plan, p32, y0, seed=2, it=0)
+    ref = O.loss_grad(prob, oracle_net(net), N, M, p64, y0, seed=2, it=0)
+    assert abs(lg - ref["loss"]) <= 1e-3 * abs(ref["loss"])
+    assert max(blockwise_rel(prob, net, N, gg, ref["grad"]).values()) <= 1e-2
+
+
+def _ac_states(shapes, M, prec, seed0=0):
+    out = []
+    for k, (d, N) in enumerate(shapes):
+        prob = I.allen_cahn(d)
+        net = dict(width=d + 10, depth=2, prec=prec)
+        plan = Plan(prob, net, N, M)
+        p = I.init_params(prob, net, N, seed=seed0 + k, out_scale=0.05).astype(np.float32)
+        out.append((prob, net, N, p, plan))
+    return out
+
+
+def test_batch_graph_replays_match_eager_steps():
+    shapes = [(20, 10), (57, 20), (130, 5)]
+    M, prec, K = 300, "bf16", 4
+    insts = _ac_states(shapes, M, prec)
+    seeds = [11 + k for k in range(len(insts))]
+    eager = [TrainState(plan, p, 0.3) for (_, _, _, p, plan) in insts]
+    # graph side: separate plans (separate workspaces) with the same inputs
+    insts2 = _ac_states(shapes, M, prec)
+    graph = [TrainState(plan, p, 0.3) for (_, _, _, p, plan) in insts2]
+    batch = Batch(graph, seeds)
+    for k in range(K):
+        for s, seed in zip(eager, seeds):
+            s.eager_step(seed, k)
+        # unrelated eager work between replays
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        batch.step()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for a, b in zip(eager, graph):
+            assert torch.equal(a.params, b.params), k
+            assert torch.equal(a.y0, b.y0), k
+            assert torch.equal(a.loss, b.loss), k
+    assert int(batch.iter.item()) == K
+
+
+def test_batch_first_step_matches_oracle():
+    """Allen–Cahn instances of uneven d and N in one graph: the loss and
+    gradient of the first step against the FP64 oracle (bf16 emulation)."""
+    shapes = [(23, 10), (96, 20), (171, 40)]
+    M, prec = 40, "bf16"
+    insts = _ac_states(shapes, M, prec, seed0=5)
+    seeds = [3 + k for k in range(len(insts))]
+    states = [TrainState(plan, p, 0.2) for (_, _, _, p, plan) in insts]
+    batch = Batch(states, seeds)
+    batch.step()
+    torch.cuda.synchronize()
+    for (prob, net, N, p, plan), s, seed in zip(insts, states, seeds):
+        ref = O.loss_grad(prob, oracle_net(net), N, M, p.astype(np.float64), 0.2, seed=seed, it=0)
+        assert abs(float(s.loss.item()) - ref["loss"]) <= 1e-3 * abs(ref["loss"])
+        g = s.grad.cpu().numpy().astype(np.float64)
+        worst = max(blockwise_rel(prob, net, N, g, ref["grad"]).values())
+        assert worst <= 1e-2, (prob["d"], N, worst)
