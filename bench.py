@@ -273,6 +273,88 @@ def tta_library(levels, iters, y0_init, target):
     return time_to_accuracy(h, target), h.y0_final, float(h.t[-1])
 
 
+def batch_leg(steps: int = 20):
+    """32 Allen–Cahn instances (d uniform on 20..200, N in {10, 20, 40},
+    M = 8192, width d + 10, bf16): one training step of every instance per
+    step, eager (separate calls) vs one graph launch, untuned vs autotuned."""
+    import torch
+    from paper_1910_11623_amd import inputs as I
+    from paper_1910_11623_amd.plan import Batch, Plan, TrainState
+
+    shapes = I.allen_cahn_batch(32, 2019)
+    Mb = 8192
+    states, seeds = [], []
+    for k, (d, Nk) in enumerate(shapes):
+        prob = I.allen_cahn(d)
+        net = dict(kind="mlp", width=d + 10, depth=2, prec="bf16")
+        plan = Plan(prob, net, Nk, Mb)
+        p = I.init_params(prob, net, Nk, seed=k, out_scale=0.05)
+        states.append(TrainState(plan, p, 0.2))
+        seeds.append(1 + k)
+    work = sum(Mb * Nk for _, Nk in shapes)
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    it = [0]
+
+    def eager():
+        for s, seed in zip(states, seeds):
+            s.eager_step(seed, it[0])
+        it[0] += 1
+
+    ms_eager = timed(eager, steps)
+    b = Batch(states, seeds, it0=10_000)
+    ms_graph = timed(b.step, steps)
+    del b
+    bt = Batch(states, seeds, autotune=True, it0=20_000)
+    ms_tuned = timed(bt.step, steps)
+    cfgs = [s.plan.get_config() for s in states]
+    finite = all(bool(torch.isfinite(s.loss).item()) for s in states)
+    del bt
+    return {"instances": len(shapes), "paths": Mb, "shapes_d_N": shapes, "prec": "bf16",
+            "path_steps_per_step": work,
+            "eager_ms": round(ms_eager, 4), "graph_ms": round(ms_graph, 4), "graph_tuned_ms": round(ms_tuned, 4),
+            "graph_tuned_path_steps_per_s": round(work / (ms_tuned * 1e-3), 1),
+            "eager_path_steps_per_s": round(work / (ms_eager * 1e-3), 1),
+            "tuned_shapes": sorted({(c["ti"], c["tw"], c["lds"], c["splits"]) for c in cfgs}),
+            "finite": finite}
+
+
+def hjb_leg(steps: int = 20):
+    """HJB d=100, N=20, M=65536, width 110x2: ms per training step, fp32 and bf16."""
+    import torch
+    from paper_1910_11623_amd import inputs as I
+    from paper_1910_11623_amd.plan import Plan, TrainState
+
+    out = {}
+    for prec in ("fp32", "bf16"):
+        prob = I.hjb(100)
+        net = dict(kind="mlp", width=110, depth=2, prec=prec)
+        plan = Plan(prob, net, 20, 65536)
+        s = TrainState(plan, I.init_params(prob, net, 20, seed=0), 4.6)
+        for k in range(3):
+            s.eager_step(1, k)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(steps):
+            s.eager_step(1, 3 + k)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[prec] = {"ms_per_step": round(ms, 4), "path_steps_per_s": round(65536 * 20 / (ms * 1e-3), 1)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +363,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy legs")
     ap.add_argument("--no-eager", action="store_true", help="skip the PyTorch-eager comparator")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched Allen-Cahn and HJB legs")
     ap.add_argument("--prec", choices=["fp32", "bf16", "both"], default="both",
                     help="which library precision(s) to time")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -343,6 +426,14 @@ def main():
             log(f"eager: {e_single[0]} ms/step, time to 1% single {e_single[1]} s, multilevel {e_multi[1]} s")
         tta["target_y0"] = target
 
+    extra = {}
+    if not args.no_extra:
+        extra["batched_allen_cahn_32"] = batch_leg()
+        log(f"batched AC x32: eager {extra['batched_allen_cahn_32']['eager_ms']} ms, graph "
+            f"{extra['batched_allen_cahn_32']['graph_ms']} ms, tuned graph {extra['batched_allen_cahn_32']['graph_tuned_ms']} ms")
+        extra["hjb_d100_M65536"] = hjb_leg()
+        log(f"HJB d=100 M=65536: {extra['hjb_d100_M65536']}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline()
@@ -365,6 +456,7 @@ def main():
                  "roofline": roof_bf, "roofline_kernel": f"k_{dom_bf}<bf16>",
                  "kernels_ms_per_launch": {k: round(v, 5) for k, v in kern_bf.items()}},
         "time_to_1pct": tta or None,
+        **extra,
     }
     print(json.dumps(line), flush=True)
 
