@@ -270,12 +270,13 @@ static void resnet_backward(const orc_problem *p, const orc_net *net, const doub
   for (int k = B; k >= 1; --k) {
     const double *ak = a + (int64_t)(k - 1) * w;
     int64_t ow = offk + (int64_t)(k - 1) * ((int64_t)w * w + w);
-    for (int o = 0; o < w; ++o) dpre[o] = dh[o] * (1.0 - ak[o] * ak[o]);
+    /* bf16 form: the derivative reads the bf16-stored activation */
+    for (int o = 0; o < w; ++o) dpre[o] = dh[o] * (1.0 - R(net, ak[o]) * R(net, ak[o]));
     outer_acc(net, w, w, dpre, h + (int64_t)(k - 1) * w, G + ow, G + ow + (int64_t)w * w);
     dense_t(net, w, w, P + ow, dpre, tmp);
     for (int o = 0; o < w; ++o) dh[o] += tmp[o];
   }
-  for (int o = 0; o < w; ++o) dpre[o] = dh[o] * (1.0 - h[o] * h[o]);
+  for (int o = 0; o < w; ++o) dpre[o] = dh[o] * (1.0 - R(net, h[o]) * R(net, h[o]));
   memcpy(u, x, sizeof(double) * d);
   u[d] = t;
   outer_acc(net, w, d + 1, dpre, u, G + offin, G + offbin);
