@@ -2,6 +2,7 @@
 // layout and the launch sequence of each hot call (declared in fbsde.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -82,14 +83,28 @@ void make_layout(fbsde_plan* P) {
   w.LAM = take(N * M * 4);
   w.QN = take(M * 4);
   w.LN = take(M * 4);
-  w.H = take(N * g.L * M * g.wp * esz);
-  w.DZ = take(N * M * g.zp * esz);
-  w.DH = take(N * g.L * M * g.wp * esz);
-  w.PF = take((N > 1 ? N - 1 : 0) * (size_t)g.packf_step * esz);
-  w.PB = take((N > 1 ? N - 1 : 0) * (size_t)g.packb_step * esz);
-  w.PBIAS = take((N > 1 ? N - 1 : 0) * (size_t)g.pbias_step * 4);
-  // wgrad splits over paths: preset by the caller (0: about 512 paths each)
-  int splits = w.splits > 0 ? w.splits : (int)((M + 511) / 512);
+  if (g.kind == 0) {
+    w.H = take(N * g.L * M * g.wp * esz);
+    w.DZ = take(N * M * g.zp * esz);
+    w.DH = take(N * g.L * M * g.wp * esz);
+    w.PF = take((N > 1 ? N - 1 : 0) * (size_t)g.packf_step * esz);
+    w.PB = take((N > 1 ? N - 1 : 0) * (size_t)g.packb_step * esz);
+    w.PBIAS = take((N > 1 ? N - 1 : 0) * (size_t)g.pbias_step * 4);
+  } else {
+    const fbsde::ResnetLayout R = fbsde::resnet_layout(g);
+    const size_t rows = (size_t)R.rows, wd = (size_t)g.w;
+    w.RPK = take((size_t)R.pk_elems * 2);
+    w.RPF = take((size_t)R.pf_elems * 4);
+    w.RH32 = take(rows * wd * 4);
+    w.RHB = take((size_t)(g.L + 1) * rows * wd * 2);
+    w.RAB = take((size_t)g.L * rows * wd * 2);
+    w.RD32 = take(rows * wd * 4);
+    w.RGB = take(2 * rows * wd * 2);
+    w.RZ = take(rows * (size_t)R.dq * 4);
+  }
+  // weight-gradient splits over paths (per-step MLP) or over chunk rows
+  // (residual network): preset by the caller, 0 = automatic
+  int splits = w.splits > 0 ? w.splits : (g.kind == 0 ? (int)((M + 511) / 512) : 8);
   if (w.splits <= 0)
     if (const char* e = getenv("FBSDE_WGRAD_SPLITS")) splits = atoi(e);
   if (splits < 1) splits = 1;
@@ -123,7 +138,7 @@ size_t reserve_bytes(fbsde_plan* P) {
   const WsLayout keep_w = P->ws;
   size_t mx = 0;
   for (int c = 0; c < P->ncand; ++c) {
-    set_tiles(P->geo, P->cand_ti[c], P->cand_tw[c]);
+    if (P->geo.kind == 0) set_tiles(P->geo, P->cand_ti[c], P->cand_tw[c]);
     P->ws.splits = kMaxTuneSplits;
     make_layout(P);
     mx = P->ws.total > mx ? P->ws.total : mx;
@@ -146,6 +161,20 @@ T* at(void* ws, size_t off) {
 template <class T>
 const T* at(const void* ws, size_t off) {
   return reinterpret_cast<const T*>(reinterpret_cast<const char*>(ws) + off);
+}
+
+fbsde::ResnetBufs resnet_bufs(const fbsde_plan* P, void* ws) {
+  const WsLayout& L = P->ws;
+  fbsde::ResnetBufs R;
+  R.pk = at<uint16_t>(ws, L.RPK);
+  R.pf = at<float>(ws, L.RPF);
+  R.h32 = at<float>(ws, L.RH32);
+  R.hb = at<uint16_t>(ws, L.RHB);
+  R.ab = at<uint16_t>(ws, L.RAB);
+  R.d32 = at<float>(ws, L.RD32);
+  R.gb = at<uint16_t>(ws, L.RGB);
+  R.z = at<float>(ws, L.RZ);
+  return R;
 }
 
 fbsde_status check_hot(const fbsde_plan* P, const void* ws) {
@@ -192,6 +221,33 @@ fbsde_status run_forward(fbsde_plan* P, const float* params, const double* y0, u
   const Geo& g = P->geo;
   const WsLayout& L = P->ws;
   hipError_t e;
+  if (g.kind == 1) {
+    const fbsde::ResnetBufs R = resnet_bufs(P, ws);
+    {
+      ProfScope ps(P, FBSDE_PROF_PACK, s);
+      if ((e = fbsde::resnet_pack(g, params, R.pk, R.pf, s)) != hipSuccess) return hip_fail(e, "pack");
+    }
+    {
+      ProfScope ps(P, FBSDE_PROF_SDE, s);
+      if ((e = fbsde::launch_sde(g, P->x0_dev, seed, iter, iter_dev, at<float>(ws, L.X), at<float>(ws, L.V),
+                                 at<float>(ws, L.QN), at<float>(ws, L.LN), s)) != hipSuccess)
+        return hip_fail(e, "sde");
+    }
+    {
+      ProfScope ps(P, FBSDE_PROF_FORWARD, s);
+      if ((e = fbsde::resnet_forward(g, R, at<float>(ws, L.X), at<float>(ws, L.V), at<float>(ws, L.C), s)) !=
+          hipSuccess)
+        return hip_fail(e, "forward");
+    }
+    {
+      ProfScope ps(P, FBSDE_PROF_SCAN, s);
+      if ((e = fbsde::launch_scan(g, y0, at<float>(ws, L.C), at<float>(ws, L.QN), at<float>(ws, L.LN),
+                                  at<float>(ws, L.Y), at<float>(ws, L.LAM), at<double>(ws, L.RED),
+                                  L.scan_blocks, s)) != hipSuccess)
+        return hip_fail(e, "scan");
+    }
+    return FBSDE_OK;
+  }
   {
     ProfScope ps(P, FBSDE_PROF_PACK, s);
     if ((e = fbsde::launch_pack(g, params, at<void>(ws, L.PF), at<void>(ws, L.PB), at<float>(ws, L.PBIAS), s)) != hipSuccess)
@@ -224,6 +280,19 @@ fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double
   const Geo& g = plan->geo;
   const WsLayout& L = plan->ws;
   hipError_t e;
+  if (g.kind == 1) {
+    {
+      ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
+      if ((e = fbsde::resnet_backward(g, resnet_bufs(plan, ws), at<float>(ws, L.X), at<float>(ws, L.V),
+                                      at<float>(ws, L.LAM), at<float>(ws, L.PART), L.splits, s)) != hipSuccess)
+        return hip_fail(e, "backward");
+    }
+    ProfScope ps(plan, FBSDE_PROF_REDUCE, s);
+    if ((e = fbsde::launch_reduce(g, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
+                                  L.scan_blocks, loss, grad_y0, s)) != hipSuccess)
+      return hip_fail(e, "reduce");
+    return FBSDE_OK;
+  }
   {
     ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
     if ((e = fbsde::launch_backward(g, at<void>(ws, L.PB), at<float>(ws, L.V), at<float>(ws, L.LAM),
@@ -284,10 +353,15 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
     return fail(FBSDE_ERR_INVALID, "unknown network kind");
   if (net->prec != FBSDE_FP32 && net->prec != FBSDE_BF16_MFMA) return fail(FBSDE_ERR_INVALID, "unknown precision");
   if (net->width < 1 || net->depth < 1) return fail(FBSDE_ERR_INVALID, "width and depth must be >= 1");
-  if (net->kind == FBSDE_NET_SHARED_RESNET)
-    return fail(FBSDE_ERR_UNSUPPORTED, "shared residual network is not implemented in this build");
-  if (p.d > 256 || net->width > 256 || net->depth > 8)
+  const bool resnet = net->kind == FBSDE_NET_SHARED_RESNET;
+  if (resnet) {
+    if (net->prec != FBSDE_BF16_MFMA)
+      return fail(FBSDE_ERR_UNSUPPORTED, "the shared residual network runs in bf16 only");
+    if (net->width % 8 != 0 || net->width > 8192 || net->depth > 32 || p.d > 8192)
+      return fail(FBSDE_ERR_UNSUPPORTED, "shared residual network: width a multiple of 8, <= 8192; depth <= 32; d <= 8192");
+  } else if (p.d > 256 || net->width > 256 || net->depth > 8) {
     return fail(FBSDE_ERR_UNSUPPORTED, "per-step MLP kernels support d <= 256, width <= 256, depth <= 8");
+  }
 
   fbsde_plan* P = new (std::nothrow) fbsde_plan();
   if (!P) return fail(FBSDE_ERR_NOMEM, "host allocation failed");
@@ -304,16 +378,28 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   g.L = net->depth;
   g.N = N;
   g.M = (int)M;
-  int ti0 = 0, tw0 = 0;
-  if (!fbsde::choose_tiles(bf ? 1 : 0, tiles(p.d, bf), tiles(net->width, bf), &ti0, &tw0)) {
-    delete P;
-    return fail(FBSDE_ERR_UNSUPPORTED, "no fused-MLP tile shape covers this d and width");
-  }
-  P->ncand = fbsde::tile_candidates(bf ? 1 : 0, ti0, tw0, P->cand_ti, P->cand_tw, 2);
+  g.kind = resnet ? 1 : 0;
   g.L = net->depth;
-  set_tiles(g, ti0, tw0);
   g.lds = 1;
   g.tpw = 0;
+  if (resnet) {
+    // chunks of whole steps, about 64k rows each
+    g.rn_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(N, 65536 / std::max<int64_t>(1, M)));
+    P->ncand = 1;
+    P->cand_ti[0] = P->cand_tw[0] = 0;
+    g.ti = g.tw = 0;
+    g.zp = g.wp = 0;
+    g.packf_step = g.packb_step = g.pbias_step = 0;
+  } else {
+    int ti0 = 0, tw0 = 0;
+    if (!fbsde::choose_tiles(bf ? 1 : 0, tiles(p.d, bf), tiles(net->width, bf), &ti0, &tw0)) {
+      delete P;
+      return fail(FBSDE_ERR_UNSUPPORTED, "no fused-MLP tile shape covers this d and width");
+    }
+    P->ncand = fbsde::tile_candidates(bf ? 1 : 0, ti0, tw0, P->cand_ti, P->cand_tw, 2);
+    g.rn_chunk = 0;
+    set_tiles(g, ti0, tw0);
+  }
   g.bf16 = bf ? 1 : 0;
   g.sde = p.sde;
   g.sde_s = (float)p.sde_p[0];
@@ -326,8 +412,13 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   g.dt = (float)(p.T / N);
   g.sqdt = (float)std::sqrt(p.T / N);
   const long long d = p.d, w = net->width, L = net->depth;
-  g.pstep = w * d + w + (L - 1) * (w * w + w) + d * w + d;
-  g.nparams = d + (long long)(N - 1) * g.pstep;
+  if (resnet) {
+    g.pstep = 0;
+    g.nparams = w * (d + 1) + w + L * (w * w + w) + d * w + d;
+  } else {
+    g.pstep = w * d + w + (L - 1) * (w * w + w) + d * w + d;
+    g.nparams = d + (long long)(N - 1) * g.pstep;
+  }
   P->ws.splits = 0;
   make_layout(P);
   P->reserve = reserve_bytes(P);
@@ -426,6 +517,12 @@ fbsde_status fbsde_prolong(const fbsde_plan* coarse, const fbsde_plan* fine, con
   if (b.N != 2 * a.N) return fail(FBSDE_ERR_INVALID, "fine plan must have twice the steps of the coarse plan");
   if (a.d != b.d || a.w != b.w || a.L != b.L || coarse->net.kind != fine->net.kind)
     return fail(FBSDE_ERR_INVALID, "coarse and fine plans must share the problem dimension and network");
+  if (a.kind == 1) {  // one network shared by all steps: the fine grid keeps it unchanged
+    hipError_t e = hipMemcpyAsync(pf, pc, (size_t)a.nparams * sizeof(float), hipMemcpyDeviceToDevice,
+                                  reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "prolong copy");
+    return FBSDE_OK;
+  }
   if (a.N < 2) return fail(FBSDE_ERR_INVALID, "coarse grid needs at least 2 steps to hold a network");
   hipError_t e = fbsde::launch_prolong(a, b, pc, pf, reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "prolong");
@@ -535,7 +632,7 @@ fbsde_status fbsde_plan_config(fbsde_plan* plan, int32_t shape, int32_t lds, int
     return fail(FBSDE_ERR_INVALID, "tiles per wave must be in [0, 64] and splits in [0, 32]");
   const Geo keep_g = plan->geo;
   const WsLayout keep_w = plan->ws;
-  set_tiles(plan->geo, plan->cand_ti[shape], plan->cand_tw[shape]);
+  if (plan->geo.kind == 0) set_tiles(plan->geo, plan->cand_ti[shape], plan->cand_tw[shape]);
   plan->geo.lds = lds ? 1 : 0;
   plan->geo.tpw = tpw;
   plan->ws.splits = splits;

@@ -30,11 +30,37 @@ struct Geo {
   long long pbias_step;   // padded fp32 biases per step: L * 16 tw + 16 ti
   int lds;                // 1: step weights may be staged in LDS (when they fit)
   int tpw;                // 16-path tiles per wave of the LDS kernels (0: automatic)
+  int kind;               // 0: per-step MLP, 1: shared residual network (L = blocks)
+  int rn_chunk;           // residual network: time steps per row chunk
 };
+
+// Shared residual network: packed weights and the per-chunk activation buffers.
+struct ResnetLayout {
+  int dq;                 // d rounded up to 8
+  long long pk_elems;     // bf16 packed weights (forward + transposed)
+  long long pf_elems;     // fp32 time column and biases
+  long long rows;         // rows per chunk = rn_chunk * M
+};
+struct ResnetBufs {
+  uint16_t* pk;           // packed bf16 weights
+  float* pf;              // w_t | b_in | b_k | b_o
+  float* h32;             // [rows][w] fp32 residual stream
+  uint16_t* hb;           // [B+1][rows][w] bf16 h_0..h_B
+  uint16_t* ab;           // [B][rows][w] bf16 a_1..a_B
+  float* d32;             // [rows][w] fp32 delta
+  uint16_t* gb;           // [2][rows][w] bf16 pre-activation gradients (ping-pong)
+  float* z;               // [rows][dq] fp32 network output
+};
+ResnetLayout resnet_layout(const Geo& g);
+hipError_t resnet_pack(const Geo& g, const float* params, uint16_t* pk, float* pf, hipStream_t s);
+hipError_t resnet_forward(const Geo& g, const ResnetBufs& R, const float* X, float* V, float* C, hipStream_t s);
+hipError_t resnet_backward(const Geo& g, const ResnetBufs& R, const float* X, const float* V, const float* LAM,
+                           float* part, int splits, hipStream_t s);
 
 // Offsets (bytes) of the sub-buffers of one workspace.
 struct WsLayout {
   size_t X, V, C, Y, LAM, QN, LN, H, DZ, DH, PF, PB, PBIAS, PART, RED, total;
+  size_t RPK, RPF, RH32, RHB, RAB, RD32, RGB, RZ;  // residual-network buffers
   int scan_blocks;
   int splits;
   long long chunk;
