@@ -283,17 +283,29 @@ def batch_leg(steps: int = 20):
 
     shapes = I.allen_cahn_batch(32, 2019)
     Mb = 8192
-    states, seeds = [], []
+    states, seeds, init = [], [], []
     for k, (d, Nk) in enumerate(shapes):
         prob = I.allen_cahn(d)
         net = dict(kind="mlp", width=d + 10, depth=2, prec="bf16")
         plan = Plan(prob, net, Nk, Mb)
         p = I.init_params(prob, net, Nk, seed=k, out_scale=0.05)
-        states.append(TrainState(plan, p, 0.2))
+        y0 = float(plan.terminal_mean(0x5A5A + k, 0).item())
+        states.append(TrainState(plan, p, y0))
+        init.append((states[-1].params.clone(), y0))
         seeds.append(1 + k)
     work = sum(Mb * Nk for _, Nk in shapes)
 
+    def reset():
+        # every phase trains from the same initial state with Adam's step
+        # count starting at 1, so the three phases do identical work
+        for s, (p, y0) in zip(states, init):
+            s.params.copy_(p)
+            s.y0.fill_(y0)
+            for t in (s.m, s.v, s.my0, s.vy0):
+                t.zero_()
+
     def timed(fn, n):
+        reset()
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -311,14 +323,19 @@ def batch_leg(steps: int = 20):
             s.eager_step(seed, it[0])
         it[0] += 1
 
+    def all_finite():
+        return all(bool(torch.isfinite(s.loss).item() and torch.isfinite(s.y0).item()) for s in states)
+
     ms_eager = timed(eager, steps)
-    b = Batch(states, seeds, it0=10_000)
+    finite = all_finite()
+    b = Batch(states, seeds)
     ms_graph = timed(b.step, steps)
+    finite = finite and all_finite()
     del b
-    bt = Batch(states, seeds, autotune=True, it0=20_000)
+    bt = Batch(states, seeds, autotune=True)
     ms_tuned = timed(bt.step, steps)
     cfgs = [s.plan.get_config() for s in states]
-    finite = all(bool(torch.isfinite(s.loss).item()) for s in states)
+    finite = finite and all_finite()
     del bt
     return {"instances": len(shapes), "paths": Mb, "shapes_d_N": shapes, "prec": "bf16",
             "path_steps_per_step": work,
@@ -355,6 +372,47 @@ def hjb_leg(steps: int = 20):
     return out
 
 
+def resnet_leg(steps: int = 3):
+    """BSB d=1000, N=64, M=16384, shared residual network (width 1024,
+    4 blocks, t as input), bf16 MFMA with recompute in the reverse sweep:
+    ms per training step and MFMA TFLOP/s of the forward and reverse phases."""
+    import torch
+    from paper_1910_11623_amd import inputs as I
+    from paper_1910_11623_amd.plan import Plan, TrainState
+
+    d, w, B, Nr, Mr = 1000, 1024, 4, 64, 16384
+    prob = I.bsb(d)
+    net = dict(kind="resnet", width=w, depth=B, prec="bf16")
+    plan = Plan(prob, net, Nr, Mr)
+    s = TrainState(plan, I.init_params(prob, net, Nr, seed=0, out_scale=0.1), 760.0)
+    s.eager_step(1, 0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        s.eager_step(1, 1 + k)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan.profile(True)
+    for k in range(steps):
+        s.eager_step(1, 10 + k)
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    rows = Nr * Mr
+    fwd_flops = 2.0 * (w * d + B * w * w + d * w) * rows
+    bwd_flops = (2.0 * (w * d + B * w * w) + 2.0 * w * d + 2.0 * B * w * w +
+                 2.0 * (d * (w + 1) + B * w * (w + 1) + w * (d + 2))) * rows
+    t_f = prof["forward"][0] / max(prof["forward"][1], 1) * 1e-3
+    t_b = prof["backward"][0] / max(prof["backward"][1], 1) * 1e-3
+    return {"ms_per_step": round(ms, 3), "path_steps_per_s": round(rows / (ms * 1e-3), 1),
+            "forward_ms": round(t_f * 1e3, 3), "backward_ms": round(t_b * 1e3, 3),
+            "forward_tflops": round(fwd_flops / t_f / 1e12, 1), "backward_tflops": round(bwd_flops / t_b / 1e12, 1),
+            "bf16_peak_tflops": PEAK_BF16_MFMA,
+            "finite": bool(torch.isfinite(s.loss).item())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +424,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the batched Allen-Cahn and HJB legs")
     ap.add_argument("--prec", choices=["fp32", "bf16", "both"], default="both",
                     help="which library precision(s) to time")
+    ap.add_argument("--only", choices=["batch", "hjb", "resnet"],
+                    help="run just one of the extra legs and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -387,6 +447,10 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
+        return
+    if args.only:
+        leg = {"batch": batch_leg, "hjb": hjb_leg, "resnet": resnet_leg}[args.only]
+        print(json.dumps({args.only: leg()}), flush=True)
         return
     if args.prec == "bf16":
         ms_bf, kern_bf, _ = time_library("bf16", args.steps, args.warmup)
@@ -433,6 +497,8 @@ def main():
             f"{extra['batched_allen_cahn_32']['graph_ms']} ms, tuned graph {extra['batched_allen_cahn_32']['graph_tuned_ms']} ms")
         extra["hjb_d100_M65536"] = hjb_leg()
         log(f"HJB d=100 M=65536: {extra['hjb_d100_M65536']}")
+        extra["resnet_bsb_d1000"] = resnet_leg()
+        log(f"ResNet BSB d=1000: {extra['resnet_bsb_d1000']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -93,18 +93,28 @@ void make_layout(fbsde_plan* P) {
   } else {
     const fbsde::ResnetLayout R = fbsde::resnet_layout(g);
     const size_t rows = (size_t)R.rows, wd = (size_t)g.w;
-    w.RPK = take((size_t)R.pk_elems * 2);
+    // bf16 GEMM operands carry 64 bytes of slack: a staged run of 8 may start
+    // up to 24 elements past the last row's valid k (its values are masked)
+    const size_t slack = 64;
+    w.RPK = take((size_t)R.pk_elems * 2 + slack);
     w.RPF = take((size_t)R.pf_elems * 4);
     w.RH32 = take(rows * wd * 4);
-    w.RHB = take((size_t)(g.L + 1) * rows * wd * 2);
-    w.RAB = take((size_t)g.L * rows * wd * 2);
+    w.RHB = take((size_t)(g.L + 1) * rows * wd * 2 + slack);
+    w.RAB = take((size_t)g.L * rows * wd * 2 + slack);
     w.RD32 = take(rows * wd * 4);
-    w.RGB = take(2 * rows * wd * 2);
+    w.RGB = take(2 * rows * wd * 2 + slack);
     w.RZ = take(rows * (size_t)R.dq * 4);
+    const size_t ldt = (size_t)R.ldt;
+    w.RHT = take((size_t)(g.L + 1) * wd * ldt * 2 + slack);
+    w.RGT = take(2 * wd * ldt * 2 + slack);
+    w.RZT = take((size_t)g.d * ldt * 2 + slack);
+    w.RXT = take((size_t)(g.d + 1) * ldt * 2 + slack);
+    w.RXB = take(rows * (size_t)R.dq * 2 + slack);
+    w.RVB = take(rows * (size_t)R.dq * 2 + slack);
   }
   // weight-gradient splits over paths (per-step MLP) or over chunk rows
   // (residual network): preset by the caller, 0 = automatic
-  int splits = w.splits > 0 ? w.splits : (g.kind == 0 ? (int)((M + 511) / 512) : 8);
+  int splits = w.splits > 0 ? w.splits : (g.kind == 0 ? (int)((M + 511) / 512) : 16);
   if (w.splits <= 0)
     if (const char* e = getenv("FBSDE_WGRAD_SPLITS")) splits = atoi(e);
   if (splits < 1) splits = 1;
@@ -174,6 +184,12 @@ fbsde::ResnetBufs resnet_bufs(const fbsde_plan* P, void* ws) {
   R.d32 = at<float>(ws, L.RD32);
   R.gb = at<uint16_t>(ws, L.RGB);
   R.z = at<float>(ws, L.RZ);
+  R.ht = at<uint16_t>(ws, L.RHT);
+  R.gt = at<uint16_t>(ws, L.RGT);
+  R.zt = at<uint16_t>(ws, L.RZT);
+  R.xt = at<uint16_t>(ws, L.RXT);
+  R.xb = at<uint16_t>(ws, L.RXB);
+  R.vb = at<uint16_t>(ws, L.RVB);
   return R;
 }
 
@@ -385,6 +401,13 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   if (resnet) {
     // chunks of whole steps, about 64k rows each
     g.rn_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(N, 65536 / std::max<int64_t>(1, M)));
+    // the GEMMs address a chunk's activations with 32-bit element offsets
+    const int64_t rows = (int64_t)g.rn_chunk * M, ldt = (rows + 7) / 8 * 8, dq = (p.d + 7) / 8 * 8;
+    const int64_t wide = std::max<int64_t>(std::max<int64_t>(net->width, dq), p.d + 1);
+    if ((rows + 32) * wide >= 0x7fffffffLL || (ldt + 32) * wide >= 0x7fffffffLL) {
+      delete P;
+      return fail(FBSDE_ERR_UNSUPPORTED, "shared residual network: M x max(width, d) must stay below 2^31");
+    }
     P->ncand = 1;
     P->cand_ti[0] = P->cand_tw[0] = 0;
     g.ti = g.tw = 0;

@@ -40,6 +40,7 @@ struct ResnetLayout {
   long long pk_elems;     // bf16 packed weights (forward + transposed)
   long long pf_elems;     // fp32 time column and biases
   long long rows;         // rows per chunk = rn_chunk * M
+  long long ldt;          // row stride of the transposed copies: rows rounded up to 8
 };
 struct ResnetBufs {
   uint16_t* pk;           // packed bf16 weights
@@ -50,6 +51,12 @@ struct ResnetBufs {
   float* d32;             // [rows][w] fp32 delta
   uint16_t* gb;           // [2][rows][w] bf16 pre-activation gradients (ping-pong)
   float* z;               // [rows][dq] fp32 network output
+  uint16_t* ht;           // [B+1][w][ldt] bf16 h_k^T (reverse sweep)
+  uint16_t* gt;           // [2][w][ldt] bf16 g^T (ping-pong)
+  uint16_t* zt;           // [d][ldt] bf16 zeta^T
+  uint16_t* xt;           // [d+1][ldt] bf16 [x; t]^T
+  uint16_t* xb;           // [rows][dq] bf16 x
+  uint16_t* vb;           // [rows][dq] bf16 zeta = lambda v
 };
 ResnetLayout resnet_layout(const Geo& g);
 hipError_t resnet_pack(const Geo& g, const float* params, uint16_t* pk, float* pf, hipStream_t s);
@@ -60,7 +67,7 @@ hipError_t resnet_backward(const Geo& g, const ResnetBufs& R, const float* X, co
 // Offsets (bytes) of the sub-buffers of one workspace.
 struct WsLayout {
   size_t X, V, C, Y, LAM, QN, LN, H, DZ, DH, PF, PB, PBIAS, PART, RED, total;
-  size_t RPK, RPF, RH32, RHB, RAB, RD32, RGB, RZ;  // residual-network buffers
+  size_t RPK, RPF, RH32, RHB, RAB, RD32, RGB, RZ, RHT, RGT, RZT, RXT, RXB, RVB;  // residual-network buffers
   int scan_blocks;
   int splits;
   long long chunk;

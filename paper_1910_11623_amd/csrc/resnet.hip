@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fbsde_internal.h"
 
 namespace fbsde {
@@ -19,8 +21,22 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128, BN = 128, BK = 32;
-constexpr int LDK = BK + 8;  // LDS row of 40 bf16 = 80 B: conflict-free 16-byte fragment reads
+constexpr int BK = 32;
+constexpr int LDK = BK + 8;
+// wave tile of the row-streaming GEMMs (16 RN_TM x 16 RN_TN) and waves per SIMD
+#ifndef RN_TM
+#define RN_TM 8
+#endif
+#ifndef RN_TN
+#define RN_TN 4
+#endif
+#ifndef RN_WPE
+#define RN_WPE 2
+#endif
+// register sets of slabs in flight (1 or 2)
+#ifndef RN_PF
+#define RN_PF 2
+#endif  // LDS row of 40 bf16 = 80 B: conflict-free 16-byte fragment reads
 
 __device__ __forceinline__ uint32_t bfbits(float f) {  // round to nearest even
   uint32_t u = __float_as_uint(f);
@@ -45,236 +61,417 @@ __device__ __forceinline__ float fast_tanh(float x) {
   return copysignf(ax < 0.4f ? small : big, x);
 }
 
-// ------------------------------------------------------------- operands
-// Element (i, k) of a GEMM operand; i runs over the operand's rows (the
-// output dimension it contributes), k over the reduction.
-enum { ROWS = 0, TRANS = 1 };
-struct Opnd {
-  const void* base;
-  long long ld;      // row stride of the stored matrix (elements)
-  int rows;          // valid i
-  int kmax;          // valid k
-  int mode;          // ROWS: base[i*ld + k];  TRANS: base[k*ld + i]
-  int f32;           // 1: fp32 storage (rounded to bf16 when staged)
-  const float* scale;  // optional scale: per row i (ROWS) or per k (TRANS)
-  int tcol;          // TRANS only: i == tcol -> t_n of row k (the time input), -1 none
-  int onescol;       // TRANS only: i == onescol -> 1 (bias column), -1 none
-  int n0, mp;        // row k of a chunk is (step n0 + k / mp, path k % mp)
-  float dt;
+// ------------------------------------------------------------------ GEMM
+// C[i][j] = sum_k A[i][k] B[j][k], both operands bf16 and k-contiguous (row
+// i of A and row j of B are runs of the reduction index).
+struct Gm {
+  const uint16_t* a; long long lda; int arows;
+  const uint16_t* b; long long ldb; int brows;
+  int K;                 // valid reduction length
+  long long kchunk;      // reduction range of one split (multiple of BK)
+  int ti, tj, ts;        // tiles over i, over j, and reduction splits
+  long long pstride;     // EPI_ACC: floats between the partial buffers of two splits
 };
-
-__device__ __forceinline__ float ld_elem(const Opnd& o, long long idx) {
-  return o.f32 ? reinterpret_cast<const float*>(o.base)[idx]
-               : bf2f(reinterpret_cast<const uint16_t*>(o.base)[idx]);
-}
-
-// 8 consecutive k of row i (ROWS), as bf16 bits packed in a uint4
-__device__ __forceinline__ uint4 load_row8(const Opnd& o, int i, int k) {
-  float v[8];
-  if (i < o.rows && k + 8 <= o.kmax) {
-    const long long idx = (long long)i * o.ld + k;
-    if (o.f32) {
-      const f32x4 a = *reinterpret_cast<const f32x4*>(reinterpret_cast<const float*>(o.base) + idx);
-      const f32x4 b = *reinterpret_cast<const f32x4*>(reinterpret_cast<const float*>(o.base) + idx + 4);
-      v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3]; v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
-    } else {
-      return *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(o.base) + idx);
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      v[e] = (i < o.rows && k + e < o.kmax) ? ld_elem(o, (long long)i * o.ld + k + e) : 0.f;
-  }
-  if (o.scale && i < o.rows) {
-    const float s = o.scale[i];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] *= s;
-  }
-  uint4 u;
-  u.x = bfbits(v[0]) | (bfbits(v[1]) << 16);
-  u.y = bfbits(v[2]) | (bfbits(v[3]) << 16);
-  u.z = bfbits(v[4]) | (bfbits(v[5]) << 16);
-  u.w = bfbits(v[6]) | (bfbits(v[7]) << 16);
-  return u;
-}
-
-// 8 consecutive i at reduction index k (TRANS), as floats
-__device__ __forceinline__ void load_col8(const Opnd& o, int i, int k, float v[8]) {
-  const bool kok = k < o.kmax;
-  if (kok && i + 8 <= o.rows && i + 8 <= (o.tcol >= 0 ? o.tcol : o.rows)) {
-    const long long idx = (long long)k * o.ld + i;
-    if (o.f32) {
-      const f32x4 a = *reinterpret_cast<const f32x4*>(reinterpret_cast<const float*>(o.base) + idx);
-      const f32x4 b = *reinterpret_cast<const f32x4*>(reinterpret_cast<const float*>(o.base) + idx + 4);
-      v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3]; v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
-    } else {
-      const uint4 u = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(o.base) + idx);
-      v[0] = __uint_as_float(u.x << 16); v[1] = __uint_as_float(u.x & 0xffff0000u);
-      v[2] = __uint_as_float(u.y << 16); v[3] = __uint_as_float(u.y & 0xffff0000u);
-      v[4] = __uint_as_float(u.z << 16); v[5] = __uint_as_float(u.z & 0xffff0000u);
-      v[6] = __uint_as_float(u.w << 16); v[7] = __uint_as_float(u.w & 0xffff0000u);
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int ii = i + e;
-      float x = 0.f;
-      if (kok) {
-        if (ii == o.tcol) x = (float)(o.n0 + k / o.mp) * o.dt;
-        else if (ii == o.onescol) x = 1.f;
-        else if (ii < o.rows && (o.tcol < 0 || ii < o.tcol)) x = ld_elem(o, (long long)k * o.ld + ii);
-      }
-      v[e] = x;
-    }
-  }
-  if (o.scale && kok) {
-    const float s = o.scale[k];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] *= s;
-  }
-}
 
 // ------------------------------------------------------------- epilogues
 enum { EPI_STORE = 0,      // out32[i][j] = acc + bias[j]
-       EPI_TANH_IN = 1,    // h0 = tanh(acc + bias[j] + t(i) w_t[j]): h32, hb
-       EPI_TANH_RES = 2,   // a = tanh(acc + bias[j]), h += a: h32 (in place), hb, ab
-       EPI_BWD_FIRST = 3,  // delta = acc, g = delta (1 - a^2): d32, gb
-       EPI_BWD_RES = 4,    // delta += acc, g = delta (1 - a^2): d32 (in place), gb
-       EPI_ACC = 5 };      // weight-gradient partials: part[off(i, j)] += acc
+       EPI_TANH_IN = 1,    // h0 = tanh(acc + bias[j] + t(i) w_t[j]): h32, hb (+ hT)
+       EPI_TANH_RES = 2,   // a = tanh(acc + bias[j]), h += a: h32 (in place), hb (+ ab, hT)
+       EPI_BWD_FIRST = 3,  // delta = acc, g = delta (1 - a^2): d32, gb, gT
+       EPI_BWD_RES = 4,    // delta += acc, g = delta (1 - a^2): d32 (in place), gb, gT
+       EPI_ACC = 5 };      // weight-gradient partials: part[base + i*wcols + j] += acc, bias from A's rows
 
 struct Epi {
   int rows, cols;          // valid output extent (i < rows, j < cols)
   const float* bias;       // [cols]
   const float* wt;         // [cols] time-column weights (EPI_TANH_IN)
-  int n0, mp;
+  int n0, mp;              // row i of a chunk is (step n0 + i / mp, path i % mp)
   float dt;
-  float* h32; long long ldh;      // fp32 residual stream / delta
-  uint16_t* ob; long long ldb;    // bf16 output (hb or gb)
-  uint16_t* ab; long long lda;    // bf16 activation out (EPI_TANH_RES) or in (EPI_BWD_*)
+  float* h32; long long ldh;      // fp32 residual stream / delta [i][j]
+  uint16_t* ob; long long ldb;    // bf16 output [i][j] (hb or gb)
+  uint16_t* ab; long long lda;    // bf16 activation, out (EPI_TANH_RES, optional) or in (EPI_BWD_*)
+  uint16_t* ot; long long ldt;    // optional bf16 transposed copy [j][i] of the ob values
   float* out32; long long ldo;    // EPI_STORE
-  float* part; long long base; int wcols;  // EPI_ACC: flat W[rows][wcols] then b[rows]; column wcols is the bias
+  float* part; long long base; int wcols;  // EPI_ACC: W[rows][wcols] at base, then the bias b[rows]
 };
 
+__device__ __forceinline__ uint2 pack4(float a, float b, float c, float d) {
+  return uint2{bfbits(a) | (bfbits(b) << 16), bfbits(c) | (bfbits(d) << 16)};
+}
+
+// Four consecutive columns j..j+3 of row i (j a multiple of 4).  With a
+// transposed copy requested, its bf16 values go to the wave's LDS block
+// `tl` at [jl + e][il] (row stride tld) and are written out afterwards.
 template <int EPI>
-__device__ __forceinline__ void epilogue(const Epi& E, int i, int j, float acc) {
-  if (i >= E.rows || j >= E.cols) return;
-  if constexpr (EPI == EPI_STORE) {
-    E.out32[(long long)i * E.ldo + j] = acc + (E.bias ? E.bias[j] : 0.f);
-  } else if constexpr (EPI == EPI_TANH_IN) {
-    const float t = rbf((float)(E.n0 + i / E.mp) * E.dt);
-    const float a = fast_tanh(acc + E.bias[j] + t * E.wt[j]);
-    E.h32[(long long)i * E.ldh + j] = a;
-    E.ob[(long long)i * E.ldb + j] = (uint16_t)bfbits(a);
-  } else if constexpr (EPI == EPI_TANH_RES) {
-    const float a = fast_tanh(acc + E.bias[j]);
-    const long long p = (long long)i * E.ldh + j;
-    const float h = E.h32[p] + a;
-    E.h32[p] = h;
-    E.ob[(long long)i * E.ldb + j] = (uint16_t)bfbits(h);
-    E.ab[(long long)i * E.lda + j] = (uint16_t)bfbits(a);
-  } else if constexpr (EPI == EPI_BWD_FIRST || EPI == EPI_BWD_RES) {
-    const long long p = (long long)i * E.ldh + j;
-    const float dlt = (EPI == EPI_BWD_RES) ? E.h32[p] + acc : acc;
-    E.h32[p] = dlt;
-    const float a = bf2f(E.ab[(long long)i * E.lda + j]);
-    E.ob[(long long)i * E.ldb + j] = (uint16_t)bfbits(dlt * (1.f - a * a));
-  } else {  // EPI_ACC
-    const long long off = (j < E.wcols) ? E.base + (long long)i * E.wcols + j
-                                        : E.base + (long long)E.rows * E.wcols + i;
-    E.part[off] += acc;
+__device__ __forceinline__ void epilogue4(const Epi& E, int i, int j, f32x4 acc, uint16_t* tl, int il, int jl,
+                                          int tld) {
+  if (i >= E.rows) return;
+  const bool full = j + 4 <= E.cols;
+  if constexpr (EPI == EPI_ACC) {
+    float* p = E.part + E.base + (long long)i * E.wcols + j;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (j + e < E.cols) p[e] += acc[e];
+    return;
+  } else {
+    float v[4];
+    if constexpr (EPI == EPI_STORE) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = acc[e] + ((E.bias && j + e < E.cols) ? E.bias[j + e] : 0.f);
+      float* o = E.out32 + (long long)i * E.ldo + j;
+      if (full) {
+        *reinterpret_cast<f32x4*>(o) = f32x4{v[0], v[1], v[2], v[3]};
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (j + e < E.cols) o[e] = v[e];
+      }
+      return;
+    } else {
+      const long long ph = (long long)i * E.ldh + j;
+      float hv[4] = {0.f, 0.f, 0.f, 0.f}, av[4] = {0.f, 0.f, 0.f, 0.f};
+      if (full) {
+        if constexpr (EPI == EPI_TANH_RES || EPI == EPI_BWD_RES) {
+          const f32x4 h = *reinterpret_cast<const f32x4*>(E.h32 + ph);
+          hv[0] = h[0]; hv[1] = h[1]; hv[2] = h[2]; hv[3] = h[3];
+        }
+        if constexpr (EPI == EPI_BWD_FIRST || EPI == EPI_BWD_RES) {
+          const uint2 u = *reinterpret_cast<const uint2*>(E.ab + (long long)i * E.lda + j);
+          av[0] = __uint_as_float(u.x << 16); av[1] = __uint_as_float(u.x & 0xffff0000u);
+          av[2] = __uint_as_float(u.y << 16); av[3] = __uint_as_float(u.y & 0xffff0000u);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (j + e >= E.cols) continue;
+          if constexpr (EPI == EPI_TANH_RES || EPI == EPI_BWD_RES) hv[e] = E.h32[ph + e];
+          if constexpr (EPI == EPI_BWD_FIRST || EPI == EPI_BWD_RES) av[e] = bf2f(E.ab[(long long)i * E.lda + j + e]);
+        }
+      }
+      float hout[4], gout[4], aout[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int jj = full ? j + e : min(j + e, E.cols - 1);  // clamp: values past cols are never stored
+        if constexpr (EPI == EPI_TANH_IN) {
+          const float t = rbf((float)(E.n0 + i / E.mp) * E.dt);
+          const float a = fast_tanh(acc[e] + E.bias[jj] + t * E.wt[jj]);
+          hout[e] = a; gout[e] = a;
+        } else if constexpr (EPI == EPI_TANH_RES) {
+          const float a = fast_tanh(acc[e] + E.bias[jj]);
+          aout[e] = a;
+          hout[e] = hv[e] + a; gout[e] = hout[e];
+        } else {  // EPI_BWD_FIRST / EPI_BWD_RES
+          const float dl = (EPI == EPI_BWD_RES) ? hv[e] + acc[e] : acc[e];
+          hout[e] = dl;
+          gout[e] = dl * (1.f - av[e] * av[e]);
+        }
+      }
+      uint16_t* ob = E.ob + (long long)i * E.ldb + j;
+      if (full) {
+        *reinterpret_cast<f32x4*>(E.h32 + ph) = f32x4{hout[0], hout[1], hout[2], hout[3]};
+        *reinterpret_cast<uint2*>(ob) = pack4(gout[0], gout[1], gout[2], gout[3]);
+        if constexpr (EPI == EPI_TANH_RES)
+          if (E.ab) *reinterpret_cast<uint2*>(E.ab + (long long)i * E.lda + j) = pack4(aout[0], aout[1], aout[2], aout[3]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (j + e >= E.cols) continue;
+          E.h32[ph + e] = hout[e];
+          ob[e] = (uint16_t)bfbits(gout[e]);
+          if constexpr (EPI == EPI_TANH_RES)
+            if (E.ab) E.ab[(long long)i * E.lda + j + e] = (uint16_t)bfbits(aout[e]);
+        }
+      }
+      if (tl) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tl[(jl + e) * tld + il] = (uint16_t)bfbits(gout[e]);
+      }
+    }
   }
 }
 
 // ------------------------------------------------------------------ GEMM
-// C[i][j] = sum_k A(i, k) B(j, k), i < M, j < N, k in [k0, k1); 128x128 tile per
-// workgroup, 4 waves of 64x64 (4 x 4 MFMA tiles), K staged 32 at a time in
-// double-buffered LDS ([row][k], 80-byte rows).  blockIdx.z selects a K
-// split: split s covers [s*kchunk, (s+1)*kchunk) and adds into part + s*pstride.
-template <int EPI>
-__global__ __launch_bounds__(256) void k_gemm(Opnd A, Opnd B, Epi E, int Kdim, long long kchunk,
-                                              long long pstride) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * LDK];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wr = wv >> 1, wc = wv & 1;
-  const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
-  const long long ks = (long long)blockIdx.z * kchunk;
-  const long long ke = min((long long)Kdim, ks + kchunk);
+// Workgroup tile (32 TM) x (32 TN): 4 waves in 2 x 2, each (16 TM) x (16 TN)
+// as TM x TN MFMA 16x16x32 tiles.  The reduction is staged BK at a time in
+// two LDS buffers (80-byte rows: conflict-free 16-byte fragment reads): the
+// global loads of slab s + 1 are in flight while slab s is multiplied.  The MFMA takes the B fragment as its
+// first operand, so every lane ends up holding four consecutive output
+// columns of one row (vector epilogue stores).  Tiles are ordered so that
+// the j-tiles of one (split, i-tile) are dispatched to the same XCD and
+// share the A slab in its L2.
+template <int EPI, int TM, int TN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RN_WPE))) void k_gemm(Gm G, Epi E) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int UA = BM / 64, UB = BN / 64;  // 16-byte staging units per thread
+  // LDS: the double-buffered A and B slabs; after the main loop the same
+  // memory holds each wave's (16 TN) x (16 TM) bf16 block of a transposed
+  // copy (272-byte rows for TM = 8: 16-byte aligned, conflict-free)
+  constexpr int TLD = 16 * TM + 8;
+  constexpr int STAGE = 2 * (BM + BN) * LDK, TBLK = 16 * TN * TLD;
+  __shared__ __attribute__((aligned(16))) uint16_t smem[STAGE > 4 * TBLK ? STAGE : 4 * TBLK];
+  uint16_t (*sA)[BM * LDK] = reinterpret_cast<uint16_t (*)[BM * LDK]>(smem);
+  uint16_t (*sB)[BN * LDK] = reinterpret_cast<uint16_t (*)[BN * LDK]>(smem + 2 * BM * LDK);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  const int wi = wv >> 1, wj = wv & 1;
+
+  const int per_split = G.ti * G.tj;
+  const int nt = per_split * G.ts;
+  int T = blockIdx.x;
+  if ((nt & 7) == 0) T = (T & 7) * (nt >> 3) + (T >> 3);
+  const int sp = T / per_split;
+  const int rem = T - sp * per_split;
+  const int it = rem / G.tj, jt = rem - it * G.tj;
+  const int i0 = it * BM, j0 = jt * BN;
+  const long long ks = (long long)sp * G.kchunk;
+  const long long ke = min((long long)G.K, ks + G.kchunk);
+  const int nk = ke > ks ? (int)((ke - ks + BK - 1) / BK) : 0;  // slabs of this split
   Epi Ez = E;
-  if constexpr (EPI == EPI_ACC) Ez.part = E.part + (long long)blockIdx.z * pstride;
+  if constexpr (EPI == EPI_ACC) Ez.part = E.part + (long long)sp * G.pstride;
 
-  f32x4 acc[4][4];
+  // Staging unit u = tid + 256 q: row u / 4, k offset 8 (u % 4).  Loads are
+  // unconditional so that the wait before each LDS write counts exactly the
+  // loads it needs: rows past the operand clamp to its last row (they only
+  // feed outputs that are never stored) and slabs past the split's end
+  // re-read its first slab.  Only the split's last slab can hold k >= ke;
+  // its runs are masked at the LDS write.  A run of 8 starting below
+  // round_up(K, 32) lies inside the operand's allocation: every row stride
+  // is a multiple of 8 and every buffer carries 64 bytes of slack.
+  int aoff[UA], boff[UB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int q = 0; q < UA; ++q) {
+    const int u = tid + 256 * q, r = min(i0 + (u >> 2), G.arows - 1);
+    aoff[q] = r * (int)G.lda + (u & 3) * 8;
+  }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  // staging: 512 units of 8 elements per operand tile, two per thread
-  auto stage = [&](int buf, long long kt) {
+  for (int q = 0; q < UB; ++q) {
+    const int u = tid + 256 * q, r = min(j0 + (u >> 2), G.brows - 1);
+    boff[q] = r * (int)G.ldb + (u & 3) * 8;
+  }
+  const int kofs = (tid & 3) * 8;  // this thread's k offset inside a slab (same for every unit)
+  auto load = [&](int slab, uint4 (&ra)[UA], uint4 (&rb)[UB]) {
+    const long long kt = (slab < nk) ? ks + (long long)slab * BK : ks;
+    const uint16_t* pa = G.a + kt;
+    const uint16_t* pb = G.b + kt;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int unit = tid + 256 * u;
-      // A
-      if (A.mode == ROWS) {
-        const int r = unit >> 2, kk = (unit & 3) * 8;
-        const uint4 v = load_row8(A, i0 + r, (int)(kt + kk));
-        *reinterpret_cast<uint4*>(&sA[buf][r * LDK + kk]) = v;
-      } else {
-        const int kk = unit >> 4, r = (unit & 15) * 8;
-        float v[8];
-        load_col8(A, i0 + r, (int)(kt + kk), v);
+    for (int q = 0; q < UA; ++q) ra[q] = *reinterpret_cast<const uint4*>(pa + aoff[q]);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) sA[buf][(r + e) * LDK + kk] = (uint16_t)bfbits(v[e]);
+    for (int q = 0; q < UB; ++q) rb[q] = *reinterpret_cast<const uint4*>(pb + boff[q]);
+  };
+  auto store = [&](int slab, int buf, const uint4 (&ra)[UA], const uint4 (&rb)[UB]) {
+    const long long kt = ks + (long long)slab * BK;
+    if (kt + BK <= ke) {  // uniform: a full slab
+#pragma unroll
+      for (int q = 0; q < UA; ++q) {
+        const int u = tid + 256 * q;
+        *reinterpret_cast<uint4*>(&sA[buf][(u >> 2) * LDK + (u & 3) * 8]) = ra[q];
       }
-      // B
-      if (B.mode == ROWS) {
-        const int r = unit >> 2, kk = (unit & 3) * 8;
-        const uint4 v = load_row8(B, j0 + r, (int)(kt + kk));
-        *reinterpret_cast<uint4*>(&sB[buf][r * LDK + kk]) = v;
-      } else {
-        const int kk = unit >> 4, r = (unit & 15) * 8;
-        float v[8];
-        load_col8(B, j0 + r, (int)(kt + kk), v);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) sB[buf][(r + e) * LDK + kk] = (uint16_t)bfbits(v[e]);
+      for (int q = 0; q < UB; ++q) {
+        const int u = tid + 256 * q;
+        *reinterpret_cast<uint4*>(&sB[buf][(u >> 2) * LDK + (u & 3) * 8]) = rb[q];
+      }
+    } else {  // the split's last slab (or a padding slab): keep k < ke only
+      const long long nv = ke - (kt + kofs);  // valid elements of this thread's runs (may be <= 0)
+      uint32_t m[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) m[e] = (2 * e + 1 < nv) ? 0xffffffffu : (2 * e < nv ? 0xffffu : 0u);
+#pragma unroll
+      for (int q = 0; q < UA; ++q) {
+        const int u = tid + 256 * q;
+        *reinterpret_cast<uint4*>(&sA[buf][(u >> 2) * LDK + (u & 3) * 8]) =
+            uint4{ra[q].x & m[0], ra[q].y & m[1], ra[q].z & m[2], ra[q].w & m[3]};
+      }
+#pragma unroll
+      for (int q = 0; q < UB; ++q) {
+        const int u = tid + 256 * q;
+        *reinterpret_cast<uint4*>(&sB[buf][(u >> 2) * LDK + (u & 3) * 8]) =
+            uint4{rb[q].x & m[0], rb[q].y & m[1], rb[q].z & m[2], rb[q].w & m[3]};
       }
     }
   };
 
-  int buf = 0;
-  if (ks < ke) stage(0, ks);
-  __syncthreads();
-  for (long long kt = ks; kt < ke; kt += BK) {
-    if (kt + BK < ke) stage(buf ^ 1, kt + BK);  // next tile into the other buffer
-    bf16x8 fa[4], fb[4];
+  f32x4 acc[TM][TN];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const uint4 u = *reinterpret_cast<const uint4*>(&sA[buf][(wr * 64 + 16 * a + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // EPI_ACC, first j-tile, left waves: row sums of A (the bias gradient)
+  const bool rowsum = (EPI == EPI_ACC) && jt == 0 && wj == 0;
+  float bsum[TM];
+#pragma unroll
+  for (int a = 0; a < TM; ++a) bsum[a] = 0.f;
+
+  auto compute = [&](int buf) {
+    bf16x8 fa[TM], fb[TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const uint4 u = *reinterpret_cast<const uint4*>(&sA[buf][(wi * 16 * TM + 16 * a + (lane & 15)) * LDK + 8 * (lane >> 4)]);
       fa[a] = __builtin_bit_cast(bf16x8, u32x4{u.x, u.y, u.z, u.w});
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const uint4 u = *reinterpret_cast<const uint4*>(&sB[buf][(wc * 64 + 16 * b + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+    for (int b = 0; b < TN; ++b) {
+      const uint4 u = *reinterpret_cast<const uint4*>(&sB[buf][(wj * 16 * TN + 16 * b + (lane & 15)) * LDK + 8 * (lane >> 4)]);
       fb[b] = __builtin_bit_cast(bf16x8, u32x4{u.x, u.y, u.z, u.w});
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < TM; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
-    __syncthreads();
-    buf ^= 1;
-  }
-  // D layout: lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 tile
+      for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[b], fa[a], acc[a][b], 0, 0, 0);
+    if constexpr (EPI == EPI_ACC) {
+      if (rowsum) {  // wave-uniform
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wr * 64 + 16 * a + 4 * (lane >> 4) + r;
-        const int j = j0 + wc * 64 + 16 * b + (lane & 15);
-        epilogue<EPI>(Ez, i, j, acc[a][b][r]);
+        for (int a = 0; a < TM; ++a) {
+          const u32x4 u = __builtin_bit_cast(u32x4, fa[a]);
+          bsum[a] += (__uint_as_float(u.x << 16) + __uint_as_float(u.x & 0xffff0000u)) +
+                     (__uint_as_float(u.y << 16) + __uint_as_float(u.y & 0xffff0000u)) +
+                     (__uint_as_float(u.z << 16) + __uint_as_float(u.z & 0xffff0000u)) +
+                     (__uint_as_float(u.w << 16) + __uint_as_float(u.w & 0xffff0000u));
+        }
       }
+    }
+  };
+
+#if RN_PF == 2
+  // two register sets: slab s + 2 is loaded while slab s is multiplied and
+  // slab s + 1 is written to LDS; an odd slab count gets a zero padding slab
+  uint4 ra0[UA], rb0[UB], ra1[UA], rb1[UB];
+  const int nk2 = (nk + 1) & ~1;
+  if (nk > 0) {
+    load(0, ra0, rb0);
+    load(1, ra1, rb1);
+    store(0, 0, ra0, rb0);
+  }
+  __syncthreads();
+  for (int s = 0; s < nk2; s += 2) {
+    load(s + 2, ra0, rb0);
+    compute(0);
+    store(s + 1, 1, ra1, rb1);
+    __syncthreads();
+    load(s + 3, ra1, rb1);
+    compute(1);
+    if (s + 2 < nk2) store(s + 2, 0, ra0, rb0);
+    __syncthreads();
+  }
+#else
+  uint4 ra[UA], rb[UB];
+  if (nk > 0) {
+    load(0, ra, rb);
+    store(0, 0, ra, rb);
+  }
+  __syncthreads();
+  for (int s = 0; s < nk; ++s) {
+    load(s + 1, ra, rb);  // past the last slab: a harmless re-read
+    compute(s & 1);
+    if (s + 1 < nk) store(s + 1, (s + 1) & 1, ra, rb);
+    __syncthreads();
+  }
+#endif
+  // lane: row i = 16a + lane % 16, columns j = 16b + 4 (lane / 16) + 0..3
+  const int i0w = i0 + wi * 16 * TM, j0w = j0 + wj * 16 * TN;
+  uint16_t* tl = nullptr;
+  if constexpr (EPI != EPI_ACC && EPI != EPI_STORE)
+    if (E.ot) tl = smem + wv * TBLK;  // LDS is free: the loop ended with a barrier
+#pragma unroll
+  for (int a = 0; a < TM; ++a) {
+    const int il = 16 * a + (lane & 15);
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int jl = 16 * b + 4 * (lane >> 4);
+      epilogue4<EPI>(Ez, i0w + il, j0w + jl, acc[a][b], tl, il, jl, TLD);
+    }
+  }
+  if constexpr (EPI != EPI_ACC && EPI != EPI_STORE) {
+    if (E.ot) {  // uniform: the wave's block, transposed rows of 16 TM bf16 written as 16-byte runs
+      __syncthreads();
+      constexpr int CPR = 2 * TM, RPI = 64 / CPR;  // 16-byte chunks per row, rows per pass
+      const int c = lane % CPR;
+#pragma unroll
+      for (int pass = 0; pass < 16 * TN / RPI; ++pass) {
+        const int jl = pass * RPI + lane / CPR;
+        const int j = j0w + jl, i = i0w + 8 * c;
+        const uint4 v = *reinterpret_cast<const uint4*>(tl + jl * TLD + 8 * c);
+        if (j < E.cols) {
+          uint16_t* o = E.ot + (long long)j * E.ldt + i;
+          if (i + 8 <= E.rows) {
+            *reinterpret_cast<uint4*>(o) = v;
+          } else {
+            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              if (i + e < E.rows) o[e] = (uint16_t)(w4[e >> 1] >> (16 * (e & 1)));
+          }
+        }
+      }
+    }
+  }
+  if constexpr (EPI == EPI_ACC) {
+    if (rowsum) {
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        float v = bsum[a];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        const int i = i0 + wi * 16 * TM + 16 * a + (lane & 15);
+        if (lane < 16 && i < Ez.rows) Ez.part[Ez.base + (long long)Ez.rows * Ez.wcols + i] += v;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- convert
+// v = src[r][c] * scale[r] (scale optional) for r < rows, c < cols:
+// rowm[r][c] = bf16(v) (if rowm) and tr[c][r] = bf16(v) (if tr); with
+// trow >= 0 also tr[trow][r] = bf16(t of row r).  64 x 64 tiles: each thread
+// reads float4 runs of src rows and writes 4-element bf16 runs of rowm; the
+// transpose goes through LDS and leaves as 4-element runs of tr rows.  The
+// src row stride is a multiple of 4; columns in [cols, stride) of rowm may
+// receive whatever src holds there (readers stop at cols).
+__global__ __launch_bounds__(256) void k_convert(const float* __restrict__ src, long long lds, int rows, int cols,
+                                                 const float* __restrict__ scale, uint16_t* __restrict__ rowm,
+                                                 long long ldr, uint16_t* __restrict__ tr, long long ldt, int trow,
+                                                 int n0, int mp, float dt) {
+  __shared__ float tile[64][65];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int t = threadIdx.x;
+  {
+    const int cg = t & 15, rg = t >> 4;
+    const int c = c0 + 4 * cg;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rl = rg + 16 * q, r = r0 + rl;
+      f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (r < rows && c < cols) {
+        v = *reinterpret_cast<const f32x4*>(src + (long long)r * lds + c);
+        if (scale) v = v * scale[r];
+        if (rowm) *reinterpret_cast<uint2*>(rowm + (long long)r * ldr + c) = pack4(v[0], v[1], v[2], v[3]);
+      }
+      tile[rl][4 * cg] = v[0]; tile[rl][4 * cg + 1] = v[1]; tile[rl][4 * cg + 2] = v[2]; tile[rl][4 * cg + 3] = v[3];
+    }
+  }
+  if (!tr) return;
+  __syncthreads();
+  {
+    const int rg = t & 15, cg = t >> 4;
+    const int r = r0 + 4 * rg;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int cl = cg + 16 * q, c = c0 + cl;
+      if (c >= cols || r >= rows) continue;
+      const float a0 = tile[4 * rg][cl], a1 = tile[4 * rg + 1][cl], a2 = tile[4 * rg + 2][cl], a3 = tile[4 * rg + 3][cl];
+      uint16_t* o = tr + (long long)c * ldt + r;
+      if (r + 4 <= rows) {
+        *reinterpret_cast<uint2*>(o) = pack4(a0, a1, a2, a3);
+      } else {
+        const float av[4] = {a0, a1, a2, a3};
+        for (int e = 0; e < 4 && r + e < rows; ++e) o[e] = (uint16_t)bfbits(av[e]);
+      }
+    }
+  }
+  if (trow >= 0 && blockIdx.x == 0 && t < 64) {
+    const int r = r0 + t;
+    if (r < rows) tr[(long long)trow * ldt + r] = (uint16_t)bfbits((float)(n0 + r / mp) * dt);
+  }
 }
 
 // ------------------------------------------------------ row epilogue
@@ -372,14 +569,20 @@ static unsigned grid1(long long n, long long cap = 65536) {
   return (unsigned)b;
 }
 
-template <int EPI>
-static hipError_t gemm(const Opnd& A, const Opnd& B, const Epi& E, int Mrows, int Ncols, int Kdim, int splits,
-                       long long pstride, hipStream_t s) {
-  long long kchunk = Kdim;
-  if (splits > 1) kchunk = ((long long)Kdim + splits - 1) / splits, kchunk = (kchunk + BK - 1) / BK * BK;
-  const int z = (int)(((long long)Kdim + kchunk - 1) / kchunk);
-  dim3 grid((unsigned)((Ncols + BN - 1) / BN), (unsigned)((Mrows + BM - 1) / BM), (unsigned)z);
-  k_gemm<EPI><<<grid, 256, 0, s>>>(A, B, E, Kdim, kchunk, pstride);
+// Launch with TM x TN wave tiles; `splits` > 1 splits the reduction (EPI_ACC only).
+template <int EPI, int TM, int TN>
+static hipError_t gemm(Gm G, const Epi& E, int Mrows, int Ncols, int splits, hipStream_t s) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  G.kchunk = G.K;
+  if (splits > 1) G.kchunk = (((long long)G.K + splits - 1) / splits + BK - 1) / BK * BK;
+  if (G.kchunk < BK) G.kchunk = BK;
+  G.ts = (int)(((long long)G.K + G.kchunk - 1) / G.kchunk);
+  if (G.ts < 1) G.ts = 1;
+  G.ti = (Mrows + BM - 1) / BM;
+  G.tj = (Ncols + BN - 1) / BN;
+  const long long nt = (long long)G.ti * G.tj * G.ts;
+  if (nt <= 0) return hipSuccess;
+  k_gemm<EPI, TM, TN><<<(unsigned)nt, 256, 0, s>>>(G, E);
   return hipGetLastError();
 }
 
@@ -388,11 +591,11 @@ static hipError_t gemm(const Opnd& A, const Opnd& B, const Epi& E, int Mrows, in
 // ===================================================== host sequencing
 using namespace rn;
 
-static Opnd opnd(const void* base, long long ld, int rows, int kmax, int mode, int f32) {
-  Opnd o;
-  o.base = base; o.ld = ld; o.rows = rows; o.kmax = kmax; o.mode = mode; o.f32 = f32;
-  o.scale = nullptr; o.tcol = -1; o.onescol = -1; o.n0 = 0; o.mp = 1; o.dt = 0.f;
-  return o;
+static Gm gm(const uint16_t* a, long long lda, int arows, const uint16_t* b, long long ldb, int brows, int K) {
+  Gm G = {};
+  G.a = a; G.lda = lda; G.arows = arows;
+  G.b = b; G.ldb = ldb; G.brows = brows; G.K = K;
+  return G;
 }
 static Epi epi0(int rows, int cols) {
   Epi e = {};
@@ -407,6 +610,7 @@ ResnetLayout resnet_layout(const Geo& g) {
   L.pk_elems = w * dq + B * w * w + d * w + B * w * w + w * dq;
   L.pf_elems = 2 * w + B * w + d;
   L.rows = (long long)g.rn_chunk * g.M;
+  L.ldt = (L.rows + 7) / 8 * 8;
   return L;
 }
 
@@ -431,38 +635,53 @@ hipError_t resnet_pack(const Geo& g, const float* params, uint16_t* pk, float* p
   return hipGetLastError();
 }
 
-// forward of the rows of steps [n0, n0 + ns): activations into the chunk buffers
+static hipError_t convert(const float* src, long long lds, int rows, int cols, const float* scale, uint16_t* rowm,
+                          long long ldr, uint16_t* tr, long long ldt, int trow, int n0, int mp, float dt,
+                          hipStream_t s) {
+  dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
+  k_convert<<<grid, 256, 0, s>>>(src, lds, rows, cols, scale, rowm, ldr, tr, ldt, trow, n0, mp, dt);
+  return hipGetLastError();
+}
+
+// Forward of the rows of steps [n0, n0 + ns).  With `recompute` (reverse
+// sweep) it also keeps a_1..a_B and the transposed bf16 copies h_k^T and
+// [x; t]^T that the weight gradients read; with `with_output` it forms Z.
 static hipError_t chunk_forward(const Geo& g, const ResnetLayout& L, const ResnetBufs& R, int n0, int ns,
-                                const float* X, bool with_output, hipStream_t s) {
+                                const float* X, bool with_output, bool recompute, hipStream_t s) {
   const int rows = ns * g.M, w = g.w, d = g.d, B = g.L;
   const float* wt = R.pf;
   const float* bin = R.pf + w;
   hipError_t e;
+  // bf16 x (and, for the reverse sweep, [x; t]^T)
+  if ((e = convert(X + (size_t)n0 * g.M * g.dp, g.dp, rows, d, nullptr, R.xb, L.dq, recompute ? R.xt : nullptr,
+                   L.ldt, d, n0, g.M, g.dt, s)) != hipSuccess)
+    return e;
   {  // h0 = tanh(W_in [x; t] + b_in)
-    Opnd A = opnd(X + (size_t)n0 * g.M * g.dp, g.dp, rows, d, ROWS, 1);
-    Opnd Bw = opnd(pk_win(g, L, R.pk), L.dq, w, d, ROWS, 0);
+    Gm G = gm(R.xb, L.dq, rows, pk_win(g, L, R.pk), L.dq, w, d);
     Epi E = epi0(rows, w);
     E.bias = bin; E.wt = wt; E.n0 = n0; E.mp = g.M; E.dt = g.dt;
     E.h32 = R.h32; E.ldh = w; E.ob = R.hb; E.ldb = w;
-    if ((e = gemm<EPI_TANH_IN>(A, Bw, E, rows, w, d, 1, 0, s)) != hipSuccess) return e;
+    if (recompute) E.ot = R.ht, E.ldt = L.ldt;
+    if ((e = gemm<EPI_TANH_IN, RN_TM, RN_TN>(G, E, rows, w, 1, s)) != hipSuccess) return e;
   }
   for (int k = 1; k <= B; ++k) {  // a_k = tanh(W_k h_{k-1} + b_k), h_k = h_{k-1} + a_k
-    Opnd A = opnd(R.hb + (size_t)(k - 1) * L.rows * w, w, rows, w, ROWS, 0);
-    Opnd Bw = opnd(pk_wk(g, L, R.pk, k), w, w, w, ROWS, 0);
+    Gm G = gm(R.hb + (size_t)(k - 1) * L.rows * w, w, rows, pk_wk(g, L, R.pk, k), w, w, w);
     Epi E = epi0(rows, w);
     E.bias = R.pf + 2 * w + (size_t)(k - 1) * w;
     E.h32 = R.h32; E.ldh = w;
     E.ob = R.hb + (size_t)k * L.rows * w; E.ldb = w;
-    E.ab = R.ab + (size_t)(k - 1) * L.rows * w; E.lda = w;
-    if ((e = gemm<EPI_TANH_RES>(A, Bw, E, rows, w, w, 1, 0, s)) != hipSuccess) return e;
+    if (recompute) {
+      E.ab = R.ab + (size_t)(k - 1) * L.rows * w; E.lda = w;
+      E.ot = R.ht + (size_t)k * w * L.ldt; E.ldt = L.ldt;
+    }
+    if ((e = gemm<EPI_TANH_RES, RN_TM, RN_TN>(G, E, rows, w, 1, s)) != hipSuccess) return e;
   }
   if (with_output) {  // Z = W_o h_B + b_o
-    Opnd A = opnd(R.hb + (size_t)B * L.rows * w, w, rows, w, ROWS, 0);
-    Opnd Bw = opnd(pk_wo(g, L, R.pk), w, d, w, ROWS, 0);
+    Gm G = gm(R.hb + (size_t)B * L.rows * w, w, rows, pk_wo(g, L, R.pk), w, d, w);
     Epi E = epi0(rows, d);
     E.bias = R.pf + 2 * w + (size_t)B * w;
     E.out32 = R.z; E.ldo = L.dq;
-    if ((e = gemm<EPI_STORE>(A, Bw, E, rows, d, w, 1, 0, s)) != hipSuccess) return e;
+    if ((e = gemm<EPI_STORE, RN_TM, RN_TN>(G, E, rows, d, 1, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -472,7 +691,7 @@ hipError_t resnet_forward(const Geo& g, const ResnetBufs& R, const float* X, flo
   hipError_t e;
   for (int n0 = 0; n0 < g.N; n0 += g.rn_chunk) {
     const int ns = min(g.rn_chunk, g.N - n0);
-    if ((e = chunk_forward(g, L, R, n0, ns, X, true, s)) != hipSuccess) return e;
+    if ((e = chunk_forward(g, L, R, n0, ns, X, true, false, s)) != hipSuccess) return e;
     const int rows = ns * g.M;
     k_row_epilogue<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(g, n0, rows, R.z, L.dq, X, V, C);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -480,9 +699,11 @@ hipError_t resnet_forward(const Geo& g, const ResnetBufs& R, const float* X, flo
   return hipSuccess;
 }
 
-// Reverse sweep of every chunk (recomputing its activations); weight
-// gradients accumulate over chunks into `splits` partial buffers of the flat
-// parameter layout (each owned by one K split of each GEMM: deterministic).
+// Reverse sweep of every chunk (recomputing its activations).  Weight
+// gradients are products over the chunk's rows of transposed bf16 copies
+// (g_k^T, h_k^T, zeta^T, [x; t]^T) and accumulate over chunks into `splits`
+// partial buffers of the flat parameter layout, one per reduction split of
+// each GEMM (fixed order: deterministic).
 hipError_t resnet_backward(const Geo& g, const ResnetBufs& R, const float* X, const float* V, const float* LAM,
                            float* part, int splits, hipStream_t s) {
   const ResnetLayout L = resnet_layout(g);
@@ -495,56 +716,52 @@ hipError_t resnet_backward(const Geo& g, const ResnetBufs& R, const float* X, co
   for (int n0 = 0; n0 < g.N; n0 += g.rn_chunk) {
     const int ns = min(g.rn_chunk, g.N - n0);
     const int rows = ns * g.M;
-    if ((e = chunk_forward(g, L, R, n0, ns, X, false, s)) != hipSuccess) return e;
+    if ((e = chunk_forward(g, L, R, n0, ns, X, false, true, s)) != hipSuccess) return e;
     const float* Vc = V + (size_t)n0 * g.M * g.dp;
     const float* lam = LAM + (size_t)n0 * g.M;  // lambda_{n+1} of every row
-    uint16_t* gcur = R.gb;
-    uint16_t* gnext = R.gb + (size_t)L.rows * w;
+    // zeta = lambda v in bf16, row-major and transposed
+    if ((e = convert(Vc, g.dp, rows, d, lam, R.vb, L.dq, R.zt, L.ldt, -1, 0, 1, 0.f, s)) != hipSuccess) return e;
+    int cur = 0;
+    uint16_t* gb[2] = {R.gb, R.gb + (size_t)L.rows * w};
+    uint16_t* gt[2] = {R.gt, R.gt + (size_t)w * L.ldt};
     {  // delta_B = W_o^T zeta, zeta = lambda v;  g_B = delta_B (1 - a_B^2)
-      Opnd A = opnd(Vc, g.dp, rows, d, ROWS, 1);
-      A.scale = lam;
-      Opnd Bw = opnd(pk_wot(g, L, R.pk), L.dq, w, d, ROWS, 0);
+      Gm G = gm(R.vb, L.dq, rows, pk_wot(g, L, R.pk), L.dq, w, d);
       Epi E = epi0(rows, w);
-      E.h32 = R.d32; E.ldh = w; E.ob = gcur; E.ldb = w;
+      E.h32 = R.d32; E.ldh = w; E.ob = gb[cur]; E.ldb = w; E.ot = gt[cur]; E.ldt = L.ldt;
       E.ab = R.ab + (size_t)(B - 1) * L.rows * w; E.lda = w;
-      if ((e = gemm<EPI_BWD_FIRST>(A, Bw, E, rows, w, d, 1, 0, s)) != hipSuccess) return e;
+      if ((e = gemm<EPI_BWD_FIRST, RN_TM, RN_TN>(G, E, rows, w, 1, s)) != hipSuccess) return e;
     }
     {  // dW_o += zeta^T h_B, db_o += sum zeta
-      Opnd A = opnd(Vc, g.dp, d, rows, TRANS, 1);
-      A.scale = lam;
-      Opnd Bw = opnd(R.hb + (size_t)B * L.rows * w, w, w, rows, TRANS, 0);
-      Bw.onescol = w;
-      Epi E = epi0(d, w + 1);
+      Gm G = gm(R.zt, L.ldt, d, R.ht + (size_t)B * w * L.ldt, L.ldt, w, rows);
+      G.pstride = g.nparams;
+      Epi E = epi0(d, w);
       E.part = part; E.base = offo; E.wcols = w;
-      if ((e = gemm<EPI_ACC>(A, Bw, E, d, w + 1, rows, splits, g.nparams, s)) != hipSuccess) return e;
+      if ((e = gemm<EPI_ACC, RN_TM, RN_TN>(G, E, d, w, splits, s)) != hipSuccess) return e;
     }
     for (int k = B; k >= 1; --k) {
       {  // dW_k += g_k^T h_{k-1}, db_k += sum g_k
-        Opnd A = opnd(gcur, w, w, rows, TRANS, 0);
-        Opnd Bw = opnd(R.hb + (size_t)(k - 1) * L.rows * w, w, w, rows, TRANS, 0);
-        Bw.onescol = w;
-        Epi E = epi0(w, w + 1);
+        Gm G = gm(gt[cur], L.ldt, w, R.ht + (size_t)(k - 1) * w * L.ldt, L.ldt, w, rows);
+        G.pstride = g.nparams;
+        Epi E = epi0(w, w);
         E.part = part; E.base = offk + (long long)(k - 1) * ((long long)w * w + w); E.wcols = w;
-        if ((e = gemm<EPI_ACC>(A, Bw, E, w, w + 1, rows, splits, g.nparams, s)) != hipSuccess) return e;
+        if ((e = gemm<EPI_ACC, RN_TM, RN_TN>(G, E, w, w, splits, s)) != hipSuccess) return e;
       }
       {  // delta_{k-1} = delta_k + W_k^T g_k;  g_{k-1} = delta_{k-1} (1 - a_{k-1}^2), a_0 := h_0
-        Opnd A = opnd(gcur, w, rows, w, ROWS, 0);
-        Opnd Bw = opnd(pk_wkt(g, L, R.pk, k), w, w, w, ROWS, 0);
+        Gm G = gm(gb[cur], w, rows, pk_wkt(g, L, R.pk, k), w, w, w);
         Epi E = epi0(rows, w);
-        E.h32 = R.d32; E.ldh = w; E.ob = gnext; E.ldb = w;
+        E.h32 = R.d32; E.ldh = w; E.ob = gb[cur ^ 1]; E.ldb = w; E.ot = gt[cur ^ 1]; E.ldt = L.ldt;
         E.ab = (k >= 2) ? R.ab + (size_t)(k - 2) * L.rows * w : R.hb;
         E.lda = w;
-        if ((e = gemm<EPI_BWD_RES>(A, Bw, E, rows, w, w, 1, 0, s)) != hipSuccess) return e;
-        uint16_t* t = gcur; gcur = gnext; gnext = t;
+        if ((e = gemm<EPI_BWD_RES, RN_TM, RN_TN>(G, E, rows, w, 1, s)) != hipSuccess) return e;
+        cur ^= 1;
       }
     }
     {  // dW_in += g_0^T [x; t], db_in += sum g_0
-      Opnd A = opnd(gcur, w, w, rows, TRANS, 0);
-      Opnd Bx = opnd(X + (size_t)n0 * g.M * g.dp, g.dp, d, rows, TRANS, 1);
-      Bx.tcol = d; Bx.onescol = d + 1; Bx.n0 = n0; Bx.mp = g.M; Bx.dt = g.dt;
-      Epi E = epi0(w, d + 2);
+      Gm G = gm(gt[cur], L.ldt, w, R.xt, L.ldt, d + 1, rows);
+      G.pstride = g.nparams;
+      Epi E = epi0(w, d + 1);
       E.part = part; E.base = 0; E.wcols = d + 1;
-      if ((e = gemm<EPI_ACC>(A, Bx, E, w, d + 2, rows, splits, g.nparams, s)) != hipSuccess) return e;
+      if ((e = gemm<EPI_ACC, RN_TM, RN_TN>(G, E, w, d + 1, splits, s)) != hipSuccess) return e;
     }
   }
   return hipSuccess;
