@@ -372,10 +372,12 @@ def hjb_leg(steps: int = 20):
     return out
 
 
-def resnet_leg(steps: int = 3):
+def resnet_leg(steps: int = 3, recompute: bool = True):
     """BSB d=1000, N=64, M=16384, shared residual network (width 1024,
-    4 blocks, t as input), bf16 MFMA with recompute in the reverse sweep:
-    ms per training step and MFMA TFLOP/s of the forward and reverse phases."""
+    4 blocks, t as input), bf16 MFMA; the reverse sweep recomputes each row
+    chunk's activations (checkpointing) or reads the ones the forward pass
+    kept: ms per training step and MFMA TFLOP/s of the forward and reverse
+    phases (the recompute's flops count only when it runs)."""
     import torch
     from paper_1910_11623_amd import inputs as I
     from paper_1910_11623_amd.plan import Plan, TrainState
@@ -383,7 +385,7 @@ def resnet_leg(steps: int = 3):
     d, w, B, Nr, Mr = 1000, 1024, 4, 64, 16384
     prob = I.bsb(d)
     net = dict(kind="resnet", width=w, depth=B, prec="bf16")
-    plan = Plan(prob, net, Nr, Mr)
+    plan = Plan(prob, net, Nr, Mr, recompute=recompute)
     s = TrainState(plan, I.init_params(prob, net, Nr, seed=0, out_scale=0.1), 760.0)
     s.eager_step(1, 0)
     torch.cuda.synchronize()
@@ -402,11 +404,14 @@ def resnet_leg(steps: int = 3):
     plan.profile(False)
     rows = Nr * Mr
     fwd_flops = 2.0 * (w * d + B * w * w + d * w) * rows
-    bwd_flops = (2.0 * (w * d + B * w * w) + 2.0 * w * d + 2.0 * B * w * w +
-                 2.0 * (d * (w + 1) + B * w * (w + 1) + w * (d + 2))) * rows
+    recompute_flops = 2.0 * (w * d + B * w * w) * rows if recompute else 0.0
+    bwd_flops = recompute_flops + (2.0 * w * d + 2.0 * B * w * w +
+                                   2.0 * (d * (w + 1) + B * w * (w + 1) + w * (d + 2))) * rows
     t_f = prof["forward"][0] / max(prof["forward"][1], 1) * 1e-3
     t_b = prof["backward"][0] / max(prof["backward"][1], 1) * 1e-3
-    return {"ms_per_step": round(ms, 3), "path_steps_per_s": round(rows / (ms * 1e-3), 1),
+    return {"recompute": bool(recompute), "workspace_gib": round(plan.ws_bytes / 2**30, 2),
+            "ms_per_step": round(ms, 3), "path_steps_per_s": round(rows / (ms * 1e-3), 1),
+            "step_mfma_tflops": round((fwd_flops + bwd_flops) / (ms * 1e-3) / 1e12, 1),
             "forward_ms": round(t_f * 1e3, 3), "backward_ms": round(t_b * 1e3, 3),
             "forward_tflops": round(fwd_flops / t_f / 1e12, 1), "backward_tflops": round(bwd_flops / t_b / 1e12, 1),
             "bf16_peak_tflops": PEAK_BF16_MFMA,
@@ -424,7 +429,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the batched Allen-Cahn and HJB legs")
     ap.add_argument("--prec", choices=["fp32", "bf16", "both"], default="both",
                     help="which library precision(s) to time")
-    ap.add_argument("--only", choices=["batch", "hjb", "resnet"],
+    ap.add_argument("--only", choices=["batch", "hjb", "resnet", "resnet_kept"],
                     help="run just one of the extra legs and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
@@ -449,7 +454,8 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
         return
     if args.only:
-        leg = {"batch": batch_leg, "hjb": hjb_leg, "resnet": resnet_leg}[args.only]
+        leg = {"batch": batch_leg, "hjb": hjb_leg, "resnet": resnet_leg,
+               "resnet_kept": lambda: resnet_leg(recompute=False)}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return
     if args.prec == "bf16":
@@ -497,8 +503,10 @@ def main():
             f"{extra['batched_allen_cahn_32']['graph_ms']} ms, tuned graph {extra['batched_allen_cahn_32']['graph_tuned_ms']} ms")
         extra["hjb_d100_M65536"] = hjb_leg()
         log(f"HJB d=100 M=65536: {extra['hjb_d100_M65536']}")
-        extra["resnet_bsb_d1000"] = resnet_leg()
-        log(f"ResNet BSB d=1000: {extra['resnet_bsb_d1000']}")
+        extra["resnet_bsb_d1000"] = resnet_leg(recompute=True)
+        log(f"ResNet BSB d=1000 (recompute): {extra['resnet_bsb_d1000']}")
+        extra["resnet_bsb_d1000_kept"] = resnet_leg(recompute=False)
+        log(f"ResNet BSB d=1000 (activations kept): {extra['resnet_bsb_d1000_kept']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -99,16 +99,17 @@ void make_layout(fbsde_plan* P) {
     w.RPK = take((size_t)R.pk_elems * 2 + slack);
     w.RPF = take((size_t)R.pf_elems * 4);
     w.RH32 = take(rows * wd * 4);
-    w.RHB = take((size_t)(g.L + 1) * rows * wd * 2 + slack);
-    w.RAB = take((size_t)g.L * rows * wd * 2 + slack);
+    const size_t kept = (size_t)R.kept;
+    w.RHB = take(kept * (g.L + 1) * rows * wd * 2 + slack);
+    w.RAB = take(kept * g.L * rows * wd * 2 + slack);
     w.RD32 = take(rows * wd * 4);
     w.RGB = take(2 * rows * wd * 2 + slack);
     w.RZ = take(rows * (size_t)R.dq * 4);
     const size_t ldt = (size_t)R.ldt;
-    w.RHT = take((size_t)(g.L + 1) * wd * ldt * 2 + slack);
+    w.RHT = take(kept * (g.L + 1) * wd * ldt * 2 + slack);
     w.RGT = take(2 * wd * ldt * 2 + slack);
     w.RZT = take((size_t)g.d * ldt * 2 + slack);
-    w.RXT = take((size_t)(g.d + 1) * ldt * 2 + slack);
+    w.RXT = take(kept * (g.d + 1) * ldt * 2 + slack);
     w.RXB = take(rows * (size_t)R.dq * 2 + slack);
     w.RVB = take(rows * (size_t)R.dq * 2 + slack);
   }
@@ -401,6 +402,7 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   if (resnet) {
     // chunks of whole steps, about 64k rows each
     g.rn_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(N, 65536 / std::max<int64_t>(1, M)));
+    g.rn_store = 0;
     // the GEMMs address a chunk's activations with 32-bit element offsets
     const int64_t rows = (int64_t)g.rn_chunk * M, ldt = (rows + 7) / 8 * 8, dq = (p.d + 7) / 8 * 8;
     const int64_t wide = std::max<int64_t>(std::max<int64_t>(net->width, dq), p.d + 1);
@@ -421,6 +423,7 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
     }
     P->ncand = fbsde::tile_candidates(bf ? 1 : 0, ti0, tw0, P->cand_ti, P->cand_tw, 2);
     g.rn_chunk = 0;
+    g.rn_store = 0;
     set_tiles(g, ti0, tw0);
   }
   g.bf16 = bf ? 1 : 0;
@@ -665,6 +668,19 @@ fbsde_status fbsde_plan_config(fbsde_plan* plan, int32_t shape, int32_t lds, int
     plan->ws = keep_w;
     return fail(FBSDE_ERR_INVALID, "configuration does not fit the reserved workspace");
   }
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_plan_set_checkpointing(fbsde_plan* plan, int32_t recompute) {
+  if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
+  if (plan->geo.kind != 1) {
+    if (recompute) return fail(FBSDE_ERR_UNSUPPORTED, "the per-step MLP always keeps its activations");
+    return FBSDE_OK;
+  }
+  plan->geo.rn_store = recompute ? 0 : 1;
+  make_layout(plan);
+  plan->reserve = reserve_bytes(plan);
+  if (plan->reserve < plan->ws.total) plan->reserve = plan->ws.total;
   return FBSDE_OK;
 }
 

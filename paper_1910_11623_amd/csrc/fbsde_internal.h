@@ -32,6 +32,7 @@ struct Geo {
   int tpw;                // 16-path tiles per wave of the LDS kernels (0: automatic)
   int kind;               // 0: per-step MLP, 1: shared residual network (L = blocks)
   int rn_chunk;           // residual network: time steps per row chunk
+  int rn_store;           // residual network: 1 = keep every chunk's activations (no recompute)
 };
 
 // Shared residual network: packed weights and the per-chunk activation buffers.
@@ -41,20 +42,22 @@ struct ResnetLayout {
   long long pf_elems;     // fp32 time column and biases
   long long rows;         // rows per chunk = rn_chunk * M
   long long ldt;          // row stride of the transposed copies: rows rounded up to 8
+  int nchunks;            // row chunks per pass
+  int kept;               // chunks whose activations have their own copy (1, or nchunks if stored)
 };
 struct ResnetBufs {
   uint16_t* pk;           // packed bf16 weights
   float* pf;              // w_t | b_in | b_k | b_o
   float* h32;             // [rows][w] fp32 residual stream
-  uint16_t* hb;           // [B+1][rows][w] bf16 h_0..h_B
-  uint16_t* ab;           // [B][rows][w] bf16 a_1..a_B
+  uint16_t* hb;           // [kept][B+1][rows][w] bf16 h_0..h_B
+  uint16_t* ab;           // [kept][B][rows][w] bf16 a_1..a_B
   float* d32;             // [rows][w] fp32 delta
   uint16_t* gb;           // [2][rows][w] bf16 pre-activation gradients (ping-pong)
   float* z;               // [rows][dq] fp32 network output
-  uint16_t* ht;           // [B+1][w][ldt] bf16 h_k^T (reverse sweep)
+  uint16_t* ht;           // [kept][B+1][w][ldt] bf16 h_k^T
   uint16_t* gt;           // [2][w][ldt] bf16 g^T (ping-pong)
   uint16_t* zt;           // [d][ldt] bf16 zeta^T
-  uint16_t* xt;           // [d+1][ldt] bf16 [x; t]^T
+  uint16_t* xt;           // [kept][d+1][ldt] bf16 [x; t]^T
   uint16_t* xb;           // [rows][dq] bf16 x
   uint16_t* vb;           // [rows][dq] bf16 zeta = lambda v
 };

@@ -611,6 +611,8 @@ ResnetLayout resnet_layout(const Geo& g) {
   L.pf_elems = 2 * w + B * w + d;
   L.rows = (long long)g.rn_chunk * g.M;
   L.ldt = (L.rows + 7) / 8 * 8;
+  L.nchunks = (g.N + g.rn_chunk - 1) / g.rn_chunk;
+  L.kept = g.rn_store ? L.nchunks : 1;
   return L;
 }
 
@@ -686,12 +688,29 @@ static hipError_t chunk_forward(const Geo& g, const ResnetLayout& L, const Resne
   return hipSuccess;
 }
 
+// The buffers of chunk c: its own activation copies when they are kept
+// across the passes, else the single shared set.
+static ResnetBufs chunk_view(const Geo& g, const ResnetLayout& L, const ResnetBufs& R, int c) {
+  ResnetBufs V = R;
+  if (L.kept > 1) {
+    const size_t w = (size_t)g.w, rows = (size_t)L.rows, ldt = (size_t)L.ldt;
+    V.hb += (size_t)c * (g.L + 1) * rows * w;
+    V.ab += (size_t)c * g.L * rows * w;
+    V.ht += (size_t)c * (g.L + 1) * w * ldt;
+    V.xt += (size_t)c * (g.d + 1) * ldt;
+  }
+  return V;
+}
+
 hipError_t resnet_forward(const Geo& g, const ResnetBufs& R, const float* X, float* V, float* C, hipStream_t s) {
   const ResnetLayout L = resnet_layout(g);
   hipError_t e;
   for (int n0 = 0; n0 < g.N; n0 += g.rn_chunk) {
     const int ns = min(g.rn_chunk, g.N - n0);
-    if ((e = chunk_forward(g, L, R, n0, ns, X, true, false, s)) != hipSuccess) return e;
+    // when activations are kept, the forward pass also writes what the
+    // reverse sweep reads (a_k, h_k^T, [x; t]^T) into the chunk's own copy
+    const ResnetBufs Rc = chunk_view(g, L, R, n0 / g.rn_chunk);
+    if ((e = chunk_forward(g, L, Rc, n0, ns, X, true, L.kept > 1, s)) != hipSuccess) return e;
     const int rows = ns * g.M;
     k_row_epilogue<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(g, n0, rows, R.z, L.dq, X, V, C);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -699,12 +718,13 @@ hipError_t resnet_forward(const Geo& g, const ResnetBufs& R, const float* X, flo
   return hipSuccess;
 }
 
-// Reverse sweep of every chunk (recomputing its activations).  Weight
+// Reverse sweep of every chunk (recomputing its activations unless the
+// forward pass kept them).  Weight
 // gradients are products over the chunk's rows of transposed bf16 copies
 // (g_k^T, h_k^T, zeta^T, [x; t]^T) and accumulate over chunks into `splits`
 // partial buffers of the flat parameter layout, one per reduction split of
 // each GEMM (fixed order: deterministic).
-hipError_t resnet_backward(const Geo& g, const ResnetBufs& R, const float* X, const float* V, const float* LAM,
+hipError_t resnet_backward(const Geo& g, const ResnetBufs& R0, const float* X, const float* V, const float* LAM,
                            float* part, int splits, hipStream_t s) {
   const ResnetLayout L = resnet_layout(g);
   const int w = g.w, d = g.d, B = g.L;
@@ -716,7 +736,9 @@ hipError_t resnet_backward(const Geo& g, const ResnetBufs& R, const float* X, co
   for (int n0 = 0; n0 < g.N; n0 += g.rn_chunk) {
     const int ns = min(g.rn_chunk, g.N - n0);
     const int rows = ns * g.M;
-    if ((e = chunk_forward(g, L, R, n0, ns, X, false, true, s)) != hipSuccess) return e;
+    const ResnetBufs R = chunk_view(g, L, R0, n0 / g.rn_chunk);
+    if (L.kept == 1)  // checkpointed: recompute the chunk's activations
+      if ((e = chunk_forward(g, L, R, n0, ns, X, false, true, s)) != hipSuccess) return e;
     const float* Vc = V + (size_t)n0 * g.M * g.dp;
     const float* lam = LAM + (size_t)n0 * g.M;  // lambda_{n+1} of every row
     // zeta = lambda v in bf16, row-major and transposed

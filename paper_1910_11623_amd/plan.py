@@ -24,7 +24,11 @@ def _stream() -> int:
 class Plan:
     """One (problem, network, N, M) configuration of the hot path."""
 
-    def __init__(self, problem: dict, net: dict, N: int, M: int, device: str | torch.device = "cuda"):
+    def __init__(self, problem: dict, net: dict, N: int, M: int, device: str | torch.device = "cuda",
+                 recompute: bool = True):
+        """`recompute` (shared residual network only): False keeps every
+        chunk's activations from the forward pass (larger workspace, no
+        recompute in the reverse sweep)."""
         self.lib = B.load()
         self.problem, self.net, self.N, self.M = problem, dict(net), int(N), int(M)
         dev = torch.device(device)
@@ -41,6 +45,9 @@ class Plan:
             n = C.c_int64()
             B.check(self.lib.fbsde_param_count(self._h, C.byref(n)))
             self.n_params = int(n.value)
+            self.recompute = bool(recompute) if self.net.get("kind") == "resnet" else False
+            if self.net.get("kind") == "resnet":
+                B.check(self.lib.fbsde_plan_set_checkpointing(self._h, int(self.recompute)))
             sz = C.c_size_t()
             B.check(self.lib.fbsde_workspace_size(self._h, C.byref(sz)))
             self.ws_bytes = int(sz.value)

@@ -75,3 +75,20 @@ def test_resnet_full_size_sampled_paths():
     yr, xr = O.paths(prob, oracle_net(net), N, p.astype(np.float64), y0, idx, seed=1, it=0)
     np.testing.assert_allclose(xN[idx], xr, rtol=2e-5, atol=2e-5)
     np.testing.assert_allclose(yN[idx], yr, rtol=2e-3, atol=2e-3)
+
+
+# several row chunks each (3 + 2 and 4 + 3 steps)
+@pytest.mark.parametrize("pname,d,w,B,N,M", [CASES[2], ("bsb", 50, 64, 2, 7, 16384)])
+def test_resnet_kept_activations_match_recompute_bitwise(pname, d, w, B, N, M):
+    """Keeping every chunk's activations from the forward pass (no recompute
+    in the reverse sweep) gives bitwise the same loss and gradient."""
+    prob = _problem(pname, d)
+    net = dict(kind="resnet", width=w, depth=B, prec="bf16")
+    p = I.init_params(prob, net, N, seed=3, out_scale=0.3).astype(np.float32)
+    a = Plan(prob, net, N, M, recompute=True)
+    b = Plan(prob, net, N, M, recompute=False)
+    assert b.ws_bytes > a.ws_bytes
+    ra = run_gpu(a, p, 0.4, seed=9, it=2)
+    rb = run_gpu(b, p, 0.4, seed=9, it=2)
+    assert ra[0] == rb[0] and ra[2] == rb[2]
+    assert np.array_equal(ra[1], rb[1])
