@@ -93,6 +93,42 @@ def time_library(prec: str, steps: int, warmup: int):
     return ms, kern, finite
 
 
+def bsb_closed_form_y0(d: int, T: float = 1.0, r: float = 0.05, sigma: float = 0.4) -> float:
+    """u(0, x0) = exp((r + sigma^2) T) |x0|^2 of the Black-Scholes-Barenblatt
+    problem (Sec. 4), x0 = (1, 0.5, 1, 0.5, ...)."""
+    x0sq = sum(1.0 if i % 2 == 0 else 0.25 for i in range(d))
+    return math.exp((r + sigma * sigma) * T) * x0sq
+
+
+def resnet_multilevel_leg(levels=(8, 16, 32, 64), iters=(300, 300, 300, 600), lr_y0: float = 0.1):
+    """BSB d=1000, M=16384, shared residual net (width 1024, 4 blocks, bf16,
+    kept activations) trained through the multilevel schedule N = 8 -> 16 ->
+    32 -> 64 (the shared net carries over unchanged): seconds per level,
+    ms per iteration and the final Y0 against the closed form."""
+    import torch
+    from paper_1910_11623_amd import inputs as I
+    from paper_1910_11623_amd.plan import Plan
+    from paper_1910_11623_amd.train import multilevel_schedule, train
+
+    d, Mr = 1000, 16384
+    prob = I.bsb(d)
+    net = dict(kind="resnet", width=1024, depth=4, prec="bf16")
+    plans = {n: Plan(prob, net, n, Mr, recompute=False) for n in levels}
+    p0 = I.init_params(prob, net, levels[0], seed=0, out_scale=0.1)
+    target = bsb_closed_form_y0(d)
+    h = train(prob, net, Mr, multilevel_schedule(levels, iters), lr=1e-3, lr_y0=lr_y0, seed=1,
+              params_init=p0, plans=plans, warmup=3)
+    torch.cuda.synchronize()
+    y_last = h.y0[-100:]
+    return {"levels": list(levels), "iters": list(iters), "lr_y0": lr_y0,
+            "level_seconds": [round(t, 3) for t in h.level_seconds],
+            "ms_per_iter": [round(1e3 * t / k, 3) for t, k in zip(h.level_seconds, iters)],
+            "y0_start": round(float(h.y0[0]), 4), "y0_final": round(h.y0_final, 4),
+            "y0_mean_last100": round(float(np.mean(y_last)), 4), "target": round(target, 4),
+            "rel_err_final": round(abs(h.y0_final / target - 1.0), 5),
+            "loss_first": float(h.loss[0]), "loss_last": float(h.loss[-1])}
+
+
 def measured_traffic(kernel: str, prec: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration),
@@ -429,7 +465,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the batched Allen-Cahn and HJB legs")
     ap.add_argument("--prec", choices=["fp32", "bf16", "both"], default="both",
                     help="which library precision(s) to time")
-    ap.add_argument("--only", choices=["batch", "hjb", "resnet", "resnet_kept"],
+    ap.add_argument("--only", choices=["batch", "hjb", "resnet", "resnet_kept", "resnet_multilevel"],
                     help="run just one of the extra legs and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
@@ -440,7 +476,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from oracle import refvalues as RV
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log(f"device {torch.cuda.get_device_name(0)}")
@@ -455,7 +490,8 @@ def main():
         return
     if args.only:
         leg = {"batch": batch_leg, "hjb": hjb_leg, "resnet": resnet_leg,
-               "resnet_kept": lambda: resnet_leg(recompute=False)}[args.only]
+               "resnet_kept": lambda: resnet_leg(recompute=False),
+               "resnet_multilevel": resnet_multilevel_leg}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return
     if args.prec == "bf16":
@@ -476,7 +512,7 @@ def main():
     dom_bf, roof_bf = roofline_entry("bf16", kern_bf)
     log(f"bf16: {ms_bf:.4f} ms/step; dominant {dom_bf} {roof_bf['achieved']} TFLOP/s")
 
-    target = RV.bsb_y0(D)
+    target = bsb_closed_form_y0(D)
     tta = {}
     if not args.no_tta:
         y0_init = 73.0
