@@ -529,18 +529,35 @@ __global__ __launch_bounds__(256) void k_scan(Geo g, const double* __restrict__ 
   const int m = blockIdx.x * 256 + threadIdx.x;
   double l2 = 0.0, lam0 = 0.0;
   if (m < g.M) {
+    // both recursions are serial in n; the loads they need are not, so
+    // they are issued SB steps at a time ahead of the arithmetic
+    constexpr int SB = 8;
     float y = (float)y0[0];
     Y[m] = y;
-    for (int n = 0; n < g.N; ++n) {
-      y = y + g.dt * phi_y(g, y) + C[(size_t)n * g.M + m];
-      Y[(size_t)(n + 1) * g.M + m] = y;
+    for (int n0 = 0; n0 < g.N; n0 += SB) {
+      float c[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q) c[q] = (n0 + q < g.N) ? C[(size_t)(n0 + q) * g.M + m] : 0.f;
+#pragma unroll
+      for (int q = 0; q < SB; ++q) {
+        if (n0 + q >= g.N) break;
+        y = y + g.dt * phi_y(g, y) + c[q];
+        Y[(size_t)(n0 + q + 1) * g.M + m] = y;
+      }
     }
     const float e = y - terminal_g(g, QN[m], LN[m]);
     l2 = (double)e * (double)e;
     float lam = 2.f * e / (float)g.M;
-    for (int n = g.N - 1; n >= 0; --n) {
-      LAM[(size_t)n * g.M + m] = lam;
-      lam = lam * (1.f + g.dt * phi_yy(g, Y[(size_t)n * g.M + m]));
+    for (int n1 = g.N - 1; n1 >= 0; n1 -= SB) {
+      float yv[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q) yv[q] = (n1 - q >= 0) ? Y[(size_t)(n1 - q) * g.M + m] : 0.f;
+#pragma unroll
+      for (int q = 0; q < SB; ++q) {
+        if (n1 - q < 0) break;
+        LAM[(size_t)(n1 - q) * g.M + m] = lam;
+        lam = lam * (1.f + g.dt * phi_yy(g, yv[q]));
+      }
     }
     lam0 = (double)lam;
   }
@@ -902,8 +919,15 @@ __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p
                                               double t_imm, const uint64_t* __restrict__ t_dev, double lr_y0,
                                               double b1d, double b2d, double epsd) {
   const float b1 = (float)b1d, b2 = (float)b2d, eps = (float)epsd;
-  const double t = t_dev ? (double)(t_dev[0] + 1) : t_imm;
-  const double c1d = 1.0 - pow(b1d, t), c2d = 1.0 - pow(b2d, t);
+  // bias corrections: one evaluation per workgroup, shared through LDS
+  __shared__ double corr[2];
+  if (threadIdx.x == 0) {
+    const double t = t_dev ? (double)(t_dev[0] + 1) : t_imm;
+    corr[0] = 1.0 - pow(b1d, t);
+    corr[1] = 1.0 - pow(b2d, t);
+  }
+  __syncthreads();
+  const double c1d = corr[0], c2d = corr[1];
   const float c1 = (float)c1d, c2 = (float)c2d;
   const long long i0 = blockIdx.x * 256LL + threadIdx.x;
   for (long long i = i0; i < n; i += (long long)gridDim.x * 256) {
@@ -1204,7 +1228,7 @@ hipError_t launch_loss_only(const Geo& g, const double* scan_part, int scan_bloc
 hipError_t launch_adam(long long n, float* p, const float* gr, float* m, float* v, double* y0,
                        const double* gy0, double* my0, double* vy0, float lr, double t, const uint64_t* t_dev,
                        double lr_y0, double b1, double b2, double eps, hipStream_t s) {
-  k_adam<<<grid1(n, 8192), 256, 0, s>>>(n, p, gr, m, v, y0, gy0, my0, vy0, lr, t, t_dev, lr_y0, b1, b2, eps);
+  k_adam<<<grid1(n, 1024), 256, 0, s>>>(n, p, gr, m, v, y0, gy0, my0, vy0, lr, t, t_dev, lr_y0, b1, b2, eps);
   return hipGetLastError();
 }
 
