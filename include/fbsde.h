@@ -195,16 +195,20 @@ fbsde_status fbsde_profile_read(fbsde_plan *plan, double *ms_host, int64_t *coun
  * changes the fp32 summation order of the weight gradient only. */
 fbsde_status fbsde_plan_config(fbsde_plan *plan, int32_t shape, int32_t lds, int32_t tpw, int32_t splits);
 /* Activation checkpointing of the shared residual network (Sec. 3.1 network
- * trained through the unrolled chain).  recompute != 0 (the default): only
- * X_n and v_n live across the passes and the reverse sweep recomputes each
- * row chunk's activations.  recompute == 0: the forward pass keeps every
- * chunk's bf16 activations and their transposed copies, so the reverse sweep
- * skips the recompute; the workspace grows by about
- * N M (B (3 w) + 2 w + d) bf16 elements.  Call before fbsde_workspace_size
- * (it changes the workspace).  Results are bitwise identical in both modes.
- * The per-step MLP always keeps its activations: UNSUPPORTED for it with
- * recompute != 0. */
-fbsde_status fbsde_plan_set_checkpointing(fbsde_plan *plan, int32_t recompute);
+ * trained through the unrolled chain).  Rows (step, path) are processed in
+ * chunks of whole steps of about chunk_rows rows (0: 262144; at least one
+ * step).  recompute != 0 (the default): only X_n and v_n live across the
+ * passes and the reverse sweep recomputes each chunk's activations.
+ * recompute == 0: the forward pass keeps every chunk's bf16 activations and
+ * their transposed copies, so the reverse sweep skips the recompute; the
+ * workspace grows by about N M (B (3 w) + 2 w + d) bf16 elements.  Call
+ * before fbsde_workspace_size (it changes the workspace).  Results are
+ * bitwise identical for every mode and chunk size except for the fp32
+ * summation order of the weight gradients, which follows the chunks.
+ * Errors: INVALID (negative chunk_rows); UNSUPPORTED (a chunk too large for
+ * 32-bit element offsets; the per-step MLP, which always keeps its
+ * activations, with recompute != 0). */
+fbsde_status fbsde_plan_set_checkpointing(fbsde_plan *plan, int32_t recompute, int64_t chunk_rows);
 /* cfg_host[6] = {shape, ti, tw, lds, tpw (resolved), splits} of the current configuration */
 fbsde_status fbsde_plan_get_config(const fbsde_plan *plan, int32_t *cfg_host);
 /* Autotuner: times fbsde_forward_backward (reps timed calls per candidate,

@@ -71,7 +71,7 @@ def load(path: str = LIB_PATH):
     L = C.CDLL(path)
     vp, u64, i64 = C.c_void_p, C.c_uint64, C.c_int64
     L.fbsde_plan_create.argtypes = [C.POINTER(Problem), C.POINTER(Net), C.c_int32, i64, C.POINTER(vp)]
-    L.fbsde_plan_set_checkpointing.argtypes = [vp, C.c_int32]
+    L.fbsde_plan_set_checkpointing.argtypes = [vp, C.c_int32, i64]
     L.fbsde_plan_destroy.argtypes = [vp]
     L.fbsde_plan_destroy.restype = None
     L.fbsde_param_count.argtypes = [vp, C.POINTER(i64)]

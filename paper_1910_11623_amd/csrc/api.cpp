@@ -142,6 +142,19 @@ void set_tiles(Geo& g, int ti, int tw) {
   g.pbias_step = 16LL * (L * g.tw + g.ti);
 }
 
+// Shared residual network: rows per chunk of whole steps (about `rows`, at
+// least one step), and whether a chunk's activations can be addressed with
+// the GEMMs' 32-bit element offsets.
+constexpr int64_t kDefaultChunkRows = 262144;
+int rn_chunk_steps(int64_t N, int64_t M, int64_t rows) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(N, rows / std::max<int64_t>(1, M)));
+}
+bool rn_offsets_fit(int64_t M, int64_t chunk_steps, int64_t width, int64_t d) {
+  const int64_t rows = chunk_steps * M, ldt = (rows + 7) / 8 * 8, dq = (d + 7) / 8 * 8;
+  const int64_t wide = std::max<int64_t>(std::max<int64_t>(width, dq), d + 1);
+  return (rows + 32) * wide < 0x7fffffffLL && (ldt + 32) * wide < 0x7fffffffLL;
+}
+
 // Largest workspace over the candidate tile shapes and the largest split count
 // the tuner may pick, so that any tuned configuration fits the caller's buffer.
 size_t reserve_bytes(fbsde_plan* P) {
@@ -401,12 +414,9 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   g.tpw = 0;
   if (resnet) {
     // chunks of whole steps, about 64k rows each
-    g.rn_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(N, 65536 / std::max<int64_t>(1, M)));
+    g.rn_chunk = rn_chunk_steps(N, M, kDefaultChunkRows);
     g.rn_store = 0;
-    // the GEMMs address a chunk's activations with 32-bit element offsets
-    const int64_t rows = (int64_t)g.rn_chunk * M, ldt = (rows + 7) / 8 * 8, dq = (p.d + 7) / 8 * 8;
-    const int64_t wide = std::max<int64_t>(std::max<int64_t>(net->width, dq), p.d + 1);
-    if ((rows + 32) * wide >= 0x7fffffffLL || (ldt + 32) * wide >= 0x7fffffffLL) {
+    if (!rn_offsets_fit(M, g.rn_chunk, net->width, p.d)) {
       delete P;
       return fail(FBSDE_ERR_UNSUPPORTED, "shared residual network: M x max(width, d) must stay below 2^31");
     }
@@ -671,12 +681,17 @@ fbsde_status fbsde_plan_config(fbsde_plan* plan, int32_t shape, int32_t lds, int
   return FBSDE_OK;
 }
 
-fbsde_status fbsde_plan_set_checkpointing(fbsde_plan* plan, int32_t recompute) {
+fbsde_status fbsde_plan_set_checkpointing(fbsde_plan* plan, int32_t recompute, int64_t chunk_rows) {
   if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
+  if (chunk_rows < 0) return fail(FBSDE_ERR_INVALID, "chunk_rows must be >= 0");
   if (plan->geo.kind != 1) {
     if (recompute) return fail(FBSDE_ERR_UNSUPPORTED, "the per-step MLP always keeps its activations");
     return FBSDE_OK;
   }
+  const int steps = rn_chunk_steps(plan->N, plan->M, chunk_rows > 0 ? chunk_rows : kDefaultChunkRows);
+  if (!rn_offsets_fit(plan->M, steps, plan->geo.w, plan->geo.d))
+    return fail(FBSDE_ERR_UNSUPPORTED, "chunk too large for 32-bit element offsets");
+  plan->geo.rn_chunk = steps;
   plan->geo.rn_store = recompute ? 0 : 1;
   make_layout(plan);
   plan->reserve = reserve_bytes(plan);

@@ -33,6 +33,10 @@ constexpr int LDK = BK + 8;
 #ifndef RN_WPE
 #define RN_WPE 2
 #endif
+// waves of a workgroup along j (2 along i)
+#ifndef RN_WJ
+#define RN_WJ 4
+#endif
 // register sets of slabs in flight (1 or 2)
 #ifndef RN_PF
 #define RN_PF 2
@@ -199,21 +203,22 @@ __device__ __forceinline__ void epilogue4(const Epi& E, int i, int j, f32x4 acc,
 // columns of one row (vector epilogue stores).  Tiles are ordered so that
 // the j-tiles of one (split, i-tile) are dispatched to the same XCD and
 // share the A slab in its L2.
-template <int EPI, int TM, int TN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RN_WPE))) void k_gemm(Gm G, Epi E) {
-  constexpr int BM = 32 * TM, BN = 32 * TN;
-  constexpr int UA = BM / 64, UB = BN / 64;  // 16-byte staging units per thread
+template <int EPI, int TM, int TN, int WJ>
+__global__ __launch_bounds__(128 * WJ) __attribute__((amdgpu_waves_per_eu(RN_WPE))) void k_gemm(Gm G, Epi E) {
+  constexpr int WI = 2, NT = 64 * WI * WJ;  // waves along i and j, threads
+  constexpr int BM = 16 * TM * WI, BN = 16 * TN * WJ;
+  constexpr int UA = BM * 4 / NT, UB = BN * 4 / NT;  // 16-byte staging units per thread
   // LDS: the double-buffered A and B slabs; after the main loop the same
   // memory holds each wave's (16 TN) x (16 TM) bf16 block of a transposed
   // copy (272-byte rows for TM = 8: 16-byte aligned, conflict-free)
   constexpr int TLD = 16 * TM + 8;
   constexpr int STAGE = 2 * (BM + BN) * LDK, TBLK = 16 * TN * TLD;
-  __shared__ __attribute__((aligned(16))) uint16_t smem[STAGE > 4 * TBLK ? STAGE : 4 * TBLK];
+  __shared__ __attribute__((aligned(16))) uint16_t smem[STAGE > WI * WJ * TBLK ? STAGE : WI * WJ * TBLK];
   uint16_t (*sA)[BM * LDK] = reinterpret_cast<uint16_t (*)[BM * LDK]>(smem);
   uint16_t (*sB)[BN * LDK] = reinterpret_cast<uint16_t (*)[BN * LDK]>(smem + 2 * BM * LDK);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  const int wi = wv >> 1, wj = wv & 1;
+  const int wi = wv / WJ, wj = wv % WJ;
 
   const int per_split = G.ti * G.tj;
   const int nt = per_split * G.ts;
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RN_WPE))) v
   Epi Ez = E;
   if constexpr (EPI == EPI_ACC) Ez.part = E.part + (long long)sp * G.pstride;
 
-  // Staging unit u = tid + 256 q: row u / 4, k offset 8 (u % 4).  Loads are
+  // Staging unit u = tid + NT q: row u / 4, k offset 8 (u % 4).  Loads are
   // unconditional so that the wait before each LDS write counts exactly the
   // loads it needs: rows past the operand clamp to its last row (they only
   // feed outputs that are never stored) and slabs past the split's end
@@ -240,12 +245,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RN_WPE))) v
   int aoff[UA], boff[UB];
 #pragma unroll
   for (int q = 0; q < UA; ++q) {
-    const int u = tid + 256 * q, r = min(i0 + (u >> 2), G.arows - 1);
+    const int u = tid + NT * q, r = min(i0 + (u >> 2), G.arows - 1);
     aoff[q] = r * (int)G.lda + (u & 3) * 8;
   }
 #pragma unroll
   for (int q = 0; q < UB; ++q) {
-    const int u = tid + 256 * q, r = min(j0 + (u >> 2), G.brows - 1);
+    const int u = tid + NT * q, r = min(j0 + (u >> 2), G.brows - 1);
     boff[q] = r * (int)G.ldb + (u & 3) * 8;
   }
   const int kofs = (tid & 3) * 8;  // this thread's k offset inside a slab (same for every unit)
@@ -263,12 +268,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RN_WPE))) v
     if (kt + BK <= ke) {  // uniform: a full slab
 #pragma unroll
       for (int q = 0; q < UA; ++q) {
-        const int u = tid + 256 * q;
+        const int u = tid + NT * q;
         *reinterpret_cast<uint4*>(&sA[buf][(u >> 2) * LDK + (u & 3) * 8]) = ra[q];
       }
 #pragma unroll
       for (int q = 0; q < UB; ++q) {
-        const int u = tid + 256 * q;
+        const int u = tid + NT * q;
         *reinterpret_cast<uint4*>(&sB[buf][(u >> 2) * LDK + (u & 3) * 8]) = rb[q];
       }
     } else {  // the split's last slab (or a padding slab): keep k < ke only
@@ -278,13 +283,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RN_WPE))) v
       for (int e = 0; e < 4; ++e) m[e] = (2 * e + 1 < nv) ? 0xffffffffu : (2 * e < nv ? 0xffffu : 0u);
 #pragma unroll
       for (int q = 0; q < UA; ++q) {
-        const int u = tid + 256 * q;
+        const int u = tid + NT * q;
         *reinterpret_cast<uint4*>(&sA[buf][(u >> 2) * LDK + (u & 3) * 8]) =
             uint4{ra[q].x & m[0], ra[q].y & m[1], ra[q].z & m[2], ra[q].w & m[3]};
       }
 #pragma unroll
       for (int q = 0; q < UB; ++q) {
-        const int u = tid + 256 * q;
+        const int u = tid + NT * q;
         *reinterpret_cast<uint4*>(&sB[buf][(u >> 2) * LDK + (u & 3) * 8]) =
             uint4{rb[q].x & m[0], rb[q].y & m[1], rb[q].z & m[2], rb[q].w & m[3]};
       }
@@ -570,9 +575,9 @@ static unsigned grid1(long long n, long long cap = 65536) {
 }
 
 // Launch with TM x TN wave tiles; `splits` > 1 splits the reduction (EPI_ACC only).
-template <int EPI, int TM, int TN>
+template <int EPI, int TM, int TN, int WJ = RN_WJ>
 static hipError_t gemm(Gm G, const Epi& E, int Mrows, int Ncols, int splits, hipStream_t s) {
-  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int BM = 32 * TM, BN = 16 * TN * WJ;
   G.kchunk = G.K;
   if (splits > 1) G.kchunk = (((long long)G.K + splits - 1) / splits + BK - 1) / BK * BK;
   if (G.kchunk < BK) G.kchunk = BK;
@@ -582,7 +587,7 @@ static hipError_t gemm(Gm G, const Epi& E, int Mrows, int Ncols, int splits, hip
   G.tj = (Ncols + BN - 1) / BN;
   const long long nt = (long long)G.ti * G.tj * G.ts;
   if (nt <= 0) return hipSuccess;
-  k_gemm<EPI, TM, TN><<<(unsigned)nt, 256, 0, s>>>(G, E);
+  k_gemm<EPI, TM, TN, WJ><<<(unsigned)nt, 128 * WJ, 0, s>>>(G, E);
   return hipGetLastError();
 }
 
@@ -710,7 +715,7 @@ hipError_t resnet_forward(const Geo& g, const ResnetBufs& R, const float* X, flo
     // when activations are kept, the forward pass also writes what the
     // reverse sweep reads (a_k, h_k^T, [x; t]^T) into the chunk's own copy
     const ResnetBufs Rc = chunk_view(g, L, R, n0 / g.rn_chunk);
-    if ((e = chunk_forward(g, L, Rc, n0, ns, X, true, L.kept > 1, s)) != hipSuccess) return e;
+    if ((e = chunk_forward(g, L, Rc, n0, ns, X, true, g.rn_store != 0, s)) != hipSuccess) return e;
     const int rows = ns * g.M;
     k_row_epilogue<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(g, n0, rows, R.z, L.dq, X, V, C);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -737,7 +742,7 @@ hipError_t resnet_backward(const Geo& g, const ResnetBufs& R0, const float* X, c
     const int ns = min(g.rn_chunk, g.N - n0);
     const int rows = ns * g.M;
     const ResnetBufs R = chunk_view(g, L, R0, n0 / g.rn_chunk);
-    if (L.kept == 1)  // checkpointed: recompute the chunk's activations
+    if (!g.rn_store)  // checkpointed: recompute the chunk's activations
       if ((e = chunk_forward(g, L, R, n0, ns, X, false, true, s)) != hipSuccess) return e;
     const float* Vc = V + (size_t)n0 * g.M * g.dp;
     const float* lam = LAM + (size_t)n0 * g.M;  // lambda_{n+1} of every row

@@ -25,10 +25,11 @@ class Plan:
     """One (problem, network, N, M) configuration of the hot path."""
 
     def __init__(self, problem: dict, net: dict, N: int, M: int, device: str | torch.device = "cuda",
-                 recompute: bool = True):
-        """`recompute` (shared residual network only): False keeps every
+                 recompute: bool = True, chunk_rows: int = 0):
+        """Shared residual network only: `recompute` False keeps every
         chunk's activations from the forward pass (larger workspace, no
-        recompute in the reverse sweep)."""
+        recompute in the reverse sweep); `chunk_rows` sets the rows per chunk
+        of whole steps (0: the library's default)."""
         self.lib = B.load()
         self.problem, self.net, self.N, self.M = problem, dict(net), int(N), int(M)
         dev = torch.device(device)
@@ -47,7 +48,7 @@ class Plan:
             self.n_params = int(n.value)
             self.recompute = bool(recompute) if self.net.get("kind") == "resnet" else False
             if self.net.get("kind") == "resnet":
-                B.check(self.lib.fbsde_plan_set_checkpointing(self._h, int(self.recompute)))
+                B.check(self.lib.fbsde_plan_set_checkpointing(self._h, int(self.recompute), int(chunk_rows)))
             sz = C.c_size_t()
             B.check(self.lib.fbsde_workspace_size(self._h, C.byref(sz)))
             self.ws_bytes = int(sz.value)

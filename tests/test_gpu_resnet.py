@@ -19,7 +19,9 @@ def _problem(name, d):
     return {"bsb": I.bsb, "hjb": I.hjb, "ac": I.allen_cahn}[name](d)
 
 
-# (problem, d, width, blocks, N, M); M = 20000 makes chunks of 3 steps (5 = 3 + 2)
+# (problem, d, width, blocks, N, M); with 65536-row chunks, M = 20000 makes
+# chunks of 3 steps (5 = 3 + 2)
+CHUNK = 65536
 CASES = [
     ("bsb", 20, 32, 2, 4, 64),
     ("hjb", 37, 40, 1, 3, 130),
@@ -34,7 +36,7 @@ def test_resnet_loss_and_gradient(pname, d, w, B, N, M):
     net = dict(kind="resnet", width=w, depth=B, prec="bf16")
     p = I.init_params(prob, net, N, seed=7, out_scale=0.3).astype(np.float32)
     y0 = 0.9 * float(np.dot(prob["x0"], prob["x0"])) if pname == "bsb" else 0.4
-    plan = Plan(prob, net, N, M)
+    plan = Plan(prob, net, N, M, chunk_rows=CHUNK)
     lg, gg, gy = run_gpu(plan, p, y0, seed=5, it=1)
     emu = O.loss_grad(prob, oracle_net(net), N, M, p.astype(np.float64), y0, seed=5, it=1)
     pure = O.loss_grad(prob, dict(oracle_net(net), bf16=False), N, M, p.astype(np.float64), y0, seed=5, it=1)
@@ -85,10 +87,27 @@ def test_resnet_kept_activations_match_recompute_bitwise(pname, d, w, B, N, M):
     prob = _problem(pname, d)
     net = dict(kind="resnet", width=w, depth=B, prec="bf16")
     p = I.init_params(prob, net, N, seed=3, out_scale=0.3).astype(np.float32)
-    a = Plan(prob, net, N, M, recompute=True)
-    b = Plan(prob, net, N, M, recompute=False)
+    a = Plan(prob, net, N, M, recompute=True, chunk_rows=CHUNK)
+    b = Plan(prob, net, N, M, recompute=False, chunk_rows=CHUNK)
     assert b.ws_bytes > a.ws_bytes
     ra = run_gpu(a, p, 0.4, seed=9, it=2)
     rb = run_gpu(b, p, 0.4, seed=9, it=2)
     assert ra[0] == rb[0] and ra[2] == rb[2]
     assert np.array_equal(ra[1], rb[1])
+
+
+def test_resnet_chunk_size_changes_only_gradient_summation_order():
+    """Chunks of 3 + 2 steps vs one chunk of 5: the same loss bitwise (rows
+    are independent in the forward pass); gradients equal up to the fp32
+    order of the sums over chunks."""
+    prob = _problem("ac", 8)
+    net = dict(kind="resnet", width=16, depth=2, prec="bf16")
+    N, M = 5, 20000
+    p = I.init_params(prob, net, N, seed=4, out_scale=0.3).astype(np.float32)
+    a = Plan(prob, net, N, M, chunk_rows=CHUNK)
+    b = Plan(prob, net, N, M)
+    ra = run_gpu(a, p, 0.4, seed=9, it=2)
+    rb = run_gpu(b, p, 0.4, seed=9, it=2)
+    assert ra[0] == rb[0]
+    np.testing.assert_allclose(ra[1], rb[1], rtol=1e-5, atol=1e-7 * np.abs(rb[1]).max())
+    assert abs(ra[2] - rb[2]) <= 1e-12 * max(1.0, abs(rb[2]))
