@@ -50,6 +50,22 @@ def kernel_flops(net_prec: str, d: int, w: int, L: int, n_steps: int, paths: int
     return {"forward": fwd, "backward": bwd, "wgrad": wgrad}
 
 
+def kernel_bytes(net_prec: str, d: int, w: int, L: int, n_steps: int, paths: int) -> dict:
+    """Algorithmic HBM bytes per launch of the MFMA kernels: every operand
+    read once, every result written once (activations and deltas in the
+    GEMM precision, path state in fp32), plus the weight-gradient partials
+    (one fp32 copy of the parameters per path split of 512 paths)."""
+    esz = 4 if net_prec == "fp32" else 2
+    dp = (d + 3) // 4 * 4
+    rows = paths * (n_steps - 1)
+    splits = (paths + 511) // 512
+    nparams = d + (n_steps - 1) * (w * (d + 1) + (L - 1) * w * (w + 1) + d * (w + 1))
+    fwd = (4 * dp + 4 * dp + 4 * dp + 4 + esz * L * w) * rows        # X, s in; v, c, activations out
+    bwd = (4 * dp + 4 + esz * L * w + esz * (L * w + d)) * rows      # v, lambda, activations in; deltas out
+    wgrad = (4 * d + esz * L * w + esz * (L * w + d)) * rows + 4 * splits * nparams
+    return {"forward": fwd, "backward": bwd, "wgrad": wgrad}
+
+
 def time_library(prec: str, steps: int, warmup: int):
     import torch
     from paper_1910_11623_amd import inputs as I
@@ -147,13 +163,24 @@ def measured_traffic(kernel: str, prec: str):
 
 
 def roofline_entry(prec: str, kern_ms: dict):
+    """Roofline of the dominant MFMA kernel, against the unit that bounds it:
+    HBM when its algorithmic intensity (flops per byte) is below the ridge
+    point peak_flops / peak_bytes, else the matrix peak of its dtype."""
     flops = kernel_flops(prec, D, W, DEPTH, N, M)
+    nbytes = kernel_bytes(prec, D, W, DEPTH, N, M)
     dom = max(flops, key=lambda k: kern_ms.get(k, 0.0))
     t = kern_ms[dom] * 1e-3
-    achieved = flops[dom] / t / 1e12
     peak = PEAK_FP32_MFMA if prec == "fp32" else PEAK_BF16_MFMA
+    ridge = peak * 1e12 / (PEAK_HBM * 1e9)
+    traffic = measured_traffic(dom, prec)
+    if flops[dom] / nbytes[dom] < ridge:
+        achieved = nbytes[dom] / t / 1e9
+        return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM, 4), "traffic": traffic,
+                     "mfma_tflops": round(flops[dom] / t / 1e12, 3)}
+    achieved = flops[dom] / t / 1e12
     return dom, {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                 "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom, prec)}
+                 "frac": round(achieved / peak, 4), "traffic": traffic}
 
 
 def cpu_baseline(target_s: float = 12.0):
