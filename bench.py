@@ -537,7 +537,8 @@ def main():
         return
     ms_bf, kern_bf, _ = time_library("bf16", args.steps, args.warmup)
     dom_bf, roof_bf = roofline_entry("bf16", kern_bf)
-    log(f"bf16: {ms_bf:.4f} ms/step; dominant {dom_bf} {roof_bf['achieved']} TFLOP/s")
+    log(f"bf16: {ms_bf:.4f} ms/step; dominant {dom_bf} {roof_bf['achieved']} {roof_bf['unit']} "
+        f"({roof_bf['bound']}-bound, {100 * roof_bf['frac']:.1f}% of peak)")
 
     target = bsb_closed_form_y0(D)
     tta = {}

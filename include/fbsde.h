@@ -27,6 +27,13 @@
  *   - Every call returns a status and never aborts; argument errors are
  *     detected on the host before any launch and leave device memory
  *     untouched.  fbsde_last_error() returns a thread-local message.
+ *   - A non-finite loss, dL/dY_0 or weight gradient is detected on the device
+ *     (in the reductions of fbsde_forward / fbsde_forward_backward) and
+ *     raises a flag in pinned host memory owned by the plan.  The next hot
+ *     call on that plan (fbsde_forward, fbsde_forward_backward,
+ *     fbsde_adam_step) returns FBSDE_ERR_NONFINITE without launching
+ *     anything and clears the flag; no call synchronises to check it, so the
+ *     report arrives once the offending work has completed.
  *   - Float parameters are one flat fp32 buffer (layout below); Y_0 is a
  *     separate fp64 scalar on the device.
  *
@@ -54,7 +61,7 @@ typedef enum {
   FBSDE_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement   */
   FBSDE_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed     */
   FBSDE_ERR_NOMEM = 4,        /* plan creation could not allocate              */
-  FBSDE_ERR_NONFINITE = 5     /* loss or gradient not finite (status check)    */
+  FBSDE_ERR_NONFINITE = 5     /* an earlier call's loss or gradient not finite */
 } fbsde_status;
 
 /* Forward SDE families (mu = 0 in every problem of Sec. 4). */

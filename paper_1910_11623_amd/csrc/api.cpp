@@ -35,6 +35,7 @@ struct fbsde_plan {
   Geo geo;
   WsLayout ws;
   float* x0_dev;  // [dp] zero-padded, owned
+  int* nf_host = nullptr;  // pinned host flag: a non-finite loss or gradient was produced
   int device;
   bool prof = false;
   ProfRing ring[FBSDE_PROF_NUM];
@@ -207,12 +208,23 @@ fbsde::ResnetBufs resnet_bufs(const fbsde_plan* P, void* ws) {
   return R;
 }
 
+// A non-finite result of an earlier call on the plan (raised on the device
+// into pinned host memory): reported once, then cleared.
+fbsde_status take_nonfinite(const fbsde_plan* P) {
+  volatile int* f = P->nf_host;
+  if (f && *f) {
+    *f = 0;
+    return fail(FBSDE_ERR_NONFINITE, "an earlier call on this plan produced a non-finite loss or gradient");
+  }
+  return FBSDE_OK;
+}
+
 fbsde_status check_hot(const fbsde_plan* P, const void* ws) {
   if (!P) return fail(FBSDE_ERR_INVALID, "plan is NULL");
   if (!ws) return fail(FBSDE_ERR_INVALID, "workspace is NULL");
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
     return fail(FBSDE_ERR_INVALID, "workspace must be 256-byte aligned");
-  return FBSDE_OK;
+  return take_nonfinite(P);
 }
 
 // Event pair around one launch (no-op unless profiling is enabled).  A ring
@@ -319,7 +331,7 @@ fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double
     }
     ProfScope ps(plan, FBSDE_PROF_REDUCE, s);
     if ((e = fbsde::launch_reduce(g, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
-                                  L.scan_blocks, loss, grad_y0, s)) != hipSuccess)
+                                  L.scan_blocks, loss, grad_y0, plan->nf_host, s)) != hipSuccess)
       return hip_fail(e, "reduce");
     return FBSDE_OK;
   }
@@ -338,7 +350,7 @@ fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double
   {
     ProfScope ps(plan, FBSDE_PROF_REDUCE, s);
     if ((e = fbsde::launch_reduce(g, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
-                                  L.scan_blocks, loss, grad_y0, s)) != hipSuccess)
+                                  L.scan_blocks, loss, grad_y0, plan->nf_host, s)) != hipSuccess)
       return hip_fail(e, "reduce");
   }
   return FBSDE_OK;
@@ -479,6 +491,15 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
     delete P;
     return hip_fail(e, "hipMemcpy x0");
   }
+  void* flag = nullptr;
+  e = hipHostMalloc(&flag, 64, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipFree(P->x0_dev);
+    delete P;
+    return fail(FBSDE_ERR_NOMEM, std::string("hipHostMalloc flag: ") + hipGetErrorString(e));
+  }
+  P->nf_host = static_cast<int*>(flag);
+  *P->nf_host = 0;
   *out = P;
   return FBSDE_OK;
 }
@@ -487,6 +508,7 @@ void fbsde_plan_destroy(fbsde_plan* plan) {
   if (!plan) return;
   (void)fbsde_profile_enable(plan, 0);
   if (plan->x0_dev) (void)hipFree(plan->x0_dev);
+  if (plan->nf_host) (void)hipHostFree(plan->nf_host);
   delete plan;
 }
 
@@ -510,7 +532,8 @@ fbsde_status fbsde_forward(fbsde_plan* plan, const float* params, const double* 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   st = run_forward(plan, params, y0, seed, iter, nullptr, ws, s);
   if (st != FBSDE_OK) return st;
-  hipError_t e = fbsde::launch_loss_only(plan->geo, at<double>(ws, plan->ws.RED), plan->ws.scan_blocks, loss, s);
+  hipError_t e = fbsde::launch_loss_only(plan->geo, at<double>(ws, plan->ws.RED), plan->ws.scan_blocks, loss,
+                                         plan->nf_host, s);
   if (e != hipSuccess) return hip_fail(e, "finalize");
   return FBSDE_OK;
 }
@@ -537,6 +560,7 @@ fbsde_status fbsde_adam_step(fbsde_plan* plan, float* params, double* y0, const 
   if (with_y0 && (!grad_y0 || !m_y0 || !v_y0))
     return fail(FBSDE_ERR_INVALID, "y0 given without grad_y0, m_y0, v_y0");
   if (t < 1) return fail(FBSDE_ERR_INVALID, "Adam step count must be >= 1");
+  if (fbsde_status st = take_nonfinite(plan); st != FBSDE_OK) return st;
   if (!(lr >= 0) || !(lr_y0 >= 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
     return fail(FBSDE_ERR_INVALID, "Adam hyper-parameters out of range");
   ProfScope ps(plan, FBSDE_PROF_ADAM, reinterpret_cast<hipStream_t>(stream));

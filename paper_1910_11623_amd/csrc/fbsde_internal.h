@@ -89,9 +89,12 @@ hipError_t launch_backward(const Geo& g, const void* packB, const float* V, cons
                            const void* H, void* DZ, void* DH, hipStream_t s);
 hipError_t launch_wgrad(const Geo& g, const float* X, const void* H, const void* DZ, const void* DH,
                         float* part, int splits, long long chunk, hipStream_t s);
-hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* grad, const double* scan_part,
-                         int scan_blocks, double* loss, double* grad_y0, hipStream_t s);
-hipError_t launch_loss_only(const Geo& g, const double* scan_part, int scan_blocks, double* loss,
+// The scan's partials are followed by an int flag: cleared by the scan, set
+// by the reduction on a non-finite gradient; the finalize step folds it (and
+// the loss, dL/dY0) into *host_flag (pinned host memory) and clears it.
+hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* grad, double* scan_part,
+                         int scan_blocks, double* loss, double* grad_y0, int* host_flag, hipStream_t s);
+hipError_t launch_loss_only(const Geo& g, double* scan_part, int scan_blocks, double* loss, int* host_flag,
                             hipStream_t s);
 hipError_t launch_adam(long long n, float* p, const float* gr, float* m, float* v, double* y0,
                        const double* gy0, double* my0, double* vy0, float lr, double t, const uint64_t* t_dev,

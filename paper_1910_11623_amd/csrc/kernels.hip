@@ -567,6 +567,8 @@ __global__ __launch_bounds__(256) void k_scan(Geo g, const double* __restrict__ 
   if (threadIdx.x == 0) {
     part[2 * blockIdx.x] = a;
     part[2 * blockIdx.x + 1] = b;
+    // the non-finite flag after the partials starts every iteration clear
+    if (blockIdx.x == 0) reinterpret_cast<int*>(part + 2 * gridDim.x)[0] = 0;
   }
 }
 
@@ -887,16 +889,22 @@ __global__ __launch_bounds__(256) void k_wgrad(Geo g, const float* __restrict__ 
 
 // ------------------------------------------------------------ reduce kernel
 __global__ __launch_bounds__(256) void k_reduce(long long P, const float* __restrict__ part, int splits,
-                                                float* __restrict__ grad) {
+                                                float* __restrict__ grad, int* __restrict__ nf) {
+  bool bad = false;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < P; e += (long long)gridDim.x * 256) {
     float s = 0.f;
     for (int k = 0; k < splits; ++k) s += part[(size_t)k * P + e];
     grad[e] = s;
+    bad |= !isfinite(s);
   }
+  if (bad) nf[0] = 1;  // every writer stores the same value
 }
 
+// Fixed-order fp64 totals of the scan partials; folds the loss, dL/dY0 and
+// the gradient flag `nf` into the plan's host flag, then clears `nf`.
 __global__ __launch_bounds__(256) void k_finalize(int M, const double* __restrict__ sp, int nb,
-                                                  double* __restrict__ loss, double* __restrict__ gy0) {
+                                                  double* __restrict__ loss, double* __restrict__ gy0,
+                                                  int* __restrict__ nf, int* __restrict__ host_flag) {
   __shared__ double sh[256];
   double a = 0.0, b = 0.0;
   for (int k = threadIdx.x; k < nb; k += 256) { a += sp[2 * k]; b += sp[2 * k + 1]; }
@@ -906,6 +914,9 @@ __global__ __launch_bounds__(256) void k_finalize(int M, const double* __restric
   if (threadIdx.x == 0) {
     if (loss) loss[0] = A / (double)M;
     if (gy0) gy0[0] = B;
+    const bool bad = nf[0] != 0 || !isfinite(A) || (gy0 != nullptr && !isfinite(B));
+    nf[0] = 0;
+    if (bad && host_flag) host_flag[0] = 1;
   }
 }
 
@@ -1210,18 +1221,25 @@ hipError_t launch_wgrad(const Geo& g, const float* X, const void* H, const void*
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* grad, const double* scan_part,
-                         int scan_blocks, double* loss, double* grad_y0, hipStream_t s) {
-  k_reduce<<<grid1(g.nparams, 4096), 256, 0, s>>>(g.nparams, part, splits, grad);
+// the non-finite flag lives right after the scan's fp64 partials
+static int* nf_flag(double* scan_part, int scan_blocks) {
+  return reinterpret_cast<int*>(scan_part + 2 * (size_t)scan_blocks);
+}
+
+hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* grad, double* scan_part,
+                         int scan_blocks, double* loss, double* grad_y0, int* host_flag, hipStream_t s) {
+  int* nf = nf_flag(scan_part, scan_blocks);
+  k_reduce<<<grid1(g.nparams, 4096), 256, 0, s>>>(g.nparams, part, splits, grad, nf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_finalize<<<1, 256, 0, s>>>(g.M, scan_part, scan_blocks, loss, grad_y0);
+  k_finalize<<<1, 256, 0, s>>>(g.M, scan_part, scan_blocks, loss, grad_y0, nf, host_flag);
   return hipGetLastError();
 }
 
-hipError_t launch_loss_only(const Geo& g, const double* scan_part, int scan_blocks, double* loss,
+hipError_t launch_loss_only(const Geo& g, double* scan_part, int scan_blocks, double* loss, int* host_flag,
                             hipStream_t s) {
-  k_finalize<<<1, 256, 0, s>>>(g.M, scan_part, scan_blocks, loss, nullptr);
+  k_finalize<<<1, 256, 0, s>>>(g.M, scan_part, scan_blocks, loss, nullptr, nf_flag(scan_part, scan_blocks),
+                               host_flag);
   return hipGetLastError();
 }
 

@@ -209,3 +209,33 @@ def test_invalid_arguments_raise():
     plan = Plan(I.bsb(4), dict(width=8), 4, 8)
     with pytest.raises(ValueError):
         plan.forward(torch.zeros(3, device="cuda"), torch.zeros((), dtype=torch.float64, device="cuda"), 0, 0)
+
+
+@pytest.mark.parametrize("kind", ["mlp", "resnet"])
+def test_nonfinite_result_reported_by_next_call(kind):
+    """A NaN weight makes the loss and gradient non-finite: the call that
+    computes them returns normally (nothing synchronises), the next hot call
+    on the plan reports FBSDE_ERR_NONFINITE once, and the one after that
+    runs again."""
+    import paper_1910_11623_amd.binding as B
+    prob = I.bsb(6)
+    net = dict(width=16, depth=2) if kind == "mlp" else dict(kind="resnet", width=16, depth=2, prec="bf16")
+    plan = Plan(prob, net, 4, 64)
+    p = I.init_params(prob, net, 4, seed=0).astype(np.float32)
+    y0 = torch.tensor(1.0, dtype=torch.float64, device="cuda")
+    good = torch.from_numpy(p).cuda()
+    bad = good.clone()
+    bad[7] = float("nan")
+    plan.forward_backward(good, y0, 1, 0)
+    torch.cuda.synchronize()
+    plan.forward_backward(good, y0, 1, 1)     # finite: no report
+    plan.forward_backward(bad, y0, 1, 2)
+    torch.cuda.synchronize()
+    with pytest.raises(B.FbsdeError) as ei:
+        plan.forward_backward(good, y0, 1, 3)
+    assert ei.value.status == B.ERR_NONFINITE
+    loss, g, gy = plan.forward_backward(good, y0, 1, 4)
+    torch.cuda.synchronize()
+    assert np.isfinite(float(loss.item())) and bool(torch.isfinite(g).all().item())
+    plan.forward_backward(good, y0, 1, 5)     # still no report
+    torch.cuda.synchronize()
