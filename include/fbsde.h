@@ -212,7 +212,8 @@ fbsde_status fbsde_plan_config(fbsde_plan *plan, int32_t shape, int32_t lds, int
  * before fbsde_workspace_size (it changes the workspace).  Results are
  * bitwise identical for every mode and chunk size except for the fp32
  * summation order of the weight gradients, which follows the chunks.
- * Errors: INVALID (negative chunk_rows); UNSUPPORTED (a chunk too large for
+ * Errors: INVALID (negative chunk_rows, or a mode that needs more workspace
+ * than an earlier fbsde_workspace_size reported); UNSUPPORTED (a chunk too large for
  * 32-bit element offsets; the per-step MLP, which always keeps its
  * activations, with recompute != 0). */
 fbsde_status fbsde_plan_set_checkpointing(fbsde_plan *plan, int32_t recompute, int64_t chunk_rows);

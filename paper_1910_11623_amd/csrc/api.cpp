@@ -43,6 +43,7 @@ struct fbsde_plan {
   int ncand = 0;
   int cand_ti[4], cand_tw[4];
   size_t reserve = 0;
+  bool ws_queried = false;  // fbsde_workspace_size was called: the reserve may not grow
 };
 
 namespace {
@@ -520,6 +521,7 @@ fbsde_status fbsde_param_count(const fbsde_plan* plan, int64_t* n) {
 
 fbsde_status fbsde_workspace_size(const fbsde_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return fail(FBSDE_ERR_INVALID, "plan or output is NULL");
+  const_cast<fbsde_plan*>(plan)->ws_queried = true;
   *bytes = plan->reserve;
   return FBSDE_OK;
 }
@@ -715,11 +717,20 @@ fbsde_status fbsde_plan_set_checkpointing(fbsde_plan* plan, int32_t recompute, i
   const int steps = rn_chunk_steps(plan->N, plan->M, chunk_rows > 0 ? chunk_rows : kDefaultChunkRows);
   if (!rn_offsets_fit(plan->M, steps, plan->geo.w, plan->geo.d))
     return fail(FBSDE_ERR_UNSUPPORTED, "chunk too large for 32-bit element offsets");
+  const Geo keep_g = plan->geo;
+  const WsLayout keep_w = plan->ws;
+  const size_t keep_r = plan->reserve;
   plan->geo.rn_chunk = steps;
   plan->geo.rn_store = recompute ? 0 : 1;
   make_layout(plan);
-  plan->reserve = reserve_bytes(plan);
-  if (plan->reserve < plan->ws.total) plan->reserve = plan->ws.total;
+  size_t r = reserve_bytes(plan);
+  if (r < plan->ws.total) r = plan->ws.total;
+  if (plan->ws_queried && r > keep_r) {  // a caller's buffer sized earlier would be too small
+    plan->geo = keep_g;
+    plan->ws = keep_w;
+    return fail(FBSDE_ERR_INVALID, "checkpointing mode needs a larger workspace: set it before fbsde_workspace_size");
+  }
+  plan->reserve = r > keep_r || !plan->ws_queried ? r : keep_r;
   return FBSDE_OK;
 }
 

@@ -573,8 +573,13 @@ __global__ __launch_bounds__(256) void k_scan(Geo g, const double* __restrict__ 
 }
 
 // ---------------------------------------------------------- backward kernel
+// Waves per workgroup of the LDS-staged reverse sweep: one workgroup per CU
+// (the step's weights fill the LDS), so the wave count sets the waves per
+// SIMD: 3 for shapes up to 8 x 8 tiles (<= 170 VGPRs), else 2.
+constexpr int bwd_waves(int ti, int tw) { return (ti <= 8 && tw <= 8) ? 12 : 8; }
+
 template <bool BF, int TI, int TW, bool LDSW>
-__global__ __launch_bounds__(LDSW ? 512 : 256) void k_backward(Geo g, const void* __restrict__ packB,
+__global__ __launch_bounds__(LDSW ? 64 * bwd_waves(TI, TW) : 256) void k_backward(Geo g, const void* __restrict__ packB,
                                                                 const float* __restrict__ V,
                                                                 const float* __restrict__ LAM,
                                                                 const void* __restrict__ H,
@@ -1083,9 +1088,10 @@ static void fwd_inst(const Geo& g, const float* params, const void* packF, const
       return true;
     }();
     (void)attr;
-    const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, 8, num_cus());
-    dim3 grid((unsigned)(((g.M + 15) / 16 + 8 * tpw - 1) / (8 * tpw)), g.N);
-    k_forward<BF, TI, TW, true><<<grid, 512, bytes, s>>>(g, params, packF, pbias, X, V, C, H, tpw);
+    constexpr int NW = 8;
+    const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, NW, num_cus());
+    dim3 grid((unsigned)(((g.M + 15) / 16 + NW * tpw - 1) / (NW * tpw)), g.N);
+    k_forward<BF, TI, TW, true><<<grid, 64 * NW, bytes, s>>>(g, params, packF, pbias, X, V, C, H, tpw);
   } else {
     dim3 grid((g.M + 63) / 64, g.N);
     k_forward<BF, TI, TW, false><<<grid, 256, 0, s>>>(g, params, packF, pbias, X, V, C, H, 1);
@@ -1102,9 +1108,10 @@ static void bwd_inst(const Geo& g, const void* packB, const float* V, const floa
       return true;
     }();
     (void)attr;
-    const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, 8, num_cus());
-    dim3 grid((unsigned)(((g.M + 15) / 16 + 8 * tpw - 1) / (8 * tpw)), g.N);
-    k_backward<BF, TI, TW, true><<<grid, 512, bytes, s>>>(g, packB, V, LAM, H, DZ, DH, tpw);
+    constexpr int NW = bwd_waves(TI, TW);
+    const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, NW, num_cus());
+    dim3 grid((unsigned)(((g.M + 15) / 16 + NW * tpw - 1) / (NW * tpw)), g.N);
+    k_backward<BF, TI, TW, true><<<grid, 64 * NW, bytes, s>>>(g, packB, V, LAM, H, DZ, DH, tpw);
   } else {
     dim3 grid((g.M + 63) / 64, g.N);
     k_backward<BF, TI, TW, false><<<grid, 256, 0, s>>>(g, packB, V, LAM, H, DZ, DH, 1);

@@ -111,3 +111,13 @@ def test_resnet_chunk_size_changes_only_gradient_summation_order():
     assert ra[0] == rb[0]
     np.testing.assert_allclose(ra[1], rb[1], rtol=1e-5, atol=1e-7 * np.abs(rb[1]).max())
     assert abs(ra[2] - rb[2]) <= 1e-12 * max(1.0, abs(rb[2]))
+
+
+def test_checkpointing_cannot_outgrow_a_reported_workspace():
+    import ctypes as C
+    import paper_1910_11623_amd.binding as B
+    prob = _problem("bsb", 20)
+    net = dict(kind="resnet", width=32, depth=2, prec="bf16")
+    plan = Plan(prob, net, 8, 4096, chunk_rows=8192)  # checkpointed, workspace already sized
+    assert plan.lib.fbsde_plan_set_checkpointing(plan._h, 0, 8192) == B.ERR_INVALID
+    assert plan.lib.fbsde_plan_set_checkpointing(plan._h, 1, 8192) == B.OK  # same size: allowed
