@@ -741,6 +741,13 @@ __device__ __forceinline__ Job job_info(const Geo& g, int job, const float* X, c
 #define FBSDE_WG_KC 32
 #endif
 constexpr int WG_KC = FBSDE_WG_KC;  // paths per LDS chunk
+// tile columns per wave of the weight-gradient kernel (its workgroup has
+// ceil(T / WG_CPW) <= 8 waves: 4 waves x 2 columns or 8 waves x 1 column)
+#ifndef FBSDE_WG_CPW
+#define FBSDE_WG_CPW 1
+#endif
+constexpr int WG_CPW = FBSDE_WG_CPW;
+constexpr int WG_THREADS = 64 * (8 / WG_CPW);
 
 template <int T>
 struct WgradLds {
@@ -788,7 +795,7 @@ __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, 
     __syncthreads();
     // ---- stage A (deltas, rows R0..) and B (activations, cols C0..) chunks
     constexpr int NV = WG_KC * 4 * T;  // float4 slots per operand chunk
-    for (int s = tid; s < 2 * NV; s += 256) {
+    for (int s = tid; s < 2 * NV; s += WG_THREADS) {
       const bool isA = s < NV;
       const int q = isA ? s : s - NV;
       const int kp = q / (4 * T), c4 = q % (4 * T);
@@ -827,7 +834,7 @@ __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, 
 #pragma unroll
         for (int i = 0; i < T; ++i) a[i] = As[kr * L::LDA + 16 * i + c16];
 #pragma unroll
-        for (int j = 0; j < CW; ++j) b[j] = Bs[kr * L::LDA + 16 * (2 * wv + j) + c16];
+        for (int j = 0; j < CW; ++j) b[j] = Bs[kr * L::LDA + 16 * (WG_CPW * wv + j) + c16];
 #pragma unroll
         for (int i = 0; i < T; ++i)
 #pragma unroll
@@ -846,7 +853,7 @@ __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, 
       }
 #pragma unroll
       for (int j = 0; j < CW; ++j) {
-        const uint16_t* src = Bs + (16 * (2 * wv + j) + c16) * L::LDT + 8 * grp;
+        const uint16_t* src = Bs + (16 * (WG_CPW * wv + j) + c16) * L::LDT + 8 * grp;
         const uint2 lo = *reinterpret_cast<const uint2*>(src), hi = *reinterpret_cast<const uint2*>(src + 4);
         b[j] = __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y});
       }
@@ -863,7 +870,7 @@ __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, 
     for (int j = 0; j < CW; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = R0 + 16 * i + 4 * grp + r, c = C0 + 16 * (2 * wv + j) + c16;
+        const int row = R0 + 16 * i + 4 * grp + r, c = C0 + 16 * (WG_CPW * wv + j) + c16;
         if (row < J.rows && c <= J.cols) {
           const long long off = (c < J.cols) ? J.base + (long long)row * J.cols + c
                                              : J.base + (long long)J.rows * J.cols + row;
@@ -873,7 +880,7 @@ __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, 
 }
 
 template <bool BF, int T>
-__global__ __launch_bounds__(256) void k_wgrad(Geo g, const float* __restrict__ X, const void* __restrict__ H,
+__global__ __launch_bounds__(WG_THREADS) void k_wgrad(Geo g, const float* __restrict__ X, const void* __restrict__ H,
                                                const void* __restrict__ DZ, const void* __restrict__ DH,
                                                float* __restrict__ part, long long chunk) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[WgradLds<T>::BYTES];
@@ -886,8 +893,8 @@ __global__ __launch_bounds__(256) void k_wgrad(Geo g, const float* __restrict__ 
   float* out = part + (size_t)blockIdx.z * g.nparams;
   const int wv = threadIdx.x >> 6;
   // tile columns of this wave inside the block: 2wv, 2wv+1 (fewer at the edge)
-  const int ncol = min(2, max(0, T - 2 * wv));
-  if (ncol == 2) wgrad_tiles<BF, T, 2>(g, J, R0, C0, p0, p1, smem, out);
+  const int ncol = min(WG_CPW, max(0, T - WG_CPW * wv));
+  if (WG_CPW == 2 && ncol == 2) wgrad_tiles<BF, T, WG_CPW>(g, J, R0, C0, p0, p1, smem, out);
   else if (ncol == 1) wgrad_tiles<BF, T, 1>(g, J, R0, C0, p0, p1, smem, out);
   else wgrad_tiles<BF, T, 0>(g, J, R0, C0, p0, p1, smem, out);
 }
@@ -1211,7 +1218,7 @@ static void wgrad_inst(const Geo& g, const float* X, const void* H, const void* 
   const unsigned groups = (unsigned)(((rmax + 16 * T - 1) / (16 * T)) * ((cmax + 16 * T - 1) / (16 * T)));
   const unsigned jobs = 1u + (unsigned)(g.N - 1) * (unsigned)(g.L + 1);
   dim3 grid(jobs, groups, splits);
-  k_wgrad<BF, T><<<grid, 256, 0, s>>>(g, X, H, DZ, DH, part, chunk);
+  k_wgrad<BF, T><<<grid, WG_THREADS, 0, s>>>(g, X, H, DZ, DH, part, chunk);
 }
 
 hipError_t launch_wgrad(const Geo& g, const float* X, const void* H, const void* DZ, const void* DH,
