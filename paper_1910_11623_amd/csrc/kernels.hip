@@ -332,8 +332,12 @@ __device__ __forceinline__ void stage_weights(unsigned char* dst, const void* sr
 // LDSW = false: one 16-path tile per wave, fragments read from global memory.
 // LDSW = true : the workgroup stages step n's fragments in LDS once, then each
 //               of its waves streams `tpw` tiles of 16 paths through them.
+// Waves per workgroup of the LDS-staged forward kernel (one workgroup per
+// CU): 3 per SIMD for shapes up to 8 x 8 tiles (<= 170 VGPRs), else 2.
+constexpr int fwd_waves(int ti, int tw) { return (ti <= 8 && tw <= 8) ? 12 : 8; }
+
 template <bool BF, int TI, int TW, bool LDSW>
-__global__ __launch_bounds__(LDSW ? 512 : 256) void k_forward(Geo g, const float* __restrict__ params,
+__global__ __launch_bounds__(LDSW ? 64 * fwd_waves(TI, TW) : 256) void k_forward(Geo g, const float* __restrict__ params,
                                                                const void* __restrict__ packF,
                                                                const float* __restrict__ pbias,
                                                                const float* __restrict__ X,
@@ -361,51 +365,20 @@ __global__ __launch_bounds__(LDSW ? 512 : 256) void k_forward(Geo g, const float
     pk = reinterpret_cast<const char*>(packF) + (size_t)(n > 0 ? n - 1 : 0) * g.packf_step * esz;
     bp = pbias + (size_t)(n > 0 ? n - 1 : 0) * g.pbias_step;
   }
-  // X_n rows of the next tile are fetched while the current tile computes;
-  // s_n rows are fetched at the start of their tile (used in the epilogue).
+  // rows of X_n are loaded at the start of their tile, rows of s_n in the
+  // epilogue; the other waves of the SIMD cover the latency
   const float* Xn = X + n * rowM;
   float* Vn = V + n * rowM;
-  f32x4 xin[TI];
-  if constexpr (TI <= 8) {
-    const int p0 = ((blockIdx.x * tpw) * nwv + wv) * 16 + col;
-#pragma unroll
-    for (int t = 0; t < TI; ++t) {
-      const int c0 = 16 * t + 4 * grp;
-      xin[t] = (n > 0 && p0 < g.M && c0 < g.dp) ? ld4(Xn + (size_t)p0 * g.dp + c0) : zero4();
-    }
-  }
   for (int it = 0; it < tpw; ++it) {
   const int tile = (blockIdx.x * tpw + it) * nwv + wv;
   if (tile * 16 >= g.M) break;
   const int p = tile * 16 + col;
   const bool valid = p < g.M;
-  // Prefetching keeps two extra tiles of rows in registers; the 16-tile
-  // shapes load just in time instead.
-  constexpr bool PF = TI <= 8;
-  f32x4 sv[TI], xv[TI];
-  if constexpr (PF) {
+  f32x4 xv[TI];
 #pragma unroll
-    for (int t = 0; t < TI; ++t) {
-      const int c0 = 16 * t + 4 * grp;
-      sv[t] = (valid && c0 < g.dp) ? ld4(Vn + (size_t)p * g.dp + c0) : zero4();
-    }
-  }
-  if (n == 0 || !PF) {
-#pragma unroll
-    for (int t = 0; t < TI; ++t) {
-      const int c0 = 16 * t + 4 * grp;
-      xv[t] = (valid && c0 < g.dp) ? ld4(Xn + (size_t)p * g.dp + c0) : zero4();
-    }
-  } else if constexpr (PF) {
-#pragma unroll
-    for (int t = 0; t < TI; ++t) xv[t] = xin[t];
-    const int pn = p + 16 * nwv;
-    const bool nxt = it + 1 < tpw && pn - col < g.M;
-#pragma unroll
-    for (int t = 0; t < TI; ++t) {
-      const int c0 = 16 * t + 4 * grp;
-      xin[t] = (nxt && pn < g.M && c0 < g.dp) ? ld4(Xn + (size_t)pn * g.dp + c0) : zero4();
-    }
+  for (int t = 0; t < TI; ++t) {
+    const int c0 = 16 * t + 4 * grp;
+    xv[t] = (valid && c0 < g.dp) ? ld4(Xn + (size_t)p * g.dp + c0) : zero4();
   }
   f32x4 Z[TI];
   if (n == 0) {
@@ -451,10 +424,10 @@ __global__ __launch_bounds__(LDSW ? 512 : 256) void k_forward(Geo g, const float
     const int c0 = 16 * t + 4 * grp;
     if (valid && c0 < g.dp) {
       float* vp = Vn + (size_t)p * g.dp + c0;
-      const f32x4 s = PF ? sv[t] : ld4(vp);
+      const f32x4 s = ld4(vp);
       f32x4 v = s;
       if (g.drv == DRV_BSB) {
-        const f32x4 x = PF ? xv[t] : ld4(Xn + (size_t)p * g.dp + c0);
+        const f32x4 x = xv[t];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           cz += Z[t][r] * s[r];
@@ -1082,7 +1055,7 @@ bool lds_fits(const Geo& g) {
          (size_t)g.packb_step * esz <= kLdsLimit;
 }
 
-int auto_tiles_per_wave(const Geo& g) { return tiles_per_wave(g, 8, num_cus()); }
+int auto_tiles_per_wave(const Geo& g) { return tiles_per_wave(g, fwd_waves(g.ti, g.tw), num_cus()); }
 
 template <bool BF, int TI, int TW>
 static void fwd_inst(const Geo& g, const float* params, const void* packF, const float* pbias, const float* X,
@@ -1095,7 +1068,7 @@ static void fwd_inst(const Geo& g, const float* params, const void* packF, const
       return true;
     }();
     (void)attr;
-    constexpr int NW = 8;
+    constexpr int NW = fwd_waves(TI, TW);
     const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, NW, num_cus());
     dim3 grid((unsigned)(((g.M + 15) / 16 + NW * tpw - 1) / (NW * tpw)), g.N);
     k_forward<BF, TI, TW, true><<<grid, 64 * NW, bytes, s>>>(g, params, packF, pbias, X, V, C, H, tpw);
