@@ -149,23 +149,23 @@ __device__ __forceinline__ f32x4 normals4(uint64_t seed, uint64_t iter, int j, i
 //   bf16: elem ((T*Ti/2 + kb)*64 + lane)*8 + j <- A[16T + lane%16][32kb + 16(j/4) + 4(lane/16) + j%4]
 // (A = W for the forward, A = W^T for the backward.)
 __device__ __forceinline__ float packed_value(const float* W, int rows, int cols, bool trans, int To,
-                                              int Ti, long long e, bool bf) {
+                                              int Ti, int e, bool bf) {
   int row, col;
   if (!bf) {
-    const int r = (int)(e & 3);
-    const long long q = e >> 2;
-    const int lane = (int)(q & 63);
-    const long long tt = q >> 6;
-    const int t = (int)(tt % Ti), T = (int)(tt / Ti);
+    const int r = e & 3;
+    const int q = e >> 2;
+    const int lane = q & 63;
+    const int tt = q >> 6;
+    const int t = tt % Ti, T = tt / Ti;
     row = 16 * T + (lane & 15);
     col = 16 * t + 4 * (lane >> 4) + r;
   } else {
-    const int j = (int)(e & 7);
-    const long long q = e >> 3;
-    const int lane = (int)(q & 63);
-    const long long tt = q >> 6;
+    const int j = e & 7;
+    const int q = e >> 3;
+    const int lane = q & 63;
+    const int tt = q >> 6;
     const int nkb = Ti / 2;
-    const int kb = (int)(tt % nkb), T = (int)(tt / nkb);
+    const int kb = tt % nkb, T = tt / nkb;
     row = 16 * T + (lane & 15);
     col = 32 * kb + 16 * (j >> 2) + 4 * (lane >> 4) + (j & 3);
   }
@@ -175,59 +175,59 @@ __device__ __forceinline__ float packed_value(const float* W, int rows, int cols
   return trans ? W[(long long)col * cols + row] : W[(long long)row * cols + col];
 }
 
+// One row of workgroups per step (blockIdx.y = n - 1); 32-bit indices
+// inside a step's packed block.
 __global__ __launch_bounds__(256) void k_pack(Geo g, const float* __restrict__ params,
                                               void* __restrict__ packF, void* __restrict__ packB,
                                               float* __restrict__ pbias) {
-  const long long per = g.packf_step + g.packb_step + g.pbias_step;
-  const long long total = (long long)(g.N - 1) * per;
+  const int per = (int)(g.packf_step + g.packb_step + g.pbias_step);
+  const int pf = (int)g.packf_step, pb = (int)g.packb_step;
   const bool bf = g.bf16;
-  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
-    const int n = 1 + (int)(e / per);
-    long long q = e % per;
-    const float* base = params + g.d + (long long)(n - 1) * g.pstep;
-    const long long lw1 = (long long)g.w * g.d + g.w, lwh = (long long)g.w * g.w + g.w;
-    if (q >= g.packf_step + g.packb_step) {  // biases, zero padded: b_1..b_L (16 tw each), b_o (16 ti)
-      const long long qb = q - g.packf_step - g.packb_step;
-      const long long hb = 16LL * g.tw;
+  const int n = 1 + (int)blockIdx.y;
+  const float* base = params + g.d + (long long)(n - 1) * g.pstep;
+  const int lw1 = g.w * g.d + g.w, lwh = g.w * g.w + g.w;
+  const int sz_in = 256 * g.tw * g.ti, sz_h = 256 * g.tw * g.tw, sz_o = 256 * g.ti * g.tw;
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < per; q += gridDim.x * 256) {
+    if (q >= pf + pb) {  // biases, zero padded: b_1..b_L (16 tw each), b_o (16 ti)
+      const int qb = q - pf - pb;
+      const int hb = 16 * g.tw;
       float val = 0.f;
-      if (qb < (long long)g.L * hb) {
-        const int l = 1 + (int)(qb / hb), i = (int)(qb % hb);
-        const float* bl = base + (l == 1 ? (long long)g.w * g.d : lw1 + (long long)(l - 2) * lwh + (long long)g.w * g.w);
+      if (qb < g.L * hb) {
+        const int l = 1 + qb / hb, i = qb % hb;
+        const float* bl = base + (l == 1 ? g.w * g.d : lw1 + (l - 2) * lwh + g.w * g.w);
         if (i < g.w) val = bl[i];
       } else {
-        const int i = (int)(qb - (long long)g.L * hb);
-        if (i < g.d) val = base[lw1 + (long long)(g.L - 1) * lwh + (long long)g.d * g.w + i];
+        const int i = qb - g.L * hb;
+        if (i < g.d) val = base[lw1 + (g.L - 1) * lwh + g.d * g.w + i];
       }
       pbias[(long long)(n - 1) * g.pbias_step + qb] = val;
       continue;
     }
-    const long long sz_in = 256LL * g.tw * g.ti, sz_h = 256LL * g.tw * g.tw, sz_o = 256LL * g.ti * g.tw;
     float val;
-    long long out_idx;
-    if (q < g.packf_step) {  // forward: W1, W2..WL, Wo
-      out_idx = (long long)(n - 1) * g.packf_step + q;
+    if (q < pf) {  // forward: W1, W2..WL, Wo
       if (q < sz_in) {
         val = packed_value(base, g.w, g.d, false, g.tw, g.ti, q, bf);
-      } else if (q < sz_in + (long long)(g.L - 1) * sz_h) {
-        const long long qq = q - sz_in;
-        const int l = 2 + (int)(qq / sz_h);
-        val = packed_value(base + lw1 + (long long)(l - 2) * lwh, g.w, g.w, false, g.tw, g.tw, qq % sz_h, bf);
+      } else if (q < sz_in + (g.L - 1) * sz_h) {
+        const int qq = q - sz_in;
+        const int l = 2 + qq / sz_h;
+        val = packed_value(base + lw1 + (l - 2) * lwh, g.w, g.w, false, g.tw, g.tw, qq % sz_h, bf);
       } else {
-        const long long qq = q - sz_in - (long long)(g.L - 1) * sz_h;
-        val = packed_value(base + lw1 + (long long)(g.L - 1) * lwh, g.d, g.w, false, g.ti, g.tw, qq, bf);
+        const int qq = q - sz_in - (g.L - 1) * sz_h;
+        val = packed_value(base + lw1 + (g.L - 1) * lwh, g.d, g.w, false, g.ti, g.tw, qq, bf);
       }
+      const long long out_idx = (long long)(n - 1) * g.packf_step + q;
       if (bf) reinterpret_cast<uint16_t*>(packF)[out_idx] = (uint16_t)bf16_bits(val);
       else reinterpret_cast<float*>(packF)[out_idx] = val;
     } else {  // backward: Wo^T (for delta_L), then W_{l+1}^T for delta_l, l = 1..L-1
-      q -= g.packf_step;
-      out_idx = (long long)(n - 1) * g.packb_step + q;
-      if (q < sz_o) {
-        val = packed_value(base + lw1 + (long long)(g.L - 1) * lwh, g.d, g.w, true, g.tw, g.ti, q, bf);
+      const int qb = q - pf;
+      if (qb < sz_o) {
+        val = packed_value(base + lw1 + (g.L - 1) * lwh, g.d, g.w, true, g.tw, g.ti, qb, bf);
       } else {
-        const long long qq = q - sz_o;
-        const int l = 1 + (int)(qq / sz_h);  // delta_l uses W_{l+1}
-        val = packed_value(base + lw1 + (long long)(l - 1) * lwh, g.w, g.w, true, g.tw, g.tw, qq % sz_h, bf);
+        const int qq = qb - sz_o;
+        const int l = 1 + qq / sz_h;  // delta_l uses W_{l+1}
+        val = packed_value(base + lw1 + (l - 1) * lwh, g.w, g.w, true, g.tw, g.tw, qq % sz_h, bf);
       }
+      const long long out_idx = (long long)(n - 1) * g.packb_step + qb;
       if (bf) reinterpret_cast<uint16_t*>(packB)[out_idx] = (uint16_t)bf16_bits(val);
       else reinterpret_cast<float*>(packB)[out_idx] = val;
     }
@@ -926,13 +926,34 @@ __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p
   const double c1d = corr[0], c2d = corr[1];
   const float c1 = (float)c1d, c2 = (float)c2d;
   const long long i0 = blockIdx.x * 256LL + threadIdx.x;
-  for (long long i = i0; i < n; i += (long long)gridDim.x * 256) {
-    const float gi = gr[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  auto upd = [&](float pi, float gi, float& mi, float& vi) {
+    mi = b1 * mi + (1.f - b1) * gi;
+    vi = b2 * vi + (1.f - b2) * gi * gi;
+    return pi - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  };
+  // 4 elements per thread when the four arrays are 16-byte aligned, then the tail
+  const bool vec = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(gr) |
+                     reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v)) & 15) == 0;
+  const long long n4 = vec ? n / 4 : 0;
+  for (long long i = i0; i < n4; i += (long long)gridDim.x * 256) {
+    f32x4 P4 = reinterpret_cast<const f32x4*>(p)[i], G4 = reinterpret_cast<const f32x4*>(gr)[i];
+    f32x4 M4 = reinterpret_cast<const f32x4*>(m)[i], V4 = reinterpret_cast<const f32x4*>(v)[i];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float mi = M4[r], vi = V4[r];
+      P4[r] = upd(P4[r], G4[r], mi, vi);
+      M4[r] = mi;
+      V4[r] = vi;
+    }
+    reinterpret_cast<f32x4*>(m)[i] = M4;
+    reinterpret_cast<f32x4*>(v)[i] = V4;
+    reinterpret_cast<f32x4*>(p)[i] = P4;
+  }
+  for (long long i = 4 * n4 + i0; i < n; i += (long long)gridDim.x * 256) {
+    float mi = m[i], vi = v[i];
+    p[i] = upd(p[i], gr[i], mi, vi);
     m[i] = mi;
     v[i] = vi;
-    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
   }
   if (i0 == 0 && y0) {
     const double gi = gy0[0];
@@ -1008,8 +1029,9 @@ static inline unsigned grid1(long long n, long long cap = 65536) {
 hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* packB, float* pbias,
                        hipStream_t s) {
   if (g.N < 2) return hipSuccess;
-  const long long total = (long long)(g.N - 1) * (g.packf_step + g.packb_step + g.pbias_step);
-  k_pack<<<grid1(total), 256, 0, s>>>(g, params, packF, packB, pbias);
+  const long long per = g.packf_step + g.packb_step + g.pbias_step;
+  dim3 grid(grid1(per, 1024), (unsigned)(g.N - 1));
+  k_pack<<<grid, 256, 0, s>>>(g, params, packF, packB, pbias);
   return hipGetLastError();
 }
 
