@@ -31,9 +31,10 @@
  *     (in the reductions of fbsde_forward / fbsde_forward_backward) and
  *     raises a flag in pinned host memory owned by the plan.  The next hot
  *     call on that plan (fbsde_forward, fbsde_forward_backward,
- *     fbsde_adam_step) returns FBSDE_ERR_NONFINITE without launching
- *     anything and clears the flag; no call synchronises to check it, so the
- *     report arrives once the offending work has completed.
+ *     fbsde_adam_step, or fbsde_batch_step of a batch that holds it) returns
+ *     FBSDE_ERR_NONFINITE without launching anything and clears the flag; no
+ *     call synchronises to check it, so the report arrives once the
+ *     offending work has completed.
  *   - Float parameters are one flat fp32 buffer (layout below); Y_0 is a
  *     separate fp64 scalar on the device.
  *

@@ -954,6 +954,9 @@ fbsde_status fbsde_batch_create(const fbsde_batch_item* items, int32_t n, double
 
 fbsde_status fbsde_batch_step(fbsde_batch* b, void* stream) {
   if (!b || !b->exec) return fail(FBSDE_ERR_INVALID, "batch is NULL");
+  // a non-finite result of an earlier step of any instance (see the plans' flags)
+  for (const fbsde_batch_item& it : b->items)
+    if (fbsde_status st = take_nonfinite(it.plan); st != FBSDE_OK) return st;
   hipError_t e = hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return FBSDE_OK;

@@ -120,3 +120,30 @@ def test_batch_first_step_matches_oracle():
         g = s.grad.cpu().numpy().astype(np.float64)
         worst = max(blockwise_rel(prob, net, N, g, ref["grad"]).values())
         assert worst <= 1e-2, (prob["d"], N, worst)
+
+
+def test_batch_step_reports_a_nonfinite_instance():
+    """A NaN weight in one instance: the graph step that computes it runs,
+    the next batch step returns FBSDE_ERR_NONFINITE without launching, and
+    the step after that runs again."""
+    import paper_1910_11623_amd.binding as B
+    shapes = [(20, 10), (33, 5)]
+    insts = _ac_states(shapes, 64, "bf16")
+    states = [TrainState(plan, p, 0.3) for (_, _, _, p, plan) in insts]
+    batch = Batch(states, [1, 2])
+    batch.step()
+    torch.cuda.synchronize()
+    states[1].params[5] = float("nan")
+    batch.step()
+    torch.cuda.synchronize()
+    with pytest.raises(B.FbsdeError) as ei:
+        batch.step()
+    assert ei.value.status == B.ERR_NONFINITE
+    assert int(batch.iter.item()) == 2   # the refused step launched nothing
+    states[1].params.copy_(torch.from_numpy(insts[1][3]).to(states[1].params.device))
+    for t in (states[1].m, states[1].v, states[1].my0, states[1].vy0):
+        t.zero_()
+    states[1].y0.fill_(0.3)
+    batch.step()
+    torch.cuda.synchronize()
+    assert int(batch.iter.item()) == 3
