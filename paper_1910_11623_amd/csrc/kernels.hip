@@ -1047,15 +1047,18 @@ hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t ite
 }
 
 // Tiles of 16 paths per wave for the LDS-resident kernels: the count that
-// minimises the makespan ceil(workgroups / CUs) * tiles, one workgroup per CU.
+// minimises the makespan ceil(workgroups / CUs) * (tiles + staging), one
+// workgroup per CU.
 static int tiles_per_wave(const Geo& g, int waves, int cus) {
+  // every workgroup first stages its step's weights in LDS, about a quarter
+  // of a tile's work: span = rounds * (t + 1/4), in quarter tiles
   const long long tiles = (g.M + 15) / 16;
   int best = 1;
   long long best_span = -1;
   for (int t = 1; t <= 64; ++t) {
     const long long gx = (tiles + (long long)waves * t - 1) / ((long long)waves * t);
     const long long wgs = gx * g.N;
-    const long long span = ((wgs + cus - 1) / cus) * t;
+    const long long span = ((wgs + cus - 1) / cus) * (4LL * t + 1);
     if (best_span < 0 || span < best_span) { best_span = span; best = t; }
   }
   return best;
