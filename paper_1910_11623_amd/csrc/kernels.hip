@@ -178,17 +178,43 @@ __device__ __forceinline__ float packed_value(const float* W, int rows, int cols
 }
 
 // One row of workgroups per step (blockIdx.y = n - 1); 32-bit indices
-// inside a step's packed block.
+// inside a step's packed block.  A thread produces one packed group (4 fp32
+// or 8 bf16 elements: the register fragment of one lane) and stores it as
+// one vector.
+template <bool BF>
+__device__ __forceinline__ void pack_group(const float* W, int rows, int cols, bool trans, int To, int Ti,
+                                           int e0, void* dst) {
+  constexpr int G = BF ? 8 : 4;
+  float v[G];
+#pragma unroll
+  for (int k = 0; k < G; ++k) v[k] = packed_value(W, rows, cols, trans, To, Ti, e0 + k, BF);
+  if constexpr (BF) {
+    uint4 u;
+    u.x = bf16_bits(v[0]) | (bf16_bits(v[1]) << 16);
+    u.y = bf16_bits(v[2]) | (bf16_bits(v[3]) << 16);
+    u.z = bf16_bits(v[4]) | (bf16_bits(v[5]) << 16);
+    u.w = bf16_bits(v[6]) | (bf16_bits(v[7]) << 16);
+    *reinterpret_cast<uint4*>(dst) = u;
+  } else {
+    *reinterpret_cast<f32x4*>(dst) = f32x4{v[0], v[1], v[2], v[3]};
+  }
+}
+
+template <bool BF>
 __global__ __launch_bounds__(256) void k_pack(Geo g, const float* __restrict__ params,
                                               void* __restrict__ packF, void* __restrict__ packB,
                                               float* __restrict__ pbias) {
-  const int per = (int)(g.packf_step + g.packb_step + g.pbias_step);
-  const int pf = (int)g.packf_step, pb = (int)g.packb_step;
-  const bool bf = g.bf16;
+  constexpr int G = BF ? 8 : 4;          // elements per packed group
+  constexpr int ESZ = BF ? 2 : 4;
+  const int pf = (int)g.packf_step / G, pb = (int)g.packb_step / G;  // groups (every block is whole groups)
+  const int nb = (int)g.pbias_step;
+  const int per = pf + pb + nb;
   const int n = 1 + (int)blockIdx.y;
   const float* base = params + g.d + (long long)(n - 1) * g.pstep;
   const int lw1 = g.w * g.d + g.w, lwh = g.w * g.w + g.w;
   const int sz_in = 256 * g.tw * g.ti, sz_h = 256 * g.tw * g.tw, sz_o = 256 * g.ti * g.tw;
+  char* F = reinterpret_cast<char*>(packF) + (size_t)(n - 1) * g.packf_step * ESZ;
+  char* Bk = reinterpret_cast<char*>(packB) + (size_t)(n - 1) * g.packb_step * ESZ;
   for (int q = blockIdx.x * 256 + threadIdx.x; q < per; q += gridDim.x * 256) {
     if (q >= pf + pb) {  // biases, zero padded: b_1..b_L (16 tw each), b_o (16 ti)
       const int qb = q - pf - pb;
@@ -205,33 +231,29 @@ __global__ __launch_bounds__(256) void k_pack(Geo g, const float* __restrict__ p
       pbias[(long long)(n - 1) * g.pbias_step + qb] = val;
       continue;
     }
-    float val;
     if (q < pf) {  // forward: W1, W2..WL, Wo
-      if (q < sz_in) {
-        val = packed_value(base, g.w, g.d, false, g.tw, g.ti, q, bf);
-      } else if (q < sz_in + (g.L - 1) * sz_h) {
-        const int qq = q - sz_in;
+      const int e = q * G;
+      char* dst = F + (size_t)e * ESZ;
+      if (e < sz_in) {
+        pack_group<BF>(base, g.w, g.d, false, g.tw, g.ti, e, dst);
+      } else if (e < sz_in + (g.L - 1) * sz_h) {
+        const int qq = e - sz_in;
         const int l = 2 + qq / sz_h;
-        val = packed_value(base + lw1 + (l - 2) * lwh, g.w, g.w, false, g.tw, g.tw, qq % sz_h, bf);
+        pack_group<BF>(base + lw1 + (l - 2) * lwh, g.w, g.w, false, g.tw, g.tw, qq % sz_h, dst);
       } else {
-        const int qq = q - sz_in - (g.L - 1) * sz_h;
-        val = packed_value(base + lw1 + (g.L - 1) * lwh, g.d, g.w, false, g.ti, g.tw, qq, bf);
+        const int qq = e - sz_in - (g.L - 1) * sz_h;
+        pack_group<BF>(base + lw1 + (g.L - 1) * lwh, g.d, g.w, false, g.ti, g.tw, qq, dst);
       }
-      const long long out_idx = (long long)(n - 1) * g.packf_step + q;
-      if (bf) reinterpret_cast<uint16_t*>(packF)[out_idx] = (uint16_t)bf16_bits(val);
-      else reinterpret_cast<float*>(packF)[out_idx] = val;
     } else {  // backward: Wo^T (for delta_L), then W_{l+1}^T for delta_l, l = 1..L-1
-      const int qb = q - pf;
-      if (qb < sz_o) {
-        val = packed_value(base + lw1 + (g.L - 1) * lwh, g.d, g.w, true, g.tw, g.ti, qb, bf);
+      const int e = (q - pf) * G;
+      char* dst = Bk + (size_t)e * ESZ;
+      if (e < sz_o) {
+        pack_group<BF>(base + lw1 + (g.L - 1) * lwh, g.d, g.w, true, g.tw, g.ti, e, dst);
       } else {
-        const int qq = qb - sz_o;
+        const int qq = e - sz_o;
         const int l = 1 + qq / sz_h;  // delta_l uses W_{l+1}
-        val = packed_value(base + lw1 + (l - 1) * lwh, g.w, g.w, true, g.tw, g.tw, qq % sz_h, bf);
+        pack_group<BF>(base + lw1 + (l - 1) * lwh, g.w, g.w, true, g.tw, g.tw, qq % sz_h, dst);
       }
-      const long long out_idx = (long long)(n - 1) * g.packb_step + qb;
-      if (bf) reinterpret_cast<uint16_t*>(packB)[out_idx] = (uint16_t)bf16_bits(val);
-      else reinterpret_cast<float*>(packB)[out_idx] = val;
     }
   }
 }
@@ -1031,9 +1053,11 @@ static inline unsigned grid1(long long n, long long cap = 65536) {
 hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* packB, float* pbias,
                        hipStream_t s) {
   if (g.N < 2) return hipSuccess;
-  const long long per = g.packf_step + g.packb_step + g.pbias_step;
+  const int G = g.bf16 ? 8 : 4;
+  const long long per = (g.packf_step + g.packb_step) / G + g.pbias_step;
   dim3 grid(grid1(per, 1024), (unsigned)(g.N - 1));
-  k_pack<<<grid, 256, 0, s>>>(g, params, packF, packB, pbias);
+  if (g.bf16) k_pack<true><<<grid, 256, 0, s>>>(g, params, packF, packB, pbias);
+  else k_pack<false><<<grid, 256, 0, s>>>(g, params, packF, packB, pbias);
   return hipGetLastError();
 }
 
