@@ -127,7 +127,7 @@ void make_layout(fbsde_plan* P) {
   splits = (int)(((long long)M + chunk - 1) / chunk);
   w.splits = splits;
   w.chunk = chunk;
-  w.PART = take((size_t)splits * (size_t)g.nparams * 4);
+  w.PART = take((size_t)splits * (size_t)g.pstride * 4);
   w.scan_blocks = (int)((M + 255) / 256);
   w.RED = take((size_t)w.scan_blocks * 2 * 8 + 64);
   w.total = off;
@@ -464,9 +464,11 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   if (resnet) {
     g.pstep = 0;
     g.nparams = w * (d + 1) + w + L * (w * w + w) + d * w + d;
+    g.pstride = (g.nparams + 3) / 4 * 4;
   } else {
     g.pstep = w * d + w + (L - 1) * (w * w + w) + d * w + d;
     g.nparams = d + (long long)(N - 1) * g.pstep;
+    g.pstride = (g.nparams + 3) / 4 * 4;
   }
   P->ws.splits = 0;
   make_layout(P);

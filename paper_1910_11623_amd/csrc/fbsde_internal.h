@@ -25,6 +25,7 @@ struct Geo {
   float dt, sqdt;
   long long pstep;        // fp32 parameters per time step (per-step MLP)
   long long nparams;      // total fp32 parameters
+  long long pstride;      // floats between two gradient-split partial copies: nparams rounded up to 4
   long long packf_step;   // packed forward fragments per step (elements)
   long long packb_step;   // packed backward fragments per step (elements)
   long long pbias_step;   // padded fp32 biases per step: L * 16 tw + 16 ti

@@ -887,7 +887,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_wgrad(Geo g, const float* __rest
   const int R0 = (blockIdx.y / ngc) * 16 * T, C0 = (blockIdx.y % ngc) * 16 * T;
   const long long p0 = (long long)blockIdx.z * chunk;
   const long long p1 = min((long long)g.M, p0 + chunk);
-  float* out = part + (size_t)blockIdx.z * g.nparams;
+  float* out = part + (size_t)blockIdx.z * g.pstride;
   const int wv = threadIdx.x >> 6;
   // tile columns of this wave inside the block: 2wv, 2wv+1 (fewer at the edge)
   const int ncol = min(WG_CPW, max(0, T - WG_CPW * wv));
@@ -897,12 +897,22 @@ __global__ __launch_bounds__(WG_THREADS) void k_wgrad(Geo g, const float* __rest
 }
 
 // ------------------------------------------------------------ reduce kernel
-__global__ __launch_bounds__(256) void k_reduce(long long P, const float* __restrict__ part, int splits,
-                                                float* __restrict__ grad, int* __restrict__ nf) {
+// grad[e] = sum over splits k (in order) of part[k * stride + e]; 4 elements
+// per thread when grad is 16-byte aligned (the partial copies always are).
+__global__ __launch_bounds__(256) void k_reduce(long long P, long long stride, const float* __restrict__ part,
+                                                int splits, float* __restrict__ grad, int* __restrict__ nf) {
   bool bad = false;
-  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < P; e += (long long)gridDim.x * 256) {
+  const long long t0 = blockIdx.x * 256LL + threadIdx.x, step = (long long)gridDim.x * 256;
+  const long long P4 = (reinterpret_cast<uintptr_t>(grad) & 15) == 0 ? P / 4 : 0;
+  for (long long e4 = t0; e4 < P4; e4 += step) {
+    f32x4 s = zero4();
+    for (int k = 0; k < splits; ++k) s += ld4(part + (size_t)k * stride + 4 * e4);
+    st4(grad + 4 * e4, s);
+    bad |= !(isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2]) && isfinite(s[3]));
+  }
+  for (long long e = 4 * P4 + t0; e < P; e += step) {
     float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part[(size_t)k * P + e];
+    for (int k = 0; k < splits; ++k) s += part[(size_t)k * stride + e];
     grad[e] = s;
     bad |= !isfinite(s);
   }
@@ -1267,7 +1277,7 @@ static int* nf_flag(double* scan_part, int scan_blocks) {
 hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* grad, double* scan_part,
                          int scan_blocks, double* loss, double* grad_y0, int* host_flag, hipStream_t s) {
   int* nf = nf_flag(scan_part, scan_blocks);
-  k_reduce<<<grid1(g.nparams, 4096), 256, 0, s>>>(g.nparams, part, splits, grad, nf);
+  k_reduce<<<grid1((g.nparams + 3) / 4, 4096), 256, 0, s>>>(g.nparams, g.pstride, part, splits, grad, nf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_finalize<<<1, 256, 0, s>>>(g.M, scan_part, scan_blocks, loss, grad_y0, nf, host_flag);

@@ -736,7 +736,7 @@ hipError_t resnet_backward(const Geo& g, const ResnetBufs& R0, const float* X, c
   const long long offbin = (long long)w * (d + 1), offk = offbin + w;
   const long long offo = offk + (long long)B * ((long long)w * w + w);
   hipError_t e;
-  k_fill<<<grid1((long long)splits * g.nparams, 16384), 256, 0, s>>>(part, (long long)splits * g.nparams);
+  k_fill<<<grid1((long long)splits * g.pstride, 16384), 256, 0, s>>>(part, (long long)splits * g.pstride);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int n0 = 0; n0 < g.N; n0 += g.rn_chunk) {
     const int ns = min(g.rn_chunk, g.N - n0);
@@ -760,7 +760,7 @@ hipError_t resnet_backward(const Geo& g, const ResnetBufs& R0, const float* X, c
     }
     {  // dW_o += zeta^T h_B, db_o += sum zeta
       Gm G = gm(R.zt, L.ldt, d, R.ht + (size_t)B * w * L.ldt, L.ldt, w, rows);
-      G.pstride = g.nparams;
+      G.pstride = g.pstride;
       Epi E = epi0(d, w);
       E.part = part; E.base = offo; E.wcols = w;
       if ((e = gemm<EPI_ACC, RN_TM, RN_TN>(G, E, d, w, splits, s)) != hipSuccess) return e;
@@ -768,7 +768,7 @@ hipError_t resnet_backward(const Geo& g, const ResnetBufs& R0, const float* X, c
     for (int k = B; k >= 1; --k) {
       {  // dW_k += g_k^T h_{k-1}, db_k += sum g_k
         Gm G = gm(gt[cur], L.ldt, w, R.ht + (size_t)(k - 1) * w * L.ldt, L.ldt, w, rows);
-        G.pstride = g.nparams;
+        G.pstride = g.pstride;
         Epi E = epi0(w, w);
         E.part = part; E.base = offk + (long long)(k - 1) * ((long long)w * w + w); E.wcols = w;
         if ((e = gemm<EPI_ACC, RN_TM, RN_TN>(G, E, w, w, splits, s)) != hipSuccess) return e;
@@ -785,7 +785,7 @@ hipError_t resnet_backward(const Geo& g, const ResnetBufs& R0, const float* X, c
     }
     {  // dW_in += g_0^T [x; t], db_in += sum g_0
       Gm G = gm(gt[cur], L.ldt, w, R.xt, L.ldt, d + 1, rows);
-      G.pstride = g.nparams;
+      G.pstride = g.pstride;
       Epi E = epi0(w, d + 1);
       E.part = part; E.base = 0; E.wcols = d + 1;
       if ((e = gemm<EPI_ACC, RN_TM, RN_TN>(G, E, w, d + 1, splits, s)) != hipSuccess) return e;
