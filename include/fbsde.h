@@ -202,6 +202,12 @@ fbsde_status fbsde_profile_read(fbsde_plan *plan, double *ms_host, int64_t *coun
  * Results are identical across shapes, LDS modes and tpw; the split count
  * changes the fp32 summation order of the weight gradient only. */
 fbsde_status fbsde_plan_config(fbsde_plan *plan, int32_t shape, int32_t lds, int32_t tpw, int32_t splits);
+/* Reports (FBSDE_ERR_NONFINITE) and clears the plan's non-finite flag
+ * without launching anything; synchronise the streams that ran the plan's
+ * work first to cover all of it.  FBSDE_OK if no non-finite result was
+ * seen since the last report. */
+fbsde_status fbsde_plan_status(fbsde_plan *plan);
+
 /* Activation checkpointing of the shared residual network (Sec. 3.1 network
  * trained through the unrolled chain).  Rows (step, path) are processed in
  * chunks of whole steps of about chunk_rows rows (0: 262144; at least one

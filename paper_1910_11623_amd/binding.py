@@ -25,7 +25,7 @@ EXPORTS = [
     "fbsde_forward", "fbsde_forward_backward", "fbsde_adam_step", "fbsde_prolong",
     "fbsde_sample_normals", "fbsde_terminal_mean", "fbsde_terminal_states",
     "fbsde_profile_enable", "fbsde_profile_read", "fbsde_plan_config", "fbsde_plan_get_config",
-    "fbsde_plan_autotune", "fbsde_plan_set_checkpointing", "fbsde_batch_create", "fbsde_batch_step", "fbsde_batch_destroy",
+    "fbsde_plan_autotune", "fbsde_plan_set_checkpointing", "fbsde_plan_status", "fbsde_batch_create", "fbsde_batch_step", "fbsde_batch_destroy",
     "fbsde_status_str", "fbsde_last_error",
 ]
 PROF_NAMES = ["pack", "sde", "forward", "scan", "backward", "wgrad", "reduce", "adam"]
@@ -72,6 +72,7 @@ def load(path: str = LIB_PATH):
     vp, u64, i64 = C.c_void_p, C.c_uint64, C.c_int64
     L.fbsde_plan_create.argtypes = [C.POINTER(Problem), C.POINTER(Net), C.c_int32, i64, C.POINTER(vp)]
     L.fbsde_plan_set_checkpointing.argtypes = [vp, C.c_int32, i64]
+    L.fbsde_plan_status.argtypes = [vp]
     L.fbsde_plan_destroy.argtypes = [vp]
     L.fbsde_plan_destroy.restype = None
     L.fbsde_param_count.argtypes = [vp, C.POINTER(i64)]

@@ -709,6 +709,11 @@ fbsde_status fbsde_plan_config(fbsde_plan* plan, int32_t shape, int32_t lds, int
   return FBSDE_OK;
 }
 
+fbsde_status fbsde_plan_status(fbsde_plan* plan) {
+  if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
+  return take_nonfinite(plan);
+}
+
 fbsde_status fbsde_plan_set_checkpointing(fbsde_plan* plan, int32_t recompute, int64_t chunk_rows) {
   if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
   if (chunk_rows < 0) return fail(FBSDE_ERR_INVALID, "chunk_rows must be >= 0");

@@ -143,6 +143,15 @@ class Plan:
     def config(self, shape: int = 0, lds: bool = True, tpw: int = 0, splits: int = 0):
         B.check(self.lib.fbsde_plan_config(self._h, int(shape), int(bool(lds)), int(tpw), int(splits)))
 
+    def finite_since_last_check(self) -> bool:
+        """Whether every loss and gradient since the last report was finite
+        (clears the report; synchronise first to cover queued work)."""
+        st = self.lib.fbsde_plan_status(self._h)
+        if st == B.ERR_NONFINITE:
+            return False
+        B.check(st)
+        return True
+
     def get_config(self) -> dict:
         c = (C.c_int32 * 6)()
         B.check(self.lib.fbsde_plan_get_config(self._h, c))

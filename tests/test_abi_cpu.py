@@ -84,3 +84,4 @@ def test_null_plan_calls(lib):
     assert lib.fbsde_param_count(None, C.byref(n)) == B.ERR_INVALID
     assert lib.fbsde_prolong(None, None, None, None, None) == B.ERR_INVALID
     assert lib.fbsde_plan_set_checkpointing(None, 1, 0) == B.ERR_INVALID
+    assert lib.fbsde_plan_status(None) == B.ERR_INVALID

@@ -239,3 +239,8 @@ def test_nonfinite_result_reported_by_next_call(kind):
     assert np.isfinite(float(loss.item())) and bool(torch.isfinite(g).all().item())
     plan.forward_backward(good, y0, 1, 5)     # still no report
     torch.cuda.synchronize()
+    assert plan.finite_since_last_check()
+    plan.forward_backward(bad, y0, 1, 6)
+    torch.cuda.synchronize()
+    assert not plan.finite_since_last_check()  # the status call reports and clears
+    assert plan.finite_since_last_check()
