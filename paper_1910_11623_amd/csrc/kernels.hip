@@ -728,16 +728,27 @@ __device__ __forceinline__ Job job_info(const Geo& g, int job, const float* X, c
   return J;
 }
 
-// LDS-staged weight-gradient GEMM.  Workgroup = (job, 128x128 output block
-// group, path split); it owns a T x T block of 16x16 output tiles and walks
-// its path range in chunks of 32 paths staged in LDS with 16-byte loads.
-// Wave w accumulates tile columns 2w and 2w+1 (the last wave may own one)
-// over all T tile rows.  Bias gradients ride along as an extra input column
-// of ones (column `cols`).
-#ifndef FBSDE_WG_KC
-#define FBSDE_WG_KC 32
+// LDS-staged weight-gradient GEMM.  Workgroup = (job, output block group,
+// path split); it owns a T x T block of 16x16 output tiles and walks its path
+// range in chunks staged in LDS.  Wave w accumulates tile column w over all T
+// tile rows (with T < 8 the last wave only stages).  Bias gradients ride along
+// as an extra input column of ones (column `cols`).
+//
+// Chunk length: the bf16 MFMA takes K = 32 paths per instruction, so the bf16
+// form stages 32 paths (transposed to k-contiguous rows); the fp32 form
+// (K = 4 per MFMA) stages 16, which halves its staging registers and keeps
+// more chunks in flight per CU.
+#ifndef FBSDE_WG_KC_F32
+#define FBSDE_WG_KC_F32 16
 #endif
-constexpr int WG_KC = FBSDE_WG_KC;  // paths per LDS chunk
+template <bool BF>
+constexpr int wg_kc() { return BF ? 32 : FBSDE_WG_KC_F32; }
+// The fp32 form loads the next chunk into registers while the MFMAs run on
+// the current one.  The bf16 form is bound by the HBM reads and the 2-byte
+// transposing LDS writes; prefetching there costs registers (two workgroups
+// per CU instead of three) and was slower, so it loads just before staging.
+template <bool BF>
+constexpr bool wg_prefetch() { return !BF; }
 // tile columns per wave of the weight-gradient kernel (its workgroup has
 // ceil(T / WG_CPW) <= 8 waves: 4 waves x 2 columns or 8 waves x 1 column)
 #ifndef FBSDE_WG_CPW
@@ -746,25 +757,19 @@ constexpr int WG_KC = FBSDE_WG_KC;  // paths per LDS chunk
 constexpr int WG_CPW = FBSDE_WG_CPW;
 constexpr int WG_THREADS = 64 * (8 / WG_CPW);
 
-template <int T>
+template <bool BF, int T>
 struct WgradLds {
+  static constexpr int KC = wg_kc<BF>();
   static constexpr int LDA = 16 * T + ((T % 2 == 0) ? 16 : 0);  // fp32 row stride (floats), == 16 mod 32
-  static constexpr int LDT = WG_KC + 4;                          // bf16 transposed row stride (elements)
-  static constexpr size_t F32_BYTES = 2ull * WG_KC * LDA * 4;
-  static constexpr size_t BF_BYTES = 2ull * 16 * T * LDT * 2;
-  static constexpr size_t BYTES = F32_BYTES > BF_BYTES ? F32_BYTES : BF_BYTES;
+  static constexpr int LDT = KC + 4;                             // bf16 transposed row stride (elements)
+  static constexpr size_t BYTES = BF ? 2ull * 16 * T * LDT * 2 : 2ull * KC * LDA * 4;
 };
 
-// 4 consecutive input columns c..c+3 of one path, with the bias column of
-// ones at `cols` and zeros beyond (src row holds `stride` valid entries)
-__device__ __forceinline__ f32x4 load_cols4(const void* base, bool f32src, bool bfsrc, size_t rowoff, int c,
-                                            int cols, int stride) {
+// 4 consecutive fp32 input columns c..c+3 of one path, with the bias column
+// of ones at `cols` and zeros beyond (src row holds `stride` valid entries)
+__device__ __forceinline__ f32x4 load_cols4(const float* base, size_t rowoff, int c, int cols, int stride) {
   f32x4 v = zero4();
-  if (c < stride) {
-    if (f32src) v = ld4(reinterpret_cast<const float*>(base) + rowoff + c);
-    else if (bfsrc) v = ld_act(base, rowoff + c, true);
-    else v = ld4(reinterpret_cast<const float*>(base) + rowoff + c);
-  }
+  if (c < stride) v = ld4(base + rowoff + c);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     if (c + e == cols) v[e] = 1.f;
@@ -773,14 +778,100 @@ __device__ __forceinline__ f32x4 load_cols4(const void* base, bool f32src, bool 
   return v;
 }
 
+// Staging of one chunk: KC paths of the deltas (A, rows R0..R0+16T) and
+// of the layer inputs (B, columns C0..C0+16T, bias column of ones), as
+// 4-element slots; slot s < NV is A, the rest B.  Each thread owns NS slots,
+// held as fp32 (f32x4) or, in the bf16 form, as packed bf16 bits (uint2).
+template <bool BF, int T>
+struct WgradStage {
+  static constexpr int NV = wg_kc<BF>() * 4 * T;
+  static constexpr int NS = (2 * NV + WG_THREADS - 1) / WG_THREADS;
+};
+template <bool BF> struct StageSlot { using type = f32x4; };
+template <> struct StageSlot<true> { using type = uint2; };
+
+// bf16 bits of 4 consecutive input columns c..c+3 of one path (bias column of
+// ones at `cols`, zeros beyond), from bf16 activations or the fp32 state X
+__device__ __forceinline__ uint2 load_cols4_bf(const void* base, bool f32src, size_t rowoff, int c, int cols,
+                                               int stride) {
+  uint32_t e[4] = {0u, 0u, 0u, 0u};
+  if (c < stride) {
+    if (f32src) {
+      const f32x4 v = ld4(reinterpret_cast<const float*>(base) + rowoff + c);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) e[i] = bf16_bits(v[i]);
+    } else {
+      const uint2 u = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(base) + rowoff + c);
+      e[0] = u.x & 0xffffu; e[1] = u.x >> 16; e[2] = u.y & 0xffffu; e[3] = u.y >> 16;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (c + i == cols) e[i] = 0x3f80u;  // 1.0
+    else if (c + i > cols) e[i] = 0u;
+  }
+  return uint2{e[0] | (e[1] << 16), e[2] | (e[3] << 16)};
+}
+
+template <bool BF, int T>
+__device__ __forceinline__ void wgrad_fetch(const Job& J, int R0, int C0, long long pc, long long p1, int tid,
+                                            typename StageSlot<BF>::type (&v)[WgradStage<BF, T>::NS]) {
+  constexpr int NV = WgradStage<BF, T>::NV;
+#pragma unroll
+  for (int k = 0; k < WgradStage<BF, T>::NS; ++k) {
+    const int s = tid + k * WG_THREADS;
+    if constexpr (BF) v[k] = uint2{0u, 0u};
+    else v[k] = zero4();
+    if (s >= 2 * NV) continue;
+    const bool isA = s < NV;
+    const int q = isA ? s : s - NV;
+    const int kp = q / (4 * T), c4 = q % (4 * T);
+    const long long p = pc + kp;
+    if (p >= p1) continue;
+    if (isA) {
+      const int r = R0 + 4 * c4;
+      if (r >= J.rows) continue;
+      if constexpr (BF) v[k] = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(J.A) + (size_t)p * J.sA + r);
+      else v[k] = ld4(reinterpret_cast<const float*>(J.A) + (size_t)p * J.sA + r);
+    } else {
+      // deltas and activations are stored in the GEMM precision; X is fp32 state
+      if constexpr (BF) v[k] = load_cols4_bf(J.B, J.Bf32, (size_t)p * J.sB, C0 + 4 * c4, J.cols, J.B ? J.sB : 0);
+      else v[k] = load_cols4(reinterpret_cast<const float*>(J.B), (size_t)p * J.sB, C0 + 4 * c4, J.cols, J.B ? J.sB : 0);
+    }
+  }
+}
+
+template <bool BF, int T>
+__device__ __forceinline__ void wgrad_put(unsigned char* smem, int tid,
+                                          const typename StageSlot<BF>::type (&v)[WgradStage<BF, T>::NS]) {
+  using L = WgradLds<BF, T>;
+  constexpr int NV = WgradStage<BF, T>::NV;
+#pragma unroll
+  for (int k = 0; k < WgradStage<BF, T>::NS; ++k) {
+    const int s = tid + k * WG_THREADS;
+    if (s >= 2 * NV) continue;
+    const bool isA = s < NV;
+    const int q = isA ? s : s - NV;
+    const int kp = q / (4 * T), c4 = q % (4 * T);
+    if constexpr (!BF) {
+      float* dst = reinterpret_cast<float*>(smem) + (isA ? 0 : L::KC * L::LDA) + kp * L::LDA + 4 * c4;
+      st4(dst, v[k]);
+    } else {
+      uint16_t* dst = reinterpret_cast<uint16_t*>(smem) + (isA ? 0 : 16 * T * L::LDT) + 4 * c4 * L::LDT + kp;
+      dst[0] = (uint16_t)(v[k].x & 0xffffu);
+      dst[L::LDT] = (uint16_t)(v[k].x >> 16);
+      dst[2 * L::LDT] = (uint16_t)(v[k].y & 0xffffu);
+      dst[3 * L::LDT] = (uint16_t)(v[k].y >> 16);
+    }
+  }
+}
+
 template <bool BF, int T, int CW>
 __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, int C0, long long p0,
                                             long long p1, unsigned char* smem, float* out_split) {
-  using L = WgradLds<T>;
+  using L = WgradLds<BF, T>;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int c16 = lane & 15, grp = lane >> 4;
-  const bool bfA = BF;               // deltas are stored in the GEMM precision
-  const bool bfB = BF && !J.Bf32;    // activations too; X is fp32 state
   constexpr int CWA = CW > 0 ? CW : 1;  // storage size (a wave with no tiles only stages)
   f32x4 acc[T][CWA];
 #pragma unroll
@@ -788,44 +879,21 @@ __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, 
 #pragma unroll
     for (int j = 0; j < CWA; ++j) acc[i][j] = zero4();
 
-  for (long long pc = p0; pc < p1; pc += WG_KC) {
+  typename StageSlot<BF>::type pre[WgradStage<BF, T>::NS];
+  if constexpr (wg_prefetch<BF>()) wgrad_fetch<BF, T>(J, R0, C0, p0, p1, tid, pre);
+  for (long long pc = p0; pc < p1; pc += L::KC) {
     __syncthreads();
-    // ---- stage A (deltas, rows R0..) and B (activations, cols C0..) chunks
-    constexpr int NV = WG_KC * 4 * T;  // float4 slots per operand chunk
-    for (int s = tid; s < 2 * NV; s += WG_THREADS) {
-      const bool isA = s < NV;
-      const int q = isA ? s : s - NV;
-      const int kp = q / (4 * T), c4 = q % (4 * T);
-      const long long p = pc + kp;
-      f32x4 v = zero4();
-      if (p < p1) {
-        if (isA) {
-          const int r = R0 + 4 * c4;
-          if (r < J.rows) {
-            v = bfA ? ld_act(J.A, (size_t)p * J.sA + r, true)
-                    : ld4(reinterpret_cast<const float*>(J.A) + (size_t)p * J.sA + r);
-          }
-        } else {
-          v = load_cols4(J.B, J.Bf32, bfB, (size_t)p * J.sB, C0 + 4 * c4, J.cols, J.B ? J.sB : 0);
-          if (BF && J.Bf32) v = round4(v, true);
-        }
-      }
-      if constexpr (!BF) {
-        float* dst = reinterpret_cast<float*>(smem) + (isA ? 0 : WG_KC * L::LDA) + kp * L::LDA + 4 * c4;
-        st4(dst, v);
-      } else {
-        uint16_t* dst = reinterpret_cast<uint16_t*>(smem) + (isA ? 0 : 16 * T * L::LDT);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) dst[(4 * c4 + e) * L::LDT + kp] = (uint16_t)bf16_bits(v[e]);
-      }
-    }
+    if constexpr (!wg_prefetch<BF>()) wgrad_fetch<BF, T>(J, R0, C0, pc, p1, tid, pre);
+    wgrad_put<BF, T>(smem, tid, pre);
     __syncthreads();
+    // the next chunk's loads are in flight during this chunk's MFMAs
+    if (wg_prefetch<BF>() && pc + L::KC < p1) wgrad_fetch<BF, T>(J, R0, C0, pc + L::KC, p1, tid, pre);
     // ---- MFMA over the chunk
     if constexpr (!BF) {
       const float* As = reinterpret_cast<const float*>(smem);
-      const float* Bs = As + WG_KC * L::LDA;
+      const float* Bs = As + L::KC * L::LDA;
 #pragma unroll
-      for (int kb = 0; kb < (CW > 0 ? WG_KC / 4 : 0); ++kb) {
+      for (int kb = 0; kb < (CW > 0 ? L::KC / 4 : 0); ++kb) {
         const int kr = 4 * kb + grp;
         float a[T], b[CWA];
 #pragma unroll
@@ -880,7 +948,7 @@ template <bool BF, int T>
 __global__ __launch_bounds__(WG_THREADS) void k_wgrad(Geo g, const float* __restrict__ X, const void* __restrict__ H,
                                                const void* __restrict__ DZ, const void* __restrict__ DH,
                                                float* __restrict__ part, long long chunk) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[WgradLds<T>::BYTES];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[WgradLds<BF, T>::BYTES];
   const Job J = job_info(g, blockIdx.x, X, H, DZ, DH);
   const int ngc = (J.cols + 1 + 16 * T - 1) / (16 * T), ngr = (J.rows + 16 * T - 1) / (16 * T);
   if ((int)blockIdx.y >= ngc * ngr) return;  // uniform over the workgroup
