@@ -314,17 +314,19 @@ __device__ __forceinline__ void layer_mm(f32x4 (&acc)[TO], const f32x4 (&in)[TIN
 #pragma unroll
   for (int T = 0; T < TO; ++T) acc[T] = zero4();
   if constexpr (!BF) {
+    // one 16-byte fragment (4 K steps of one output tile) at a time: the
+    // four MFMAs on it accumulate back to back into the same tile, and only
+    // a few fragments are live, which leaves registers for the callers'
+    // early loads
     const f32x4* A = reinterpret_cast<const f32x4*>(pack);
 #pragma unroll
-    for (int t = 0; t < TIN; ++t) {
-      f32x4 a[TO];
+    for (int t = 0; t < TIN; ++t)
 #pragma unroll
-      for (int T = 0; T < TO; ++T) a[T] = A[((size_t)T * TIN + t) * 64 + lane];
+      for (int T = 0; T < TO; ++T) {
+        const f32x4 a = A[((size_t)T * TIN + t) * 64 + lane];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int T = 0; T < TO; ++T) acc[T] = mfma_f32(a[T][r], in[t][r], acc[T]);
-    }
+        for (int r = 0; r < 4; ++r) acc[T] = mfma_f32(a[r], in[t][r], acc[T]);
+      }
   } else {
     static_assert(TIN % 2 == 0, "bf16 K blocks span two tiles");
     const bf16x8* A = reinterpret_cast<const bf16x8*>(pack);
@@ -344,12 +346,44 @@ __device__ __forceinline__ f32x4 bias4(const float* b, int base, int n) {
   return v;
 }
 
+// Path tiles (16 paths each) of one step are split evenly over the
+// workgroups of that step (blockIdx.x); inside a workgroup, wave w takes
+// tiles t0 + w, t0 + w + waves, ... so the per-wave counts differ by at most
+// one and consecutive waves read consecutive paths.
+struct TileRange { int t0, t1; };
+__device__ __forceinline__ TileRange tile_range(int M) {
+  const int tiles = (M + 15) / 16;
+  const int per = (tiles + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int t0 = (int)blockIdx.x * per;
+  return TileRange{t0, min(tiles, t0 + per)};
+}
+
 // ----------------------------------------------------------- forward kernel
-// Copy one step's packed fragments (bytes, multiple of 16) into LDS.
-__device__ __forceinline__ void stage_weights(unsigned char* dst, const void* src, size_t bytes) {
+// Copy `bytes` (a multiple of 16) from global memory into LDS without the
+// barrier.  Each thread issues up to 16 loads of 16 bytes before its first
+// LDS write, so a step's fragments (~150 KB over 768 threads) arrive after
+// one memory latency instead of one per 16-byte row.  Indices past the end
+// are clamped to the last row (those lanes write the same value to the same
+// LDS row), so loads and writes are unconditional and all loads are in
+// flight together.
+__device__ __forceinline__ void copy_to_lds(unsigned char* dst, const void* src, size_t bytes) {
+  constexpr int B = 16;
   const uint4* s = reinterpret_cast<const uint4*>(src);
   uint4* d = reinterpret_cast<uint4*>(dst);
-  for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+  const int n = (int)(bytes / 16), stride = (int)blockDim.x;
+  if (n <= 0) return;
+  for (int base = (int)threadIdx.x; base < n; base += B * stride) {
+    uint4 r[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) r[k] = s[min(base + k * stride, n - 1)];
+#pragma unroll
+    for (int k = 0; k < B; ++k) d[min(base + k * stride, n - 1)] = r[k];
+  }
+}
+
+// Copy one step's packed fragments (bytes, multiple of 16) into LDS.
+__device__ __forceinline__ void stage_weights(unsigned char* dst, const void* src, size_t bytes) {
+  copy_to_lds(dst, src, bytes);
   __syncthreads();
 }
 
@@ -378,9 +412,7 @@ __global__ __launch_bounds__(LDSW ? 64 * fwd_waves(TI, TW) : 256) void k_forward
   if constexpr (LDSW) {
     if (n > 0) {
       const size_t wbytes = (size_t)g.packf_step * esz;
-      const uint4* sb = reinterpret_cast<const uint4*>(pbias + (size_t)(n - 1) * g.pbias_step);
-      uint4* db = reinterpret_cast<uint4*>(wsm + wbytes);
-      for (int i = threadIdx.x; i < g.pbias_step / 4; i += blockDim.x) db[i] = sb[i];
+      copy_to_lds(wsm + wbytes, pbias + (size_t)(n - 1) * g.pbias_step, (size_t)g.pbias_step * 4);
       stage_weights(wsm, reinterpret_cast<const char*>(packF) + (size_t)(n - 1) * wbytes, wbytes);
     }
     pk = reinterpret_cast<const char*>(wsm);
@@ -389,13 +421,16 @@ __global__ __launch_bounds__(LDSW ? 64 * fwd_waves(TI, TW) : 256) void k_forward
     pk = reinterpret_cast<const char*>(packF) + (size_t)(n > 0 ? n - 1 : 0) * g.packf_step * esz;
     bp = pbias + (size_t)(n > 0 ? n - 1 : 0) * g.pbias_step;
   }
-  // rows of X_n are loaded at the start of their tile, rows of s_n in the
-  // epilogue; the other waves of the SIMD cover the latency
+  // rows of X_n and (up to 8 tiles of d) s_n are loaded at the start of
+  // their tile, before the tile's activation stores: vector-memory operations
+  // complete in order, so a load issued after those stores would also wait
+  // for their writes.  Wider s rows are loaded in the epilogue (registers).
   const float* Xn = X + n * rowM;
   float* Vn = V + n * rowM;
+  const TileRange tr = tile_range(g.M);
   for (int it = 0; it < tpw; ++it) {
-  const int tile = (blockIdx.x * tpw + it) * nwv + wv;
-  if (tile * 16 >= g.M) break;
+  const int tile = tr.t0 + it * nwv + wv;
+  if (tile >= tr.t1) break;
   const int p = tile * 16 + col;
   const bool valid = p < g.M;
   f32x4 xv[TI];
@@ -403,6 +438,15 @@ __global__ __launch_bounds__(LDSW ? 64 * fwd_waves(TI, TW) : 256) void k_forward
   for (int t = 0; t < TI; ++t) {
     const int c0 = 16 * t + 4 * grp;
     xv[t] = (valid && c0 < g.dp) ? ld4(Xn + (size_t)p * g.dp + c0) : zero4();
+  }
+  constexpr bool SE = TI <= 8;
+  f32x4 sv[SE ? TI : 1];
+  if constexpr (SE) {
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      sv[t] = (valid && c0 < g.dp) ? ld4(Vn + (size_t)p * g.dp + c0) : zero4();
+    }
   }
   f32x4 Z[TI];
   if (n == 0) {
@@ -448,7 +492,9 @@ __global__ __launch_bounds__(LDSW ? 64 * fwd_waves(TI, TW) : 256) void k_forward
     const int c0 = 16 * t + 4 * grp;
     if (valid && c0 < g.dp) {
       float* vp = Vn + (size_t)p * g.dp + c0;
-      const f32x4 s = ld4(vp);
+      f32x4 s;
+      if constexpr (SE) s = sv[t];
+      else s = ld4(vp);
       f32x4 v = s;
       if (g.drv == DRV_BSB) {
         const f32x4 x = xv[t];
@@ -602,18 +648,19 @@ __global__ __launch_bounds__(LDSW ? 64 * bwd_waves(TI, TW) : 256) void k_backwar
   // v_n rows and lambda_{n+1} of the next tile are fetched one tile ahead
   f32x4 vnx[TI];
   float lnx = 0.f;
+  const TileRange tr = tile_range(g.M);
   if constexpr (TI <= 8 && TW <= 8) {
-    const int p0 = ((blockIdx.x * tpw) * nwv + wv) * 16 + col;
-    lnx = p0 < g.M ? LAM[(size_t)n * g.M + p0] : 0.f;
+    const int p0 = (tr.t0 + wv) * 16 + col;
+    lnx = (tr.t0 + wv < tr.t1 && p0 < g.M) ? LAM[(size_t)n * g.M + p0] : 0.f;
 #pragma unroll
     for (int t = 0; t < TI; ++t) {
       const int c0 = 16 * t + 4 * grp;
-      vnx[t] = (p0 < g.M && c0 < g.dp) ? ld4(Vn + (size_t)p0 * g.dp + c0) : zero4();
+      vnx[t] = (tr.t0 + wv < tr.t1 && p0 < g.M && c0 < g.dp) ? ld4(Vn + (size_t)p0 * g.dp + c0) : zero4();
     }
   }
   for (int it = 0; it < tpw; ++it) {
-  const int tile = (blockIdx.x * tpw + it) * nwv + wv;
-  if (tile * 16 >= g.M) break;
+  const int tile = tr.t0 + it * nwv + wv;
+  if (tile >= tr.t1) break;
   const int p = tile * 16 + col;
   const bool valid = p < g.M;
   constexpr bool PF = TI <= 8 && TW <= 8;
@@ -630,7 +677,7 @@ __global__ __launch_bounds__(LDSW ? 64 * bwd_waves(TI, TW) : 256) void k_backwar
   for (int t = 0; t < TI; ++t) zeta[t] = round4(lam * vnx[t], BF);
   if constexpr (PF) {
     const int pn = p + 16 * nwv;
-    const bool nxt = it + 1 < tpw && pn - col < g.M;
+    const bool nxt = it + 1 < tpw && tile + nwv < tr.t1;
     lnx = (nxt && pn < g.M) ? LAM[(size_t)n * g.M + pn] : 0.f;
 #pragma unroll
     for (int t = 0; t < TI; ++t) {
@@ -1149,18 +1196,21 @@ hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t ite
 }
 
 // Tiles of 16 paths per wave for the LDS-resident kernels: the count that
-// minimises the makespan ceil(workgroups / CUs) * (tiles + staging), one
-// workgroup per CU.
+// minimises the makespan ceil(workgroups / CUs) * (work per SIMD + staging),
+// one workgroup per CU.  A workgroup of `waves` waves gets ceil(tiles / gx)
+// tiles of its step, dealt to its waves in turn, so each of the 4 SIMDs runs
+// about a quarter of them; staging the step's weights in LDS costs about a
+// quarter of one wave's tile.  In units of 1 / (4 * waves) of a wave-tile:
+// span = rounds * (16 * ceil(per_wg / 4) + waves).
 static int tiles_per_wave(const Geo& g, int waves, int cus) {
-  // every workgroup first stages its step's weights in LDS, about a quarter
-  // of a tile's work: span = rounds * (t + 1/4), in quarter tiles
   const long long tiles = (g.M + 15) / 16;
   int best = 1;
   long long best_span = -1;
   for (int t = 1; t <= 64; ++t) {
     const long long gx = (tiles + (long long)waves * t - 1) / ((long long)waves * t);
+    const long long per_wg = (tiles + gx - 1) / gx;
     const long long wgs = gx * g.N;
-    const long long span = ((wgs + cus - 1) / cus) * (4LL * t + 1);
+    const long long span = ((wgs + cus - 1) / cus) * (16LL * ((per_wg + 3) / 4) + waves);
     if (best_span < 0 || span < best_span) { best_span = span; best = t; }
   }
   return best;
