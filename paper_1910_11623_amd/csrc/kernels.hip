@@ -574,7 +574,38 @@ __global__ __launch_bounds__(256) void k_scan(Geo g, const double* __restrict__ 
   __shared__ double sh[256];
   const int m = blockIdx.x * 256 + threadIdx.x;
   double l2 = 0.0, lam0 = 0.0;
-  if (m < g.M) {
+  constexpr int NR = 64;  // time grids up to NR steps keep c_n and Y_n in registers
+  if (m < g.M && g.N <= NR) {
+    // every c_n load is issued up front (indices clamped, so unconditional),
+    // Y_n stays in registers for the reverse recursion: two memory latencies
+    // per path instead of one per batch of steps in each direction
+    float cv[NR], yv[NR + 1];
+    const float qn = QN[m], ln = LN[m];  // terminal inputs, fetched with the c_n
+#pragma unroll
+    for (int n = 0; n < NR; ++n) cv[n] = C[(size_t)min(n, g.N - 1) * g.M + m];
+    float y = (float)y0[0];
+    yv[0] = y;
+    Y[m] = y;
+#pragma unroll
+    for (int n = 0; n < NR; ++n) {
+      if (n < g.N) {
+        y = y + g.dt * phi_y(g, y) + cv[n];
+        yv[n + 1] = y;
+        Y[(size_t)(n + 1) * g.M + m] = y;
+      }
+    }
+    const float e = y - terminal_g(g, qn, ln);
+    l2 = (double)e * (double)e;
+    float lam = 2.f * e / (float)g.M;
+#pragma unroll
+    for (int n = NR - 1; n >= 0; --n) {
+      if (n < g.N) {
+        LAM[(size_t)n * g.M + m] = lam;
+        lam = lam * (1.f + g.dt * phi_yy(g, yv[n]));
+      }
+    }
+    lam0 = (double)lam;
+  } else if (m < g.M) {
     // both recursions are serial in n; the loads they need are not, so
     // they are issued SB steps at a time ahead of the arithmetic
     constexpr int SB = 8;
@@ -1017,6 +1048,28 @@ __global__ __launch_bounds__(WG_THREADS) void k_wgrad(Geo g, const float* __rest
 // ------------------------------------------------------------ reduce kernel
 // grad[e] = sum over splits k (in order) of part[k * stride + e]; 4 elements
 // per thread when grad is 16-byte aligned (the partial copies always are).
+// fp64 loss and dY0 from the scan's per-block partials (one wave; strided
+// per-lane sums, then a fixed xor butterfly, so the result is deterministic)
+__device__ __forceinline__ void finalize_wave(int M, const double* __restrict__ sp, int nb, double* loss,
+                                              double* gy0, int* nf, int* host_flag) {
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 64) { a += sp[2 * k]; b += sp[2 * k + 1]; }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  if (threadIdx.x == 0) {
+    if (loss) loss[0] = a / (double)M;
+    if (gy0) gy0[0] = b;
+    const bool bad = nf[0] != 0 || !isfinite(a) || (gy0 != nullptr && !isfinite(b));
+    nf[0] = 0;
+    if (bad && host_flag) host_flag[0] = 1;
+  }
+}
+
+// grad[e] = sum over splits k (in order) of part[k * stride + e]; 4 elements
+// per thread, any non-finite sum raises the device flag
 __global__ __launch_bounds__(256) void k_reduce(long long P, long long stride, const float* __restrict__ part,
                                                 int splits, float* __restrict__ grad, int* __restrict__ nf) {
   bool bad = false;
@@ -1039,22 +1092,10 @@ __global__ __launch_bounds__(256) void k_reduce(long long P, long long stride, c
 
 // Fixed-order fp64 totals of the scan partials; folds the loss, dL/dY0 and
 // the gradient flag `nf` into the plan's host flag, then clears `nf`.
-__global__ __launch_bounds__(256) void k_finalize(int M, const double* __restrict__ sp, int nb,
-                                                  double* __restrict__ loss, double* __restrict__ gy0,
-                                                  int* __restrict__ nf, int* __restrict__ host_flag) {
-  __shared__ double sh[256];
-  double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < nb; k += 256) { a += sp[2 * k]; b += sp[2 * k + 1]; }
-  const double A = block_sum_256(a, sh);
-  __syncthreads();
-  const double B = block_sum_256(b, sh);
-  if (threadIdx.x == 0) {
-    if (loss) loss[0] = A / (double)M;
-    if (gy0) gy0[0] = B;
-    const bool bad = nf[0] != 0 || !isfinite(A) || (gy0 != nullptr && !isfinite(B));
-    nf[0] = 0;
-    if (bad && host_flag) host_flag[0] = 1;
-  }
+__global__ __launch_bounds__(64) void k_finalize(int M, const double* __restrict__ sp, int nb,
+                                                 double* __restrict__ loss, double* __restrict__ gy0,
+                                                 int* __restrict__ nf, int* __restrict__ host_flag) {
+  finalize_wave(M, sp, nb, loss, gy0, nf, host_flag);
 }
 
 // -------------------------------------------------------------- Adam kernel
@@ -1067,7 +1108,22 @@ __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p
                                               double t_imm, const uint64_t* __restrict__ t_dev, double lr_y0,
                                               double b1d, double b2d, double epsd) {
   const float b1 = (float)b1d, b2 = (float)b2d, eps = (float)epsd;
-  // bias corrections: one evaluation per workgroup, shared through LDS
+  const long long i0 = blockIdx.x * 256LL + threadIdx.x;
+  // 4 elements per thread when the four arrays are 16-byte aligned, then the tail
+  const bool vec = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(gr) |
+                     reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v)) & 15) == 0;
+  const long long n4 = vec ? n / 4 : 0;
+  // the first element's loads are issued before the bias corrections are
+  // known, so their latency overlaps the workgroup's pow evaluations
+  f32x4 P4 = zero4(), G4 = zero4(), M4 = zero4(), V4 = zero4();
+  if (i0 < n4) {
+    P4 = reinterpret_cast<const f32x4*>(p)[i0];
+    G4 = reinterpret_cast<const f32x4*>(gr)[i0];
+    M4 = reinterpret_cast<const f32x4*>(m)[i0];
+    V4 = reinterpret_cast<const f32x4*>(v)[i0];
+  }
+  // bias corrections: one evaluation per workgroup, shared through LDS (the
+  // same device code for an immediate step count and a device-side counter)
   __shared__ double corr[2];
   if (threadIdx.x == 0) {
     const double t = t_dev ? (double)(t_dev[0] + 1) : t_imm;
@@ -1077,19 +1133,18 @@ __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p
   __syncthreads();
   const double c1d = corr[0], c2d = corr[1];
   const float c1 = (float)c1d, c2 = (float)c2d;
-  const long long i0 = blockIdx.x * 256LL + threadIdx.x;
   auto upd = [&](float pi, float gi, float& mi, float& vi) {
     mi = b1 * mi + (1.f - b1) * gi;
     vi = b2 * vi + (1.f - b2) * gi * gi;
     return pi - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
   };
-  // 4 elements per thread when the four arrays are 16-byte aligned, then the tail
-  const bool vec = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(gr) |
-                     reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v)) & 15) == 0;
-  const long long n4 = vec ? n / 4 : 0;
   for (long long i = i0; i < n4; i += (long long)gridDim.x * 256) {
-    f32x4 P4 = reinterpret_cast<const f32x4*>(p)[i], G4 = reinterpret_cast<const f32x4*>(gr)[i];
-    f32x4 M4 = reinterpret_cast<const f32x4*>(m)[i], V4 = reinterpret_cast<const f32x4*>(v)[i];
+    if (i != i0) {
+      P4 = reinterpret_cast<const f32x4*>(p)[i];
+      G4 = reinterpret_cast<const f32x4*>(gr)[i];
+      M4 = reinterpret_cast<const f32x4*>(m)[i];
+      V4 = reinterpret_cast<const f32x4*>(v)[i];
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       float mi = M4[r], vi = V4[r];
@@ -1401,13 +1456,13 @@ hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* gra
   k_reduce<<<grid1((g.nparams + 3) / 4, 4096), 256, 0, s>>>(g.nparams, g.pstride, part, splits, grad, nf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_finalize<<<1, 256, 0, s>>>(g.M, scan_part, scan_blocks, loss, grad_y0, nf, host_flag);
+  k_finalize<<<1, 64, 0, s>>>(g.M, scan_part, scan_blocks, loss, grad_y0, nf, host_flag);
   return hipGetLastError();
 }
 
 hipError_t launch_loss_only(const Geo& g, double* scan_part, int scan_blocks, double* loss, int* host_flag,
                             hipStream_t s) {
-  k_finalize<<<1, 256, 0, s>>>(g.M, scan_part, scan_blocks, loss, nullptr, nf_flag(scan_part, scan_blocks),
+  k_finalize<<<1, 64, 0, s>>>(g.M, scan_part, scan_blocks, loss, nullptr, nf_flag(scan_part, scan_blocks),
                                host_flag);
   return hipGetLastError();
 }
