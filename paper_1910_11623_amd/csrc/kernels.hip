@@ -947,18 +947,22 @@ __device__ __forceinline__ void wgrad_put(unsigned char* smem, int tid,
   }
 }
 
-template <bool BF, int T, int CW>
+// One wave's share of the T x T tile block: NR tile rows from rt0 times NC
+// tile columns from ct0 (NR = NC = 0: the wave only stages).
+template <bool BF, int T, int NR, int NC>
 __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, int C0, long long p0,
-                                            long long p1, unsigned char* smem, float* out_split) {
+                                            long long p1, unsigned char* smem, float* out_split, int rt0,
+                                            int ct0) {
   using L = WgradLds<BF, T>;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int c16 = lane & 15, grp = lane >> 4;
-  constexpr int CWA = CW > 0 ? CW : 1;  // storage size (a wave with no tiles only stages)
-  f32x4 acc[T][CWA];
+  constexpr bool MM = NR > 0 && NC > 0;
+  constexpr int NRA = NR > 0 ? NR : 1, NCA = NC > 0 ? NC : 1;  // storage sizes
+  f32x4 acc[NRA][NCA];
 #pragma unroll
-  for (int i = 0; i < T; ++i)
+  for (int i = 0; i < NRA; ++i)
 #pragma unroll
-    for (int j = 0; j < CWA; ++j) acc[i][j] = zero4();
+    for (int j = 0; j < NCA; ++j) acc[i][j] = zero4();
 
   typename StageSlot<BF>::type pre[WgradStage<BF, T>::NS];
   if constexpr (wg_prefetch<BF>()) wgrad_fetch<BF, T>(J, R0, C0, p0, p1, tid, pre);
@@ -969,54 +973,54 @@ __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, 
     __syncthreads();
     // the next chunk's loads are in flight during this chunk's MFMAs
     if (wg_prefetch<BF>() && pc + L::KC < p1) wgrad_fetch<BF, T>(J, R0, C0, pc + L::KC, p1, tid, pre);
+    if constexpr (!MM) continue;
     // ---- MFMA over the chunk
     if constexpr (!BF) {
-      const float* As = reinterpret_cast<const float*>(smem);
-      const float* Bs = As + L::KC * L::LDA;
+      const float* As = reinterpret_cast<const float*>(smem) + 16 * rt0 + c16;
+      const float* Bs = reinterpret_cast<const float*>(smem) + L::KC * L::LDA + 16 * ct0 + c16;
 #pragma unroll
-      for (int kb = 0; kb < (CW > 0 ? L::KC / 4 : 0); ++kb) {
+      for (int kb = 0; kb < L::KC / 4; ++kb) {
         const int kr = 4 * kb + grp;
-        float a[T], b[CWA];
+        float a[NRA], b[NCA];
 #pragma unroll
-        for (int i = 0; i < T; ++i) a[i] = As[kr * L::LDA + 16 * i + c16];
+        for (int i = 0; i < NR; ++i) a[i] = As[kr * L::LDA + 16 * i];
 #pragma unroll
-        for (int j = 0; j < CW; ++j) b[j] = Bs[kr * L::LDA + 16 * (WG_CPW * wv + j) + c16];
+        for (int j = 0; j < NC; ++j) b[j] = Bs[kr * L::LDA + 16 * j];
 #pragma unroll
-        for (int i = 0; i < T; ++i)
+        for (int i = 0; i < NR; ++i)
 #pragma unroll
-          for (int j = 0; j < CW; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
+          for (int j = 0; j < NC; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
       }
     } else {
       const uint16_t* As = reinterpret_cast<const uint16_t*>(smem);
       const uint16_t* Bs = As + 16 * T * L::LDT;
-      if (CW == 0) continue;
-      bf16x8 a[T], b[CWA];
+      bf16x8 a[NRA], b[NCA];
 #pragma unroll
-      for (int i = 0; i < T; ++i) {
-        const uint16_t* src = As + (16 * i + c16) * L::LDT + 8 * grp;
+      for (int i = 0; i < NR; ++i) {
+        const uint16_t* src = As + (16 * (rt0 + i) + c16) * L::LDT + 8 * grp;
         const uint2 lo = *reinterpret_cast<const uint2*>(src), hi = *reinterpret_cast<const uint2*>(src + 4);
         a[i] = __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y});
       }
 #pragma unroll
-      for (int j = 0; j < CW; ++j) {
-        const uint16_t* src = Bs + (16 * (WG_CPW * wv + j) + c16) * L::LDT + 8 * grp;
+      for (int j = 0; j < NC; ++j) {
+        const uint16_t* src = Bs + (16 * (ct0 + j) + c16) * L::LDT + 8 * grp;
         const uint2 lo = *reinterpret_cast<const uint2*>(src), hi = *reinterpret_cast<const uint2*>(src + 4);
         b[j] = __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y});
       }
 #pragma unroll
-      for (int i = 0; i < T; ++i)
+      for (int i = 0; i < NR; ++i)
 #pragma unroll
-        for (int j = 0; j < CW; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < NC; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
     }
   }
   // ---- partial sums of this path split, scattered to the flat layout
 #pragma unroll
-  for (int i = 0; i < T; ++i)
+  for (int i = 0; i < NR; ++i)
 #pragma unroll
-    for (int j = 0; j < CW; ++j)
+    for (int j = 0; j < NC; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = R0 + 16 * i + 4 * grp + r, c = C0 + 16 * (WG_CPW * wv + j) + c16;
+        const int row = R0 + 16 * (rt0 + i) + 4 * grp + r, c = C0 + 16 * (ct0 + j) + c16;
         if (row < J.rows && c <= J.cols) {
           const long long off = (c < J.cols) ? J.base + (long long)row * J.cols + c
                                              : J.base + (long long)J.rows * J.cols + row;
@@ -1038,11 +1042,19 @@ __global__ __launch_bounds__(WG_THREADS) void k_wgrad(Geo g, const float* __rest
   const long long p1 = min((long long)g.M, p0 + chunk);
   float* out = part + (size_t)blockIdx.z * g.pstride;
   const int wv = threadIdx.x >> 6;
-  // tile columns of this wave inside the block: 2wv, 2wv+1 (fewer at the edge)
-  const int ncol = min(WG_CPW, max(0, T - WG_CPW * wv));
-  if (WG_CPW == 2 && ncol == 2) wgrad_tiles<BF, T, WG_CPW>(g, J, R0, C0, p0, p1, smem, out);
-  else if (ncol == 1) wgrad_tiles<BF, T, 1>(g, J, R0, C0, p0, p1, smem, out);
-  else wgrad_tiles<BF, T, 0>(g, J, R0, C0, p0, p1, smem, out);
+  if constexpr (WG_CPW == 1 && T == 7) {
+    // 7 x 7 tiles over 8 waves: waves 0..6 take tile rows 0..5 of column wv,
+    // wave 7 takes tile row 6 of every column, so every wave multiplies (6
+    // or 7 tiles) and each SIMD's pair of waves carries 12 or 13 tiles
+    if (wv < T) wgrad_tiles<BF, T, T - 1, 1>(g, J, R0, C0, p0, p1, smem, out, 0, wv);
+    else wgrad_tiles<BF, T, 1, T>(g, J, R0, C0, p0, p1, smem, out, T - 1, 0);
+  } else {
+    // tile columns of this wave inside the block: WG_CPW per wave (fewer at the edge)
+    const int ncol = min(WG_CPW, max(0, T - WG_CPW * wv));
+    if (WG_CPW == 2 && ncol == 2) wgrad_tiles<BF, T, T, WG_CPW>(g, J, R0, C0, p0, p1, smem, out, 0, WG_CPW * wv);
+    else if (ncol == 1) wgrad_tiles<BF, T, T, 1>(g, J, R0, C0, p0, p1, smem, out, 0, WG_CPW * wv);
+    else wgrad_tiles<BF, T, 0, 0>(g, J, R0, C0, p0, p1, smem, out, 0, 0);
+  }
 }
 
 // ------------------------------------------------------------ reduce kernel
