@@ -391,8 +391,9 @@ __device__ __forceinline__ void stage_weights(unsigned char* dst, const void* sr
 }
 
 // LDSW = false: one 16-path tile per wave, fragments read from global memory.
-// LDSW = true : the workgroup stages step n's fragments in LDS once, then each
-//               of its waves streams `tpw` tiles of 16 paths through them.
+// LDSW = true : the workgroup stages step n's fragments in LDS once, then its
+//               waves stream its share of the step's 16-path tiles (at most
+//               `tpw` each, see tile_range) through them.
 // Waves per workgroup of the LDS-staged forward kernel (one workgroup per
 // CU): 3 per SIMD for shapes up to 8 x 8 tiles (<= 170 VGPRs), else 2.
 constexpr int fwd_waves(int ti, int tw) { return (ti <= 8 && tw <= 8) ? 12 : 8; }
