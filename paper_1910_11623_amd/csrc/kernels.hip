@@ -1355,7 +1355,7 @@ static void bwd_inst(const Geo& g, const void* packB, const float* V, const floa
 struct TileShape { int bf, ti, tw; };
 static const TileShape kShapes[] = {
     {0, 1, 2}, {0, 2, 2}, {0, 4, 4}, {0, 7, 7}, {0, 8, 8}, {0, 16, 16},
-    {1, 2, 2}, {1, 4, 4}, {1, 8, 8}, {1, 16, 16},
+    {1, 2, 2}, {1, 4, 4}, {1, 6, 6}, {1, 8, 8}, {1, 10, 10}, {1, 12, 12}, {1, 14, 14}, {1, 16, 16},
 };
 
 int tile_candidates(int bf16, int ti_min, int tw_min, int* ti, int* tw, int cap) {
@@ -1395,7 +1395,11 @@ bool choose_tiles(int bf16, int ti_min, int tw_min, int* ti, int* tw) {
     if (g.bf16) {                                                                 \
       if (g.ti == 2 && g.tw == 2) FN<true, 2, 2>(__VA_ARGS__);                    \
       else if (g.ti == 4 && g.tw == 4) FN<true, 4, 4>(__VA_ARGS__);               \
+      else if (g.ti == 6 && g.tw == 6) FN<true, 6, 6>(__VA_ARGS__);               \
       else if (g.ti == 8 && g.tw == 8) FN<true, 8, 8>(__VA_ARGS__);               \
+      else if (g.ti == 10 && g.tw == 10) FN<true, 10, 10>(__VA_ARGS__);           \
+      else if (g.ti == 12 && g.tw == 12) FN<true, 12, 12>(__VA_ARGS__);           \
+      else if (g.ti == 14 && g.tw == 14) FN<true, 14, 14>(__VA_ARGS__);           \
       else if (g.ti == 16 && g.tw == 16) FN<true, 16, 16>(__VA_ARGS__);           \
       else return hipErrorInvalidValue;                                           \
     } else {                                                                      \

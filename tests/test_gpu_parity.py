@@ -80,7 +80,12 @@ def test_fp32_loss_and_gradient(pname, d, w, L, N, M):
 
 
 @pytest.mark.parametrize("pname,d,w,N,M", [("hjb", 100, 110, 6, 64), ("bsb", 10, 20, 16, 256),
-                                            ("ac", 20, 30, 10, 70)])
+                                            ("ac", 20, 30, 10, 70),
+                                            ("hjb", 80, 90, 5, 100),    # 6 x 6 bf16 tiles
+                                            ("hjb", 140, 150, 4, 50),   # 10 x 10 bf16 tiles
+                                            ("hjb", 150, 160, 5, 90),   # 12 x 12 bf16 tiles
+                                            ("hjb", 200, 210, 4, 40),   # 14 x 14 bf16 tiles
+                                            ("hjb", 230, 240, 3, 33)])  # 16 x 16 bf16 tiles
 def test_bf16_loss_and_gradient(pname, d, w, N, M):
     prob = _problem(pname, d)
     net = dict(kind="mlp", width=w, depth=2, prec="bf16")
