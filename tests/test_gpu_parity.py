@@ -61,6 +61,7 @@ FP32_CASES = [
     ("bsb", 100, 110, 2, 8, 96),   # d=100, w=110 shape at reduced N, M
     ("hjb", 100, 110, 2, 20, 48),  # HJB d=100 shape at reduced M
     ("ac", 130, 140, 2, 3, 40),    # d, w above 128: 16-tile kernels
+    ("hjb", 256, 256, 2, 3, 21),   # largest per-step shape: d = w = 256 (16 x 16 tiles, no padding)
 ]
 
 
@@ -85,7 +86,8 @@ def test_fp32_loss_and_gradient(pname, d, w, L, N, M):
                                             ("hjb", 140, 150, 4, 50),   # 10 x 10 bf16 tiles
                                             ("hjb", 150, 160, 5, 90),   # 12 x 12 bf16 tiles
                                             ("hjb", 200, 210, 4, 40),   # 14 x 14 bf16 tiles
-                                            ("hjb", 230, 240, 3, 33)])  # 16 x 16 bf16 tiles
+                                            ("hjb", 230, 240, 3, 33),   # 16 x 16 bf16 tiles
+                                            ("hjb", 256, 256, 3, 21)])  # largest per-step shape
 def test_bf16_loss_and_gradient(pname, d, w, N, M):
     prob = _problem(pname, d)
     net = dict(kind="mlp", width=w, depth=2, prec="bf16")
