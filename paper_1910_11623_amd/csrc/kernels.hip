@@ -813,8 +813,10 @@ __device__ __forceinline__ Job job_info(const Geo& g, int job, const float* X, c
 // LDS-staged weight-gradient GEMM.  Workgroup = (job, output block group,
 // path split); it owns a T x T block of 16x16 output tiles and walks its path
 // range in chunks staged in LDS.  Wave w accumulates tile column w over all T
-// tile rows (with T < 8 the last wave only stages).  Bias gradients ride along
-// as an extra input column of ones (column `cols`).
+// tile rows (with T < 8 the waves past T only stage), except for T = 7, where
+// waves 0..6 take tile rows 0..5 of their column and wave 7 takes tile row 6
+// of every column (see k_wgrad).  Bias gradients ride along as an extra input
+// column of ones (column `cols`).
 //
 // Chunk length: the bf16 MFMA takes K = 32 paths per instruction, so the bf16
 // form stages 32 paths (transposed to k-contiguous rows); the fp32 form
