@@ -114,7 +114,9 @@ void orc_adam(int64_t n, double *theta, const double *g, double *m, double *v,
 /* Multilevel warm start (Sec. 3.2): per-step nets of a coarse grid with Nc
  * steps copied to a fine grid with Nf = 2 Nc steps; fine net j takes coarse
  * net clamp(floor(j/2), 1, Nc-1); z0 copied.  For the shared ResNet the map
- * is the identity.  Returns 0, or nonzero if Nf != 2 Nc. */
+ * is the identity.  Returns 0, or nonzero if Nf != 2 Nc.  The paper gives
+ * the level sequence but not this map, so the map itself is a reading:
+ * parity unpinned beyond the exact copy it performs. */
 int orc_prolong(const orc_problem *p, const orc_net *net, int Nc, int Nf,
                 const double *pc, double *pf);
 
