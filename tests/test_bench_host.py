@@ -1,0 +1,76 @@
+"""Host-side logic of bench.py (no GPU): the algorithmic flop and byte models
+behind the roofline entry, the choice of the bound, the counter-traffic
+lookup and the single-GPU guard."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_flop_model_at_d100():
+    f = bench.kernel_flops("fp32", 100, 110, 2, 32, 4096)
+    rows = 4096 * 31
+    # d -> w, w -> w, w -> d products, two flops per multiply-add
+    assert f["forward"] == 2 * (110 * 100 + 110 * 110 + 100 * 110) * rows == 68_200 * rows
+    # the reverse sweep has no input gradient at the first layer
+    assert f["backward"] == 2 * (110 * 100 + 110 * 110) * rows
+    # weight gradients: same products plus one add per bias, plus dZ0
+    assert f["wgrad"] == (68_200 + 2 * 110 + 100) * rows + 100 * 4096
+
+
+def test_byte_model_at_d100():
+    b32 = bench.kernel_bytes("fp32", 100, 110, 2, 32, 4096)
+    b16 = bench.kernel_bytes("bf16", 100, 110, 2, 32, 4096)
+    rows = 4096 * 31
+    splits, nparams = 8, 100 + 31 * (110 * 101 + 110 * 111 + 100 * 111)
+    # X, activations and deltas per path-step: 2560 bytes in fp32
+    assert b32["wgrad"] == 2560 * rows + 4 * splits * nparams
+    # bf16 halves the activations and deltas, not the fp32 path state
+    assert b16["wgrad"] == (400 + 2 * 220 + 2 * 320) * rows + 4 * splits * nparams
+    assert b16["forward"] < b32["forward"]
+
+
+def test_roofline_bound_follows_intensity():
+    kern = {"forward": 0.10, "backward": 0.08, "wgrad": 0.12}
+    dom, r = bench.roofline_entry("fp32", kern)
+    assert dom == "wgrad"
+    # fp32 weight gradients: ~24 flop/B, above the fp32 ridge of 19.7
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-3)
+    dom, r = bench.roofline_entry("bf16", kern)
+    # bf16 is far below its ridge (2.5 PF / 8 TB/s): reported against HBM
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    flops = bench.kernel_flops("bf16", 100, 110, 2, 32, 4096)["wgrad"]
+    assert r["mfma_tflops"] == pytest.approx(flops / 0.12e-3 / 1e12, rel=1e-3)
+
+
+def test_traffic_lookup_requires_the_profiled_source(tmp_path, monkeypatch):
+    rec = json.load(open(os.path.join(ROOT, "profiles", "bsb_d100_traffic.json")))
+    t = bench.measured_traffic("wgrad", "fp32")
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    import hashlib
+    if hashlib.sha256(src).hexdigest() == rec["source_sha256"]:
+        per = rec["per_launch"]["wgrad_fp32"]
+        assert t == int(round(per["read_bytes"] + per["write_bytes"]))
+    else:
+        assert t is None
+    # a counter file taken on another source gives no traffic figure
+    fake = dict(rec, source_sha256="0" * 64)
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "bsb_d100_traffic.json").write_text(json.dumps(fake))
+    (tmp_path / os.path.dirname(rec["source"])).mkdir(parents=True)
+    (tmp_path / rec["source"]).write_bytes(src)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("wgrad", "fp32") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert "one GPU" in (r.stdout + r.stderr)
