@@ -941,7 +941,11 @@ __device__ __forceinline__ void wgrad_put(unsigned char* smem, int tid,
       float* dst = reinterpret_cast<float*>(smem) + (isA ? 0 : L::KC * L::LDA) + kp * L::LDA + 4 * c4;
       st4(dst, v[k]);
     } else {
-      uint16_t* dst = reinterpret_cast<uint16_t*>(smem) + (isA ? 0 : 16 * T * L::LDT) + 4 * c4 * L::LDT + kp;
+      // the 8-path group of a row is XOR-swizzled by bits 4-5 of the row, so
+      // that a wave's 2-byte transposing writes (rows 4 apart) spread over
+      // twice as many LDS banks; fragment reads stay 16 contiguous bytes
+      const int kps = kp ^ (8 * ((c4 >> 2) & 3));  // rows 4c4..4c4+3: (row >> 4) & 3
+      uint16_t* dst = reinterpret_cast<uint16_t*>(smem) + (isA ? 0 : 16 * T * L::LDT) + 4 * c4 * L::LDT + kps;
       dst[0] = (uint16_t)(v[k].x & 0xffffu);
       dst[L::LDT] = (uint16_t)(v[k].x >> 16);
       dst[2 * L::LDT] = (uint16_t)(v[k].y & 0xffffu);
@@ -1000,13 +1004,13 @@ __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, 
       bf16x8 a[NRA], b[NCA];
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
-        const uint16_t* src = As + (16 * (rt0 + i) + c16) * L::LDT + 8 * grp;
+        const uint16_t* src = As + (16 * (rt0 + i) + c16) * L::LDT + 8 * (grp ^ ((rt0 + i) & 3));
         const uint2 lo = *reinterpret_cast<const uint2*>(src), hi = *reinterpret_cast<const uint2*>(src + 4);
         a[i] = __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y});
       }
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
-        const uint16_t* src = Bs + (16 * (ct0 + j) + c16) * L::LDT + 8 * grp;
+        const uint16_t* src = Bs + (16 * (ct0 + j) + c16) * L::LDT + 8 * (grp ^ ((ct0 + j) & 3));
         const uint2 lo = *reinterpret_cast<const uint2*>(src), hi = *reinterpret_cast<const uint2*>(src + 4);
         b[j] = __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y});
       }
