@@ -22,7 +22,14 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 32;
-constexpr int LDK = BK + 8;
+constexpr int LDK = BK;  // 64-byte slab rows, 16-byte groups XOR-swizzled (slab_off)
+
+// Element offset of the 16-byte group g (k = 8g .. 8g + 7) of slab row `row`:
+// the group index is XORed with bits 1-2 of the row, so that both the
+// staging writes (2 rows x 4 groups per 8 lanes) and the fragment reads (8
+// consecutive rows, one group per 8 lanes) touch 8 distinct 16-byte bank
+// groups: no LDS bank conflicts on either side.
+__device__ __forceinline__ int slab_off(int row, int g) { return row * LDK + 8 * (g ^ ((row >> 1) & 3)); }
 // wave tile of the row-streaming GEMMs (16 RN_TM x 16 RN_TN) and waves per SIMD
 #ifndef RN_TM
 #define RN_TM 8
@@ -197,7 +204,7 @@ __device__ __forceinline__ void epilogue4(const Epi& E, int i, int j, f32x4 acc,
 // ------------------------------------------------------------------ GEMM
 // Workgroup tile (32 TM) x (32 TN): 4 waves in 2 x 2, each (16 TM) x (16 TN)
 // as TM x TN MFMA 16x16x32 tiles.  The reduction is staged BK at a time in
-// two LDS buffers (80-byte rows: conflict-free 16-byte fragment reads): the
+// two LDS buffers (64-byte rows, swizzled: conflict-free 16-byte writes and reads): the
 // global loads of slab s + 1 are in flight while slab s is multiplied.  The MFMA takes the B fragment as its
 // first operand, so every lane ends up holding four consecutive output
 // columns of one row (vector epilogue stores).  Tiles are ordered so that
@@ -269,12 +276,12 @@ __global__ __launch_bounds__(128 * WJ) __attribute__((amdgpu_waves_per_eu(RN_WPE
 #pragma unroll
       for (int q = 0; q < UA; ++q) {
         const int u = tid + NT * q;
-        *reinterpret_cast<uint4*>(&sA[buf][(u >> 2) * LDK + (u & 3) * 8]) = ra[q];
+        *reinterpret_cast<uint4*>(&sA[buf][slab_off(u >> 2, u & 3)]) = ra[q];
       }
 #pragma unroll
       for (int q = 0; q < UB; ++q) {
         const int u = tid + NT * q;
-        *reinterpret_cast<uint4*>(&sB[buf][(u >> 2) * LDK + (u & 3) * 8]) = rb[q];
+        *reinterpret_cast<uint4*>(&sB[buf][slab_off(u >> 2, u & 3)]) = rb[q];
       }
     } else {  // the split's last slab (or a padding slab): keep k < ke only
       const long long nv = ke - (kt + kofs);  // valid elements of this thread's runs (may be <= 0)
@@ -284,13 +291,13 @@ __global__ __launch_bounds__(128 * WJ) __attribute__((amdgpu_waves_per_eu(RN_WPE
 #pragma unroll
       for (int q = 0; q < UA; ++q) {
         const int u = tid + NT * q;
-        *reinterpret_cast<uint4*>(&sA[buf][(u >> 2) * LDK + (u & 3) * 8]) =
+        *reinterpret_cast<uint4*>(&sA[buf][slab_off(u >> 2, u & 3)]) =
             uint4{ra[q].x & m[0], ra[q].y & m[1], ra[q].z & m[2], ra[q].w & m[3]};
       }
 #pragma unroll
       for (int q = 0; q < UB; ++q) {
         const int u = tid + NT * q;
-        *reinterpret_cast<uint4*>(&sB[buf][(u >> 2) * LDK + (u & 3) * 8]) =
+        *reinterpret_cast<uint4*>(&sB[buf][slab_off(u >> 2, u & 3)]) =
             uint4{rb[q].x & m[0], rb[q].y & m[1], rb[q].z & m[2], rb[q].w & m[3]};
       }
     }
@@ -311,12 +318,12 @@ __global__ __launch_bounds__(128 * WJ) __attribute__((amdgpu_waves_per_eu(RN_WPE
     bf16x8 fa[TM], fb[TN];
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
-      const uint4 u = *reinterpret_cast<const uint4*>(&sA[buf][(wi * 16 * TM + 16 * a + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+      const uint4 u = *reinterpret_cast<const uint4*>(&sA[buf][slab_off(wi * 16 * TM + 16 * a + (lane & 15), lane >> 4)]);
       fa[a] = __builtin_bit_cast(bf16x8, u32x4{u.x, u.y, u.z, u.w});
     }
 #pragma unroll
     for (int b = 0; b < TN; ++b) {
-      const uint4 u = *reinterpret_cast<const uint4*>(&sB[buf][(wj * 16 * TN + 16 * b + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+      const uint4 u = *reinterpret_cast<const uint4*>(&sB[buf][slab_off(wj * 16 * TN + 16 * b + (lane & 15), lane >> 4)]);
       fb[b] = __builtin_bit_cast(bf16x8, u32x4{u.x, u.y, u.z, u.w});
     }
 #pragma unroll
