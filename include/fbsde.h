@@ -59,7 +59,7 @@ extern "C" {
 typedef enum {
   FBSDE_OK = 0,
   FBSDE_ERR_INVALID = 1,      /* bad argument (null pointer, size, enum)       */
-  FBSDE_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement   */
+  FBSDE_ERR_UNSUPPORTED = 2,  /* valid request the library does not implement */
   FBSDE_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed     */
   FBSDE_ERR_NOMEM = 4,        /* plan creation could not allocate              */
   FBSDE_ERR_NONFINITE = 5     /* an earlier call's loss or gradient not finite */
