@@ -680,26 +680,45 @@ __global__ __launch_bounds__(LDSW ? 64 * bwd_waves(TI, TW) : 256) void k_backwar
   }
   const float* Vn = V + n * rowM;
   const size_t hM = (size_t)g.M * g.wp;
-  // v_n rows and lambda_{n+1} of the next tile are fetched one tile ahead
-  f32x4 vnx[TI];
+  // v_n rows and lambda_{n+1} of the next tile are fetched one tile ahead.
+  // With PF the tanh activations each epilogue needs are fetched one epilogue
+  // ahead too, issued after the current epilogue's arithmetic and before its
+  // stores: loads and stores retire in issue order, so waiting for them then
+  // does not wait for the stores' completion; the last epilogue fetches the
+  // next tile's first. Where the extra live registers would spill (fp32 8 x 8
+  // tiles and the variant that reads its weights from global memory, !XT)
+  // each layer's activations are fetched just before its product.
+  constexpr bool PF = TI <= 8 && TW <= 8;
+  constexpr bool XT = PF && LDSW && (BF || TI + TW < 16);
+  f32x4 vnx[TI], hv[TW];
   float lnx = 0.f;
   const TileRange tr = tile_range(g.M);
-  if constexpr (TI <= 8 && TW <= 8) {
+  auto load_h = [&](int pp, bool ok, int li) {
+#pragma unroll
+    for (int T = 0; T < TW; ++T) {
+      const size_t idx = ((size_t)n * g.L + li) * hM + (size_t)pp * g.wp + 16 * T + 4 * grp;
+      hv[T] = ok ? ld_act(H, idx, BF) : zero4();
+    }
+  };
+  if constexpr (PF) {
     const int p0 = (tr.t0 + wv) * 16 + col;
-    lnx = (tr.t0 + wv < tr.t1 && p0 < g.M) ? LAM[(size_t)n * g.M + p0] : 0.f;
+    const bool ok = tr.t0 + wv < tr.t1 && p0 < g.M;
+    lnx = ok ? LAM[(size_t)n * g.M + p0] : 0.f;
 #pragma unroll
     for (int t = 0; t < TI; ++t) {
       const int c0 = 16 * t + 4 * grp;
-      vnx[t] = (tr.t0 + wv < tr.t1 && p0 < g.M && c0 < g.dp) ? ld4(Vn + (size_t)p0 * g.dp + c0) : zero4();
+      vnx[t] = (ok && c0 < g.dp) ? ld4(Vn + (size_t)p0 * g.dp + c0) : zero4();
     }
+    if (XT && n > 0) load_h(p0, ok, g.L - 1);
   }
   for (int it = 0; it < tpw; ++it) {
   const int tile = tr.t0 + it * nwv + wv;
   if (tile >= tr.t1) break;
   const int p = tile * 16 + col;
   const bool valid = p < g.M;
-  constexpr bool PF = TI <= 8 && TW <= 8;
   const float lam = PF ? lnx : (valid ? LAM[(size_t)n * g.M + p] : 0.f);
+  const int pn = p + 16 * nwv;
+  const bool nxt = it + 1 < tpw && tile + nwv < tr.t1 && pn < g.M;
   f32x4 zeta[TI];
   if constexpr (!PF) {
 #pragma unroll
@@ -711,59 +730,46 @@ __global__ __launch_bounds__(LDSW ? 64 * bwd_waves(TI, TW) : 256) void k_backwar
 #pragma unroll
   for (int t = 0; t < TI; ++t) zeta[t] = round4(lam * vnx[t], BF);
   if constexpr (PF) {
-    const int pn = p + 16 * nwv;
-    const bool nxt = it + 1 < tpw && tile + nwv < tr.t1;
-    lnx = (nxt && pn < g.M) ? LAM[(size_t)n * g.M + pn] : 0.f;
+    lnx = nxt ? LAM[(size_t)n * g.M + pn] : 0.f;
 #pragma unroll
     for (int t = 0; t < TI; ++t) {
       const int c0 = 16 * t + 4 * grp;
-      vnx[t] = (nxt && pn < g.M && c0 < g.dp) ? ld4(Vn + (size_t)pn * g.dp + c0) : zero4();
+      vnx[t] = (nxt && c0 < g.dp) ? ld4(Vn + (size_t)pn * g.dp + c0) : zero4();
     }
   }
 #pragma unroll
   for (int t = 0; t < TI; ++t)
     if (valid) st_act(DZ, ((size_t)n * g.M + p) * g.zp + 16 * t + 4 * grp, zeta[t], BF);
   if (n == 0) continue;
-  f32x4 dl[TW], acc[TW], hv[TW];
-  {
-    const int l = g.L;
-    if constexpr (PF) {
-#pragma unroll
-      for (int T = 0; T < TW; ++T) {
-        const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
-        hv[T] = valid ? ld_act(H, idx, BF) : zero4();
-      }
-    }
-    layer_mm<BF, TW, TI>(acc, zeta, pk, lane);
+  f32x4 dl[TW], acc[TW];
+  // delta_l = (acc) * (1 - h^2) for layer l, then the next epilogue's loads,
+  // then the stores of delta_l
+  auto epilogue = [&](int l) {
+    if constexpr (!PF) load_h(p, valid, l - 1);
 #pragma unroll
     for (int T = 0; T < TW; ++T) {
-      const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
-      if constexpr (!PF) hv[T] = valid ? ld_act(H, idx, BF) : zero4();
 #pragma unroll
       for (int r = 0; r < 4; ++r) dl[T][r] = acc[T][r] * (1.f - hv[T][r] * hv[T][r]);
       dl[T] = round4(dl[T], BF);
+    }
+    if constexpr (XT) {
+      if (l > 1) load_h(p, valid, l - 2);
+      else load_h(pn, nxt, g.L - 1);
+    }
+#pragma unroll
+    for (int T = 0; T < TW; ++T) {
+      const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
       if (valid) st_act(DH, idx, dl[T], BF);
     }
-  }
+  };
+  if constexpr (PF && !XT) load_h(p, valid, g.L - 1);
+  layer_mm<BF, TW, TI>(acc, zeta, pk, lane);
+  epilogue(g.L);
   const char* pkl = pk + 256ULL * TW * TI * esz;
   for (int l = g.L - 1; l >= 1; --l) {
-    if constexpr (PF) {
-#pragma unroll
-      for (int T = 0; T < TW; ++T) {
-        const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
-        hv[T] = valid ? ld_act(H, idx, BF) : zero4();
-      }
-    }
+    if constexpr (PF && !XT) load_h(p, valid, l - 1);
     layer_mm<BF, TW, TW>(acc, dl, pkl + (size_t)(l - 1) * 256ULL * TW * TW * esz, lane);
-#pragma unroll
-    for (int T = 0; T < TW; ++T) {
-      const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
-      if constexpr (!PF) hv[T] = valid ? ld_act(H, idx, BF) : zero4();
-#pragma unroll
-      for (int r = 0; r < 4; ++r) dl[T][r] = acc[T][r] * (1.f - hv[T][r] * hv[T][r]);
-      dl[T] = round4(dl[T], BF);
-      if (valid) st_act(DH, idx, dl[T], BF);
-    }
+    epilogue(l);
   }
   }
 }
