@@ -128,7 +128,7 @@ void make_layout(fbsde_plan* P) {
   w.splits = splits;
   w.chunk = chunk;
   w.PART = take((size_t)splits * (size_t)g.pstride * 4);
-  w.scan_blocks = (int)((M + 255) / 256);
+  w.scan_blocks = (int)((M + 63) / 64);  // one wave per scan workgroup
   w.RED = take((size_t)w.scan_blocks * 2 * 8 + 64);
   w.total = off;
 }

@@ -568,12 +568,22 @@ __device__ __forceinline__ double block_sum_256(double v, double* sh) {
   return sh[0];
 }
 
-__global__ __launch_bounds__(256) void k_scan(Geo g, const double* __restrict__ y0,
-                                              const float* __restrict__ C, const float* __restrict__ QN,
-                                              const float* __restrict__ LN, float* __restrict__ Y,
-                                              float* __restrict__ LAM, double* __restrict__ part) {
-  __shared__ double sh[256];
-  const int m = blockIdx.x * 256 + threadIdx.x;
+// fixed-order fp64 sum over one wave (xor butterfly; every lane gets the
+// same total, since each pairwise add sees the same two operands)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// One wave per workgroup: the paths' serial recursions leave the SIMDs idle,
+// so spreading the waves over as many CUs as possible shortens the latency
+// chain each CU's memory pipeline serves.
+__global__ __launch_bounds__(64) void k_scan(Geo g, const double* __restrict__ y0,
+                                             const float* __restrict__ C, const float* __restrict__ QN,
+                                             const float* __restrict__ LN, float* __restrict__ Y,
+                                             float* __restrict__ LAM, double* __restrict__ part) {
+  const int m = blockIdx.x * 64 + threadIdx.x;
   double l2 = 0.0, lam0 = 0.0;
   constexpr int NR = 64;  // time grids up to NR steps keep c_n and Y_n in registers
   if (m < g.M && g.N <= NR) {
@@ -639,9 +649,8 @@ __global__ __launch_bounds__(256) void k_scan(Geo g, const double* __restrict__ 
     }
     lam0 = (double)lam;
   }
-  const double a = block_sum_256(l2, sh);
-  __syncthreads();
-  const double b = block_sum_256(lam0, sh);
+  const double a = wave_sum(l2);
+  const double b = wave_sum(lam0);
   if (threadIdx.x == 0) {
     part[2 * blockIdx.x] = a;
     part[2 * blockIdx.x + 1] = b;
@@ -1078,7 +1087,19 @@ __global__ __launch_bounds__(WG_THREADS) void k_wgrad(Geo g, const float* __rest
 __device__ __forceinline__ void finalize_wave(int M, const double* __restrict__ sp, int nb, double* loss,
                                               double* gy0, int* nf, int* host_flag) {
   double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < nb; k += 64) { a += sp[2 * k]; b += sp[2 * k + 1]; }
+  // each lane adds partials k, k + 64, k + 128, ... in that order; the loads
+  // of eight of them are issued before their adds (missing ones add 0)
+  for (int k0 = threadIdx.x; k0 < nb; k0 += 64 * 8) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = k0 + 64 * q;
+      av[q] = k < nb ? sp[2 * k] : 0.0;
+      bv[q] = k < nb ? sp[2 * k + 1] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) { a += av[q]; b += bv[q]; }
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     a += __shfl_xor(a, o);
@@ -1433,7 +1454,7 @@ hipError_t launch_forward(const Geo& g, const float* params, const void* packF, 
 
 hipError_t launch_scan(const Geo& g, const double* y0, const float* C, const float* QN, const float* LN,
                        float* Y, float* LAM, double* part, int blocks, hipStream_t s) {
-  k_scan<<<blocks, 256, 0, s>>>(g, y0, C, QN, LN, Y, LAM, part);
+  k_scan<<<blocks, 64, 0, s>>>(g, y0, C, QN, LN, Y, LAM, part);
   return hipGetLastError();
 }
 
