@@ -61,6 +61,7 @@ FP32_CASES = [
     ("bsb", 100, 110, 2, 8, 96),   # d=100, w=110 shape at reduced N, M
     ("hjb", 100, 110, 2, 20, 48),  # HJB d=100 shape at reduced M
     ("hjb", 120, 125, 2, 3, 45),   # 8 x 8 fp32 tiles (reverse sweep loads each layer before its product)
+    ("hjb", 3, 5, 2, 3, 100003),   # 1563 one-wave scan workgroups (ragged), 64 gradient splits
     ("ac", 130, 140, 2, 3, 40),    # d, w above 128: 16-tile kernels
     ("hjb", 256, 256, 2, 3, 21),   # largest per-step shape: d = w = 256 (16 x 16 tiles, no padding)
 ]
