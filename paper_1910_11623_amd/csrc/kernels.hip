@@ -1520,7 +1520,9 @@ hipError_t launch_loss_only(const Geo& g, double* scan_part, int scan_blocks, do
 hipError_t launch_adam(long long n, float* p, const float* gr, float* m, float* v, double* y0,
                        const double* gy0, double* my0, double* vy0, float lr, double t, const uint64_t* t_dev,
                        double lr_y0, double b1, double b2, double eps, hipStream_t s) {
-  k_adam<<<grid1(n, 1024), 256, 0, s>>>(n, p, gr, m, v, y0, gy0, my0, vy0, lr, t, t_dev, lr_y0, b1, b2, eps);
+  // one thread per 4 elements, so that no thread takes a second serial pass
+  k_adam<<<grid1((n + 3) / 4, 8192), 256, 0, s>>>(n, p, gr, m, v, y0, gy0, my0, vy0, lr, t, t_dev, lr_y0, b1, b2,
+                                                  eps);
   return hipGetLastError();
 }
 
