@@ -5,11 +5,12 @@
 //   pack      flat fp32 parameters -> MFMA A-fragments (forward W, backward W^T)
 //   sde       Philox + Box–Muller increments, Euler–Maruyama X_n, s_n = sigma(X_n) dW_n
 //             (eq. disc equations; mu = 0), and |X_N|^2, sum X_N per path
-//   forward   per (step n, 64 paths): Z_n = NN_n(X_n) on MFMA, the Z-dependent part
+//   forward   per (step n, tile of 16 paths per wave): Z_n = NN_n(X_n) on MFMA, the Z-dependent part
 //             c_n of the Y update and v_n = phi_z dt + s_n
 //   scan      per path: Y_{n+1} = Y_n + dt phi_y(Y_n) + c_n, terminal mismatch,
 //             fp64 loss partials, lambda_n = dL/dY_n, fp64 dL/dY0 partials
-//   backward  per (step n, 64 paths): zeta_n = lambda_{n+1} v_n, deltas through NN_n on MFMA
+//   backward  per (step n, tile of 16 paths per wave): zeta_n = lambda_{n+1} v_n, deltas through
+//             NN_n on MFMA
 //   wgrad     dW = sum over paths of delta (x) activation, split over path ranges
 //   reduce    fixed-order sum of the split partials into the flat gradient
 //
