@@ -127,6 +127,20 @@ void fbsde_plan_destroy(fbsde_plan *plan);
 /* Number of fp32 parameters in the flat layout above. */
 fbsde_status fbsde_param_count(const fbsde_plan *plan, int64_t *n_params_host);
 
+/* Block table of the flat layout above (Sec. 2.2: Y_0 aside, the trainable
+ * parameters are z0 and the weights and biases of every network).  A block
+ * is z0 (per-step MLP only) or one W or one b of one dense layer, in layout
+ * order.  Host outputs, each nullable:
+ *   n_params_host : total fp32 parameters (as fbsde_param_count);
+ *   n_blocks_host : number of blocks B;
+ *   offsets_host  : [B + 1] first element of every block, then n_params;
+ *   shapes_host   : [B][2] (rows, cols) of every block: W is (out, in),
+ *                   b and z0 are (len, 1).
+ * Query B first with the arrays NULL, then pass arrays of that size.
+ * Errors: INVALID (NULL plan). */
+fbsde_status fbsde_param_layout(const fbsde_plan *plan, int64_t *n_params_host, int64_t *n_blocks_host,
+                                int64_t *offsets_host, int32_t *shapes_host);
+
 /* Bytes of device workspace the hot calls of this plan need. */
 fbsde_status fbsde_workspace_size(const fbsde_plan *plan, size_t *bytes_host);
 

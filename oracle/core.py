@@ -22,9 +22,10 @@ NET = {"mlp": 0, "resnet": 1}
 
 
 def build() -> str:
-    """Compile liboracle.so with gcc (plain C99, -O2, no fast-math)."""
+    """Compile liboracle.so with gcc (plain C99, -O2, no fast-math; OpenMP
+    over path chunks, whose sums are combined in a fixed order)."""
     src = os.path.join(HERE, "oracle.c")
-    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-o", LIB_PATH, src, "-lm"]
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-Wall", "-shared", "-fPIC", "-o", LIB_PATH, src, "-lm"]
     subprocess.check_call(cmd)
     return LIB_PATH
 
@@ -65,6 +66,9 @@ def lib():
         L.orc_loss_exact_bsb.restype = C.c_int
         L.orc_loss_exact_bsb.argtypes = [C.POINTER(_Problem), C.c_int, C.c_int64, C.c_double, dp,
                                          C.c_uint64, C.c_uint64, C.c_int, dp]
+        L.orc_loss_given_z.restype = C.c_int
+        L.orc_loss_given_z.argtypes = [C.POINTER(_Problem), C.c_int, C.c_int64, C.c_double, dp, C.c_uint64,
+                                       C.c_uint64, dp, C.c_double, dp]
         L.orc_adam.argtypes = [C.c_int64, dp, dp, dp, dp, C.c_int64, C.c_double, C.c_double,
                                C.c_double, C.c_double]
         L.orc_prolong.restype = C.c_int
@@ -73,6 +77,12 @@ def lib():
         L.orc_round_bf16.argtypes = [C.c_double]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's path loop (results do not depend on it)."""
+    C.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+    lib()
 
 
 def _ptr(a):
@@ -187,6 +197,24 @@ def loss_exact_bsb(problem: dict, N: int, M: int, y0: float, *, xi=None, seed=0,
     loss = np.zeros(1)
     rc = lib().orc_loss_exact_bsb(C.byref(ps), int(N), int(M), float(y0), _ptr(xi),
                                   C.c_uint64(seed), C.c_uint64(it), int(bool(flip)), _ptr(loss))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return float(loss[0])
+
+
+def loss_given_z(problem: dict, N: int, M: int, y0: float, Z, *, xi=None, seed=0, it=0, drv_sign=1.0):
+    """Loss of the Euler scheme driven by the given Z[n][m][i] (no network)."""
+    ps, _keep = _problem(problem)
+    d = int(problem["d"])
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    if Z.shape != (N, M, d):
+        raise ValueError("Z must be [N][M][d]")
+    if xi is not None:
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+        assert xi.shape == (N, M, d)
+    loss = np.zeros(1)
+    rc = lib().orc_loss_given_z(C.byref(ps), int(N), int(M), float(y0), _ptr(xi), C.c_uint64(seed),
+                                C.c_uint64(it), _ptr(Z), float(drv_sign), _ptr(loss))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return float(loss[0])

@@ -152,56 +152,97 @@ int64_t orc_param_count(const orc_problem *p, const orc_net *net, int N) {
   return resnet_count(p->d, net->width, net->depth);
 }
 
+/* In bf16 mode every GEMM operand is rounded once (R).  The weight blocks
+ * arrive already rounded (see rounded_weights); a vector operand is rounded
+ * into `buf` once per product instead of once per multiply (same values). */
+static const double *rvec(const orc_net *net, int n, const double *v, double *buf) {
+  if (!net->bf16) return v;
+  for (int i = 0; i < n; ++i) buf[i] = orc_round_bf16(v[i]);
+  return buf;
+}
+
 /* dense layer: out[o] = sum_i R(W[o][i]) R(in[i]) + b[o] */
 static void dense(const orc_net *net, int nout, int nin, const double *W, const double *b,
-                  const double *in, double *out) {
+                  const double *in, double *out, double *buf) {
+  const double *x = rvec(net, nin, in, buf);
   for (int o = 0; o < nout; ++o) {
     double s = 0.0;
-    for (int i = 0; i < nin; ++i) s += R(net, W[(int64_t)o * nin + i]) * R(net, in[i]);
+    for (int i = 0; i < nin; ++i) s += W[(int64_t)o * nin + i] * x[i];
     out[o] = s + b[o];
   }
 }
 
 /* transposed product and outer-product accumulation for the reverse sweep */
 static void dense_t(const orc_net *net, int nout, int nin, const double *W, const double *delta,
-                    double *out_in) {
+                    double *out_in, double *buf) {
+  const double *dl = rvec(net, nout, delta, buf);
   for (int i = 0; i < nin; ++i) {
     double s = 0.0;
-    for (int o = 0; o < nout; ++o) s += R(net, W[(int64_t)o * nin + i]) * R(net, delta[o]);
+    for (int o = 0; o < nout; ++o) s += W[(int64_t)o * nin + i] * dl[o];
     out_in[i] = s;
   }
 }
 static void outer_acc(const orc_net *net, int nout, int nin, const double *delta, const double *in,
-                      double *gW, double *gb) {
+                      double *gW, double *gb, double *buf) {
+  const double *x = rvec(net, nin, in, buf);
   for (int o = 0; o < nout; ++o) {
     double dl = R(net, delta[o]);
-    for (int i = 0; i < nin; ++i) gW[(int64_t)o * nin + i] += dl * R(net, in[i]);
+    for (int i = 0; i < nin; ++i) gW[(int64_t)o * nin + i] += dl * x[i];
     gb[o] += dl;
   }
+}
+
+/* Weight blocks of the flat layout rounded to bf16 (biases and z0 are not
+ * GEMM operands and stay as they are).  Returns params itself in fp64 mode,
+ * else a malloc'd copy the caller frees. */
+static double *rounded_weights(const orc_problem *p, const orc_net *net, int N, const double *params) {
+  if (!net->bf16) return (double *)params;
+  const int d = p->d, w = net->width, L = net->depth;
+  const int64_t npar = orc_param_count(p, net, N);
+  double *q = (double *)malloc(sizeof(double) * (size_t)(npar > 0 ? npar : 1));
+  memcpy(q, params, sizeof(double) * (size_t)npar);
+  /* (out, in) of every dense layer of one network */
+  int lo[36], li[36], nl = 0;
+  if (net->kind == ORC_NET_PER_STEP_MLP) {
+    lo[nl] = w; li[nl++] = d;
+    for (int l = 1; l < L; ++l) { lo[nl] = w; li[nl++] = w; }
+  } else {
+    lo[nl] = w; li[nl++] = d + 1;
+    for (int k = 0; k < L; ++k) { lo[nl] = w; li[nl++] = w; }
+  }
+  lo[nl] = d; li[nl++] = w;
+  const int nets = net->kind == ORC_NET_PER_STEP_MLP ? N - 1 : 1;
+  int64_t off = net->kind == ORC_NET_PER_STEP_MLP ? d : 0;
+  for (int n = 0; n < nets; ++n)
+    for (int k = 0; k < nl; ++k) {
+      for (int64_t e = 0; e < (int64_t)lo[k] * li[k]; ++e) q[off + e] = orc_round_bf16(q[off + e]);
+      off += (int64_t)lo[k] * li[k] + lo[k];
+    }
+  return q;
 }
 
 /* Per-step MLP (Sec. 2.2, one network per time step): d -> w tanh
  * (-> w tanh) x (L-1) -> d linear.  acts[l] holds hidden layer l (w values),
  * after the bf16 rounding that the later layers see. */
 static void mlp_forward(const orc_problem *p, const orc_net *net, const double *P,
-                        const double *x, double *acts, double *z) {
+                        const double *x, double *acts, double *z, double *rb) {
   const int d = p->d, w = net->width, L = net->depth;
   const double *W = P, *b = P + (int64_t)w * d;
-  dense(net, w, d, W, b, x, acts);
+  dense(net, w, d, W, b, x, acts, rb);
   for (int o = 0; o < w; ++o) acts[o] = R(net, tanh(acts[o]));
   const double *q = b + w;
   for (int l = 1; l < L; ++l) {
     const double *Wl = q, *bl = q + (int64_t)w * w;
-    dense(net, w, w, Wl, bl, acts + (int64_t)(l - 1) * w, acts + (int64_t)l * w);
+    dense(net, w, w, Wl, bl, acts + (int64_t)(l - 1) * w, acts + (int64_t)l * w, rb);
     for (int o = 0; o < w; ++o) acts[(int64_t)l * w + o] = R(net, tanh(acts[(int64_t)l * w + o]));
     q = bl + w;
   }
-  dense(net, d, w, q, q + (int64_t)d * w, acts + (int64_t)(L - 1) * w, z);
+  dense(net, d, w, q, q + (int64_t)d * w, acts + (int64_t)(L - 1) * w, z, rb);
 }
 
 static void mlp_backward(const orc_problem *p, const orc_net *net, const double *P, double *G,
                          const double *x, const double *acts, const double *zeta,
-                         double *work /* 2w */) {
+                         double *work /* 2w */, double *rb) {
   const int d = p->d, w = net->width, L = net->depth;
   /* offsets of every layer */
   const int64_t off1 = 0, offb1 = (int64_t)w * d;
@@ -209,17 +250,17 @@ static void mlp_backward(const orc_problem *p, const orc_net *net, const double 
   int64_t offo = offh + (int64_t)(L - 1) * ((int64_t)w * w + w);
   double *dcur = work, *dnext = work + w;
   /* output layer */
-  outer_acc(net, d, w, zeta, acts + (int64_t)(L - 1) * w, G + offo, G + offo + (int64_t)d * w);
-  dense_t(net, d, w, P + offo, zeta, dcur);
+  outer_acc(net, d, w, zeta, acts + (int64_t)(L - 1) * w, G + offo, G + offo + (int64_t)d * w, rb);
+  dense_t(net, d, w, P + offo, zeta, dcur, rb);
   for (int l = L - 1; l >= 0; --l) {
     const double *h = acts + (int64_t)l * w;
     for (int o = 0; o < w; ++o) dcur[o] *= (1.0 - h[o] * h[o]);
     if (l == 0) {
-      outer_acc(net, w, d, dcur, x, G + off1, G + offb1);
+      outer_acc(net, w, d, dcur, x, G + off1, G + offb1, rb);
     } else {
       int64_t ow = offh + (int64_t)(l - 1) * ((int64_t)w * w + w);
-      outer_acc(net, w, w, dcur, acts + (int64_t)(l - 1) * w, G + ow, G + ow + (int64_t)w * w);
-      dense_t(net, w, w, P + ow, dcur, dnext);
+      outer_acc(net, w, w, dcur, acts + (int64_t)(l - 1) * w, G + ow, G + ow + (int64_t)w * w, rb);
+      dense_t(net, w, w, P + ow, dcur, dnext, rb);
       double *t = dcur; dcur = dnext; dnext = t;
     }
   }
@@ -229,89 +270,119 @@ static void mlp_backward(const orc_problem *p, const orc_net *net, const double 
  * forward-Euler step of eq. (ode) with h = 1):
  *   h_0 = tanh(Win [x; t] + bin),  h_k = h_{k-1} + tanh(W_k h_{k-1} + b_k),
  *   Z = Wo h_B + bo.
- * acts holds h_0..h_B (fp64, the residual stream) and a_1..a_B. */
+ * acts holds h_0..h_B (fp64, the residual stream) and a_1..a_B; u is d + 1
+ * scratch values. */
 static void resnet_forward(const orc_problem *p, const orc_net *net, const double *P,
-                           const double *x, double t, double *acts, double *z) {
+                           const double *x, double t, double *acts, double *z, double *u, double *rb) {
   const int d = p->d, w = net->width, B = net->depth;
-  double *u = (double *)malloc(sizeof(double) * (d + 1));
   memcpy(u, x, sizeof(double) * d);
   u[d] = t;
   const double *Win = P, *bin = P + (int64_t)w * (d + 1);
   double *h = acts;
-  dense(net, w, d + 1, Win, bin, u, h);
+  dense(net, w, d + 1, Win, bin, u, h, rb);
   for (int o = 0; o < w; ++o) h[o] = tanh(h[o]);
   const double *q = bin + w;
   double *a = acts + (int64_t)(B + 1) * w;
   for (int k = 1; k <= B; ++k) {
     const double *Wk = q, *bk = q + (int64_t)w * w;
     double *ak = a + (int64_t)(k - 1) * w;
-    dense(net, w, w, Wk, bk, h + (int64_t)(k - 1) * w, ak);
+    dense(net, w, w, Wk, bk, h + (int64_t)(k - 1) * w, ak, rb);
     for (int o = 0; o < w; ++o) {
       ak[o] = tanh(ak[o]);
       h[(int64_t)k * w + o] = h[(int64_t)(k - 1) * w + o] + ak[o];
     }
     q = bk + w;
   }
-  dense(net, d, w, q, q + (int64_t)d * w, h + (int64_t)B * w, z);
-  free(u);
+  dense(net, d, w, q, q + (int64_t)d * w, h + (int64_t)B * w, z, rb);
 }
 
 static void resnet_backward(const orc_problem *p, const orc_net *net, const double *P, double *G,
                             const double *x, double t, const double *acts, const double *zeta,
-                            double *work /* 3w + d + 1 */) {
+                            double *work /* 3w + d + 1 */, double *rb) {
   const int d = p->d, w = net->width, B = net->depth;
   const int64_t offin = 0, offbin = (int64_t)w * (d + 1);
   const int64_t offk = offbin + w;
   const int64_t offo = offk + (int64_t)B * ((int64_t)w * w + w);
   const double *h = acts, *a = acts + (int64_t)(B + 1) * w;
   double *dh = work, *dpre = work + w, *tmp = work + 2 * w, *u = work + 3 * w;
-  outer_acc(net, d, w, zeta, h + (int64_t)B * w, G + offo, G + offo + (int64_t)d * w);
-  dense_t(net, d, w, P + offo, zeta, dh);
+  outer_acc(net, d, w, zeta, h + (int64_t)B * w, G + offo, G + offo + (int64_t)d * w, rb);
+  dense_t(net, d, w, P + offo, zeta, dh, rb);
   for (int k = B; k >= 1; --k) {
     const double *ak = a + (int64_t)(k - 1) * w;
     int64_t ow = offk + (int64_t)(k - 1) * ((int64_t)w * w + w);
     /* bf16 form: the derivative reads the bf16-stored activation */
     for (int o = 0; o < w; ++o) dpre[o] = dh[o] * (1.0 - R(net, ak[o]) * R(net, ak[o]));
-    outer_acc(net, w, w, dpre, h + (int64_t)(k - 1) * w, G + ow, G + ow + (int64_t)w * w);
-    dense_t(net, w, w, P + ow, dpre, tmp);
+    outer_acc(net, w, w, dpre, h + (int64_t)(k - 1) * w, G + ow, G + ow + (int64_t)w * w, rb);
+    dense_t(net, w, w, P + ow, dpre, tmp, rb);
     for (int o = 0; o < w; ++o) dh[o] += tmp[o];
   }
   for (int o = 0; o < w; ++o) dpre[o] = dh[o] * (1.0 - R(net, h[o]) * R(net, h[o]));
   memcpy(u, x, sizeof(double) * d);
   u[d] = t;
-  outer_acc(net, w, d + 1, dpre, u, G + offin, G + offbin);
+  outer_acc(net, w, d + 1, dpre, u, G + offin, G + offbin, rb);
+}
+
+/* Per-path scratch of one thread: the whole history of one path. */
+typedef struct {
+  double *X, *Zs, *S, *Y, *A, *xim, *dw, *zeta, *pz, *work, *u, *rb;
+} path_buf;
+
+static int path_buf_alloc(path_buf *b, const orc_problem *p, const orc_net *net, int N) {
+  const int d = p->d, w = net->width;
+  const int mlp = (net->kind == ORC_NET_PER_STEP_MLP);
+  const int64_t nacts = mlp ? (int64_t)net->depth * w : (int64_t)(2 * net->depth + 1) * w;
+  const int nr = (d + 1 > w ? d + 1 : w);
+  b->X = (double *)calloc((size_t)(N + 1) * d, sizeof(double));
+  b->Zs = (double *)calloc((size_t)N * d, sizeof(double));
+  b->S = (double *)calloc((size_t)N * d, sizeof(double));
+  b->Y = (double *)calloc((size_t)(N + 1), sizeof(double));
+  b->A = (double *)calloc((size_t)N * nacts + 1, sizeof(double));
+  b->xim = (double *)calloc((size_t)d, sizeof(double));
+  b->dw = (double *)calloc((size_t)d, sizeof(double));
+  b->zeta = (double *)calloc((size_t)d, sizeof(double));
+  b->pz = (double *)calloc((size_t)d, sizeof(double));
+  b->work = (double *)calloc((size_t)(3 * w + d + 1), sizeof(double));
+  b->u = (double *)calloc((size_t)(d + 1), sizeof(double));
+  b->rb = (double *)calloc((size_t)nr, sizeof(double));
+  return b->X && b->Zs && b->S && b->Y && b->A && b->xim && b->dw && b->zeta && b->pz && b->work && b->u &&
+         b->rb;
+}
+
+static void path_buf_free(path_buf *b) {
+  free(b->X); free(b->Zs); free(b->S); free(b->Y); free(b->A); free(b->xim); free(b->dw);
+  free(b->zeta); free(b->pz); free(b->work); free(b->u); free(b->rb);
 }
 
 /* Forward Euler–Maruyama sweep of one path m, eq. (disc equations) with
  * mu = 0; stores X_n, Z_n, s_n = sigma(X_n) dW_n, Y_n and the network
- * activations of every step.  xi: [N][Mx][d] normals or NULL for Philox. */
-static void path_forward(const orc_problem *p, const orc_net *net, int N, const double *params,
+ * activations of every step.  xi: [N][Mx][d] normals or NULL for Philox.
+ * P holds the parameters with bf16-rounded weights in bf16 mode. */
+static void path_forward(const orc_problem *p, const orc_net *net, int N, const double *P,
                          double y0, const double *xi, int64_t Mx, uint64_t seed, uint64_t iter,
-                         int64_t m, double *X, double *Zs, double *S, double *Y, double *A,
-                         double *xim, double *dw) {
+                         int64_t m, path_buf *b) {
   const int d = p->d, w = net->width;
   const int mlp = (net->kind == ORC_NET_PER_STEP_MLP);
   const int64_t nacts = mlp ? (int64_t)net->depth * w : (int64_t)(2 * net->depth + 1) * w;
   const int64_t pstep = mlp ? mlp_step_count(d, w, net->depth) : 0;
   const double dt = p->T / N, sdt = sqrt(dt);
-  memcpy(X, p->x0, sizeof(double) * d);
-  Y[0] = y0;
+  memcpy(b->X, p->x0, sizeof(double) * d);
+  b->Y[0] = y0;
   for (int n = 0; n < N; ++n) {
-    const double *xn = X + (int64_t)n * d;
-    double *zn = Zs + (int64_t)n * d, *sn = S + (int64_t)n * d;
+    const double *xn = b->X + (int64_t)n * d;
+    double *zn = b->Zs + (int64_t)n * d, *sn = b->S + (int64_t)n * d;
     if (mlp && n == 0) {
-      memcpy(zn, params, sizeof(double) * d);                 /* Z_0 = z0 */
+      memcpy(zn, P, sizeof(double) * d);                      /* Z_0 = z0 */
     } else if (mlp) {
-      mlp_forward(p, net, params + d + (int64_t)(n - 1) * pstep, xn, A + (int64_t)n * nacts, zn);
+      mlp_forward(p, net, P + d + (int64_t)(n - 1) * pstep, xn, b->A + (int64_t)n * nacts, zn, b->rb);
     } else {
-      resnet_forward(p, net, params, xn, n * dt, A + (int64_t)n * nacts, zn);
+      resnet_forward(p, net, P, xn, n * dt, b->A + (int64_t)n * nacts, zn, b->u, b->rb);
     }
-    if (xi) memcpy(xim, xi + ((int64_t)n * Mx + m) * d, sizeof(double) * d);
-    else normals_one(seed, iter, n, m, d, xim);
-    for (int i = 0; i < d; ++i) dw[i] = sdt * xim[i];
-    diffusion(p, xn, dw, sn);
-    Y[n + 1] = Y[n] + driver(p, xn, Y[n], zn) * dt + dot(d, zn, sn);
-    for (int i = 0; i < d; ++i) X[(int64_t)(n + 1) * d + i] = xn[i] + sn[i];
+    if (xi) memcpy(b->xim, xi + ((int64_t)n * Mx + m) * d, sizeof(double) * d);
+    else normals_one(seed, iter, n, m, d, b->xim);
+    for (int i = 0; i < d; ++i) b->dw[i] = sdt * b->xim[i];
+    diffusion(p, xn, b->dw, sn);
+    b->Y[n + 1] = b->Y[n] + driver(p, xn, b->Y[n], zn) * dt + dot(d, zn, sn);
+    for (int i = 0; i < d; ++i) b->X[(int64_t)(n + 1) * d + i] = xn[i] + sn[i];
   }
 }
 
@@ -322,6 +393,8 @@ static int check_args(const orc_problem *p, const orc_net *net, int N, int64_t M
   if (!p || !net || p->d < 1 || N < 1 || M < 1 || !(p->T > 0.0) || !p->x0) return 1;
   if (net->width < 1 || net->depth < 1) return 1;
   if (net->kind != ORC_NET_PER_STEP_MLP && net->kind != ORC_NET_SHARED_RESNET) return 1;
+  if (net->kind == ORC_NET_PER_STEP_MLP && net->depth > 34) return 1;
+  if (net->kind == ORC_NET_SHARED_RESNET && net->depth > 34) return 1;
   return 0;
 }
 
@@ -337,55 +410,102 @@ int orc_loss_grad(const orc_problem *p, const orc_net *net, int N, int64_t M,
   const int64_t pstep = mlp ? mlp_step_count(d, w, net->depth) : 0;
   const int64_t npar = orc_param_count(p, net, N);
   const double dt = p->T / N;
-
-  double *X = (double *)calloc((size_t)(N + 1) * d, sizeof(double));
-  double *Zs = (double *)calloc((size_t)N * d, sizeof(double));
-  double *S = (double *)calloc((size_t)N * d, sizeof(double));
-  double *Y = (double *)calloc((size_t)(N + 1), sizeof(double));
-  double *A = (double *)calloc((size_t)N * nacts + 1, sizeof(double));
-  double *xim = (double *)calloc((size_t)d, sizeof(double));
-  double *dw = (double *)calloc((size_t)d, sizeof(double));
-  double *zeta = (double *)calloc((size_t)d, sizeof(double));
-  double *pz = (double *)calloc((size_t)d, sizeof(double));
-  double *work = (double *)calloc((size_t)(3 * w + d + 1), sizeof(double));
+  const int want_adj = grad || grad_y0;
+  const int64_t nch = (M + ORC_PATH_CHUNK - 1) / ORC_PATH_CHUNK;
+  double *P = rounded_weights(p, net, N, params);
   if (grad) memset(grad, 0, sizeof(double) * (size_t)npar);
   double gy0 = 0.0, lsum = 0.0;
+  int fail = 0;
 
-  for (int64_t m = 0; m < M; ++m) {
-    path_forward(p, net, N, params, y0, xi ? xi : NULL, M, seed, iter, m, X, Zs, S, Y, A, xim, dw);
-    const double *xN = X + (int64_t)N * d;
-    double e = Y[N] - terminal(p, xN);
-    lsum += e * e;
-    if (XN) memcpy(XN + m * d, xN, sizeof(double) * d);
-    if (YN) YN[m] = Y[N];
-    if (Ypath) for (int n = 0; n <= N; ++n) Ypath[(int64_t)n * M + m] = Y[n];
-
-    if (grad || grad_y0) {
-      /* reverse sweep: lambda_n = dL/dY_n, zeta_n = dL/dZ_n */
-      double lam = 2.0 * e / (double)M;
-      for (int n = N - 1; n >= 0; --n) {
-        const double *xn = X + (int64_t)n * d, *zn = Zs + (int64_t)n * d, *sn = S + (int64_t)n * d;
-        driver_dz(p, xn, zn, pz);
-        for (int i = 0; i < d; ++i) zeta[i] = lam * (pz[i] * dt + sn[i]);
-        double lam_prev = lam * (1.0 + driver_dy(p, Y[n]) * dt);
-        if (grad) {
-          if (mlp && n == 0) {
-            for (int i = 0; i < d; ++i) grad[i] += R(net, zeta[i]);
-          } else if (mlp) {
-            int64_t off = d + (int64_t)(n - 1) * pstep;
-            mlp_backward(p, net, params + off, grad + off, xn, A + (int64_t)n * nacts, zeta, work);
-          } else {
-            resnet_backward(p, net, params, grad, xn, n * dt, A + (int64_t)n * nacts, zeta, work);
+#pragma omp parallel
+  {
+    path_buf b;
+    int ok = path_buf_alloc(&b, p, net, N);
+    double *gpart = grad ? (double *)calloc((size_t)npar, sizeof(double)) : NULL;
+    if (grad && !gpart) ok = 0;
+#pragma omp for ordered schedule(dynamic, 1)
+    for (int64_t c = 0; c < nch; ++c) {
+      /* chunk c: paths [c K, (c+1) K), summed from zero in path order */
+      double lc = 0.0, gc = 0.0;
+      if (ok) {
+        if (gpart) memset(gpart, 0, sizeof(double) * (size_t)npar);
+        const int64_t m1 = (c + 1) * ORC_PATH_CHUNK < M ? (c + 1) * ORC_PATH_CHUNK : M;
+        for (int64_t m = c * ORC_PATH_CHUNK; m < m1; ++m) {
+          path_forward(p, net, N, P, y0, xi, M, seed, iter, m, &b);
+          const double *xN = b.X + (int64_t)N * d;
+          double e = b.Y[N] - terminal(p, xN);
+          lc += e * e;
+          if (XN) memcpy(XN + m * d, xN, sizeof(double) * d);
+          if (YN) YN[m] = b.Y[N];
+          if (Ypath) for (int n = 0; n <= N; ++n) Ypath[(int64_t)n * M + m] = b.Y[n];
+          if (!want_adj) continue;
+          /* reverse sweep: lambda_n = dL/dY_n, zeta_n = dL/dZ_n */
+          double lam = 2.0 * e / (double)M;
+          for (int n = N - 1; n >= 0; --n) {
+            const double *xn = b.X + (int64_t)n * d, *zn = b.Zs + (int64_t)n * d, *sn = b.S + (int64_t)n * d;
+            driver_dz(p, xn, zn, b.pz);
+            for (int i = 0; i < d; ++i) b.zeta[i] = lam * (b.pz[i] * dt + sn[i]);
+            double lam_prev = lam * (1.0 + driver_dy(p, b.Y[n]) * dt);
+            if (gpart) {
+              if (mlp && n == 0) {
+                for (int i = 0; i < d; ++i) gpart[i] += R(net, b.zeta[i]);
+              } else if (mlp) {
+                int64_t off = d + (int64_t)(n - 1) * pstep;
+                mlp_backward(p, net, P + off, gpart + off, xn, b.A + (int64_t)n * nacts, b.zeta, b.work, b.rb);
+              } else {
+                resnet_backward(p, net, P, gpart, xn, n * dt, b.A + (int64_t)n * nacts, b.zeta, b.work, b.rb);
+              }
+            }
+            lam = lam_prev;
           }
+          gc += lam;
         }
-        lam = lam_prev;
       }
-      gy0 += lam;
+#pragma omp ordered
+      {
+        /* chunk partials enter the totals in chunk order */
+        if (!ok) fail = 1;
+        lsum += lc;
+        gy0 += gc;
+        if (grad && gpart && ok)
+          for (int64_t k = 0; k < npar; ++k) grad[k] += gpart[k];
+      }
     }
+    free(gpart);
+    path_buf_free(&b);
   }
+  if (P != params) free(P);
+  if (fail) return 2;
   *loss = lsum / (double)M;
   if (grad_y0) *grad_y0 = gy0;
-  free(X); free(Zs); free(S); free(Y); free(A); free(xim); free(dw); free(zeta); free(pz); free(work);
+  return 0;
+}
+
+int orc_loss_given_z(const orc_problem *p, int N, int64_t M, double y0, const double *xi,
+                     uint64_t seed, uint64_t iter, const double *Z, double drv_sign, double *loss) {
+  if (!p || p->d < 1 || N < 1 || M < 1 || !(p->T > 0.0) || !p->x0 || !Z || !loss) return 1;
+  const int d = p->d;
+  const double dt = p->T / N, sdt = sqrt(dt);
+  double *x = (double *)malloc(sizeof(double) * d), *dw = (double *)malloc(sizeof(double) * d);
+  double *sn = (double *)malloc(sizeof(double) * d), *xim = (double *)malloc(sizeof(double) * d);
+  double lsum = 0.0;
+  for (int64_t m = 0; m < M; ++m) {
+    memcpy(x, p->x0, sizeof(double) * d);
+    double y = y0;
+    for (int n = 0; n < N; ++n) {
+      const double *z = Z + ((int64_t)n * M + m) * d;
+      if (xi) memcpy(xim, xi + ((int64_t)n * M + m) * d, sizeof(double) * d);
+      else normals_one(seed, iter, n, m, d, xim);
+      for (int i = 0; i < d; ++i) dw[i] = sdt * xim[i];
+      diffusion(p, x, dw, sn);
+      y = y + drv_sign * driver(p, x, y, z) * dt + dot(d, z, sn);
+      for (int i = 0; i < d; ++i) x[i] += sn[i];
+    }
+    double e = y - terminal(p, x);
+    lsum += e * e;
+  }
+  *loss = lsum / (double)M;
+  free(x); free(dw); free(sn); free(xim);
   return 0;
 }
 
@@ -459,21 +579,22 @@ int orc_prolong(const orc_problem *p, const orc_net *net, int Nc, int Nf,
 int orc_paths(const orc_problem *p, const orc_net *net, int N, const double *params, double y0,
               uint64_t seed, uint64_t iter, const int64_t *idx, int64_t k, double *YN, double *XN) {
   if (check_args(p, net, N, 1) || !params || !idx || k < 0) return 1;
-  const int d = p->d, w = net->width;
-  const int mlp = (net->kind == ORC_NET_PER_STEP_MLP);
-  const int64_t nacts = mlp ? (int64_t)net->depth * w : (int64_t)(2 * net->depth + 1) * w;
-  double *X = (double *)calloc((size_t)(N + 1) * d, sizeof(double));
-  double *Zs = (double *)calloc((size_t)N * d, sizeof(double));
-  double *S = (double *)calloc((size_t)N * d, sizeof(double));
-  double *Y = (double *)calloc((size_t)(N + 1), sizeof(double));
-  double *A = (double *)calloc((size_t)N * nacts + 1, sizeof(double));
-  double *xim = (double *)calloc((size_t)d, sizeof(double));
-  double *dw = (double *)calloc((size_t)d, sizeof(double));
-  for (int64_t i = 0; i < k; ++i) {
-    path_forward(p, net, N, params, y0, NULL, 0, seed, iter, idx[i], X, Zs, S, Y, A, xim, dw);
-    if (YN) YN[i] = Y[N];
-    if (XN) memcpy(XN + i * d, X + (int64_t)N * d, sizeof(double) * d);
+  const int d = p->d;
+  double *P = rounded_weights(p, net, N, params);
+  int fail = 0;
+#pragma omp parallel
+  {
+    path_buf b;
+    int ok = path_buf_alloc(&b, p, net, N);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t i = 0; i < k; ++i) {
+      if (!ok) { fail = 1; continue; }
+      path_forward(p, net, N, P, y0, NULL, 0, seed, iter, idx[i], &b);
+      if (YN) YN[i] = b.Y[N];
+      if (XN) memcpy(XN + i * d, b.X + (int64_t)N * d, sizeof(double) * d);
+    }
+    path_buf_free(&b);
   }
-  free(X); free(Zs); free(S); free(Y); free(A); free(xim); free(dw);
-  return 0;
+  if (P != params) free(P);
+  return fail ? 2 : 0;
 }

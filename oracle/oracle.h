@@ -80,6 +80,13 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
  * the log and V = (u >> 8) 2^-24 in [0,1) under the angle. */
 void orc_normals(uint64_t seed, uint64_t iter, int N, int64_t M, int d, double *xi);
 
+/* Sums over paths (the batch mean of Sec. 2.2 eq. (loss), dL/dY0 and the
+ * weight gradients) are formed per chunk of ORC_PATH_CHUNK consecutive paths,
+ * each chunk summed from zero in path order, and the chunk partials are added
+ * in chunk order.  The association is fixed by this constant alone, so the
+ * result does not depend on how many OpenMP threads evaluate the chunks. */
+#define ORC_PATH_CHUNK 64
+
 /* One loss evaluation and (optionally) its gradient.
  *   xi      : [N][M][d] normals, or NULL to draw them with orc_normals
  *   grad    : [param_count] or NULL ; grad_y0 : or NULL
@@ -106,6 +113,16 @@ int orc_paths(const orc_problem *p, const orc_net *net, int N, const double *par
 int orc_loss_exact_bsb(const orc_problem *p, int N, int64_t M, double y0,
                        const double *xi, uint64_t seed, uint64_t iter,
                        int flip, double *loss);
+
+/* The Euler scheme of eq. (disc equations) driven by a given Z process
+ * instead of a network: Z is [N][M][d] (Z_n of path m), Y_0 = y0, the same
+ * normals, diffusion, driver phi and terminal g as orc_loss_grad.  phi enters
+ * multiplied by drv_sign (1 for the convention dY = phi dt + Z^T sigma dW).
+ * Writes the loss (1/M) sum_m (Y_N - g(X_N))^2.  Fed with Y_0 = u(0, x0) and
+ * Z_n = grad u(t_n, X_n) of a problem's exact solution, the mean loss must
+ * vanish like O(dt): this pins the driver and terminal branches. */
+int orc_loss_given_z(const orc_problem *p, int N, int64_t M, double y0, const double *xi,
+                     uint64_t seed, uint64_t iter, const double *Z, double drv_sign, double *loss);
 
 /* Adam (Kingma & Ba 2015), one step t >= 1 on n parameters. */
 void orc_adam(int64_t n, double *theta, const double *g, double *m, double *v,

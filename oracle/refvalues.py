@@ -31,12 +31,22 @@ def bsb_u(t, x, T=1.0, r=0.05, sigma=0.4):
     return math.exp((r + sigma * sigma) * (T - t)) * float(np.dot(x, x))
 
 
-def hjb_y0_quad(d: int = 100, T: float = 1.0) -> float:
-    """-ln E[2 / (1 + 2 T q)], q ~ chi^2_d, by adaptive quadrature."""
+def hjb_y0_quad(d: int = 100, T: float = 1.0, lam: float = 1.0) -> float:
+    """-(1/lam) ln E[(2 / (1 + 2 T q))^lam], q ~ chi^2_d, by adaptive
+    quadrature (u(0, 0) of the Cole–Hopf formula; lam = 1 in Sec. 4)."""
     lo, hi = stats.chi2.ppf(1e-15, d), stats.chi2.ppf(1.0 - 1e-15, d)
-    f = lambda q: 2.0 / (1.0 + 2.0 * T * q) * stats.chi2.pdf(q, d)
+    f = lambda q: (2.0 / (1.0 + 2.0 * T * q)) ** lam * stats.chi2.pdf(q, d)
     val, _err = integrate.quad(f, lo, hi, limit=500, epsabs=0.0, epsrel=1e-13)
-    return float(-math.log(val))
+    return float(-math.log(val) / lam)
+
+
+def hjb_mean_g(d: int = 100, T: float = 1.0) -> float:
+    """E[g(X_T)] = E[ln((1 + 2 T q) / 2)], q ~ chi^2_d: the value Y0 would take
+    without the driver (lam = 0)."""
+    lo, hi = stats.chi2.ppf(1e-15, d), stats.chi2.ppf(1.0 - 1e-15, d)
+    f = lambda q: math.log(0.5 * (1.0 + 2.0 * T * q)) * stats.chi2.pdf(q, d)
+    val, _err = integrate.quad(f, lo, hi, limit=500, epsabs=0.0, epsrel=1e-13)
+    return float(val)
 
 
 def hjb_y0_mc(d: int = 100, T: float = 1.0, n: int = 10 ** 6, seed: int = 7):
@@ -55,6 +65,49 @@ def hjb_y0_mc(d: int = 100, T: float = 1.0, n: int = 10 ** 6, seed: int = 7):
     var = acc2 / n - mean * mean
     se = math.sqrt(var / n)
     return float(-math.log(mean)), float(se / mean)
+
+
+def hjb_grad_u(tau, X, lam: float = 1.0, n_par: int = 160, n_perp: int = 48):
+    """grad u of the Hamilton–Jacobi–Bellman problem at time-to-go tau > 0 and
+    points X [K][d], from the Cole–Hopf formula of Sec. 4:
+    u = -(1/lam) ln w, w(tau, x) = E[exp(-lam g(x + sqrt(2) W_tau))] with
+    g(y) = ln((1 + |y|^2) / 2), so exp(-g) = 2 / (1 + |y|^2) (the formula is
+    written for lam = 1; other lam use exp(-lam g) = (2 / (1 + |y|^2))^lam).
+    grad w = E[-lam exp(-lam g(y)) 2 y / (1 + |y|^2)] and grad u = -grad w / (lam w).
+    Both expectations depend on x through rho = |x| only: with s = sqrt(2 tau)
+    and x along e_1, |y|^2 = (rho + s xi)^2 + s^2 q, xi ~ N(0, 1) and
+    q ~ chi^2_{d-1} independent, and grad w points along x.  Gauss–Hermite in
+    xi times generalized Gauss–Laguerre in q / 2 (exact for the chi-square
+    weight); returns (u [K], grad u [K][d])."""
+    from numpy.polynomial.hermite_e import hermegauss
+    from scipy.special import roots_genlaguerre
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    K, d = X.shape
+    s = math.sqrt(2.0 * tau)
+    xi, wx = hermegauss(n_par)
+    wx = wx / math.sqrt(2.0 * math.pi)
+    if d > 1:
+        r, wr = roots_genlaguerre(n_perp, 0.5 * (d - 1) - 1.0)
+        wr = wr / math.gamma(0.5 * (d - 1))
+        q = 2.0 * r
+    else:
+        q, wr = np.zeros(1), np.ones(1)
+    rho = np.sqrt((X * X).sum(1))
+    u = np.empty(K)
+    gr = np.empty(K)
+    for a in range(0, K, 256):
+        b = min(K, a + 256)
+        yp = rho[a:b, None, None] + s * xi[None, :, None]          # component along x
+        y2 = yp * yp + s * s * q[None, None, :]
+        e = (2.0 / (1.0 + y2)) ** lam                               # exp(-lam g(y))
+        wgt = wx[None, :, None] * wr[None, None, :]
+        w = (e * wgt).sum((1, 2))
+        dw = (-lam * e * 2.0 * yp / (1.0 + y2) * wgt).sum((1, 2))
+        u[a:b] = -np.log(w) / lam
+        gr[a:b] = -dw / (lam * w)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        unit = np.where(rho[:, None] > 0, X / rho[:, None], 0.0)
+    return u, gr[:, None] * unit
 
 
 def radial_heat_quad(d: int, tau: float, g) -> float:

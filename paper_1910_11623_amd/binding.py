@@ -21,7 +21,7 @@ NET_KIND = {"mlp": 0, "resnet": 1}
 PREC = {"fp32": 0, "bf16": 1}
 
 EXPORTS = [
-    "fbsde_plan_create", "fbsde_plan_destroy", "fbsde_param_count", "fbsde_workspace_size",
+    "fbsde_plan_create", "fbsde_plan_destroy", "fbsde_param_count", "fbsde_param_layout", "fbsde_workspace_size",
     "fbsde_forward", "fbsde_forward_backward", "fbsde_adam_step", "fbsde_prolong",
     "fbsde_sample_normals", "fbsde_terminal_mean", "fbsde_terminal_states",
     "fbsde_profile_enable", "fbsde_profile_read", "fbsde_plan_config", "fbsde_plan_get_config",
@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH):
     L.fbsde_plan_destroy.argtypes = [vp]
     L.fbsde_plan_destroy.restype = None
     L.fbsde_param_count.argtypes = [vp, C.POINTER(i64)]
+    L.fbsde_param_layout.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(C.c_int32)]
     L.fbsde_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.fbsde_forward.argtypes = [vp, vp, vp, u64, u64, vp, vp, vp]
     L.fbsde_forward_backward.argtypes = [vp, vp, vp, vp, vp, vp, u64, u64, vp, vp]

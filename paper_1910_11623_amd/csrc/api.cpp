@@ -521,6 +521,41 @@ fbsde_status fbsde_param_count(const fbsde_plan* plan, int64_t* n) {
   return FBSDE_OK;
 }
 
+fbsde_status fbsde_param_layout(const fbsde_plan* plan, int64_t* n_params, int64_t* n_blocks, int64_t* offsets,
+                                int32_t* shapes) {
+  if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
+  const Geo& g = plan->geo;
+  // dense layers of one network as (out, in)
+  std::vector<std::pair<int, int>> layers;
+  if (g.kind == 0) {
+    layers.push_back({g.w, g.d});
+    for (int l = 2; l <= g.L; ++l) layers.push_back({g.w, g.w});
+  } else {
+    layers.push_back({g.w, g.d + 1});
+    for (int k = 1; k <= g.L; ++k) layers.push_back({g.w, g.w});
+  }
+  layers.push_back({g.d, g.w});
+  int64_t blk = 0, off = 0;
+  auto add = [&](int rows, int cols) {
+    if (offsets) offsets[blk] = off;
+    if (shapes) { shapes[2 * blk] = rows; shapes[2 * blk + 1] = cols; }
+    off += (int64_t)rows * cols;
+    ++blk;
+  };
+  const int nets = g.kind == 0 ? g.N - 1 : 1;
+  if (g.kind == 0) add(g.d, 1);  // z0
+  for (int n = 0; n < nets; ++n)
+    for (const auto& lo : layers) {
+      add(lo.first, lo.second);  // W
+      add(lo.first, 1);          // b
+    }
+  if (offsets) offsets[blk] = off;
+  if (off != g.nparams) return fail(FBSDE_ERR_INVALID, "internal: block table does not cover the parameters");
+  if (n_params) *n_params = g.nparams;
+  if (n_blocks) *n_blocks = blk;
+  return FBSDE_OK;
+}
+
 fbsde_status fbsde_workspace_size(const fbsde_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return fail(FBSDE_ERR_INVALID, "plan or output is NULL");
   const_cast<fbsde_plan*>(plan)->ws_queried = true;

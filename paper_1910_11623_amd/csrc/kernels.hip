@@ -263,8 +263,13 @@ __global__ __launch_bounds__(256) void k_pack(Geo g, const float* __restrict__ p
 }
 
 // --------------------------------------------------------------- SDE kernel
-// Thread = (path m, dims 4j..4j+3); a block holds whole paths so that
-// |X_N|^2 and sum X_N reduce in LDS in a fixed order.
+// A path's G = dp / 4 groups of 4 dims are spread over T = min(G, 256)
+// consecutive threads of a block (thread j takes groups j, j + T, ...); a
+// block holds floor(256 / T) whole paths, so |X_N|^2 and sum X_N reduce in
+// LDS in a fixed order: per thread over its groups, then over the path's T
+// threads.
+__device__ __forceinline__ int sde_threads_per_path(int dp) { return min(dp / 4, 256); }
+
 __global__ __launch_bounds__(256) void k_sde(Geo g, const float* __restrict__ x0, uint64_t seed,
                                              uint64_t iter_imm, const uint64_t* __restrict__ iter_dev,
                                              float* __restrict__ X, float* __restrict__ V,
@@ -272,37 +277,41 @@ __global__ __launch_bounds__(256) void k_sde(Geo g, const float* __restrict__ x0
   const uint64_t iter = iter_dev ? iter_dev[0] : iter_imm;
   __shared__ float sq[256], sl[256];
   const int G = g.dp / 4;
-  const int ppb = max(1, 256 / G);
-  const int lp = threadIdx.x / G, j = threadIdx.x % G;
+  const int T = sde_threads_per_path(g.dp);
+  const int ppb = 256 / T;
+  const int lp = threadIdx.x / T, j0 = threadIdx.x % T;
   const int m = blockIdx.x * ppb + lp;
   const bool active = lp < ppb && m < g.M;
   float q = 0.f, lin = 0.f;
   if (active) {
-    f32x4 x = ld4(x0 + 4 * j);
     const size_t rowM = (size_t)g.M * g.dp;
-    const size_t off = (size_t)m * g.dp + 4 * j;
-    for (int n = 0; n < g.N; ++n) {
-      const f32x4 z = normals4(seed, iter, j, n, m);
-      f32x4 s;
+    for (int j = j0; j < G; j += T) {
+      f32x4 x = ld4(x0 + 4 * j);
+      const size_t off = (size_t)m * g.dp + 4 * j;
+      for (int n = 0; n < g.N; ++n) {
+        const f32x4 z = normals4(seed, iter, j, n, m);
+        f32x4 s;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float dw = g.sqdt * z[r];
-        s[r] = (4 * j + r < g.d) ? (g.sde == SDE_GBM ? g.sde_s * x[r] * dw : g.sde_s * dw) : 0.f;
+        for (int r = 0; r < 4; ++r) {
+          const float dw = g.sqdt * z[r];
+          s[r] = (4 * j + r < g.d) ? (g.sde == SDE_GBM ? g.sde_s * x[r] * dw : g.sde_s * dw) : 0.f;
+        }
+        st4(X + n * rowM + off, x);
+        st4(V + n * rowM + off, s);
+        x += s;
       }
-      st4(X + n * rowM + off, x);
-      st4(V + n * rowM + off, s);
-      x += s;
+      st4(X + (size_t)g.N * rowM + off, x);
+      q += x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3];
+      lin += x[0] + x[1] + x[2] + x[3];
     }
-    st4(X + (size_t)g.N * rowM + off, x);
-    q = x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3];
-    lin = x[0] + x[1] + x[2] + x[3];
   }
   sq[threadIdx.x] = q;
   sl[threadIdx.x] = lin;
   __syncthreads();
-  if (active && j == 0) {
+  if (active && j0 == 0) {
+    // the path's T threads are threadIdx.x .. threadIdx.x + T - 1 < 256
     float a = 0.f, b = 0.f;
-    for (int k = 0; k < G; ++k) { a += sq[threadIdx.x + k]; b += sl[threadIdx.x + k]; }
+    for (int k = 0; k < T; ++k) { a += sq[threadIdx.x + k]; b += sl[threadIdx.x + k]; }
     QN[m] = a;
     LN[m] = b;
   }
@@ -1293,8 +1302,8 @@ hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* pac
 
 hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t iter, const uint64_t* iter_dev,
                       float* X, float* V, float* QN, float* LN, hipStream_t s) {
-  const int G = g.dp / 4;
-  const int ppb = G >= 256 ? 1 : 256 / G;
+  const int T = g.dp / 4 < 256 ? g.dp / 4 : 256;  // threads per path, as in k_sde
+  const int ppb = 256 / T;
   const unsigned blocks = (unsigned)((g.M + ppb - 1) / ppb);
   k_sde<<<blocks, 256, 0, s>>>(g, x0, seed, iter, iter_dev, X, V, QN, LN);
   return hipGetLastError();

@@ -67,6 +67,16 @@ class Plan:
             self._h = None
 
     # ---------------------------------------------------------------- calls
+    def param_layout(self) -> list:
+        """[(offset, rows, cols)] of every block of the flat parameter layout
+        (z0, then W and b of every dense layer), from fbsde_param_layout."""
+        nb = C.c_int64()
+        B.check(self.lib.fbsde_param_layout(self._h, None, C.byref(nb), None, None))
+        offs = (C.c_int64 * (nb.value + 1))()
+        shp = (C.c_int32 * (2 * nb.value))()
+        B.check(self.lib.fbsde_param_layout(self._h, None, None, offs, shp))
+        return [(int(offs[k]), int(shp[2 * k]), int(shp[2 * k + 1])) for k in range(nb.value)]
+
     def _check_params(self, params: torch.Tensor):
         if params.dtype != torch.float32 or params.numel() != self.n_params or not params.is_contiguous():
             raise ValueError(f"params must be a contiguous fp32 tensor of {self.n_params} elements")
