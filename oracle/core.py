@@ -41,6 +41,12 @@ class _Net(C.Structure):
     _fields_ = [("kind", C.c_int), ("width", C.c_int), ("depth", C.c_int), ("bf16", C.c_int)]
 
 
+class _UNet(C.Structure):
+    _fields_ = [("arch", C.c_int), ("width", C.c_int), ("depth", C.c_int), ("eps", C.c_double)]
+
+
+UARCH = {"fc": 0, "res": 1, "nais": 2}
+
 _lib = None
 
 
@@ -75,6 +81,18 @@ def lib():
         L.orc_prolong.argtypes = [C.POINTER(_Problem), C.POINTER(_Net), C.c_int, C.c_int, dp, dp]
         L.orc_round_bf16.restype = C.c_double
         L.orc_round_bf16.argtypes = [C.c_double]
+        L.orc_unet_param_count.restype = C.c_int64
+        L.orc_unet_param_count.argtypes = [C.POINTER(_Problem), C.POINTER(_UNet)]
+        L.orc_unet_loss_grad.restype = C.c_int
+        L.orc_unet_loss_grad.argtypes = [C.POINTER(_Problem), C.POINTER(_UNet), C.c_int, C.c_int64, dp, dp,
+                                         C.c_uint64, C.c_uint64, C.c_double, dp, dp, dp, dp]
+        L.orc_unet_loss_given_uz.restype = C.c_int
+        L.orc_unet_loss_given_uz.argtypes = [C.POINTER(_Problem), C.c_int, C.c_int64, dp, C.c_uint64, C.c_uint64,
+                                             dp, dp, C.c_double, dp]
+        L.orc_unet_eval.restype = C.c_int
+        L.orc_unet_eval.argtypes = [C.POINTER(_Problem), C.POINTER(_UNet), dp, C.c_int64, dp, dp, dp, dp]
+        L.orc_unet_nais_project.restype = C.c_int
+        L.orc_unet_nais_project.argtypes = [C.POINTER(_Problem), C.POINTER(_UNet), dp, C.c_double]
         _lib = L
     return _lib
 
@@ -240,3 +258,92 @@ def prolong(problem: dict, net: dict, Nc: int, Nf: int, pc):
 
 def round_bf16(x: float) -> float:
     return float(lib().orc_round_bf16(float(x)))
+
+
+# ------------------------------------------------ the paper's own formulation
+def _unet(n: dict):
+    s = _UNet()
+    s.arch = UARCH[n.get("arch", "fc")]
+    s.width = int(n["width"])
+    s.depth = int(n.get("depth", 3))
+    s.eps = float(n.get("eps", 0.01))
+    return s
+
+
+def unet_param_count(problem: dict, net: dict) -> int:
+    ps, _keep = _problem(problem)
+    return int(lib().orc_unet_param_count(C.byref(ps), C.byref(_unet(net))))
+
+
+def unet_loss_grad(problem: dict, net: dict, N: int, M: int, params, *, xi=None, seed: int = 0, it: int = 0,
+                   kappa: float = 0.0, want_grad: bool = True, want_uz: bool = False):
+    """Residual loss of Sec. 2.2 eq. (loss) with Y_n = u(t_n, X_n) and
+    Z_n = grad u (one network for every step), the optional terminal-gradient
+    penalty kappa |Z_N - grad g(X_N)|^2, and the exact parameter gradient."""
+    ps, _keep = _problem(problem)
+    ns = _unet(net)
+    npar = unet_param_count(problem, net)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    if params.shape != (npar,):
+        raise ValueError(f"params must have shape ({npar},), got {params.shape}")
+    d = int(problem["d"])
+    if xi is not None:
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+        if xi.shape != (N, M, d):
+            raise ValueError("xi must be [N][M][d]")
+    loss = np.zeros(1)
+    grad = np.zeros(npar) if want_grad else None
+    U = np.zeros((N + 1, M)) if want_uz else None
+    Z = np.zeros((N + 1, M, d)) if want_uz else None
+    rc = lib().orc_unet_loss_grad(C.byref(ps), C.byref(ns), int(N), int(M), _ptr(params), _ptr(xi),
+                                  C.c_uint64(seed), C.c_uint64(it), float(kappa), _ptr(loss), _ptr(grad),
+                                  _ptr(U), _ptr(Z))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    out = {"loss": float(loss[0])}
+    if want_grad:
+        out["grad"] = grad
+    if want_uz:
+        out.update(U=U, Z=Z)
+    return out
+
+
+def unet_loss_given_uz(problem: dict, N: int, M: int, U, Z, *, xi=None, seed=0, it=0, kappa=0.0):
+    ps, _keep = _problem(problem)
+    d = int(problem["d"])
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    if U.shape != (N + 1, M) or Z.shape != (N + 1, M, d):
+        raise ValueError("U must be [N+1][M] and Z [N+1][M][d]")
+    if xi is not None:
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+    loss = np.zeros(1)
+    rc = lib().orc_unet_loss_given_uz(C.byref(ps), int(N), int(M), _ptr(xi), C.c_uint64(seed), C.c_uint64(it),
+                                      _ptr(U), _ptr(Z), float(kappa), _ptr(loss))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return float(loss[0])
+
+
+def unet_eval(problem: dict, net: dict, params, t, X):
+    """u(t, x) and grad_x u(t, x) of the network at the rows (t[i], X[i])."""
+    ps, _keep = _problem(problem)
+    ns = _unet(net)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    t = np.ascontiguousarray(t, dtype=np.float64).ravel()
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(t.size, int(problem["d"]))
+    u = np.zeros(t.size)
+    Z = np.zeros_like(X)
+    rc = lib().orc_unet_eval(C.byref(ps), C.byref(ns), _ptr(params), t.size, _ptr(t), _ptr(X), _ptr(u), _ptr(Z))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return u, Z
+
+
+def unet_nais_project(problem: dict, net: dict, params, c: float):
+    """In-place NAIS projection of every R_k (|R_k^T R_k|_F <= c)."""
+    ps, _keep = _problem(problem)
+    assert params.dtype == np.float64 and params.flags.c_contiguous
+    rc = lib().orc_unet_nais_project(C.byref(ps), C.byref(_unet(net)), _ptr(params), float(c))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")

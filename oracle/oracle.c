@@ -598,3 +598,471 @@ int orc_paths(const orc_problem *p, const orc_net *net, int N, const double *par
   if (P != params) free(P);
   return fail ? 2 : 0;
 }
+
+/* ======================================================================== */
+/* The paper's own formulation: one u-network, Z = grad u, residual loss     */
+/* (Sec. 2.2 eq. (loss); blocks of Sec. 3.1).  Plain fp64 throughout.        */
+/* ======================================================================== */
+static int unet_check(const orc_problem *p, const orc_unet *net, int N, int64_t M) {
+  if (!p || !net || p->d < 1 || N < 1 || M < 1 || !(p->T > 0.0) || !p->x0) return 1;
+  if (net->width < 1 || net->depth < 0 || net->depth > 64) return 1;
+  if (net->arch != ORC_U_FC && net->arch != ORC_U_RES && net->arch != ORC_U_NAIS) return 1;
+  return 0;
+}
+
+static int64_t unet_block_count(int d, int w, int arch) {
+  int64_t c = (int64_t)w * w + w;
+  if (arch == ORC_U_NAIS) c += (int64_t)w * (d + 1);
+  return c;
+}
+
+int64_t orc_unet_param_count(const orc_problem *p, const orc_unet *net) {
+  const int d = p->d, w = net->width;
+  return (int64_t)w * (d + 1) + w + (int64_t)net->depth * unet_block_count(d, w, net->arch) + w + 1;
+}
+
+/* Pointers into the flat layout (and, for NAIS, the block matrices A_k
+ * formed from R_k once per call). */
+typedef struct {
+  const double *W0, *b0, *wo, *bo;
+  const double *A[64], *E[64], *b[64];  /* E[k] NULL unless NAIS */
+  int64_t oW0, ob0, owo, obo, oA[64], oE[64], ob[64];
+  double *Abuf;                          /* NAIS: K w x w matrices */
+} unet_view;
+
+static int unet_view_make(const orc_problem *p, const orc_unet *net, const double *P, unet_view *v) {
+  const int d = p->d, w = net->width, K = net->depth;
+  int64_t off = 0;
+  v->oW0 = off; off += (int64_t)w * (d + 1);
+  v->ob0 = off; off += w;
+  v->Abuf = NULL;
+  if (net->arch == ORC_U_NAIS) {
+    v->Abuf = (double *)malloc(sizeof(double) * (size_t)((int64_t)K * w * w + 1));
+    if (!v->Abuf) return 1;
+  }
+  for (int k = 0; k < K; ++k) {
+    v->oA[k] = off; off += (int64_t)w * w;
+    if (net->arch == ORC_U_NAIS) { v->oE[k] = off; off += (int64_t)w * (d + 1); } else v->oE[k] = -1;
+    v->ob[k] = off; off += w;
+  }
+  v->owo = off; off += w;
+  v->obo = off;
+  v->W0 = P + v->oW0; v->b0 = P + v->ob0; v->wo = P + v->owo; v->bo = P + v->obo;
+  for (int k = 0; k < K; ++k) {
+    v->b[k] = P + v->ob[k];
+    v->E[k] = net->arch == ORC_U_NAIS ? P + v->oE[k] : NULL;
+    if (net->arch == ORC_U_NAIS) {
+      /* A_k = -R_k^T R_k - eps I */
+      const double *Rk = P + v->oA[k];
+      double *Ak = v->Abuf + (int64_t)k * w * w;
+      for (int a = 0; a < w; ++a)
+        for (int c = 0; c < w; ++c) {
+          double s = 0.0;
+          for (int q = 0; q < w; ++q) s += Rk[(int64_t)q * w + a] * Rk[(int64_t)q * w + c];
+          Ak[(int64_t)a * w + c] = -s - (a == c ? net->eps : 0.0);
+        }
+      v->A[k] = Ak;
+    } else {
+      v->A[k] = P + v->oA[k];
+    }
+  }
+  return 0;
+}
+
+/* Per-row state of one network evaluation: h_k (k = 0..K), alpha_k
+ * (k = 1..K, index k-1), the input-gradient sweep hh_k = du/dh_k and
+ * g_k = the pre-activation gradients (k = 0..K). */
+typedef struct { double *h, *al, *hh, *g, *zb; } unet_row;
+
+static void unet_forward_row(const orc_problem *p, const orc_unet *net, const unet_view *v,
+                             const double *z, unet_row *r, double *u) {
+  const int d = p->d, w = net->width, K = net->depth;
+  const double c = net->arch == ORC_U_FC ? 0.0 : 1.0;
+  double *h0 = r->h;
+  for (int a = 0; a < w; ++a) {
+    double s = v->b0[a];
+    for (int i = 0; i <= d; ++i) s += v->W0[(int64_t)a * (d + 1) + i] * z[i];
+    h0[a] = tanh(s);
+  }
+  for (int k = 1; k <= K; ++k) {
+    const double *hp = r->h + (int64_t)(k - 1) * w;
+    double *hk = r->h + (int64_t)k * w, *ak = r->al + (int64_t)(k - 1) * w;
+    const double *A = v->A[k - 1], *E = v->E[k - 1], *b = v->b[k - 1];
+    for (int a = 0; a < w; ++a) {
+      double s = b[a];
+      for (int q = 0; q < w; ++q) s += A[(int64_t)a * w + q] * hp[q];
+      if (E)
+        for (int i = 0; i <= d; ++i) s += E[(int64_t)a * (d + 1) + i] * z[i];
+      ak[a] = tanh(s);
+      hk[a] = c * hp[a] + ak[a];
+    }
+  }
+  const double *hK = r->h + (int64_t)K * w;
+  double s = v->bo[0];
+  for (int a = 0; a < w; ++a) s += v->wo[a] * hK[a];
+  *u = s;
+}
+
+/* Z = grad_x u by the reverse sweep of the network for its scalar output:
+ * hh_K = w_o; g_k = hh_k (1 - alpha_k^2); hh_{k-1} = c hh_k + A_k^T g_k;
+ * g_0 = hh_0 (1 - h_0^2); grad_z u = W_0^T g_0 + sum_k E_k^T g_k. */
+static void unet_zgrad_row(const orc_problem *p, const orc_unet *net, const unet_view *v, unet_row *r,
+                           double *Z) {
+  const int d = p->d, w = net->width, K = net->depth;
+  const double c = net->arch == ORC_U_FC ? 0.0 : 1.0;
+  memcpy(r->hh + (int64_t)K * w, v->wo, sizeof(double) * w);
+  double *zg = r->zb;  /* d + 1 */
+  for (int i = 0; i <= d; ++i) zg[i] = 0.0;
+  for (int k = K; k >= 1; --k) {
+    const double *hk = r->hh + (int64_t)k * w, *ak = r->al + (int64_t)(k - 1) * w;
+    double *gk = r->g + (int64_t)k * w, *hp = r->hh + (int64_t)(k - 1) * w;
+    const double *A = v->A[k - 1], *E = v->E[k - 1];
+    for (int a = 0; a < w; ++a) gk[a] = hk[a] * (1.0 - ak[a] * ak[a]);
+    for (int q = 0; q < w; ++q) {
+      double s = 0.0;
+      for (int a = 0; a < w; ++a) s += A[(int64_t)a * w + q] * gk[a];
+      hp[q] = c * hk[q] + s;
+    }
+    if (E)
+      for (int i = 0; i <= d; ++i) {
+        double s = 0.0;
+        for (int a = 0; a < w; ++a) s += E[(int64_t)a * (d + 1) + i] * gk[a];
+        zg[i] += s;
+      }
+  }
+  double *g0 = r->g;
+  for (int a = 0; a < w; ++a) g0[a] = r->hh[a] * (1.0 - r->h[a] * r->h[a]);
+  for (int i = 0; i < d; ++i) {
+    double s = 0.0;
+    for (int a = 0; a < w; ++a) s += v->W0[(int64_t)a * (d + 1) + i] * g0[a];
+    Z[i] = zg[i] + s;
+  }
+}
+
+/* Reverse sweep of one row for the seeds ub = dL/du and Zb = dL/dZ
+ * (accumulates into G in the flat layout; the gradient of A_k goes to G at
+ * A_k's offset also for NAIS, converted to R_k by the caller).  work: 4w. */
+static void unet_adjoint_row(const orc_problem *p, const orc_unet *net, const unet_view *v, const double *z,
+                             const unet_row *r, double ub, const double *Zb, double *G, double *work) {
+  const int d = p->d, w = net->width, K = net->depth;
+  const double c = net->arch == ORC_U_FC ? 0.0 : 1.0;
+  double *gb = work, *hhb = work + w, *hb = work + 2 * w, *alb = work + 3 * w;
+  /* alb holds alpha-bar partials of every block: K w values after work + 3w */
+  /* ---- second-order part, k = 0..K in forward order ---- */
+  /* g_0 = hh_0 (1 - h_0^2), Z = W_0x^T g_0 */
+  const double *h0 = r->h, *hh0 = r->hh, *g0 = r->g;
+  for (int a = 0; a < w; ++a) {
+    double s = 0.0;
+    for (int i = 0; i < d; ++i) s += v->W0[(int64_t)a * (d + 1) + i] * Zb[i];
+    gb[a] = s;
+    for (int i = 0; i < d; ++i) G[v->oW0 + (int64_t)a * (d + 1) + i] += g0[a] * Zb[i];
+  }
+  for (int a = 0; a < w; ++a) {
+    hhb[a] = gb[a] * (1.0 - h0[a] * h0[a]);
+    hb[a] = gb[a] * hh0[a] * (-2.0 * h0[a]);  /* h_0-bar partial */
+  }
+  for (int k = 1; k <= K; ++k) {
+    const double *A = v->A[k - 1], *E = v->E[k - 1];
+    const double *gk = r->g + (int64_t)k * w, *hhk = r->hh + (int64_t)k * w, *ak = r->al + (int64_t)(k - 1) * w;
+    double *albk = alb + (int64_t)(k - 1) * w;
+    double *gA = G + v->oA[k - 1];
+    /* gamma-bar_k = A_k hh-bar_{k-1} (+ E_k zb); A-bar_k += g_k hh-bar_{k-1}^T */
+    for (int a = 0; a < w; ++a) {
+      double s = 0.0;
+      for (int q = 0; q < w; ++q) s += A[(int64_t)a * w + q] * hhb[q];
+      if (E) {
+        double *gE = G + v->oE[k - 1];
+        for (int i = 0; i < d; ++i) {
+          s += E[(int64_t)a * (d + 1) + i] * Zb[i];
+          gE[(int64_t)a * (d + 1) + i] += gk[a] * Zb[i];
+        }
+      }
+      for (int q = 0; q < w; ++q) gA[(int64_t)a * w + q] += gk[a] * hhb[q];
+      gb[a] = s;
+    }
+    for (int a = 0; a < w; ++a) {
+      hhb[a] = c * hhb[a] + gb[a] * (1.0 - ak[a] * ak[a]);
+      albk[a] = gb[a] * hhk[a] * (-2.0 * ak[a]);
+    }
+  }
+  /* hh_K = w_o */
+  for (int a = 0; a < w; ++a) G[v->owo + a] += hhb[a];
+  /* ---- first-order part: u = w_o . h_K + b_o, then the blocks backwards ---- */
+  const double *hK = r->h + (int64_t)K * w;
+  double *hbar = gb;  /* reuse: h-bar_k */
+  for (int a = 0; a < w; ++a) {
+    hbar[a] = ub * v->wo[a];
+    G[v->owo + a] += ub * hK[a];
+  }
+  G[v->obo] += ub;
+  for (int k = K; k >= 1; --k) {
+    const double *A = v->A[k - 1], *E = v->E[k - 1];
+    const double *ak = r->al + (int64_t)(k - 1) * w, *hp = r->h + (int64_t)(k - 1) * w;
+    const double *albk = alb + (int64_t)(k - 1) * w;
+    double *abar = hhb;  /* reuse */
+    for (int a = 0; a < w; ++a) abar[a] = (albk[a] + hbar[a]) * (1.0 - ak[a] * ak[a]);
+    double *gA = G + v->oA[k - 1], *gbk = G + v->ob[k - 1];
+    for (int a = 0; a < w; ++a) {
+      for (int q = 0; q < w; ++q) gA[(int64_t)a * w + q] += abar[a] * hp[q];
+      gbk[a] += abar[a];
+      if (E) {
+        double *gE = G + v->oE[k - 1];
+        for (int i = 0; i <= d; ++i) gE[(int64_t)a * (d + 1) + i] += abar[a] * z[i];
+      }
+    }
+    for (int q = 0; q < w; ++q) {
+      double s = 0.0;
+      for (int a = 0; a < w; ++a) s += A[(int64_t)a * w + q] * abar[a];
+      hbar[q] = c * hbar[q] + s;
+    }
+  }
+  for (int a = 0; a < w; ++a) {
+    double ab0 = (hbar[a] + hb[a]) * (1.0 - h0[a] * h0[a]);
+    for (int i = 0; i <= d; ++i) G[v->oW0 + (int64_t)a * (d + 1) + i] += ab0 * z[i];
+    G[v->ob0 + a] += ab0;
+  }
+}
+
+static void terminal_grad(const orc_problem *p, const double *x, double *out) {
+  double q = dot(p->d, x, x);
+  for (int i = 0; i < p->d; ++i) {
+    switch (p->g) {
+      case ORC_G_NORM2: out[i] = 2.0 * x[i]; break;
+      case ORC_G_LOGHALF: out[i] = 2.0 * x[i] / (1.0 + q); break;
+      case ORC_G_INV: {
+        double den = p->g_p[0] + p->g_p[1] * q;
+        out[i] = -2.0 * p->g_p[1] * x[i] / (den * den);
+        break;
+      }
+      default: out[i] = p->g_p[0]; break;
+    }
+  }
+}
+
+/* Euler–Maruyama path of X (mu = 0) for path m: X [N+1][d], S [N][d] */
+static void unet_path_x(const orc_problem *p, int N, const double *xi, int64_t Mx, uint64_t seed, uint64_t iter,
+                        int64_t m, double *X, double *S, double *xim) {
+  const int d = p->d;
+  const double sdt = sqrt(p->T / N);
+  memcpy(X, p->x0, sizeof(double) * d);
+  for (int n = 0; n < N; ++n) {
+    if (xi) memcpy(xim, xi + ((int64_t)n * Mx + m) * d, sizeof(double) * d);
+    else normals_one(seed, iter, n, m, d, xim);
+    for (int i = 0; i < d; ++i) xim[i] *= sdt;
+    diffusion(p, X + (int64_t)n * d, xim, S + (int64_t)n * d);
+    for (int i = 0; i < d; ++i) X[(int64_t)(n + 1) * d + i] = X[(int64_t)n * d + i] + S[(int64_t)n * d + i];
+  }
+}
+
+/* Residuals of one path and their seeds: r [N], e, pen [d]; ub [N+1],
+ * Zb [N+1][d] (dL/du_n and dL/dZ_n with the 1/M of the batch mean). */
+static double unet_path_residuals(const orc_problem *p, int N, int64_t M, const double *X, const double *S,
+                                  const double *u, const double *Z, double kappa, double *ub, double *Zb,
+                                  double *pz, double *gx) {
+  const int d = p->d;
+  const double dt = p->T / N;
+  double l = 0.0;
+  for (int n = 0; n <= N; ++n) ub[n] = 0.0;
+  for (int64_t k = 0; k < (int64_t)(N + 1) * d; ++k) Zb[k] = 0.0;
+  for (int n = 0; n < N; ++n) {
+    const double *xn = X + (int64_t)n * d, *zn = Z + (int64_t)n * d, *sn = S + (int64_t)n * d;
+    const double rn = u[n + 1] - u[n] - driver(p, xn, u[n], zn) * dt - dot(d, zn, sn);
+    l += rn * rn;
+    const double c = 2.0 * rn / (double)M;
+    ub[n + 1] += c;
+    ub[n] -= c * (1.0 + driver_dy(p, u[n]) * dt);
+    driver_dz(p, xn, zn, pz);
+    for (int i = 0; i < d; ++i) Zb[(int64_t)n * d + i] -= c * (pz[i] * dt + sn[i]);
+  }
+  const double *xN = X + (int64_t)N * d, *zN = Z + (int64_t)N * d;
+  const double e = u[N] - terminal(p, xN);
+  l += e * e;
+  ub[N] += 2.0 * e / (double)M;
+  if (kappa != 0.0) {
+    terminal_grad(p, xN, gx);
+    for (int i = 0; i < d; ++i) {
+      const double q = zN[i] - gx[i];
+      l += kappa * q * q;
+      Zb[(int64_t)N * d + i] += 2.0 * kappa * q / (double)M;
+    }
+  }
+  return l;
+}
+
+int orc_unet_loss_grad(const orc_problem *p, const orc_unet *net, int N, int64_t M,
+                       const double *params, const double *xi, uint64_t seed, uint64_t iter,
+                       double kappa, double *loss, double *grad, double *U, double *Zout) {
+  if (unet_check(p, net, N, M) || !params || !loss) return 1;
+  const int d = p->d, w = net->width, K = net->depth;
+  const int64_t npar = orc_unet_param_count(p, net);
+  const double dt = p->T / N;
+  const int64_t nch = (M + ORC_PATH_CHUNK - 1) / ORC_PATH_CHUNK;
+  unet_view v;
+  if (unet_view_make(p, net, params, &v)) return 2;
+  /* gradient with respect to A_k (NAIS: converted to R_k at the end) */
+  double *GA = grad ? (double *)calloc((size_t)npar, sizeof(double)) : NULL;
+  if (grad && !GA) { free(v.Abuf); return 2; }
+  double lsum = 0.0;
+  int fail = 0;
+#pragma omp parallel
+  {
+    const int64_t rows = N + 1;
+    double *X = (double *)malloc(sizeof(double) * (size_t)(rows * d));
+    double *S = (double *)malloc(sizeof(double) * (size_t)(N * d));
+    double *xim = (double *)malloc(sizeof(double) * d);
+    double *u = (double *)malloc(sizeof(double) * (size_t)rows);
+    double *Z = (double *)malloc(sizeof(double) * (size_t)(rows * d));
+    double *ub = (double *)malloc(sizeof(double) * (size_t)rows);
+    double *Zb = (double *)malloc(sizeof(double) * (size_t)(rows * d));
+    double *pz = (double *)malloc(sizeof(double) * d), *gx = (double *)malloc(sizeof(double) * d);
+    double *zin = (double *)malloc(sizeof(double) * (size_t)(rows * (d + 1)));
+    /* per-row network state of the whole path */
+    const int64_t hs = (int64_t)(K + 1) * w;
+    double *H = (double *)malloc(sizeof(double) * (size_t)(rows * hs));
+    double *AL = (double *)malloc(sizeof(double) * (size_t)(rows * (K > 0 ? K * w : 1)));
+    double *HH = (double *)malloc(sizeof(double) * (size_t)(rows * hs));
+    double *GG = (double *)malloc(sizeof(double) * (size_t)(rows * hs));
+    double *zb = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    double *work = (double *)malloc(sizeof(double) * (size_t)((3 + K) * w + 1));
+    double *gpart = grad ? (double *)calloc((size_t)npar, sizeof(double)) : NULL;
+    int ok = X && S && xim && u && Z && ub && Zb && pz && gx && zin && H && AL && HH && GG && zb && work &&
+             (!grad || gpart);
+#pragma omp for ordered schedule(dynamic, 1)
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      double lc = 0.0;
+      if (ok) {
+        if (gpart) memset(gpart, 0, sizeof(double) * (size_t)npar);
+        const int64_t m1 = (ch + 1) * ORC_PATH_CHUNK < M ? (ch + 1) * ORC_PATH_CHUNK : M;
+        for (int64_t m = ch * ORC_PATH_CHUNK; m < m1; ++m) {
+          unet_path_x(p, N, xi, M, seed, iter, m, X, S, xim);
+          for (int n = 0; n <= N; ++n) {
+            double *z = zin + (int64_t)n * (d + 1);
+            memcpy(z, X + (int64_t)n * d, sizeof(double) * d);
+            z[d] = n * dt;
+            unet_row r = {H + n * hs, AL + (int64_t)n * K * w, HH + n * hs, GG + n * hs, zb};
+            unet_forward_row(p, net, &v, z, &r, &u[n]);
+            unet_zgrad_row(p, net, &v, &r, Z + (int64_t)n * d);
+          }
+          if (U) for (int n = 0; n <= N; ++n) U[(int64_t)n * M + m] = u[n];
+          if (Zout)
+            for (int n = 0; n <= N; ++n) memcpy(Zout + ((int64_t)n * M + m) * d, Z + (int64_t)n * d, sizeof(double) * d);
+          lc += unet_path_residuals(p, N, M, X, S, u, Z, kappa, ub, Zb, pz, gx);
+          if (!gpart) continue;
+          for (int n = 0; n <= N; ++n) {
+            unet_row r = {H + n * hs, AL + (int64_t)n * K * w, HH + n * hs, GG + n * hs, zb};
+            unet_adjoint_row(p, net, &v, zin + (int64_t)n * (d + 1), &r, ub[n], Zb + (int64_t)n * d, gpart,
+                             work);
+          }
+        }
+      }
+#pragma omp ordered
+      {
+        if (!ok) fail = 1;
+        lsum += lc;
+        if (GA && gpart && ok)
+          for (int64_t k = 0; k < npar; ++k) GA[k] += gpart[k];
+      }
+    }
+    free(X); free(S); free(xim); free(u); free(Z); free(ub); free(Zb); free(pz); free(gx); free(zin);
+    free(H); free(AL); free(HH); free(GG); free(zb); free(work); free(gpart);
+  }
+  if (!fail && grad) {
+    memcpy(grad, GA, sizeof(double) * (size_t)npar);
+    if (net->arch == ORC_U_NAIS) {
+      /* A = -R^T R - eps I  =>  R-bar = -R (A-bar + A-bar^T) */
+      for (int k = 0; k < K; ++k) {
+        const double *Rk = params + v.oA[k], *Ab = GA + v.oA[k];
+        double *gR = grad + v.oA[k];
+        for (int q = 0; q < w; ++q)
+          for (int c2 = 0; c2 < w; ++c2) {
+            double s = 0.0;
+            for (int a = 0; a < w; ++a)
+              s += Rk[(int64_t)q * w + a] * (Ab[(int64_t)a * w + c2] + Ab[(int64_t)c2 * w + a]);
+            gR[(int64_t)q * w + c2] = -s;
+          }
+      }
+    }
+  }
+  free(GA);
+  free(v.Abuf);
+  if (fail) return 2;
+  *loss = lsum / (double)M;
+  return 0;
+}
+
+int orc_unet_loss_given_uz(const orc_problem *p, int N, int64_t M, const double *xi, uint64_t seed,
+                           uint64_t iter, const double *U, const double *Z, double kappa, double *loss) {
+  if (!p || p->d < 1 || N < 1 || M < 1 || !(p->T > 0.0) || !p->x0 || !U || !Z || !loss) return 1;
+  const int d = p->d;
+  double *X = (double *)malloc(sizeof(double) * (size_t)((N + 1) * d));
+  double *S = (double *)malloc(sizeof(double) * (size_t)(N * d));
+  double *xim = (double *)malloc(sizeof(double) * d);
+  double *u = (double *)malloc(sizeof(double) * (size_t)(N + 1));
+  double *Zp = (double *)malloc(sizeof(double) * (size_t)((N + 1) * d));
+  double *ub = (double *)malloc(sizeof(double) * (size_t)(N + 1));
+  double *Zb = (double *)malloc(sizeof(double) * (size_t)((N + 1) * d));
+  double *pz = (double *)malloc(sizeof(double) * d), *gx = (double *)malloc(sizeof(double) * d);
+  double lsum = 0.0;
+  for (int64_t m = 0; m < M; ++m) {
+    unet_path_x(p, N, xi, M, seed, iter, m, X, S, xim);
+    for (int n = 0; n <= N; ++n) {
+      u[n] = U[(int64_t)n * M + m];
+      memcpy(Zp + (int64_t)n * d, Z + ((int64_t)n * M + m) * d, sizeof(double) * d);
+    }
+    lsum += unet_path_residuals(p, N, M, X, S, u, Zp, kappa, ub, Zb, pz, gx);
+  }
+  *loss = lsum / (double)M;
+  free(X); free(S); free(xim); free(u); free(Zp); free(ub); free(Zb); free(pz); free(gx);
+  return 0;
+}
+
+int orc_unet_eval(const orc_problem *p, const orc_unet *net, const double *params, int64_t R,
+                  const double *T, const double *X, double *u, double *Z) {
+  if (unet_check(p, net, 1, 1) || !params || R < 0 || (R > 0 && (!T || !X))) return 1;
+  const int d = p->d, w = net->width, K = net->depth;
+  unet_view v;
+  if (unet_view_make(p, net, params, &v)) return 2;
+  const int64_t hs = (int64_t)(K + 1) * w;
+  double *H = (double *)malloc(sizeof(double) * (size_t)hs), *AL = (double *)malloc(sizeof(double) * (size_t)(K * w + 1));
+  double *HH = (double *)malloc(sizeof(double) * (size_t)hs), *GG = (double *)malloc(sizeof(double) * (size_t)hs);
+  double *zb = (double *)malloc(sizeof(double) * (size_t)(d + 1)), *z = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+  double *Zr = (double *)malloc(sizeof(double) * d);
+  for (int64_t i = 0; i < R; ++i) {
+    memcpy(z, X + i * d, sizeof(double) * d);
+    z[d] = T[i];
+    unet_row r = {H, AL, HH, GG, zb};
+    double ui;
+    unet_forward_row(p, net, &v, z, &r, &ui);
+    if (u) u[i] = ui;
+    if (Z) {
+      unet_zgrad_row(p, net, &v, &r, Zr);
+      memcpy(Z + i * d, Zr, sizeof(double) * d);
+    }
+  }
+  free(H); free(AL); free(HH); free(GG); free(zb); free(z); free(Zr);
+  free(v.Abuf);
+  return 0;
+}
+
+int orc_unet_nais_project(const orc_problem *p, const orc_unet *net, double *params, double c) {
+  if (!p || !net || !params || net->arch != ORC_U_NAIS || !(c > 0.0)) return 1;
+  const int d = p->d, w = net->width, K = net->depth;
+  int64_t off = (int64_t)w * (d + 1) + w;
+  for (int k = 0; k < K; ++k) {
+    double *Rk = params + off;
+    double f2 = 0.0;  /* |R^T R|_F^2 */
+    for (int a = 0; a < w; ++a)
+      for (int b = 0; b < w; ++b) {
+        double s = 0.0;
+        for (int q = 0; q < w; ++q) s += Rk[(int64_t)q * w + a] * Rk[(int64_t)q * w + b];
+        f2 += s * s;
+      }
+    const double f = sqrt(f2);
+    if (f > c) {
+      const double sc = sqrt(c / f);
+      for (int64_t e = 0; e < (int64_t)w * w; ++e) Rk[e] *= sc;
+    }
+    off += unet_block_count(d, w, net->arch);
+  }
+  return 0;
+}

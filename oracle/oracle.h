@@ -140,6 +140,63 @@ int orc_prolong(const orc_problem *p, const orc_net *net, int Nc, int Nf,
 /* Round-to-nearest-even fp64 -> fp32 -> bfloat16 -> fp64 (bf16 emulation). */
 double orc_round_bf16(double x);
 
+/* ======================================================================== */
+/* The paper's own formulation (Sec. 2.2, eq. (loss); Sec. 3.1)              */
+/* ======================================================================== */
+/* One network u(t, x; Theta) for every time step; Y_n = u(t_n, X_n) and
+ * Z_n = grad_x u(t_n, X_n) (the exact input gradient of the network).  The
+ * network takes z = [x; t] (t appended as input d+1) and is
+ *   h_0 = tanh(W_0 z + b_0),
+ *   h_k = c h_{k-1} + tanh(A_k h_{k-1} (+ E_k z) + b_k),   k = 1..K,
+ *   u   = w_o . h_K + b_o,
+ * with
+ *   FC  : c = 0 (K + 1 fully connected tanh layers of width w),
+ *   RES : c = 1 (residual blocks, a forward-Euler step with h = 1, Sec. 3.1),
+ *   NAIS: c = 1, A_k = -R_k^T R_k - eps I and the input injection E_k z
+ *         (Sec. 3.1, the non-autonomous input-output stable block; the
+ *         trainable parameters are R_k, E_k, b_k).
+ * Flat layout: W_0[w][d+1] b_0[w]; per block FC/RES: A_k[w][w] b_k[w],
+ * NAIS: R_k[w][w] E_k[w][d+1] b_k[w]; then w_o[w] b_o. */
+enum { ORC_U_FC = 0, ORC_U_RES = 1, ORC_U_NAIS = 2 };
+
+typedef struct {
+  int arch;     /* ORC_U_*                                      */
+  int width;    /* w                                            */
+  int depth;    /* K blocks after the input layer               */
+  double eps;   /* NAIS: A_k = -R_k^T R_k - eps I               */
+} orc_unet;
+
+int64_t orc_unet_param_count(const orc_problem *p, const orc_unet *net);
+
+/* Loss of eq. (loss) as a batch mean,
+ *   L = (1/M) sum_m [ sum_{n<N} r_n^2 + (u_N - g(X_N))^2 + kappa |Z_N - grad g(X_N)|^2 ],
+ *   r_n = u_{n+1} - u_n - phi(t_n, X_n, u_n, Z_n) dt - Z_n . sigma(X_n) dW_n,
+ * (the kappa term is the terminal-gradient penalty the paper proposes after
+ * eq. (loss); kappa = 0 leaves it out), and its exact gradient with respect
+ * to the flat parameters by a hand-written reverse sweep that includes the
+ * second-order terms of Z = grad u.  Paths use the same Philox normals as
+ * orc_loss_grad (xi NULL) or the given xi [N][M][d].  Optional outputs:
+ * U [N+1][M] (u_n of every path), Zout [N+1][M][d].  Returns 0 on success. */
+int orc_unet_loss_grad(const orc_problem *p, const orc_unet *net, int N, int64_t M,
+                       const double *params, const double *xi, uint64_t seed, uint64_t iter,
+                       double kappa, double *loss, double *grad, double *U, double *Zout);
+
+/* The residual loss above with u_n and Z_n given per row instead of a
+ * network: U [N+1][M], Z [N+1][M][d].  Fed with the exact solution of a
+ * problem, the mean loss must vanish like O(dt) (pins the residual, the
+ * driver and the penalty term). */
+int orc_unet_loss_given_uz(const orc_problem *p, int N, int64_t M, const double *xi, uint64_t seed,
+                           uint64_t iter, const double *U, const double *Z, double kappa, double *loss);
+
+/* u(t, x) and grad_x u(t, x) of the network at given rows: T [R], X [R][d]
+ * -> u [R], Z [R][d] (either output may be NULL). */
+int orc_unet_eval(const orc_problem *p, const orc_unet *net, const double *params, int64_t R,
+                  const double *T, const double *X, double *u, double *Z);
+
+/* NAIS projection (Sec. 3.1): every R_k with |R_k^T R_k|_F > c is scaled by
+ * sqrt(c / |R_k^T R_k|_F), so that |R_k^T R_k|_F <= c afterwards. */
+int orc_unet_nais_project(const orc_problem *p, const orc_unet *net, double *params, double c);
+
 #ifdef __cplusplus
 }
 #endif

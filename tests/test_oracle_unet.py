@@ -1,0 +1,358 @@
+"""CPU pins of the oracle's paper formulation (Sec. 2.2 eq. (loss): one
+network u(t, x), Y_n = u(t_n, X_n), Z_n = grad u, per-step residuals plus the
+terminal term and the terminal-gradient penalty; FC, residual and NAIS
+blocks of Sec. 3.1), each against something the oracle does not compute
+itself: central differences, torch float64 double-backward autograd, the
+closed-form solutions of Sec. 4, an exactly solvable degenerate network and
+the definition of the NAIS projection."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import core as O
+from oracle import refvalues as RV
+from paper_1910_11623_amd import inputs as I
+
+ARCHS = ["fc", "res", "nais"]
+
+
+def _problem(name, d):
+    return {"bsb": I.bsb, "hjb": I.hjb, "ac": I.allen_cahn}[name](d)
+
+
+def _params(prob, net, seed=0, scale=0.4):
+    n = O.unet_param_count(prob, net)
+    return np.random.default_rng(seed).standard_normal(n) * scale
+
+
+def test_param_count_layout():
+    d, w, K = 5, 7, 3
+    prob = I.bsb(d)
+    base = w * (d + 1) + w + w + 1
+    assert O.unet_param_count(prob, dict(arch="fc", width=w, depth=K)) == base + K * (w * w + w)
+    assert O.unet_param_count(prob, dict(arch="res", width=w, depth=K)) == base + K * (w * w + w)
+    assert O.unet_param_count(prob, dict(arch="nais", width=w, depth=K)) == base + K * (w * w + w * (d + 1) + w)
+
+
+@pytest.mark.parametrize("arch", ARCHS)
+@pytest.mark.parametrize("pname", ["bsb", "hjb", "ac"])
+def test_gradient_matches_finite_differences(arch, pname):
+    """The hand-written reverse sweep (with the second-order terms of
+    Z = grad u and the penalty) against central differences of the loss."""
+    prob = _problem(pname, 3)
+    net = dict(arch=arch, width=4, depth=2, eps=0.01)
+    p = _params(prob, net, seed=hash((arch, pname)) % 1000)
+    N, M, kap = 3, 5, 0.7
+    g = O.unet_loss_grad(prob, net, N, M, p, seed=3, it=1, kappa=kap)["grad"]
+    fd = np.zeros_like(p)
+    for k in range(p.size):
+        h = 1e-6 * max(1.0, abs(p[k]))
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        lp = O.unet_loss_grad(prob, net, N, M, pp, seed=3, it=1, kappa=kap, want_grad=False)["loss"]
+        lm = O.unet_loss_grad(prob, net, N, M, pm, seed=3, it=1, kappa=kap, want_grad=False)["loss"]
+        fd[k] = (lp - lm) / (2 * h)
+    assert np.linalg.norm(g - fd) <= 1e-7 * np.linalg.norm(fd)
+
+
+@pytest.mark.parametrize("arch", ARCHS)
+def test_z_is_the_input_gradient_of_u(arch):
+    """Z = grad_x u of the evaluation routine against central differences of
+    its own u in x."""
+    prob = I.hjb(4)
+    net = dict(arch=arch, width=6, depth=3, eps=0.01)
+    p = _params(prob, net, seed=5)
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((7, 4))
+    t = rng.uniform(0, 1, 7)
+    _, Z = O.unet_eval(prob, net, p, t, X)
+    h = 1e-6
+    for i in range(4):
+        e = np.zeros_like(X)
+        e[:, i] = h
+        fd = (O.unet_eval(prob, net, p, t, X + e)[0] - O.unet_eval(prob, net, p, t, X - e)[0]) / (2 * h)
+        np.testing.assert_allclose(Z[:, i], fd, rtol=1e-7, atol=1e-9)
+
+
+def _torch_loss(prob, net, N, M, p, xi, kappa):
+    """The same loss built from torch float64 modules, Z by autograd.grad with
+    create_graph (double backward gives the parameter gradient)."""
+    import torch
+    d, w, K = prob["d"], net["width"], net["depth"]
+    P = torch.tensor(p, dtype=torch.float64, requires_grad=True)
+    off = [0]
+
+    def take(*shape):
+        n = int(np.prod(shape))
+        t = P[off[0]:off[0] + n].reshape(*shape)
+        off[0] += n
+        return t
+    W0, b0 = take(w, d + 1), take(w)
+    blocks = []
+    for _ in range(K):
+        A = take(w, w)
+        E = take(w, d + 1) if net["arch"] == "nais" else None
+        blocks.append((A, E, take(w)))
+    wo, bo = take(w), take(1)
+    eps = net.get("eps", 0.01)
+    c = 0.0 if net["arch"] == "fc" else 1.0
+
+    def u_of(z):
+        h = torch.tanh(z @ W0.T + b0)
+        for A, E, b in blocks:
+            Am = -(A.T @ A) - eps * torch.eye(w, dtype=torch.float64) if net["arch"] == "nais" else A
+            pre = h @ Am.T + b
+            if E is not None:
+                pre = pre + z @ E.T
+            h = c * h + torch.tanh(pre)
+        return h @ wo + bo
+    dt = prob["T"] / N
+    x0 = torch.tensor(prob["x0"], dtype=torch.float64)
+    X = [x0.expand(M, d)]
+    S = []
+    for n in range(N):
+        dw = torch.tensor(xi[n], dtype=torch.float64) * math.sqrt(dt)
+        s = prob["sde_s"] * (X[n] * dw if prob["sde"] == "gbm_diag" else dw)
+        S.append(s)
+        X.append(X[n] + s)
+    us, Zs = [], []
+    for n in range(N + 1):
+        x = X[n].clone().requires_grad_(True)
+        z = torch.cat([x, torch.full((M, 1), n * dt, dtype=torch.float64)], 1)
+        u = u_of(z)
+        (Z,) = torch.autograd.grad(u.sum(), x, create_graph=True)
+        us.append(u)
+        Zs.append(Z)
+    L = torch.zeros((), dtype=torch.float64)
+    for n in range(N):
+        y, Z, x = us[n], Zs[n], X[n]
+        if prob["drv"] == "bsb":
+            phi = prob["drv_p"][0] * (y - (Z * x).sum(1))
+        elif prob["drv"] == "hjb":
+            phi = prob["drv_p"][0] * (Z * Z).sum(1)
+        else:
+            phi = y ** 3 - y
+        r = us[n + 1] - y - phi * dt - (Z * S[n]).sum(1)
+        L = L + (r * r).sum()
+    xN = X[N]
+    q = (xN * xN).sum(1)
+    if prob["g"] == "norm2":
+        g, gg = q, 2 * xN
+    elif prob["g"] == "loghalf":
+        g, gg = torch.log(0.5 * (1 + q)), 2 * xN / (1 + q)[:, None]
+    else:
+        a, b = prob["g_p"]
+        g, gg = 1.0 / (a + b * q), -2 * b * xN / ((a + b * q) ** 2)[:, None]
+    L = L + ((us[N] - g) ** 2).sum() + kappa * ((Zs[N] - gg) ** 2).sum()
+    L = L / M
+    L.backward()
+    return float(L.item()), P.grad.numpy().copy()
+
+
+@pytest.mark.parametrize("arch", ARCHS)
+@pytest.mark.parametrize("pname", ["bsb", "hjb", "ac"])
+def test_gradient_matches_torch_double_backward(arch, pname):
+    prob = _problem(pname, 5)
+    net = dict(arch=arch, width=8, depth=2, eps=0.01)
+    p = _params(prob, net, seed=11, scale=0.3)
+    N, M, kap = 4, 6, 0.5
+    xi = O.normals(2, 0, N, M, 5)
+    o = O.unet_loss_grad(prob, net, N, M, p, xi=xi, kappa=kap)
+    lt, gt = _torch_loss(prob, net, N, M, p, xi, kap)
+    assert o["loss"] == pytest.approx(lt, rel=1e-12)
+    assert np.linalg.norm(o["grad"] - gt) <= 1e-10 * np.linalg.norm(gt)
+
+
+def _slope(Ns, losses):
+    return -np.polyfit(np.log(Ns), np.log(losses), 1)[0]
+
+
+def _bsb_exact_uz(prob, N, M, xi):
+    """u and grad u of the closed form exp((r + s^2)(T - t)) |x|^2 on the
+    Euler paths of the normals xi."""
+    r, s, T = prob["drv_p"][0], prob["sde_s"], prob["T"]
+    dt = T / N
+    X = np.broadcast_to(prob["x0"], (M, prob["d"])).copy()
+    U = np.zeros((N + 1, M))
+    Z = np.zeros((N + 1, M, prob["d"]))
+    for n in range(N + 1):
+        c = math.exp((r + s * s) * (T - n * dt))
+        U[n] = c * (X * X).sum(1)
+        Z[n] = 2 * c * X
+        if n < N:
+            X = X + s * X * xi[n] * math.sqrt(dt)
+    return U, Z
+
+
+def _bsb_losses(prob, Ns, M, kappa=0.0):
+    out = {}
+    for N in Ns:
+        xi = O.normals(9, 0, N, M, prob["d"])
+        U, Z = _bsb_exact_uz(prob, N, M, xi)
+        r = prob["drv_p"][0]
+        out[N] = {"exact": O.unet_loss_given_uz(prob, N, M, U, Z, xi=xi, kappa=kappa),
+                  "flip": O.unet_loss_given_uz(dict(prob, drv_p=[-r, 0.0]), N, M, U, Z, xi=xi),
+                  "none": O.unet_loss_given_uz(dict(prob, drv_p=[0.0, 0.0]), N, M, U, Z, xi=xi)}
+    return out
+
+
+def test_residual_loss_with_the_exact_solution_vanishes_like_dt():
+    """Sec. 4 Black–Scholes–Barenblatt closed form fed as u and Z: every
+    residual is the Euler scheme's local error, so at r = 0.05, sigma = 0.4
+    the mean loss falls like dt (slope 0.8-1.2); the terminal term and the
+    penalty vanish exactly (Z_N = grad g).  The closed form holds for any r
+    and sigma: at r = 1, sigma = 0.2 the driver dominates each residual and a
+    flipped or missing driver is caught by orders of magnitude."""
+    Ns, M = [8, 16, 32, 64], 512
+    r = _bsb_losses(I.bsb(4), Ns, M)
+    assert 0.8 < _slope(Ns, [r[n]["exact"] for n in Ns]) < 1.2
+    rk = _bsb_losses(I.bsb(4), [16], M, kappa=3.0)
+    assert rk[16]["exact"] == pytest.approx(r[16]["exact"], rel=1e-12)
+    s = _bsb_losses(I.bsb(4, r=1.0, sigma=0.2), [8, 64], M)
+    assert s[64]["exact"] < s[8]["exact"] / 8
+    assert s[64]["flip"] > 1000 * s[64]["exact"]
+    assert s[64]["none"] > 200 * s[64]["exact"]
+
+
+def _hjb_exact_uz(prob, N, M, xi, lam):
+    dt = prob["T"] / N
+    d = prob["d"]
+    X = np.zeros((M, d))
+    U = np.zeros((N + 1, M))
+    Z = np.zeros((N + 1, M, d))
+    for n in range(N + 1):
+        tau = prob["T"] - n * dt
+        if tau > 0:
+            U[n], Z[n] = RV.hjb_grad_u(tau, X, lam=lam, n_par=120, n_perp=40)
+        else:
+            q = (X * X).sum(1)
+            U[n], Z[n] = np.log(0.5 * (1 + q)), 2 * X / (1 + q)[:, None]
+        if n < N:
+            X = X + math.sqrt(2.0 * dt) * xi[n]
+    return U, Z
+
+
+def test_hjb_residual_loss_with_the_cole_hopf_solution():
+    """Hamilton–Jacobi–Bellman (lam |z|^2, ln((1 + |x|^2) / 2)) at d = 2 with
+    u and grad u from the Cole–Hopf formula: loss like dt at lam = 1; the
+    penalty vanishes because grad u(T, .) = grad g; at lam = 8 (same closed
+    form) a flipped, halved or missing driver is caught."""
+    d, M = 2, 256
+    Ns = [8, 16, 32]
+    prob = I.hjb(d)
+    ex = []
+    for N in Ns:
+        xi = O.normals(4, 0, N, M, d)
+        U, Z = _hjb_exact_uz(prob, N, M, xi, 1.0)
+        ex.append(O.unet_loss_given_uz(prob, N, M, U, Z, xi=xi))
+        assert O.unet_loss_given_uz(prob, N, M, U, Z, xi=xi, kappa=2.0) == pytest.approx(ex[-1], rel=1e-12)
+    assert 0.8 < _slope(Ns, ex) < 1.2
+    p8 = I.hjb(d, lam=8.0)
+    xi = O.normals(4, 0, 32, M, d)
+    U, Z = _hjb_exact_uz(p8, 32, M, xi, 8.0)
+    e = O.unet_loss_given_uz(p8, 32, M, U, Z, xi=xi)
+    assert O.unet_loss_given_uz(dict(p8, drv_p=[-8.0, 0.0]), 32, M, U, Z, xi=xi) > 20 * e
+    assert O.unet_loss_given_uz(dict(p8, drv_p=[4.0, 0.0]), 32, M, U, Z, xi=xi) > 2.5 * e
+    assert O.unet_loss_given_uz(dict(p8, drv_p=[0.0, 0.0]), 32, M, U, Z, xi=xi) > 6 * e
+
+
+@pytest.mark.parametrize("arch", ARCHS)
+def test_constant_network_exact_loss(arch):
+    """All weight matrices zero: u is the constant w_o . h_K + b_o with
+    h_0 = tanh(b_0), h_k = c h_{k-1} + tanh(b_k) (NAIS: A_k = -eps I acts on
+    h_{k-1}), and Z = 0.  With phi = a y + b, g = a' sum x + c' the loss is
+    N (a u + b)^2 dt^2 + mean (u - g(X_N))^2 + kappa d a'^2 exactly."""
+    d, w, K, N, M = 3, 5, 2, 4, 9
+    prob = dict(I.hjb(d), drv="linear", drv_p=[0.3, -0.2], g="linear", g_p=[0.7, 0.1],
+                x0=np.array([0.2, -0.1, 0.5]))
+    eps = 0.01
+    net = dict(arch=arch, width=w, depth=K, eps=eps)
+    rng = np.random.default_rng(3)
+    p = np.zeros(O.unet_param_count(prob, net))
+    off = w * (d + 1)
+    b0 = rng.standard_normal(w)
+    p[off:off + w] = b0
+    off += w
+    bs = []
+    for _ in range(K):
+        off += w * w + (w * (d + 1) if arch == "nais" else 0)
+        bs.append(rng.standard_normal(w))
+        p[off:off + w] = bs[-1]
+        off += w
+    wo, bo = rng.standard_normal(w), 0.37
+    p[off:off + w] = wo
+    p[off + w] = bo
+    h = np.tanh(b0)
+    for b in bs:
+        pre = (-eps * h if arch == "nais" else 0.0) + b
+        h = (0.0 if arch == "fc" else 1.0) * h + np.tanh(pre)
+    u = float(wo @ h + bo)
+    xi = O.normals(6, 0, N, M, d)
+    dt = prob["T"] / N
+    xN = prob["x0"] + prob["sde_s"] * math.sqrt(dt) * xi.sum(0)
+    g = 0.7 * xN.sum(1) + 0.1
+    kap = 1.3
+    want = N * (0.3 * u - 0.2) ** 2 * dt * dt + float(np.mean((u - g) ** 2)) + kap * d * 0.7 ** 2
+    got = O.unet_loss_grad(prob, net, N, M, p, xi=xi, kappa=kap, want_grad=False)["loss"]
+    assert got == pytest.approx(want, rel=1e-12)
+
+
+def test_nais_projection():
+    """|R_k^T R_k|_F <= c afterwards; blocks already inside are untouched and
+    the others are scaled by exactly sqrt(c / |R_k^T R_k|_F); nothing else
+    changes."""
+    d, w, K = 3, 6, 3
+    prob = I.bsb(d)
+    net = dict(arch="nais", width=w, depth=K, eps=0.01)
+    p = _params(prob, net, seed=2, scale=0.5)
+    off0 = w * (d + 1) + w
+    blk = w * w + w * (d + 1) + w
+    # shrink block 1 so that it is already feasible
+    p[off0 + blk:off0 + blk + w * w] *= 0.05
+    q = p.copy()
+    c = 1.0 - 2 * 0.01
+    O.unet_nais_project(prob, net, q, c)
+    for k in range(K):
+        R0 = p[off0 + k * blk:off0 + k * blk + w * w].reshape(w, w)
+        R1 = q[off0 + k * blk:off0 + k * blk + w * w].reshape(w, w)
+        f0 = np.linalg.norm(R0.T @ R0)
+        f1 = np.linalg.norm(R1.T @ R1)
+        if f0 <= c:
+            assert np.array_equal(R0, R1)
+        else:
+            assert f1 == pytest.approx(c, rel=1e-12)
+            np.testing.assert_allclose(R1, R0 * math.sqrt(c / f0), rtol=1e-14)
+    mask = np.ones(p.size, bool)
+    for k in range(K):
+        mask[off0 + k * blk:off0 + k * blk + w * w] = False
+    assert np.array_equal(p[mask], q[mask])
+
+
+def test_nais_block_matrix_is_negative_definite():
+    """A = -R^T R - eps I: with a one-block NAIS network on a zero input and
+    zero biases and E, the block maps h_0 to h_0 + tanh(A h_0); recover A h_0
+    from u along unit output vectors and check h_0^T A h_0 <= -eps |h_0|^2."""
+    d, w = 2, 4
+    prob = I.bsb(d)
+    net = dict(arch="nais", width=w, depth=1, eps=0.05)
+    rng = np.random.default_rng(8)
+    p = np.zeros(O.unet_param_count(prob, net))
+    off = w * (d + 1)
+    b0 = rng.uniform(-0.8, 0.8, w)
+    p[off:off + w] = b0                       # h_0 = tanh(b0) for z = 0
+    off += w
+    R = rng.standard_normal((w, w)) * 0.4
+    p[off:off + w * w] = R.ravel()
+    off += w * w + w * (d + 1) + w           # E = 0, b_1 = 0
+    h0 = np.tanh(b0)
+    Ah = np.zeros(w)
+    for j in range(w):
+        q = p.copy()
+        q[off:off + w] = np.eye(w)[j]         # u = h_1[j]
+        u, _ = O.unet_eval(prob, net, q, np.zeros(1), np.zeros((1, d)))
+        Ah[j] = np.arctanh(u[0] - h0[j])
+    A = -R.T @ R - 0.05 * np.eye(w)
+    np.testing.assert_allclose(Ah, A @ h0, rtol=1e-10, atol=1e-12)
+    assert h0 @ Ah <= -0.05 * (h0 @ h0) + 1e-12
