@@ -50,23 +50,41 @@ def kernel_flops(net_prec: str, d: int, w: int, L: int, n_steps: int, paths: int
     return {"forward": fwd, "backward": bwd, "wgrad": wgrad}
 
 
-def kernel_bytes(net_prec: str, d: int, w: int, L: int, n_steps: int, paths: int) -> dict:
-    """Algorithmic HBM bytes per launch of the MFMA kernels: every operand
-    read once, every result written once (activations and deltas in the
-    GEMM precision, path state in fp32), plus the weight-gradient partials
-    (one fp32 copy of the parameters per path split of 512 paths)."""
+def step_net_params(d: int, w: int, L: int) -> int:
+    """Weights and biases of one step's MLP (d -> w -> ... -> w -> d)."""
+    return w * (d + 1) + (L - 1) * w * (w + 1) + d * (w + 1)
+
+
+def kernel_alg_bytes(net_prec: str, d: int, w: int, L: int, n_steps: int, paths: int) -> dict:
+    """Algorithmic HBM bytes per launch of the MFMA kernels on the method's
+    own basis: the step networks' weights once per pass (in the GEMM
+    precision; the weight gradient written once in fp32) and two fp32
+    scalars per path-step (Y_n or c_n, lambda), the Brownian increments and
+    hence X_n being regenerable from their counters.  Whatever an
+    implementation keeps between its kernels (X_n, activations, deltas) is
+    not algorithmic: the counter traffic over these bytes measures it."""
     esz = 4 if net_prec == "fp32" else 2
-    dp = (d + 3) // 4 * 4
     rows = paths * (n_steps - 1)
-    splits = (paths + 511) // 512
-    nparams = d + (n_steps - 1) * (w * (d + 1) + (L - 1) * w * (w + 1) + d * (w + 1))
-    fwd = (4 * dp + 4 * dp + 4 * dp + 4 + esz * L * w) * rows        # X, s in; v, c, activations out
-    bwd = (4 * dp + 4 + esz * L * w + esz * (L * w + d)) * rows      # v, lambda, activations in; deltas out
-    wgrad = (4 * d + esz * L * w + esz * (L * w + d)) * rows + 4 * splits * nparams
-    return {"forward": fwd, "backward": bwd, "wgrad": wgrad}
+    nw = (n_steps - 1) * step_net_params(d, w, L)
+    per_row = 8
+    return {"forward": esz * nw + per_row * rows,
+            "backward": esz * nw + per_row * rows,
+            "wgrad": 4 * nw + per_row * rows}
 
 
-def time_library(prec: str, steps: int, warmup: int):
+def _quantiles(xs) -> dict:
+    a = np.sort(np.asarray(xs, dtype=np.float64))
+    return {"n": int(a.size), "median": round(float(np.median(a)), 5),
+            "p10": round(float(np.percentile(a, 10)), 5), "p90": round(float(np.percentile(a, 90)), 5),
+            "mean": round(float(a.mean()), 5)}
+
+
+def time_library(prec: str, steps: int, warmup: int, min_samples: int = 100):
+    """Training steps of the throughput configuration: the mean over exactly
+    `steps` timed steps (HIP events around the whole region), then the
+    median / p10 / p90 of at least `min_samples` single steps (one event
+    pair per step, a separate run), then per-kernel durations from the
+    library's own HIP events on its launch stream."""
     import torch
     from paper_1910_11623_amd import inputs as I
     from paper_1910_11623_amd.plan import Plan
@@ -80,33 +98,45 @@ def time_library(prec: str, steps: int, warmup: int):
     my, vy = torch.zeros_like(y0), torch.zeros_like(y0)
     out = (torch.empty((), dtype=torch.float64, device="cuda"), torch.empty_like(params),
            torch.empty((), dtype=torch.float64, device="cuda"))
+    k_next = [0]
 
-    def step(k):
+    def step():
+        k = k_next[0]
         plan.forward_backward(params, y0, 1, k, out=out)
         plan.adam_step(params, y0, out[1], out[2], m, v, my, vy, k + 1, lr=1e-3, lr_y0=1e-2)
+        k_next[0] = k + 1
 
-    for k in range(warmup):
-        step(k)
+    for _ in range(warmup):
+        step()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for k in range(steps):
-        step(warmup + k)
+    for _ in range(steps):
+        step()
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
 
+    ns = max(min_samples, steps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(ns + 1)]
+    ev[0].record()
+    for i in range(ns):
+        step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    stats = _quantiles([ev[i].elapsed_time(ev[i + 1]) for i in range(ns)])
+
     # per-kernel durations, HIP events recorded by the library around each launch
     plan.profile(True)
     nprof = max(20, min(steps, 200))
-    for k in range(nprof):
-        step(warmup + steps + k)
+    for _ in range(nprof):
+        step()
     torch.cuda.synchronize()
     prof = plan.profile_read()
     plan.profile(False)
     kern = {k: (t / c if c else 0.0) for k, (t, c) in prof.items()}
     finite = bool(torch.isfinite(out[0]).item())
-    return ms, kern, finite
+    return ms, stats, kern, finite
 
 
 def bsb_closed_form_y0(d: int, T: float = 1.0, r: float = 0.05, sigma: float = 0.4) -> float:
@@ -163,50 +193,95 @@ def measured_traffic(kernel: str, prec: str):
 
 
 def roofline_entry(prec: str, kern_ms: dict):
-    """Roofline of the dominant MFMA kernel, against the unit that bounds it:
-    HBM when its algorithmic intensity (flops per byte) is below the ridge
-    point peak_flops / peak_bytes, else the matrix peak of its dtype."""
+    """Roofline of the dominant MFMA kernel (the longest of forward, reverse
+    sweep and weight gradient): its algorithmic flops per launch over its
+    average launch duration, against the dense matrix peak of its own dtype
+    (157.3 TFLOP/s fp32, 2.5 PFLOP/s bf16).  On the method's byte basis
+    (weights once per pass, X_n and two scalars per path-step) every one of
+    these kernels sits far above the ridge point, so the matrix peak is the
+    bound.  `traffic` is the counter-measured HBM bytes per launch and
+    `traffic_ratio` its multiple of the algorithmic bytes."""
     flops = kernel_flops(prec, D, W, DEPTH, N, M)
-    nbytes = kernel_bytes(prec, D, W, DEPTH, N, M)
+    nbytes = kernel_alg_bytes(prec, D, W, DEPTH, N, M)
     dom = max(flops, key=lambda k: kern_ms.get(k, 0.0))
     t = kern_ms[dom] * 1e-3
     peak = PEAK_FP32_MFMA if prec == "fp32" else PEAK_BF16_MFMA
-    ridge = peak * 1e12 / (PEAK_HBM * 1e9)
     traffic = measured_traffic(dom, prec)
-    if flops[dom] / nbytes[dom] < ridge:
-        achieved = nbytes[dom] / t / 1e9
-        return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM, 4), "traffic": traffic,
-                     "mfma_tflops": round(flops[dom] / t / 1e12, 3)}
     achieved = flops[dom] / t / 1e12
     return dom, {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                 "frac": round(achieved / peak, 4), "traffic": traffic}
+                 "frac": round(achieved / peak, 4), "traffic": traffic,
+                 "algorithmic_bytes": int(nbytes[dom]),
+                 "traffic_ratio": None if traffic is None else round(traffic / nbytes[dom], 2),
+                 "kernel_ms": round(kern_ms[dom], 5)}
 
 
-def cpu_baseline(target_s: float = 12.0):
-    """The FP64 C oracle, single-threaded, on a bounded sample of the same
-    workload: one forward + reverse sweep over a subset of the paths."""
+def step_roofline(prec: str, ms: float) -> dict:
+    """The whole training step on the same basis: algorithmic flops of the
+    forward, reverse sweep and weight gradients over the step time, against
+    the matrix peak of the dtype."""
+    fl = sum(kernel_flops(prec, D, W, DEPTH, N, M).values())
+    peak = PEAK_FP32_MFMA if prec == "fp32" else PEAK_BF16_MFMA
+    return {"flops": int(fl), "achieved": round(fl / (ms * 1e-3) / 1e12, 3), "peak": peak,
+            "frac": round(fl / (ms * 1e-3) / 1e12 / peak, 4)}
+
+
+def _host_cpu() -> dict:
+    """Core count the process may use and the CPU model of the host."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = min(avail, int(omp)) if omp and omp.isdigit() and int(omp) > 0 else avail
+    return {"nproc": os.cpu_count(), "affinity": avail, "omp_num_threads": omp, "threads": threads,
+            "model": model}
+
+
+def _oracle_rate(threads: int, target_s: float):
+    """Path-steps/s of the FP64 C oracle (forward + reverse sweep of the
+    throughput configuration) on `threads` OpenMP threads, over a sample of
+    about `target_s` seconds: a prefix of the paths, or whole batches of
+    successive iterations when one batch takes less than that."""
     from oracle import core as O
     from paper_1910_11623_amd import inputs as I
 
+    O.set_threads(threads)
     prob = I.bsb(D)
     net = dict(kind="mlp", width=W, depth=DEPTH)
     p = I.init_params(prob, net, N, seed=0)
+    probe = 64 * threads
     t0 = time.perf_counter()
-    O.loss_grad(prob, net, N, 16, p, 73.0, seed=1, it=0)
-    t16 = time.perf_counter() - t0
-    per_path = max(t16 / 16, 1e-6)
-    ms = int(max(16, min(M, round(target_s / per_path))))
-    # when the whole batch takes less than the target, repeat it over
-    # successive iterations (fresh Brownian increments each time)
-    reps = int(max(1, min(8, round(target_s / (per_path * M))))) if ms == M else 1
+    O.loss_grad(prob, net, N, probe, p, 73.0, seed=1, it=0)
+    per_path = max((time.perf_counter() - t0) / probe, 1e-7)
+    ms = int(max(probe, min(M, round(target_s / per_path / 64) * 64)))
+    reps = int(max(1, min(16, round(target_s / (per_path * M))))) if ms >= M else 1
+    ms = min(ms, M)
     t0 = time.perf_counter()
     for it in range(reps):
         O.loss_grad(prob, net, N, ms, p, 73.0, seed=1, it=it)
     dt = time.perf_counter() - t0
     what = f"{ms} of {M} paths" if reps == 1 else f"all {M} paths, {reps} iterations"
-    return {"value": round(reps * ms * N / dt, 2), "unit": "path-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what}, forward + reverse sweep at N={N}, d={D}, width {W}x{DEPTH} ({dt:.1f} s)"}
+    return reps * ms * N / dt, f"{what} ({dt:.1f} s)"
+
+
+def cpu_baseline(target_s: float = 10.0):
+    """The FP64 C oracle on the host: with OpenMP over path chunks on every
+    core this process may use (the reported value), and on one thread."""
+    host = _host_cpu()
+    v_all, what_all = _oracle_rate(host["threads"], target_s)
+    v_one, what_one = _oracle_rate(1, target_s)
+    return {"value": round(v_all, 2), "unit": "path-steps/s", "cores": host["threads"], "kind": "oracle",
+            "sample": f"forward + reverse sweep at N={N}, d={D}, width {W}x{DEPTH}: {what_all} on "
+                      f"{host['threads']} threads; single thread {what_one}",
+            "single_thread_value": round(v_one, 2), "host": host}
 
 
 # ------------------------------------------------------- plain FP32 eager
@@ -267,8 +342,11 @@ def eager_prolong(model_c, prob, Nf, device):
     return eager_model(prob, Nf, flat, float(model_c.y0.item()), device)
 
 
-def eager_run(levels, iters, y0_init, check_every=100, target=None, max_seconds=90.0):
-    """Plain FP32 eager training; returns (ms/step at the finest level, time to 1%)."""
+def eager_run(levels, iters, y0_init, check_every=100, target=None, max_seconds=90.0, lr_y0=1e-2):
+    """Plain FP32 eager training with the same schedule as the library's
+    legs; stops once Y0 has held within 1% for 100 finest-level iterations.
+    Returns (ms/step at the finest level, seconds to 1%, final Y0,
+    iteration index of the first accurate iteration)."""
     import torch
     from paper_1910_11623_amd import inputs as I
 
@@ -292,7 +370,7 @@ def eager_run(levels, iters, y0_init, check_every=100, target=None, max_seconds=
     for li, Nl in enumerate(levels):
         if li > 0:
             model = eager_prolong(model, prob, Nl, "cuda")
-        opt = torch.optim.Adam([{"params": [model.y0], "lr": 1e-2},
+        opt = torch.optim.Adam([{"params": [model.y0], "lr": lr_y0},
                                 {"params": [p for n_, p in model.named_parameters() if n_ != "y0"], "lr": 1e-3}])
         ylog = torch.empty(iters[li], device="cuda")
         lv_t0 = time.perf_counter()
@@ -307,6 +385,10 @@ def eager_run(levels, iters, y0_init, check_every=100, target=None, max_seconds=
                 torch.cuda.synchronize()
                 if time.perf_counter() - t_start > max_seconds:
                     break
+                if Nl == levels[-1] and target is not None:
+                    yk = ylog[:done].cpu().numpy()
+                    if _tta(yk, np.arange(done, dtype=np.float64), np.full(done, Nl), target, Nl) is not None:
+                        break
         torch.cuda.synchronize()
         lv_dt = time.perf_counter() - lv_t0
         t_prev = ts[-1][-1] if ts else 0.0
@@ -318,8 +400,9 @@ def eager_run(levels, iters, y0_init, check_every=100, target=None, max_seconds=
         if time.perf_counter() - t_start > max_seconds:
             break
     y, t, Nn = np.concatenate(ys), np.concatenate(ts), np.concatenate(Ns)
-    tta = _tta(y, t, Nn, target, levels[-1])
-    return ms_fine, tta, float(y[-1]) if len(y) else None
+    i = _tta(y, np.arange(len(y), dtype=np.float64), Nn, target, levels[-1])
+    tta = None if i is None else float(t[int(i)])
+    return ms_fine, tta, float(y[-1]) if len(y) else None, None if i is None else int(i)
 
 
 def _tta(y, t, Nn, target, finest, rel=0.01, hold=100):
@@ -330,15 +413,57 @@ def _tta(y, t, Nn, target, finest, rel=0.01, hold=100):
     return None
 
 
-def tta_library(levels, iters, y0_init, target):
+LR_Y0_TTA = 0.1     # y0's Adam rate in the time-to-accuracy legs (networks: 1e-3)
+SINGLE = ([32], [3000])
+MULTI = ([4, 8, 16, 32], [600, 600, 600, 1500])
+MULTI_SWITCH = ([4, 8, 16, 32], [1500, 1500, 1500, 1500])
+SWITCH_REL = 1e-3
+
+
+def tta_library(prec, levels, iters, y0_init, target, switch_rel=None):
+    """One training run of the library through a schedule: seconds and
+    iterations until Y0 holds within 1% of the target on the finest level."""
     from paper_1910_11623_amd import inputs as I
-    from paper_1910_11623_amd.train import multilevel_schedule, time_to_accuracy, train
+    from paper_1910_11623_amd.train import first_accurate_iteration, multilevel_schedule, train
 
     prob = I.bsb(D)
-    net = dict(kind="mlp", width=W, depth=DEPTH, prec="fp32")
-    h = train(prob, net, M, multilevel_schedule(levels, iters), lr=1e-3, lr_y0=1e-2, seed=1, init_seed=0,
-              y0_init=y0_init, warmup=5)
-    return time_to_accuracy(h, target), h.y0_final, float(h.t[-1])
+    net = dict(kind="mlp", width=W, depth=DEPTH, prec=prec)
+    h = train(prob, net, M, multilevel_schedule(levels, iters), lr=1e-3, lr_y0=LR_Y0_TTA, seed=1, init_seed=0,
+              y0_init=y0_init, warmup=5, switch_rel=switch_rel)
+    i = first_accurate_iteration(h, target)
+    return {"seconds": None if i is None else round(float(h.t[i]), 4),
+            "iterations": i, "level_iters": h.level_iters,
+            "level_seconds": [round(t, 4) for t in h.level_seconds],
+            "y0_final": round(h.y0_final, 4), "run_seconds": round(float(h.t[-1]), 4)}
+
+
+def tta_legs(target: float, eager: bool = True) -> dict:
+    """Time to Y0 within 1% of the closed form (held for 100 iterations on
+    the N = 32 grid), from y0 = 73: the library in fp32 and bf16, single
+    level, multilevel with fixed per-level budgets and multilevel with the
+    early switch; the plain FP32 PyTorch-eager form single level and
+    multilevel with the fixed budgets."""
+    y0_init = 73.0
+    out = {"target_y0": target, "y0_start": y0_init, "lr": 1e-3, "lr_y0": LR_Y0_TTA,
+           "single_level": {"levels": SINGLE[0], "iters": SINGLE[1]},
+           "multilevel": {"levels": MULTI[0], "iters": MULTI[1]},
+           "multilevel_early_switch": {"levels": MULTI_SWITCH[0], "max_iters": MULTI_SWITCH[1],
+                                       "switch_rel": SWITCH_REL, "window": 100}}
+    for prec in ("fp32", "bf16"):
+        r = {"single_level": tta_library(prec, *SINGLE, y0_init, target),
+             "multilevel": tta_library(prec, *MULTI, y0_init, target),
+             "multilevel_early_switch": tta_library(prec, *MULTI_SWITCH, y0_init, target, switch_rel=SWITCH_REL)}
+        out[f"library_{prec}"] = r
+        log(f"time to 1% ({prec}): " + ", ".join(f"{k} {v['seconds']} s / {v['iterations']} it" for k, v in r.items()))
+    if eager:
+        e_single = eager_run(*SINGLE, y0_init, target=target, lr_y0=LR_Y0_TTA)
+        e_multi = eager_run(*MULTI, y0_init, target=target, lr_y0=LR_Y0_TTA)
+        out["eager_fp32"] = {
+            "ms_per_step": None if e_single[0] is None else round(e_single[0], 4),
+            "single_level": {"seconds": e_single[1], "iterations": e_single[3], "y0_final": e_single[2]},
+            "multilevel": {"seconds": e_multi[1], "iterations": e_multi[3], "y0_final": e_multi[2]}}
+        log(f"eager: {e_single[0]} ms/step, time to 1% single {e_single[1]} s, multilevel {e_multi[1]} s")
+    return out
 
 
 def batch_leg(steps: int = 20):
@@ -535,43 +660,26 @@ def main():
         print(json.dumps({args.only: leg()}), flush=True)
         return
     if args.prec == "bf16":
-        ms_bf, kern_bf, _ = time_library("bf16", args.steps, args.warmup)
-        log(f"bf16 only: {ms_bf:.4f} ms/step; kernels " + ", ".join(f"{k}={v:.4f}" for k, v in kern_bf.items()))
+        ms_bf, st_bf, kern_bf, _ = time_library("bf16", args.steps, args.warmup)
+        log(f"bf16 only: {ms_bf:.4f} ms/step {st_bf}; kernels " + ", ".join(f"{k}={v:.4f}" for k, v in kern_bf.items()))
         return
-    ms, kern, finite = time_library("fp32", args.steps, args.warmup)
+    ms, stats, kern, finite = time_library("fp32", args.steps, args.warmup)
     value = M * N / (ms * 1e-3)
-    log(f"fp32: {ms:.4f} ms/step, {value:.4e} path-steps/s; kernels (ms/launch) "
+    log(f"fp32: {ms:.4f} ms/step ({stats}), {value:.4e} path-steps/s; kernels (ms/launch) "
         + ", ".join(f"{k}={v:.4f}" for k, v in kern.items()))
     dom, roof = roofline_entry("fp32", kern)
     log(f"dominant kernel {dom}: {roof['achieved']} TFLOP/s of {roof['peak']}")
     if args.prec == "fp32":
-        print(json.dumps({"ms_per_step": ms, "kernels_ms_per_launch": kern, "roofline": roof,
+        print(json.dumps({"ms_per_step": ms, "step_ms": stats, "kernels_ms_per_launch": kern, "roofline": roof,
                           "roofline_kernel": dom}), flush=True)
         return
-    ms_bf, kern_bf, _ = time_library("bf16", args.steps, args.warmup)
+    ms_bf, stats_bf, kern_bf, _ = time_library("bf16", args.steps, args.warmup)
     dom_bf, roof_bf = roofline_entry("bf16", kern_bf)
-    log(f"bf16: {ms_bf:.4f} ms/step; dominant {dom_bf} {roof_bf['achieved']} {roof_bf['unit']} "
-        f"({roof_bf['bound']}-bound, {100 * roof_bf['frac']:.1f}% of peak)")
+    log(f"bf16: {ms_bf:.4f} ms/step ({stats_bf}); dominant {dom_bf} {roof_bf['achieved']} {roof_bf['unit']} "
+        f"({100 * roof_bf['frac']:.1f}% of the bf16 matrix peak)")
 
     target = bsb_closed_form_y0(D)
-    tta = {}
-    if not args.no_tta:
-        y0_init = 73.0
-        single = tta_library([32], [3000], y0_init, target)
-        multi = tta_library([4, 8, 16, 32], [600, 600, 600, 1500], y0_init, target)
-        tta["library_fp32_single_level_s"] = single[0]
-        tta["library_fp32_multilevel_s"] = multi[0]
-        tta["library_final_y0"] = [single[1], multi[1]]
-        log(f"time to 1%: single {single[0]} s, multilevel {multi[0]} s (Y0 {single[1]:.4f}, {multi[1]:.4f})")
-        if not args.no_eager:
-            e_single = eager_run([32], [3000], y0_init, target=target)
-            e_multi = eager_run([4, 8, 16, 32], [600, 600, 600, 1500], y0_init, target=target)
-            tta["eager_fp32_single_level_s"] = e_single[1]
-            tta["eager_fp32_multilevel_s"] = e_multi[1]
-            tta["eager_fp32_ms_per_step"] = round(e_single[0], 4) if e_single[0] else None
-            tta["eager_final_y0"] = [e_single[2], e_multi[2]]
-            log(f"eager: {e_single[0]} ms/step, time to 1% single {e_single[1]} s, multilevel {e_multi[1]} s")
-        tta["target_y0"] = target
+    tta = tta_legs(target, eager=not args.no_eager) if not args.no_tta else None
 
     extra = {}
     if not args.no_extra:
@@ -601,12 +709,15 @@ def main():
         "roofline": roof,
         "roofline_kernel": f"k_{dom}<fp32>",
         "cpu_baseline": cpu,
+        "step_ms": stats,
+        "step_roofline": step_roofline("fp32", ms),
         "kernels_ms_per_launch": {k: round(v, 5) for k, v in kern.items()},
         "finite": finite,
         "bf16": {"ms_per_step": round(ms_bf, 5), "value": round(M * N / (ms_bf * 1e-3), 1),
+                 "step_ms": stats_bf, "step_roofline": step_roofline("bf16", ms_bf),
                  "roofline": roof_bf, "roofline_kernel": f"k_{dom_bf}<bf16>",
                  "kernels_ms_per_launch": {k: round(v, 5) for k, v in kern_bf.items()}},
-        "time_to_1pct": tta or None,
+        "time_to_1pct": tta,
         **extra,
     }
     print(json.dumps(line), flush=True)

@@ -4,7 +4,8 @@ parameters of each level initialise the next through fbsde_prolong).
 
 Every hot step is a library call on torch's current stream; Y0 and the loss
 are logged on the device each iteration and read back once per level, so
-the loop never synchronises the host inside a level.
+the loop never synchronises the host inside a level (the optional early
+level switch reads Y0 back once per check window).
 """
 from __future__ import annotations
 
@@ -21,7 +22,7 @@ from .plan import Plan
 @dataclasses.dataclass
 class Level:
     N: int
-    iters: int
+    iters: int   # iteration budget of the level (the most it runs)
 
 
 @dataclasses.dataclass
@@ -33,6 +34,7 @@ class History:
     level_seconds: list
     params: torch.Tensor
     y0_final: float
+    level_iters: list = dataclasses.field(default_factory=list)  # iterations each level ran
 
 
 def multilevel_schedule(levels, iters_per_level) -> list:
@@ -44,11 +46,16 @@ def multilevel_schedule(levels, iters_per_level) -> list:
 def train(problem: dict, net: dict, M: int, schedule: list, *, lr: float = 1e-3, lr_y0: float = 1e-2,
           seed: int = 1, init_seed: int = 0, y0_init: float | None = None,
           params_init: np.ndarray | None = None, device: str = "cuda", plans: dict | None = None,
-          warmup: int = 0) -> History:
+          warmup: int = 0, switch_rel: float | None = None, switch_window: int = 100) -> History:
     """Adam over the levels of `schedule` (a list of Level).  y0 starts at the
     pilot mean of g(X_N) on the first level unless y0_init is given.  Adam
     moments restart at every level.  `warmup` untimed iterations run on the
-    first level (on a copy of the parameters) before the clock starts."""
+    first level (on a copy of the parameters) before the clock starts.
+
+    Level switch: every level but the last runs its whole budget, unless
+    `switch_rel` is given; then it also ends as soon as Y0 has changed by
+    less than `switch_rel` (relative) over the last `switch_window`
+    iterations, checked once per window (the only host synchronisation)."""
     plans = {} if plans is None else plans
 
     def plan_for(N):
@@ -66,10 +73,11 @@ def train(problem: dict, net: dict, M: int, schedule: list, *, lr: float = 1e-3,
     y0 = torch.tensor(float(y0_init), dtype=torch.float64, device=P0.device)
 
     if warmup > 0:
-        _run_level(P0, params.clone(), y0.clone(), warmup, lr, lr_y0, seed + 7919, None, None, 0)
+        st = _AdamState(params)
+        _run_iters(P0, params.clone(), y0.clone(), st, 0, warmup, lr, lr_y0, seed + 7919, None, None, 0)
     torch.cuda.synchronize()
 
-    Ns, ys, ls, ts, level_seconds = [], [], [], [], []
+    Ns, ys, ls, ts, level_seconds, level_iters = [], [], [], [], [], []
     t_start = time.perf_counter()
     t_prev = 0.0
     it0 = 0
@@ -82,38 +90,74 @@ def train(problem: dict, net: dict, M: int, schedule: list, *, lr: float = 1e-3,
             params = Pc.prolong_to(P, params)
         ylog = torch.empty(lv.iters, dtype=torch.float64, device=P.device)
         llog = torch.empty(lv.iters, dtype=torch.float64, device=P.device)
-        params, y0 = _run_level(P, params, y0, lv.iters, lr, lr_y0, seed, ylog, llog, it0)
+        st = _AdamState(params)
+        last = li == len(schedule) - 1
+        if switch_rel is None or last:
+            _run_iters(P, params, y0, st, 0, lv.iters, lr, lr_y0, seed, ylog, llog, it0)
+            done = lv.iters
+        else:
+            done = 0
+            while done < lv.iters:
+                k = min(switch_window, lv.iters - done)
+                _run_iters(P, params, y0, st, done, k, lr, lr_y0, seed, ylog, llog, it0)
+                done += k
+                if done >= 2 * switch_window:
+                    a_, b_ = ylog[done - 1 - switch_window].item(), ylog[done - 1].item()
+                    if abs(b_ - a_) <= switch_rel * abs(b_):
+                        break
         torch.cuda.synchronize()
         t_now = time.perf_counter() - t_start
         dt_level = t_now - t_prev
         level_seconds.append(dt_level)
-        Ns.append(np.full(lv.iters, lv.N))
-        ys.append(ylog.cpu().numpy())
-        ls.append(llog.cpu().numpy())
-        ts.append(t_prev + dt_level * (np.arange(1, lv.iters + 1) / lv.iters))
+        level_iters.append(done)
+        Ns.append(np.full(done, lv.N))
+        ys.append(ylog[:done].cpu().numpy())
+        ls.append(llog[:done].cpu().numpy())
+        ts.append(t_prev + dt_level * (np.arange(1, done + 1) / done))
         t_prev = t_now
-        it0 += lv.iters
+        it0 += done
     return History(N=np.concatenate(Ns), y0=np.concatenate(ys), loss=np.concatenate(ls),
                    t=np.concatenate(ts), level_seconds=level_seconds, params=params,
-                   y0_final=float(y0.item()))
+                   y0_final=float(y0.item()), level_iters=level_iters)
 
 
-def _run_level(P: Plan, params, y0, iters, lr, lr_y0, seed, ylog, llog, it0):
-    dev = P.device
-    m = torch.zeros_like(params)
-    v = torch.zeros_like(params)
-    my = torch.zeros((), dtype=torch.float64, device=dev)
-    vy = torch.zeros((), dtype=torch.float64, device=dev)
-    loss = torch.empty((), dtype=torch.float64, device=dev)
-    grad = torch.empty_like(params)
-    gy = torch.empty((), dtype=torch.float64, device=dev)
-    for k in range(iters):
-        P.forward_backward(params, y0, seed, it0 + k, out=(loss, grad, gy))
-        P.adam_step(params, y0, grad, gy, m, v, my, vy, k + 1, lr=lr, lr_y0=lr_y0)
+class _AdamState:
+    """Adam moments of one level (zero at the level's start)."""
+
+    def __init__(self, params):
+        dev = params.device
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.my = torch.zeros((), dtype=torch.float64, device=dev)
+        self.vy = torch.zeros((), dtype=torch.float64, device=dev)
+        self.loss = torch.empty((), dtype=torch.float64, device=dev)
+        self.grad = torch.empty_like(params)
+        self.gy = torch.empty((), dtype=torch.float64, device=dev)
+
+
+def _run_iters(P: Plan, params, y0, st: _AdamState, k0, iters, lr, lr_y0, seed, ylog, llog, it0):
+    """Iterations k0 .. k0 + iters - 1 of a level (Adam step count k + 1),
+    updating params and y0 in place."""
+    for k in range(k0, k0 + iters):
+        P.forward_backward(params, y0, seed, it0 + k, out=(st.loss, st.grad, st.gy))
+        P.adam_step(params, y0, st.grad, st.gy, st.m, st.v, st.my, st.vy, k + 1, lr=lr, lr_y0=lr_y0)
         if llog is not None:
-            llog[k].copy_(loss, non_blocking=True)
+            llog[k].copy_(st.loss, non_blocking=True)
             ylog[k].copy_(y0, non_blocking=True)
-    return params, y0
+
+
+def first_accurate_iteration(h: History, target: float, rel: float = 0.01, hold: int = 100,
+                             finest_N: int | None = None) -> int | None:
+    """Index (over all levels) of the first iteration on the finest level
+    from which Y0 stays within `rel` of `target` for the next `hold`
+    iterations (None if never)."""
+    finest_N = int(h.N.max()) if finest_N is None else finest_N
+    ok = (np.abs(h.y0 / target - 1.0) <= rel) & (h.N == finest_N)
+    n = len(ok)
+    for i in range(n - hold + 1):
+        if ok[i:i + hold].all():
+            return i
+    return None
 
 
 def time_to_accuracy(h: History, target: float, rel: float = 0.01, hold: int = 100,
@@ -121,10 +165,5 @@ def time_to_accuracy(h: History, target: float, rel: float = 0.01, hold: int = 1
     """Seconds until the first iteration on the finest level from which Y0
     stays within `rel` of `target` for the next `hold` iterations (None if
     never)."""
-    finest_N = int(h.N.max()) if finest_N is None else finest_N
-    ok = (np.abs(h.y0 / target - 1.0) <= rel) & (h.N == finest_N)
-    n = len(ok)
-    for i in range(n - hold + 1):
-        if ok[i:i + hold].all():
-            return float(h.t[i])
-    return None
+    i = first_accurate_iteration(h, target, rel, hold, finest_N)
+    return None if i is None else float(h.t[i])

@@ -72,3 +72,28 @@ def blockwise_rel(problem, net, N, g, gref):
 
 def run_oracle(problem, net, N, M, p64, y0, seed, it, grad=True):
     return O.loss_grad(problem, oracle_net(net), N, M, p64, y0, seed=seed, it=it, want_grad=grad)
+
+
+def maxrel(a, b):
+    """max |a - b| / max |b| (elementwise error on the block's own scale)."""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    den = float(np.abs(b).max()) if b.size else 0.0
+    err = float(np.abs(a - b).max()) if b.size else 0.0
+    return err / den if den > 0 else err
+
+
+def blockwise_maxrel(problem, net, N, g, gref):
+    return {name: maxrel(g[s], gref[s]) for name, s in blocks(problem, net, N)}
+
+
+def check_grad(problem, net, N, g, gref, tol):
+    """Every parameter block's gradient within `tol`, normwise
+    (|g - g*| / |g*|) and elementwise (max |g - g*| / max |g*|)."""
+    br = blockwise_rel(problem, net, N, g, gref)
+    bm = blockwise_maxrel(problem, net, N, g, gref)
+    worst = max(br.items(), key=lambda kv: kv[1])
+    worst_m = max(bm.items(), key=lambda kv: kv[1])
+    print(f"gradient: worst normwise {worst[0]} {worst[1]:.2e}, worst elementwise {worst_m[0]} {worst_m[1]:.2e}",
+          flush=True)
+    assert worst[1] <= tol, ("normwise", worst)
+    assert worst_m[1] <= tol, ("elementwise", worst_m)

@@ -25,29 +25,38 @@ def test_flop_model_at_d100():
 
 
 def test_byte_model_at_d100():
-    b32 = bench.kernel_bytes("fp32", 100, 110, 2, 32, 4096)
-    b16 = bench.kernel_bytes("bf16", 100, 110, 2, 32, 4096)
+    b32 = bench.kernel_alg_bytes("fp32", 100, 110, 2, 32, 4096)
+    b16 = bench.kernel_alg_bytes("bf16", 100, 110, 2, 32, 4096)
     rows = 4096 * 31
-    splits, nparams = 8, 100 + 31 * (110 * 101 + 110 * 111 + 100 * 111)
-    # X, activations and deltas per path-step: 2560 bytes in fp32
-    assert b32["wgrad"] == 2560 * rows + 4 * splits * nparams
-    # bf16 halves the activations and deltas, not the fp32 path state
-    assert b16["wgrad"] == (400 + 2 * 220 + 2 * 320) * rows + 4 * splits * nparams
-    assert b16["forward"] < b32["forward"]
+    nw = 31 * (110 * 101 + 110 * 111 + 100 * 111)   # weights and biases of the 31 step networks
+    # weights once in the GEMM precision and two fp32 scalars per path-step
+    assert b32["forward"] == 4 * nw + 8 * rows
+    assert b16["forward"] == 2 * nw + 8 * rows
+    # the weight gradient is written once in fp32 whatever the GEMM precision
+    assert b16["wgrad"] == b32["wgrad"] == 4 * nw + 8 * rows
 
 
-def test_roofline_bound_follows_intensity():
+def test_roofline_uses_the_matrix_peak_of_the_dtype():
     kern = {"forward": 0.10, "backward": 0.08, "wgrad": 0.12}
     dom, r = bench.roofline_entry("fp32", kern)
     assert dom == "wgrad"
-    # fp32 weight gradients: ~24 flop/B, above the fp32 ridge of 19.7
     assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-3)
+    flops = bench.kernel_flops("fp32", 100, 110, 2, 32, 4096)["wgrad"]
+    assert r["achieved"] == pytest.approx(flops / 0.12e-3 / 1e12, rel=1e-3)
     dom, r = bench.roofline_entry("bf16", kern)
-    # bf16 is far below its ridge (2.5 PF / 8 TB/s): reported against HBM
-    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["bound"] == "mfma" and r["peak"] == 2500.0
     flops = bench.kernel_flops("bf16", 100, 110, 2, 32, 4096)["wgrad"]
-    assert r["mfma_tflops"] == pytest.approx(flops / 0.12e-3 / 1e12, rel=1e-3)
+    assert r["frac"] == pytest.approx(flops / 0.12e-3 / 1e12 / 2500.0, rel=1e-3)
+    # intensity on the algorithmic byte basis is far above both ridge points
+    nbytes = bench.kernel_alg_bytes("bf16", 100, 110, 2, 32, 4096)["wgrad"]
+    assert flops / nbytes > 2500.0 / 8.0
+    assert r["algorithmic_bytes"] == nbytes
+
+
+def test_step_quantiles():
+    q = bench._quantiles([1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0, 8.0, 9.0, 10.0])
+    assert q["n"] == 10 and q["median"] == 5.5 and q["p10"] == pytest.approx(1.9) and q["p90"] == pytest.approx(9.1)
 
 
 def test_traffic_lookup_requires_the_profiled_source(tmp_path, monkeypatch):
