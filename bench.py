@@ -466,6 +466,189 @@ def tta_legs(target: float, eager: bool = True) -> dict:
     return out
 
 
+# ----------------------------------------- the paper's own formulation
+PAPER_D, PAPER_W, PAPER_K, PAPER_N, PAPER_M = 100, 256, 3, 50, 100
+
+
+def unet_flops_per_row(d: int, w: int, K: int) -> int:
+    """Algorithmic flops of one row (one path at one grid point) of a
+    training step of the u-network: per block product (w x w) the forward,
+    the input-gradient sweep, the second-order sweep, the reverse sweep and
+    two weight-gradient terms (12 w^2); the input layer (d x w) the same
+    minus the reverse product into x (10 d w); the output dot products."""
+    return 12 * K * w * w + 10 * d * w + 4 * w
+
+
+def eager_unet_step_ms(N_: int, M_: int, steps: int = 20, warmup: int = 3) -> float:
+    """Plain FP32 PyTorch-eager form of the same formulation (Z by autograd
+    with create_graph, residual loss, double backward, torch Adam)."""
+    import torch
+    from paper_1910_11623_amd import inputs as I
+
+    torch.backends.cuda.matmul.allow_tf32 = False
+    prob = I.bsb(PAPER_D)
+    d, w, K = PAPER_D, PAPER_W, PAPER_K
+    layers = [torch.nn.Linear(d + 1, w)] + [torch.nn.Linear(w, w) for _ in range(K)] + [torch.nn.Linear(w, 1)]
+    net = torch.nn.ModuleList(layers).cuda()
+    opt = torch.optim.Adam(net.parameters(), lr=1e-3)
+    r, s_ = prob["drv_p"][0], prob["sde_s"]
+    dt = prob["T"] / N_
+    x0 = torch.tensor(prob["x0"], dtype=torch.float32, device="cuda")
+    t = (torch.arange(N_ + 1, device="cuda", dtype=torch.float32) * dt).repeat_interleave(M_)[:, None]
+
+    def step():
+        dW = torch.randn(N_, M_, d, device="cuda") * math.sqrt(dt)
+        X = [x0.expand(M_, d)]
+        for n in range(N_):
+            X.append(X[-1] * (1 + s_ * dW[n]))
+        Xa = torch.cat(X, 0).requires_grad_(True)
+        h = torch.cat([Xa, t], 1)
+        for k, lin in enumerate(net):
+            h = lin(h)
+            if k < len(net) - 1:
+                h = torch.tanh(h)
+        u = h[:, 0]
+        (Z,) = torch.autograd.grad(u.sum(), Xa, create_graph=True)
+        U, Zr, Xr = u.view(N_ + 1, M_), Z.view(N_ + 1, M_, d), Xa.view(N_ + 1, M_, d)
+        S = s_ * Xr[:-1] * dW
+        phi = r * (U[:-1] - (Zr[:-1] * Xr[:-1]).sum(2))
+        res = U[1:] - U[:-1] - phi * dt - (Zr[:-1] * S).sum(2)
+        L = ((res ** 2).sum() + ((U[-1] - (Xr[-1] ** 2).sum(1)) ** 2).sum()) / M_
+        opt.zero_grad(set_to_none=True)
+        L.backward()
+        opt.step()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def paper_leg(steps: int = 100, tta: bool = True):
+    """The paper's own formulation (Sec. 2.2 eq. (loss), Sec. 4.1 set-up):
+    BSB d = 100, one u-network with four fully connected tanh layers of
+    width 256 (input layer + 3 blocks), Z = grad u, residual loss, fp32.
+    Training steps at the paper's M = 100, N = 50 and at M = 4096, N = 32;
+    time until u(0, x0) holds within 1% of the closed form, single level
+    (N = 32) against the multilevel schedule 2 -> 4 -> 8 -> 16 -> 32 of
+    Sec. 3.2; the plain FP32 PyTorch-eager form of the same method."""
+    import torch
+    from paper_1910_11623_amd import inputs as I
+    from paper_1910_11623_amd.plan import UPlan
+    from paper_1910_11623_amd.train import first_accurate_iteration, multilevel_schedule, train_unet
+
+    prob = I.bsb(PAPER_D)
+    net = dict(kind="u_fc", width=PAPER_W, depth=PAPER_K)
+    out = {"network": f"u-network, {PAPER_K + 1} fully connected tanh layers x {PAPER_W}, fp32",
+           "flops_per_row": unet_flops_per_row(PAPER_D, PAPER_W, PAPER_K)}
+    for (Nn, Mm) in ((PAPER_N, PAPER_M), (32, 4096)):
+        plan = UPlan(prob, net, Nn, Mm)
+        p = torch.from_numpy(I.init_unet_params(prob, dict(arch="fc", width=PAPER_W, depth=PAPER_K),
+                                                seed=0).astype(np.float32)).cuda()
+        m, v = torch.zeros_like(p), torch.zeros_like(p)
+        o = (torch.empty((), dtype=torch.float64, device="cuda"), torch.empty_like(p),
+             torch.empty((), dtype=torch.float64, device="cuda"))
+
+        def step(k):
+            plan.forward_backward(p, 1, k, out=o)
+            plan.adam_step(p, o[1], m, v, k + 1)
+        for k in range(5):
+            step(k)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record()
+        for k in range(steps):
+            step(5 + k)
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        q = _quantiles([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+        ms = q["median"]
+        rows = (Nn + 1) * Mm
+        tf = out["flops_per_row"] * rows / (ms * 1e-3) / 1e12
+        out[f"M{Mm}_N{Nn}"] = {"step_ms": q, "path_steps_per_s": round(Mm * Nn / (ms * 1e-3), 1),
+                               "tflops": round(tf, 2), "frac_fp32_peak": round(tf / PEAK_FP32_MFMA, 4),
+                               "finite": bool(torch.isfinite(o[0]).item())}
+        log(f"paper formulation M={Mm} N={Nn}: {ms:.4f} ms/step, {tf:.1f} TFLOP/s")
+    try:
+        out["eager_fp32_M100_N50_ms_per_step"] = round(eager_unet_step_ms(PAPER_N, PAPER_M), 4)
+    except Exception as e:  # the comparator is context; the leg keeps its own numbers
+        out["eager_fp32_M100_N50_ms_per_step"] = f"failed: {e}"
+    if tta:
+        target = bsb_closed_form_y0(PAPER_D)
+        res = {}
+        for name, sched, sw in (("single_level", multilevel_schedule([32], [6000]), None),
+                                ("multilevel", multilevel_schedule([2, 4, 8, 16, 32], [1000] * 4 + [6000]), None),
+                                ("multilevel_early_switch",
+                                 multilevel_schedule([2, 4, 8, 16, 32], [3000] * 4 + [6000]), SWITCH_REL)):
+            h = train_unet(prob, net, PAPER_M, sched, lr=1e-3, seed=1, init_seed=0, warmup=3, switch_rel=sw)
+            i = first_accurate_iteration(h, target)
+            res[name] = {"seconds": None if i is None else round(float(h.t[i]), 4), "iterations": i,
+                         "level_iters": h.level_iters, "y0_final": round(h.y0_final, 4),
+                         "loss_final": float(h.loss[-1]), "run_seconds": round(float(h.t[-1]), 3)}
+            log(f"paper formulation time to 1% ({name}): {res[name]}")
+        out["time_to_1pct"] = dict(res, target_y0=round(target, 4), M=PAPER_M)
+    return out
+
+
+def generalisation_leg(iters: int = 4000, deltas=(0.0, 0.05, 0.1, 0.2, 0.4), N_: int = 32, M_: int = 100,
+                       n_dirs: int = 4):
+    """Sec. 4 generalisation experiment: u-networks of the three block types
+    (fully connected, residual, NAIS), trained at x0 with the same budget,
+    evaluated without re-optimisation on paths from perturbed initial
+    conditions x0 + delta |x0| e (e a random unit direction): the mean over
+    paths and grid points of |u(t_n, X_n) - u*(t_n, X_n)| / u*(t_n, X_n)
+    against the closed form u* = exp((r + sigma^2)(T - t)) |x|^2."""
+    import torch
+    from paper_1910_11623_amd import inputs as I
+    from paper_1910_11623_amd.plan import UPlan
+    from paper_1910_11623_amd.train import multilevel_schedule, train_unet
+
+    prob = I.bsb(PAPER_D)
+    r, sg, T = prob["drv_p"][0], prob["sde_s"], prob["T"]
+    x0 = np.asarray(prob["x0"], dtype=np.float64)
+    rng = np.random.default_rng(11)
+    dirs = rng.standard_normal((n_dirs, PAPER_D))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    out = {"iters": iters, "N": N_, "M": M_, "deltas": list(deltas), "width": PAPER_W, "blocks": PAPER_K}
+    for kind in ("u_fc", "u_res", "u_nais"):
+        net = dict(kind=kind, width=PAPER_W, depth=PAPER_K)
+        t0 = time.perf_counter()
+        h = train_unet(prob, net, M_, multilevel_schedule([N_], [iters]), lr=1e-3, seed=1, init_seed=0)
+        train_s = time.perf_counter() - t0
+        ev = UPlan(prob, net, N_, M_)
+        errs = []
+        for delta in deltas:
+            e_d = []
+            for k in range(n_dirs if delta > 0 else 1):
+                xs = x0 + delta * np.linalg.norm(x0) * dirs[k]
+                ev.set_x0(xs)
+                ev.forward_backward(h.params, 7, 1000 + k, grad=False)
+                u, _ = ev.states()
+                torch.cuda.synchronize()
+                u = u.cpu().numpy().astype(np.float64).reshape(N_ + 1, M_)
+                # the paths of the evaluation, for the closed form
+                xi = ev.sample_normals(7, 1000 + k).cpu().numpy().astype(np.float64)
+                X = np.broadcast_to(xs, (M_, PAPER_D)).copy()
+                rel = []
+                for n in range(N_ + 1):
+                    us = math.exp((r + sg * sg) * (T - n * T / N_)) * (X * X).sum(1)
+                    rel.append(np.abs(u[n] - us) / us)
+                    if n < N_:
+                        X = X * (1.0 + sg * math.sqrt(T / N_) * xi[n])
+                e_d.append(float(np.mean(rel)))
+            errs.append(round(float(np.mean(e_d)), 5))
+        out[kind] = {"mean_rel_error": errs, "train_seconds": round(train_s, 2),
+                     "y0_final": round(h.y0_final, 4), "loss_final": float(h.loss[-1])}
+        log(f"generalisation {kind}: {errs}")
+    return out
+
+
 def batch_leg(steps: int = 20):
     """32 Allen–Cahn instances (d uniform on 20..200, N in {10, 20, 40},
     M = 8192, width d + 10, bf16): one training step of every instance per
@@ -630,7 +813,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the batched Allen-Cahn and HJB legs")
     ap.add_argument("--prec", choices=["fp32", "bf16", "both"], default="both",
                     help="which library precision(s) to time")
-    ap.add_argument("--only", choices=["batch", "hjb", "resnet", "resnet_kept", "resnet_multilevel"],
+    ap.add_argument("--only", choices=["batch", "hjb", "resnet", "resnet_kept", "resnet_multilevel", "paper",
+                                       "generalisation"],
                     help="run just one of the extra legs and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
@@ -656,7 +840,8 @@ def main():
     if args.only:
         leg = {"batch": batch_leg, "hjb": hjb_leg, "resnet": resnet_leg,
                "resnet_kept": lambda: resnet_leg(recompute=False),
-               "resnet_multilevel": resnet_multilevel_leg}[args.only]
+               "resnet_multilevel": resnet_multilevel_leg, "paper": paper_leg,
+               "generalisation": generalisation_leg}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return
     if args.prec == "bf16":
@@ -692,6 +877,7 @@ def main():
         log(f"ResNet BSB d=1000 (recompute): {extra['resnet_bsb_d1000']}")
         extra["resnet_bsb_d1000_kept"] = resnet_leg(recompute=False)
         log(f"ResNet BSB d=1000 (activations kept): {extra['resnet_bsb_d1000_kept']}")
+        extra["paper_formulation_bsb_d100"] = paper_leg(tta=not args.no_tta)
 
     cpu = None
     if not args.no_cpu_baseline:

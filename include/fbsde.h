@@ -45,6 +45,9 @@
  *   shared residual net (depth B blocks, Sec. 3.1 with h = 1):
  *       Win[w][d+1] bin[w]  (column d multiplies t_n),
  *       (W_k[w][w] b_k[w]) for k = 1..B, Wo[d][w] bo[d]
+ *   u-network (depth K blocks; column d of W_0 and E_k multiplies t):
+ *       W_0[w][d+1] b_0[w], per block A_k[w][w] (U_NAIS: R_k[w][w] E_k[w][d+1])
+ *       b_k[w], then w_o[w] b_o
  */
 #ifndef FBSDE_H
 #define FBSDE_H
@@ -96,7 +99,28 @@ typedef struct {
   int32_t g;     double g_p[2];    /* fbsde_terminal and its parameters     */
 } fbsde_problem;
 
-typedef enum { FBSDE_NET_PER_STEP_MLP = 0, FBSDE_NET_SHARED_RESNET = 1 } fbsde_net_kind;
+/* Network kinds.  PER_STEP_MLP and SHARED_RESNET are Z-networks of the
+ * Deep-BSDE form above (Y advanced by the scheme from a trainable Y_0, loss
+ * on the terminal mismatch).  The U_* kinds are the paper's own formulation
+ * (Sec. 2.2, eq. (loss)): one network u(t, x) for every step, Y_n = u(t_n, X_n),
+ * Z_n = grad_x u(t_n, X_n) (exact input gradient of the network), loss
+ *   (1/M) sum_m [ sum_{n<N} r_n^2 + (u_N - g(X_N))^2 + kappa |Z_N - grad g(X_N)|^2 ],
+ *   r_n = u_{n+1} - u_n - phi(t_n, X_n, u_n, Z_n) dt - Z_n . sigma(X_n) dW_n;
+ * the kappa term is the terminal-gradient penalty proposed after eq. (loss)
+ * (fbsde_plan_set_unet_loss; kappa = 0 by default).  Input z = [x; t]; with
+ * depth = K >= 1 blocks of width w:
+ *   h_0 = tanh(W_0 z + b_0), h_k = c h_{k-1} + tanh(A_k h_{k-1} (+ E_k z) + b_k),
+ *   u = w_o . h_K + b_o,
+ *   U_FC:   c = 0 (K + 1 fully connected tanh layers),
+ *   U_RES:  c = 1 (Sec. 3.1 residual block, forward-Euler step h = 1),
+ *   U_NAIS: c = 1, A_k = -R_k^T R_k - eps I and the input injection E_k z
+ *           (Sec. 3.1; trainable R_k, E_k, b_k; eps from
+ *           fbsde_plan_set_unet_loss, 0.01 by default).
+ * fp32 only. */
+typedef enum {
+  FBSDE_NET_PER_STEP_MLP = 0, FBSDE_NET_SHARED_RESNET = 1,
+  FBSDE_NET_U_FC = 2, FBSDE_NET_U_RES = 3, FBSDE_NET_U_NAIS = 4
+} fbsde_net_kind;
 
 /* Arithmetic of the network GEMMs.  Path state (X, Y, Z, lambda) is fp32
  * in both; the loss and dL/dY0 are reduced in fp64.
@@ -118,7 +142,8 @@ typedef struct fbsde_plan fbsde_plan;
 /* Create a plan for N time steps (dt = T/N, t_n = n dt) and M paths on the
  * current HIP device.  Validates everything, copies x0 to the device (the
  * only allocation the library makes, owned by the plan).  Limits of this
- * build: per-step MLP with d <= 256, w <= 256, 1 <= depth <= 8.
+ * build: per-step MLP with d <= 256, w <= 256, 1 <= depth <= 8; u-network
+ * with 1 <= depth <= 16, d, w <= 8192, (N + 1) M < 2^29.
  * Errors: INVALID, UNSUPPORTED, NOMEM, HIP. */
 fbsde_status fbsde_plan_create(const fbsde_problem *problem, const fbsde_net *net, int32_t N,
                                int64_t M, fbsde_plan **out);
@@ -273,6 +298,43 @@ fbsde_status fbsde_batch_create(const fbsde_batch_item *items, int32_t n, double
                                 int32_t autotune, void *stream, fbsde_batch **out);
 fbsde_status fbsde_batch_step(fbsde_batch *batch, void *stream);
 void fbsde_batch_destroy(fbsde_batch *batch);
+
+/* ---- the paper's own formulation (U_* network kinds) ----------------------
+ * Hot calls of these plans are fbsde_unet_forward_backward and
+ * fbsde_adam_step (y0 arguments NULL); fbsde_forward, fbsde_forward_backward,
+ * tuning and batches return UNSUPPORTED / INVALID for them.  Workspace,
+ * parameter count and layout, profiling and prolongation (the identity:
+ * one network for every step) are shared with the other kinds. */
+
+/* kappa >= 0: weight of the terminal-gradient penalty (Sec. 2.2, after
+ * eq. (loss)); eps >= 0: NAIS diagonal shift.  Not a hot call. */
+fbsde_status fbsde_plan_set_unet_loss(fbsde_plan *plan, double kappa, double eps);
+
+/* One evaluation of the loss above on the Brownian increments of (seed,
+ * iter) (same Philox counters as fbsde_forward): *loss_dev (fp64, the sums in
+ * fp64 in a fixed order), u(0, x0) into *y0_dev (fp64, nullable) and, when
+ * grad_dev is non-NULL, the exact gradient [n_params] fp32 through the
+ * network, its input gradient Z and the residuals (reverse sweep with the
+ * second-order terms).  Deterministic.  Errors: INVALID, HIP, NONFINITE (an
+ * earlier call's result). */
+fbsde_status fbsde_unet_forward_backward(fbsde_plan *plan, const float *params_dev, float *grad_dev,
+                                         double *loss_dev, double *y0_dev, uint64_t seed, uint64_t iter,
+                                         void *ws_dev, void *stream);
+
+/* NAIS projection (Sec. 3.1): every R_k with |R_k^T R_k|_F > c is scaled in
+ * place by sqrt(c / |R_k^T R_k|_F).  Uses the workspace. */
+fbsde_status fbsde_unet_nais_project(fbsde_plan *plan, float *params_dev, double c, void *ws_dev,
+                                     void *stream);
+
+/* After fbsde_unet_forward_backward on ws_dev: u of every row (n, m) into
+ * u_dev [(N+1) M] fp32 and Z into z_dev [(N+1) M][d] (row n M + m; either
+ * pointer may be NULL). */
+fbsde_status fbsde_unet_states(fbsde_plan *plan, const void *ws_dev, float *u_dev, float *z_dev, void *stream);
+
+/* Replace the plan's initial state x0 ([d], host; copied to the device).
+ * Not a hot call (synchronous copy).  Used to evaluate a trained network
+ * from a perturbed initial condition (Sec. 4, generalisation). */
+fbsde_status fbsde_plan_set_x0(fbsde_plan *plan, const double *x0_host);
 
 const char *fbsde_status_str(fbsde_status s);
 const char *fbsde_last_error(void);

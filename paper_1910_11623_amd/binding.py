@@ -17,7 +17,7 @@ OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_HIP, ERR_NOMEM, ERR_NONFINITE = range(6)
 SDE = {"gbm_diag": 0, "scaled_bm": 1}
 DRV = {"bsb": 0, "hjb": 1, "ac": 2, "linear": 3}
 TERM = {"norm2": 0, "loghalf": 1, "inv": 2, "linear": 3}
-NET_KIND = {"mlp": 0, "resnet": 1}
+NET_KIND = {"mlp": 0, "resnet": 1, "u_fc": 2, "u_res": 3, "u_nais": 4}
 PREC = {"fp32": 0, "bf16": 1}
 
 EXPORTS = [
@@ -26,6 +26,8 @@ EXPORTS = [
     "fbsde_sample_normals", "fbsde_terminal_mean", "fbsde_terminal_states",
     "fbsde_profile_enable", "fbsde_profile_read", "fbsde_plan_config", "fbsde_plan_get_config",
     "fbsde_plan_autotune", "fbsde_plan_set_checkpointing", "fbsde_plan_status", "fbsde_batch_create", "fbsde_batch_step", "fbsde_batch_destroy",
+    "fbsde_plan_set_unet_loss", "fbsde_unet_forward_backward", "fbsde_unet_nais_project", "fbsde_unet_states",
+    "fbsde_plan_set_x0",
     "fbsde_status_str", "fbsde_last_error",
 ]
 PROF_NAMES = ["pack", "sde", "forward", "scan", "backward", "wgrad", "reduce", "adam"]
@@ -96,6 +98,11 @@ def load(path: str = LIB_PATH):
     L.fbsde_batch_step.argtypes = [vp, vp]
     L.fbsde_batch_destroy.argtypes = [vp]
     L.fbsde_batch_destroy.restype = None
+    L.fbsde_plan_set_unet_loss.argtypes = [vp, C.c_double, C.c_double]
+    L.fbsde_unet_forward_backward.argtypes = [vp, vp, vp, vp, vp, u64, u64, vp, vp]
+    L.fbsde_unet_nais_project.argtypes = [vp, vp, C.c_double, vp, vp]
+    L.fbsde_unet_states.argtypes = [vp, vp, vp, vp, vp]
+    L.fbsde_plan_set_x0.argtypes = [vp, C.POINTER(C.c_double)]
     L.fbsde_status_str.argtypes = [C.c_int]
     L.fbsde_status_str.restype = C.c_char_p
     L.fbsde_last_error.argtypes = []

@@ -85,7 +85,39 @@ void make_layout(fbsde_plan* P) {
   w.LAM = take(N * M * 4);
   w.QN = take(M * 4);
   w.LN = take(M * 4);
-  if (g.kind == 0) {
+  if (g.kind == 2) {
+    // u-network: every buffer carries 256 bytes of slack past its end (the
+    // GEMMs' 16-byte staging loads may run up to 15 floats past a row's
+    // last valid k)
+    const fbsde::UnetLayout U = fbsde::unet_layout(g);
+    const size_t R = (size_t)U.R, wq = (size_t)U.wq, K = (size_t)U.K, wd = (size_t)g.w, dp = (size_t)g.dp;
+    const bool nais = g.uarch == 2;
+    auto tk = [&](size_t floats) { return take(floats * 4 + 256); };
+    w.UU = tk(R);
+    w.UZ = tk(R * dp);
+    w.UUB = tk(R);
+    w.UZB = tk(R * dp);
+    w.UH = tk((K + 1) * R * wq);
+    w.UAL = tk(g.uarch == 0 ? 0 : K * R * wq);
+    w.UHH = tk(K * R * wq);
+    w.UG = tk((K + 1) * R * wq);
+    w.UHHB = tk((K + 1) * R * wq);
+    w.UHB0 = tk(R * wq);
+    w.UALB = tk(K * R * wq);
+    w.UHBAR = tk(R * wq);
+    w.UABAR = tk((K + 1) * R * wq);
+    w.UW0X = tk(wd * dp);
+    w.UW0T = tk(wd);
+    w.UAK = tk(K * wd * wq);
+    w.URK = tk(nais ? K * wd * wq : 0);
+    w.UEX = tk(nais ? K * wd * dp : 0);
+    w.UET = tk(nais ? K * wd : 0);
+    w.UP = tk(nais ? R * wq : 0);
+    w.UABARW = tk(nais ? K * wd * wd : 0);
+    w.UPART = tk((size_t)U.slots * (size_t)U.pstride);
+    w.UCB = tk(R);
+    w.ULP = take(((R + 31) / 32) * 8 + 64);  // one fp64 partial per 32-row residual workgroup, then the flag
+  } else if (g.kind == 0) {
     w.H = take(N * g.L * M * g.wp * esz);
     w.DZ = take(N * M * g.zp * esz);
     w.DH = take(N * g.L * M * g.wp * esz);
@@ -127,7 +159,8 @@ void make_layout(fbsde_plan* P) {
   splits = (int)(((long long)M + chunk - 1) / chunk);
   w.splits = splits;
   w.chunk = chunk;
-  w.PART = take((size_t)splits * (size_t)g.pstride * 4);
+  // (the u-network keeps its partial sums in its own buffer)
+  w.PART = take(g.kind == 2 ? 0 : (size_t)splits * (size_t)g.pstride * 4);
   w.scan_blocks = (int)((M + 63) / 64);  // one wave per scan workgroup
   w.RED = take((size_t)w.scan_blocks * 2 * 8 + 64);
   w.total = off;
@@ -207,6 +240,38 @@ fbsde::ResnetBufs resnet_bufs(const fbsde_plan* P, void* ws) {
   R.xb = at<uint16_t>(ws, L.RXB);
   R.vb = at<uint16_t>(ws, L.RVB);
   return R;
+}
+
+fbsde::UnetBufs unet_bufs(const fbsde_plan* P, void* ws) {
+  const WsLayout& L = P->ws;
+  fbsde::UnetBufs B;
+  B.X = at<float>(ws, L.X);
+  B.S = at<float>(ws, L.V);
+  B.U = at<float>(ws, L.UU);
+  B.Z = at<float>(ws, L.UZ);
+  B.UB = at<float>(ws, L.UUB);
+  B.ZB = at<float>(ws, L.UZB);
+  B.H = at<float>(ws, L.UH);
+  B.AL = at<float>(ws, L.UAL);
+  B.HH = at<float>(ws, L.UHH);
+  B.G = at<float>(ws, L.UG);
+  B.HHB = at<float>(ws, L.UHHB);
+  B.HB0 = at<float>(ws, L.UHB0);
+  B.ALB = at<float>(ws, L.UALB);
+  B.HBAR = at<float>(ws, L.UHBAR);
+  B.ABAR = at<float>(ws, L.UABAR);
+  B.W0x = at<float>(ws, L.UW0X);
+  B.w0t = at<float>(ws, L.UW0T);
+  B.Ak = at<float>(ws, L.UAK);
+  B.Rk = at<float>(ws, L.URK);
+  B.Ex = at<float>(ws, L.UEX);
+  B.et = at<float>(ws, L.UET);
+  B.P = at<float>(ws, L.UP);
+  B.Abar = at<float>(ws, L.UABARW);
+  B.part = at<float>(ws, L.UPART);
+  B.CB = at<float>(ws, L.UCB);
+  B.lpart = at<double>(ws, L.ULP);
+  return B;
 }
 
 // A non-finite result of an earlier call on the plan (raised on the device
@@ -392,12 +457,20 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
     return fail(FBSDE_ERR_INVALID, "problem parameters are not finite");
   if (N < 1) return fail(FBSDE_ERR_INVALID, "N must be >= 1");
   if (M < 1 || M > 0x7fffffffLL) return fail(FBSDE_ERR_INVALID, "M must be in [1, 2^31)");
-  if (net->kind != FBSDE_NET_PER_STEP_MLP && net->kind != FBSDE_NET_SHARED_RESNET)
+  if (net->kind != FBSDE_NET_PER_STEP_MLP && net->kind != FBSDE_NET_SHARED_RESNET && net->kind != FBSDE_NET_U_FC &&
+      net->kind != FBSDE_NET_U_RES && net->kind != FBSDE_NET_U_NAIS)
     return fail(FBSDE_ERR_INVALID, "unknown network kind");
   if (net->prec != FBSDE_FP32 && net->prec != FBSDE_BF16_MFMA) return fail(FBSDE_ERR_INVALID, "unknown precision");
   if (net->width < 1 || net->depth < 1) return fail(FBSDE_ERR_INVALID, "width and depth must be >= 1");
   const bool resnet = net->kind == FBSDE_NET_SHARED_RESNET;
-  if (resnet) {
+  const bool unet = net->kind >= FBSDE_NET_U_FC;
+  if (unet) {
+    if (net->prec != FBSDE_FP32) return fail(FBSDE_ERR_UNSUPPORTED, "the u-network runs in fp32 only");
+    if (net->depth > 16 || p.d > 8192 || net->width > 8192)
+      return fail(FBSDE_ERR_UNSUPPORTED, "u-network: depth (blocks after the input layer) <= 16, d <= 8192, width <= 8192");
+    if ((long long)(N + 1) * M > 0x7fffffffLL / 4)
+      return fail(FBSDE_ERR_UNSUPPORTED, "u-network: (N + 1) M must stay below 2^29 rows");
+  } else if (resnet) {
     if (net->prec != FBSDE_BF16_MFMA)
       return fail(FBSDE_ERR_UNSUPPORTED, "the shared residual network runs in bf16 only");
     if (net->width % 8 != 0 || net->width > 8192 || net->depth > 32 || p.d > 8192)
@@ -421,11 +494,22 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   g.L = net->depth;
   g.N = N;
   g.M = (int)M;
-  g.kind = resnet ? 1 : 0;
+  g.kind = unet ? 2 : resnet ? 1 : 0;
   g.L = net->depth;
   g.lds = 1;
   g.tpw = 0;
-  if (resnet) {
+  g.uarch = unet ? net->kind - FBSDE_NET_U_FC : 0;
+  g.kappa = 0.f;
+  g.ueps = 0.01f;
+  if (unet) {
+    P->ncand = 1;
+    P->cand_ti[0] = P->cand_tw[0] = 0;
+    g.ti = g.tw = 0;
+    g.zp = g.wp = 0;
+    g.packf_step = g.packb_step = g.pbias_step = 0;
+    g.rn_chunk = 0;
+    g.rn_store = 0;
+  } else if (resnet) {
     // chunks of whole steps, about 64k rows each
     g.rn_chunk = rn_chunk_steps(N, M, kDefaultChunkRows);
     g.rn_store = 0;
@@ -461,7 +545,12 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   g.dt = (float)(p.T / N);
   g.sqdt = (float)std::sqrt(p.T / N);
   const long long d = p.d, w = net->width, L = net->depth;
-  if (resnet) {
+  if (unet) {
+    const long long blk = w * w + (g.uarch == 2 ? w * (d + 1) : 0) + w;
+    g.pstep = 0;
+    g.nparams = w * (d + 1) + w + L * blk + w + 1;
+    g.pstride = (g.nparams + 3) / 4 * 4;
+  } else if (resnet) {
     g.pstep = 0;
     g.nparams = w * (d + 1) + w + L * (w * w + w) + d * w + d;
     g.pstride = (g.nparams + 3) / 4 * 4;
@@ -527,6 +616,29 @@ fbsde_status fbsde_param_layout(const fbsde_plan* plan, int64_t* n_params, int64
   const Geo& g = plan->geo;
   // dense layers of one network as (out, in)
   std::vector<std::pair<int, int>> layers;
+  if (g.kind == 2) {  // W_0, b_0, per block (A_k | R_k, [E_k], b_k), w_o, b_o
+    int64_t blk = 0, off = 0;
+    auto add = [&](int rows, int cols) {
+      if (offsets) offsets[blk] = off;
+      if (shapes) { shapes[2 * blk] = rows; shapes[2 * blk + 1] = cols; }
+      off += (int64_t)rows * cols;
+      ++blk;
+    };
+    add(g.w, g.d + 1);
+    add(g.w, 1);
+    for (int k = 0; k < g.L; ++k) {
+      add(g.w, g.w);
+      if (g.uarch == 2) add(g.w, g.d + 1);
+      add(g.w, 1);
+    }
+    add(1, g.w);
+    add(1, 1);
+    if (offsets) offsets[blk] = off;
+    if (off != g.nparams) return fail(FBSDE_ERR_INVALID, "internal: block table does not cover the parameters");
+    if (n_params) *n_params = g.nparams;
+    if (n_blocks) *n_blocks = blk;
+    return FBSDE_OK;
+  }
   if (g.kind == 0) {
     layers.push_back({g.w, g.d});
     for (int l = 2; l <= g.L; ++l) layers.push_back({g.w, g.w});
@@ -567,6 +679,7 @@ fbsde_status fbsde_forward(fbsde_plan* plan, const float* params, const double* 
                            uint64_t iter, double* loss, void* ws, void* stream) {
   fbsde_status st = check_hot(plan, ws);
   if (st != FBSDE_OK) return st;
+  if (plan->geo.kind == 2) return fail(FBSDE_ERR_UNSUPPORTED, "u-network plans use fbsde_unet_forward_backward");
   if (!params || !y0 || !loss) return fail(FBSDE_ERR_INVALID, "params, y0 and loss must be non-NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   st = run_forward(plan, params, y0, seed, iter, nullptr, ws, s);
@@ -582,6 +695,7 @@ fbsde_status fbsde_forward_backward(fbsde_plan* plan, const float* params, const
                                     void* stream) {
   fbsde_status st = check_hot(plan, ws);
   if (st != FBSDE_OK) return st;
+  if (plan->geo.kind == 2) return fail(FBSDE_ERR_UNSUPPORTED, "u-network plans use fbsde_unet_forward_backward");
   if (!params || !y0 || !grad || !grad_y0 || !loss)
     return fail(FBSDE_ERR_INVALID, "params, y0, grad, grad_y0 and loss must be non-NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -609,6 +723,82 @@ fbsde_status fbsde_adam_step(fbsde_plan* plan, float* params, double* y0, const 
   return FBSDE_OK;
 }
 
+fbsde_status fbsde_plan_set_unet_loss(fbsde_plan* plan, double kappa, double eps) {
+  if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
+  if (plan->geo.kind != 2) return fail(FBSDE_ERR_INVALID, "not a u-network plan");
+  if (!(kappa >= 0) || !std::isfinite(kappa) || !(eps >= 0) || !std::isfinite(eps))
+    return fail(FBSDE_ERR_INVALID, "kappa and eps must be finite and >= 0");
+  plan->geo.kappa = (float)kappa;
+  plan->geo.ueps = (float)eps;
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_unet_forward_backward(fbsde_plan* plan, const float* params, float* grad, double* loss,
+                                         double* y0, uint64_t seed, uint64_t iter, void* ws, void* stream) {
+  fbsde_status st = check_hot(plan, ws);
+  if (st != FBSDE_OK) return st;
+  if (plan->geo.kind != 2) return fail(FBSDE_ERR_INVALID, "not a u-network plan");
+  if (!params || !loss) return fail(FBSDE_ERR_INVALID, "params and loss must be non-NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const Geo& g = plan->geo;
+  const WsLayout& L = plan->ws;
+  hipError_t e;
+  {
+    ProfScope ps(plan, FBSDE_PROF_SDE, s);
+    if ((e = fbsde::launch_sde(g, plan->x0_dev, seed, iter, nullptr, at<float>(ws, L.X), at<float>(ws, L.V),
+                               at<float>(ws, L.QN), at<float>(ws, L.LN), s)) != hipSuccess)
+      return hip_fail(e, "sde");
+  }
+  const fbsde::UnetBufs B = unet_bufs(plan, ws);
+  const long long rows = (long long)(g.N + 1) * g.M;
+  int* nf = reinterpret_cast<int*>(B.lpart + (rows + 31) / 32);
+  {
+    ProfScope ps(plan, FBSDE_PROF_FORWARD, s);
+    if ((e = fbsde::unet_forward_backward(g, B, params, grad, loss, y0, nf, plan->nf_host, grad != nullptr, s)) !=
+        hipSuccess)
+      return hip_fail(e, "u-network");
+  }
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_unet_nais_project(fbsde_plan* plan, float* params, double c, void* ws, void* stream) {
+  fbsde_status st = check_hot(plan, ws);
+  if (st != FBSDE_OK) return st;
+  if (plan->geo.kind != 2 || plan->geo.uarch != 2) return fail(FBSDE_ERR_INVALID, "not a NAIS u-network plan");
+  if (!params || !(c > 0) || !std::isfinite(c)) return fail(FBSDE_ERR_INVALID, "params NULL or c not > 0");
+  hipError_t e = fbsde::unet_nais_project(plan->geo, unet_bufs(plan, ws), params, (float)c,
+                                          reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "nais projection");
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_unet_states(fbsde_plan* plan, const void* ws, float* u, float* z, void* stream) {
+  fbsde_status st = check_hot(plan, ws);
+  if (st != FBSDE_OK) return st;
+  if (plan->geo.kind != 2) return fail(FBSDE_ERR_INVALID, "not a u-network plan");
+  const Geo& g = plan->geo;
+  const long long R = (long long)(g.N + 1) * g.M;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (u && (e = hipMemcpyAsync(u, at<float>(ws, plan->ws.UU), (size_t)R * 4, hipMemcpyDeviceToDevice, s)) !=
+               hipSuccess)
+    return hip_fail(e, "copy u");
+  if (z && (e = hipMemcpy2DAsync(z, (size_t)g.d * 4, at<float>(ws, plan->ws.UZ), (size_t)g.dp * 4, (size_t)g.d * 4,
+                                 (size_t)R, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(e, "copy Z");
+  return FBSDE_OK;
+}
+
+fbsde_status fbsde_plan_set_x0(fbsde_plan* plan, const double* x0_host) {
+  if (!plan || !x0_host) return fail(FBSDE_ERR_INVALID, "NULL argument");
+  if (!finite_all(x0_host, plan->geo.d)) return fail(FBSDE_ERR_INVALID, "x0 is not finite");
+  std::vector<float> tmp((size_t)plan->geo.dp, 0.f);
+  for (int i = 0; i < plan->geo.d; ++i) tmp[(size_t)i] = (float)x0_host[i];
+  hipError_t e = hipMemcpy(plan->x0_dev, tmp.data(), tmp.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy x0");
+  return FBSDE_OK;
+}
+
 fbsde_status fbsde_prolong(const fbsde_plan* coarse, const fbsde_plan* fine, const float* pc, float* pf,
                            void* stream) {
   if (!coarse || !fine || !pc || !pf) return fail(FBSDE_ERR_INVALID, "NULL argument");
@@ -616,7 +806,7 @@ fbsde_status fbsde_prolong(const fbsde_plan* coarse, const fbsde_plan* fine, con
   if (b.N != 2 * a.N) return fail(FBSDE_ERR_INVALID, "fine plan must have twice the steps of the coarse plan");
   if (a.d != b.d || a.w != b.w || a.L != b.L || coarse->net.kind != fine->net.kind)
     return fail(FBSDE_ERR_INVALID, "coarse and fine plans must share the problem dimension and network");
-  if (a.kind == 1) {  // one network shared by all steps: the fine grid keeps it unchanged
+  if (a.kind != 0) {  // one network shared by all steps: the fine grid keeps it unchanged
     hipError_t e = hipMemcpyAsync(pf, pc, (size_t)a.nparams * sizeof(float), hipMemcpyDeviceToDevice,
                                   reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "prolong copy");
@@ -726,6 +916,7 @@ fbsde_status fbsde_profile_read(fbsde_plan* plan, double* ms, int64_t* count, in
 // ------------------------------------------------------------------ tuning
 fbsde_status fbsde_plan_config(fbsde_plan* plan, int32_t shape, int32_t lds, int32_t tpw, int32_t splits) {
   if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
+  if (plan->geo.kind == 2) return fail(FBSDE_ERR_UNSUPPORTED, "u-network plans have no tuning configurations");
   if (shape < 0 || shape >= plan->ncand) return fail(FBSDE_ERR_INVALID, "shape index out of range");
   if (tpw < 0 || tpw > 64 || splits < 0 || splits > kMaxTuneSplits)
     return fail(FBSDE_ERR_INVALID, "tiles per wave must be in [0, 64] and splits in [0, 32]");
@@ -753,7 +944,7 @@ fbsde_status fbsde_plan_set_checkpointing(fbsde_plan* plan, int32_t recompute, i
   if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
   if (chunk_rows < 0) return fail(FBSDE_ERR_INVALID, "chunk_rows must be >= 0");
   if (plan->geo.kind != 1) {
-    if (recompute) return fail(FBSDE_ERR_UNSUPPORTED, "the per-step MLP always keeps its activations");
+    if (recompute) return fail(FBSDE_ERR_UNSUPPORTED, "only the shared residual Z-network recomputes activations");
     return FBSDE_OK;
   }
   const int steps = rn_chunk_steps(plan->N, plan->M, chunk_rows > 0 ? chunk_rows : kDefaultChunkRows);
@@ -914,6 +1105,7 @@ fbsde_status fbsde_batch_create(const fbsde_batch_item* items, int32_t n, double
     const fbsde_batch_item& it = items[i];
     fbsde_status st = check_hot(it.plan, it.ws_dev);
     if (st != FBSDE_OK) return st;
+    if (it.plan->geo.kind == 2) return fail(FBSDE_ERR_UNSUPPORTED, "batches hold Deep-BSDE plans only");
     if (!it.params_dev || !it.y0_dev || !it.grad_dev || !it.grad_y0_dev || !it.loss_dev || !it.m_dev ||
         !it.v_dev || !it.m_y0_dev || !it.v_y0_dev)
       return fail(FBSDE_ERR_INVALID, "batch item " + std::to_string(i) + " has a NULL buffer");

@@ -31,7 +31,10 @@ struct Geo {
   long long pbias_step;   // padded fp32 biases per step: L * 16 tw + 16 ti
   int lds;                // 1: step weights may be staged in LDS (when they fit)
   int tpw;                // 16-path tiles per wave of the LDS kernels (0: automatic)
-  int kind;               // 0: per-step MLP, 1: shared residual network (L = blocks)
+  int kind;               // 0: per-step MLP, 1: shared residual network (L = blocks), 2: u-network
+  int uarch;              // u-network blocks: 0 fully connected, 1 residual, 2 NAIS
+  float kappa;            // u-network: weight of the terminal-gradient penalty
+  float ueps;             // u-network NAIS: A_k = -R_k^T R_k - ueps I
   int rn_chunk;           // residual network: time steps per row chunk
   int rn_store;           // residual network: 1 = keep every chunk's activations (no recompute)
 };
@@ -68,10 +71,60 @@ hipError_t resnet_forward(const Geo& g, const ResnetBufs& R, const float* X, flo
 hipError_t resnet_backward(const Geo& g, const ResnetBufs& R, const float* X, const float* V, const float* LAM,
                            float* part, int splits, hipStream_t s);
 
+// The paper's own formulation (u-network over all rows r = n M + m,
+// n = 0..N): offsets of the flat parameter blocks and the partial-sum rows.
+struct UnetLayout {
+  long long R;            // rows (N + 1) M
+  long long wq;           // row stride of the width-w buffers: w rounded up to 4
+  int K;                  // blocks after the input layer
+  long long blk;          // parameters per block
+  long long off_W0, off_b0, off_blk0, off_wo, off_bo;
+  int slots;              // partial sums per parameter
+  long long off_abar;     // NAIS: dA_k scratch inside a partial row
+  long long pstride;      // floats per partial row
+};
+struct UnetBufs {
+  const float* X;         // [N+1][M][dp] path states (the SDE kernel's X)
+  const float* S;         // [N][M][dp] sigma(X_n) dW_n (the SDE kernel's V)
+  float* U;               // [R] u
+  float* Z;               // [R][dp] grad_x u
+  float* UB;              // [R] dL/du
+  float* ZB;              // [R][dp] dL/dZ
+  float* CB;              // [R] residual weights
+  float* H;               // [K+1][R][wq] h_0..h_K
+  float* AL;              // [K][R][wq] alpha_1..alpha_K (residual and NAIS; fully connected reads H)
+  float* HH;              // [K][R][wq] du/dh_0..du/dh_{K-1}
+  float* G;               // [K+1][R][wq] pre-activation gradients of u
+  float* HHB;             // [K+1][R][wq] adjoints of HH (HHB_K: of w_o)
+  float* HB0;             // [R][wq] h_0-adjoint part from the input-gradient sweep
+  float* ALB;             // [K][R][wq] alpha-adjoint parts from the input-gradient sweep
+  float* HBAR;            // [R][wq] running h-adjoint of the reverse sweep
+  float* ABAR;            // [K+1][R][wq] pre-activation adjoints
+  float* W0x;             // [w][dp] x columns of W_0
+  float* w0t;             // [w] t column of W_0
+  float* Ak;              // [K][w][wq] block matrices A_k
+  float* Rk;              // NAIS [K][w][wq] R_k
+  float* Ex;              // NAIS [K][w][dp] x columns of E_k
+  float* et;              // NAIS [K][w] t column of E_k
+  float* P;               // NAIS [R][wq] injection products
+  float* Abar;            // NAIS [K][w][w] summed dA_k
+  float* part;            // [slots][pstride] weight-gradient partial sums
+  double* lpart;          // fp64 loss partials (one per residual workgroup), then an int flag
+};
+UnetLayout unet_layout(const Geo& g);
+// One training evaluation: forward, Z = grad u, residual loss (fp64) and,
+// with want_grad, the parameter gradient; u(0, x0) into *y0 (fp64, nullable).
+hipError_t unet_forward_backward(const Geo& g, const UnetBufs& B, const float* params, float* grad, double* loss,
+                                 double* y0, int* nf, int* host_flag, bool want_grad, hipStream_t s);
+// NAIS projection of every R_k (|R_k^T R_k|_F <= c) in place.
+hipError_t unet_nais_project(const Geo& g, const UnetBufs& B, float* params, float c, hipStream_t s);
+
 // Offsets (bytes) of the sub-buffers of one workspace.
 struct WsLayout {
   size_t X, V, C, Y, LAM, QN, LN, H, DZ, DH, PF, PB, PBIAS, PART, RED, total;
   size_t RPK, RPF, RH32, RHB, RAB, RD32, RGB, RZ, RHT, RGT, RZT, RXT, RXB, RVB;  // residual-network buffers
+  size_t UU, UZ, UUB, UZB, UH, UAL, UHH, UG, UHHB, UHB0, UALB, UHBAR, UABAR, UW0X, UW0T, UAK, URK, UEX, UET, UP,
+      UABARW, UPART, ULP, UCB;  // u-network buffers
   int scan_blocks;
   int splits;
   long long chunk;

@@ -1,0 +1,894 @@
+// The paper's own formulation (Sec. 2.2 eq. (loss), blocks of Sec. 3.1): one
+// network u(t, x) for every time step, Y_n = u(t_n, X_n), Z_n = grad_x u,
+// the per-step residuals r_n = u_{n+1} - u_n - phi dt - Z_n . sigma dW_n, the
+// terminal term and the terminal-gradient penalty kappa |Z_N - grad g|^2,
+// trained through a hand-written reverse sweep that includes the
+// second-order terms of Z.  fp32 throughout (MFMA v_mfma_f32_16x16x4f32).
+//
+// Rows r = n M + m (n = 0..N, every path at every grid point) are
+// independent given the weights, so every product of the network is one
+// GEMM over all rows.  The network (K >= 1 blocks of width w):
+//   h_0 = tanh(W_0 [x; t] + b_0),  h_k = c h_{k-1} + alpha_k,
+//   alpha_k = tanh(A_k h_{k-1} (+ E_k [x; t]) + b_k),  u = w_o . h_K + b_o,
+// c = 0 (fully connected), 1 (residual, NAIS).  Per iteration:
+//   forward     H_0 = tanh(X W0x^T + b_0 + t w0t), H_k = c H_{k-1} + tanh(H_{k-1} A_k^T + b_k)
+//   input grad  G_K = w_o (1 - alpha_K^2), HH_{k-1} = c HH_k + G_k A_k,
+//               G_{k-1} = HH_{k-1} (1 - alpha_{k-1}^2)  (alpha_0 = h_0),  Z = G_0 W0x
+//   residuals   per path: ub = dL/du, ZB = dL/dZ, fp64 loss partials
+//   second order HHB_0 = (ZB W0x^T)(1 - h_0^2), HB0 = (ZB W0x^T) HH_0 (-2 h_0),
+//               HHB_k = c HHB_{k-1} + (HHB_{k-1} A_k^T)(1 - alpha_k^2),
+//               ALB_k = (HHB_{k-1} A_k^T) HH_k (-2 alpha_k)
+//   reverse     ABAR_K = (ALB_K + ub w_o)(1 - alpha_K^2), HBAR_{k-1} = c HBAR_k + ABAR_k A_k,
+//               ABAR_{k-1} = (ALB_{k-1} + HBAR_{k-1})(1 - alpha_{k-1}^2), ABAR_0 with + HB0 and h_0
+//   weights     dA_k = G_k^T HHB_{k-1} + ABAR_k^T H_{k-1}, dW0x = G_0^T ZB + ABAR_0^T X,
+//               biases, t column and w_o as column sums; split over row ranges, fixed-order reduce.
+// NAIS (A_k = -R_k^T R_k - eps I, injection E_k [x; t]) adds the products of
+// E_k in the forward, input-gradient and second-order passes, dE_k and
+// dR_k = -R_k (dA_k + dA_k^T).
+//
+// Operands of every GEMM are read either k-contiguous ([i][k], rows of the
+// reduction index) or k-major ([k][i]), so neither the row buffers nor the
+// weights are ever transposed in memory: a product with W^T reads W k-major,
+// and a weight gradient reads both row buffers k-major (k = rows).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fbsde_internal.h"
+
+namespace fbsde {
+namespace un {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 16;   // reduction slab (floats): four MFMA k-steps of 4
+constexpr int PAD = 16;  // LDS row padding: rows 16 banks apart, so a fragment read (4 rows x 16 floats) is conflict-free
+
+__device__ __forceinline__ float fast_tanh(float x) {
+  // sign(x) (1 - 2 / (exp(2|x|) + 1)) with the hardware exp2 and reciprocal;
+  // odd Taylor series through x^13 below 0.4 (relative error a few ulp)
+  const float ax = fabsf(x);
+  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * ax);
+  const float big = fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+  const float x2 = ax * ax;
+  float q = 21844.0f / 6081075.0f;
+  q = fmaf(q, x2, -1382.0f / 155925.0f);
+  q = fmaf(q, x2, 62.0f / 2835.0f);
+  q = fmaf(q, x2, -17.0f / 315.0f);
+  q = fmaf(q, x2, 2.0f / 15.0f);
+  q = fmaf(q, x2, -1.0f / 3.0f);
+  const float small = fmaf(ax * x2, q, ax);
+  return copysignf(ax < 0.4f ? small : big, x);
+}
+
+// ------------------------------------------------------------------ GEMM
+// C[i][j] = sum_k A(i, k) B(j, k) over k in the split's range.
+struct UGemm {
+  const float* a; long long lda; int arows;  // A: [arows][lda] k-contiguous, or [K][lda] k-major
+  const float* b; long long ldb; int brows;
+  int K;
+  long long kchunk;  // reduction range of one split (multiple of BK)
+  int ti, tj, ts;    // tiles over i, j and splits
+};
+
+enum {
+  U_STORE = 0,  // out0[i][j] (+)= acc + bias[j] + t_i wt[j]
+  U_LIFT = 1,   // out0 = H_0 = tanh(acc + bias + t_i wt)
+  U_BLOCK = 2,  // alpha = tanh(acc + bias (+ in1)); out1 = alpha; out0 = c in0 + alpha; out2 = w_o (1 - alpha^2)
+  U_ZBACK = 3,  // hh = c (in0 or w_o) + acc; out0 = hh; out1 = hh (1 - in1^2)
+  U_S0 = 4,     // out0 = acc (1 - in0^2); out1 = acc in1 (-2 in0)
+  U_SBLK = 5,   // gb = acc (+ in3); out0 = c in0 + gb (1 - in1^2); alb = gb (in2 or w_o)(-2 in1): out1; out2 = (alb + ub w_o)(1 - in1^2)
+  U_RBLK = 6,   // hb = c (in0 or ub w_o) + acc; out0 = hb; out1 = (in2 + hb)(1 - in1^2), in2 = ALB or HB0
+  U_PART = 7,   // part[slot][pbase + i pld + j] = acc
+  U_NAISA = 8   // out0[i][j] = -acc - eps [i == j]
+};
+
+struct UEpi {
+  int rows, cols;         // valid output extent
+  int mp;                 // paths per grid point: row i is at t = (i / mp) dt
+  float dt, c, eps;
+  int acc;                // U_STORE: add to out0 instead of storing
+  const float* bias; const float* wt; const float* wo; const float* ub;
+  const float* in0; const float* in1; const float* in2; const float* in3;
+  float* out0; float* out1; float* out2;
+  long long ld;           // row stride of the row buffers touched by the epilogue
+  float* part; long long pbase, pstride; int pld, slot0;
+};
+
+template <int EPI>
+__device__ __forceinline__ void epi4(const UEpi& E, int i, int j, f32x4 v, int sp) {
+  if (i >= E.rows) return;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int jj = j + q;
+    if (jj >= E.cols) return;
+    const float a = v[q];
+    const long long o = (long long)i * E.ld + jj;
+    if constexpr (EPI == U_PART) {
+      E.part[(long long)(E.slot0 + sp) * E.pstride + E.pbase + (long long)i * E.pld + jj] = a;
+    } else if constexpr (EPI == U_NAISA) {
+      E.out0[o] = -a - (i == jj ? E.eps : 0.f);
+    } else if constexpr (EPI == U_STORE) {
+      float x = a;
+      if (E.bias) x += E.bias[jj];
+      if (E.wt) x += (float)(i / E.mp) * E.dt * E.wt[jj];
+      E.out0[o] = E.acc ? E.out0[o] + x : x;
+    } else if constexpr (EPI == U_LIFT) {
+      E.out0[o] = fast_tanh(a + E.bias[jj] + (float)(i / E.mp) * E.dt * E.wt[jj]);
+    } else if constexpr (EPI == U_BLOCK) {
+      const float al = fast_tanh(a + E.bias[jj] + (E.in1 ? E.in1[o] : 0.f));
+      if (E.out1) E.out1[o] = al;
+      E.out0[o] = (E.c != 0.f ? E.c * E.in0[o] : 0.f) + al;
+      if (E.out2) E.out2[o] = E.wo[jj] * (1.f - al * al);
+    } else if constexpr (EPI == U_ZBACK) {
+      const float prev = E.in0 ? E.in0[o] : E.wo[jj];
+      const float hh = (E.c != 0.f ? E.c * prev : 0.f) + a;
+      E.out0[o] = hh;
+      const float dv = E.in1[o];
+      E.out1[o] = hh * (1.f - dv * dv);
+    } else if constexpr (EPI == U_S0) {
+      const float h0 = E.in0[o];
+      E.out0[o] = a * (1.f - h0 * h0);
+      E.out1[o] = a * E.in1[o] * (-2.f * h0);
+    } else if constexpr (EPI == U_SBLK) {
+      const float gb = a + (E.in3 ? E.in3[o] : 0.f);
+      const float al = E.in1[o];
+      E.out0[o] = (E.c != 0.f ? E.c * E.in0[o] : 0.f) + gb * (1.f - al * al);
+      const float alb = gb * (E.in2 ? E.in2[o] : E.wo[jj]) * (-2.f * al);
+      E.out1[o] = alb;
+      if (E.out2) E.out2[o] = (alb + E.ub[i] * E.wo[jj]) * (1.f - al * al);
+    } else if constexpr (EPI == U_RBLK) {
+      const float prev = E.in0 ? E.in0[o] : E.ub[i] * E.wo[jj];
+      const float hb = (E.c != 0.f ? E.c * prev : 0.f) + a;
+      E.out0[o] = hb;
+      const float dv = E.in1[o];
+      E.out1[o] = (E.in2[o] + hb) * (1.f - dv * dv);
+    }
+  }
+}
+
+// Workgroup of 4 waves (2 x 2), wave tile (16 TM) x (16 TN) as TM x TN MFMA
+// 16x16 tiles.  The reduction is staged BK floats at a time in two LDS
+// buffers; both operands sit in LDS k-major ([k][i], row stride BM + PAD),
+// so every MFMA reads one float per lane from each (lane: i = lane % 16,
+// k = 4 s + lane / 16 for k-step s).  k-contiguous operands are transposed
+// while they are written to LDS; k-major ones are copied as 16-byte runs.
+// Global loads are unconditional (rows and k clamp to the operand's last
+// valid ones; every buffer carries slack past its end) and values at k past
+// the split's end are zeroed at the LDS write.
+template <bool AKM, bool BKM, int EPI, int TM, int TN>
+__global__ __launch_bounds__(256) void k_ugemm(UGemm G, UEpi E) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int LDA = BM + PAD, LDB = BN + PAD;
+  constexpr int UA = BM * BK / 4 / 256, UB = BN * BK / 4 / 256;  // 16-byte staging units per thread
+  __shared__ __attribute__((aligned(16))) float sA[2][BK * LDA];
+  __shared__ __attribute__((aligned(16))) float sB[2][BK * LDB];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wi = wv >> 1, wj = wv & 1;
+  const int g4 = lane >> 4, l16 = lane & 15;
+
+  const int per_split = G.ti * G.tj;
+  const int nt = per_split * G.ts;
+  int T = blockIdx.x;
+  if ((nt & 7) == 0) T = (T & 7) * (nt >> 3) + (T >> 3);  // consecutive tiles on one XCD
+  const int sp = T / per_split;
+  const int rem = T - sp * per_split;
+  const int it = rem / G.tj, jt = rem - it * G.tj;
+  const int i0 = it * BM, j0 = jt * BN;
+  const long long ks = (long long)sp * G.kchunk;
+  const long long ke = min((long long)G.K, ks + G.kchunk);
+  const int nk = ke > ks ? (int)((ke - ks + BK - 1) / BK) : 0;
+
+  // per-unit source offsets (without the slab's k offset)
+  long long aoff[UA], boff[UB];
+  int akq[UA], bkq[UB];   // k-contiguous: k offset of the unit; k-major: k row of the unit
+  int acol[UA], bcol[UB]; // LDS column (row index i) of the unit
+#pragma unroll
+  for (int q = 0; q < UA; ++q) {
+    const int u = tid + 256 * q;
+    if constexpr (!AKM) {
+      const int r = u >> 2;
+      akq[q] = 4 * (u & 3);
+      acol[q] = r;
+      aoff[q] = (long long)min(i0 + r, G.arows - 1) * G.lda + akq[q];
+    } else {
+      const int kr = u / (BM / 4), c4 = u % (BM / 4);
+      akq[q] = kr;
+      acol[q] = 4 * c4;
+      aoff[q] = (long long)min(i0 + 4 * c4, (int)G.lda - 4);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < UB; ++q) {
+    const int u = tid + 256 * q;
+    if constexpr (!BKM) {
+      const int r = u >> 2;
+      bkq[q] = 4 * (u & 3);
+      bcol[q] = r;
+      boff[q] = (long long)min(j0 + r, G.brows - 1) * G.ldb + bkq[q];
+    } else {
+      const int kr = u / (BN / 4), c4 = u % (BN / 4);
+      bkq[q] = kr;
+      bcol[q] = 4 * c4;
+      boff[q] = (long long)min(j0 + 4 * c4, (int)G.ldb - 4);
+    }
+  }
+  auto load = [&](int slab, f32x4 (&ra)[UA], f32x4 (&rb)[UB]) {
+    const long long kt = ks + (long long)(slab < nk ? slab : 0) * BK;
+#pragma unroll
+    for (int q = 0; q < UA; ++q) {
+      if constexpr (!AKM) {
+        ra[q] = *reinterpret_cast<const f32x4*>(G.a + aoff[q] + kt);
+      } else {
+        const long long k = min(kt + akq[q], (long long)G.K - 1);
+        ra[q] = *reinterpret_cast<const f32x4*>(G.a + k * G.lda + aoff[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < UB; ++q) {
+      if constexpr (!BKM) {
+        rb[q] = *reinterpret_cast<const f32x4*>(G.b + boff[q] + kt);
+      } else {
+        const long long k = min(kt + bkq[q], (long long)G.K - 1);
+        rb[q] = *reinterpret_cast<const f32x4*>(G.b + k * G.ldb + boff[q]);
+      }
+    }
+  };
+  auto store = [&](int slab, int buf, const f32x4 (&ra)[UA], const f32x4 (&rb)[UB]) {
+    const long long kt = ks + (long long)slab * BK;
+#pragma unroll
+    for (int q = 0; q < UA; ++q) {
+      if constexpr (!AKM) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          sA[buf][(akq[q] + e) * LDA + acol[q]] = (kt + akq[q] + e < ke) ? ra[q][e] : 0.f;
+      } else {
+        const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
+        *reinterpret_cast<f32x4*>(&sA[buf][akq[q] * LDA + acol[q]]) = (kt + akq[q] < ke) ? ra[q] : z;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < UB; ++q) {
+      if constexpr (!BKM) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          sB[buf][(bkq[q] + e) * LDB + bcol[q]] = (kt + bkq[q] + e < ke) ? rb[q][e] : 0.f;
+      } else {
+        const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
+        *reinterpret_cast<f32x4*>(&sB[buf][bkq[q] * LDB + bcol[q]]) = (kt + bkq[q] < ke) ? rb[q] : z;
+      }
+    }
+  };
+
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      float fa[TM], fb[TN];
+      const int kr = 4 * s + g4;
+#pragma unroll
+      for (int a = 0; a < TM; ++a) fa[a] = sA[buf][kr * LDA + wi * 16 * TM + 16 * a + l16];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) fb[b] = sB[buf][kr * LDB + wj * 16 * TN + 16 * b + l16];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[b], fa[a], acc[a][b], 0, 0, 0);
+    }
+  };
+
+  f32x4 ra[UA], rb[UB];
+  if (nk > 0) {
+    load(0, ra, rb);
+    store(0, 0, ra, rb);
+  }
+  __syncthreads();
+  for (int s = 0; s < nk; ++s) {
+    load(s + 1, ra, rb);  // past the last slab: a harmless re-read of the first
+    compute(s & 1);
+    if (s + 1 < nk) store(s + 1, (s + 1) & 1, ra, rb);
+    __syncthreads();
+  }
+  // lane: row i = .. + l16, columns j = .. + 4 (lane / 16) + 0..3
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+      epi4<EPI>(E, i0 + wi * 16 * TM + 16 * a + l16, j0 + wj * 16 * TN + 16 * b + 4 * g4, acc[a][b], sp);
+}
+
+// ------------------------------------------------------- u = H_K w_o + b_o
+// One wave per row (lanes stride over the width, fixed xor butterfly).
+__global__ __launch_bounds__(256) void k_urowdot(long long R, int w, long long ld, const float* __restrict__ H,
+                                                 const float* __restrict__ wo, const float* __restrict__ bo,
+                                                 float* __restrict__ u, double* __restrict__ y0) {
+  const int lane = threadIdx.x & 63;
+  const long long r = blockIdx.x * 4LL + (threadIdx.x >> 6);
+  if (r >= R) return;
+  float s = 0.f;
+  for (int a = lane; a < w; a += 64) s += H[r * ld + a] * wo[a];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) {
+    const float v = s + bo[0];
+    u[r] = v;
+    if (r == 0 && y0) y0[0] = (double)v;  // u(0, x0): every path starts at x0
+  }
+}
+
+// --------------------------------------------------------------- residuals
+struct ResArgs {
+  int d, dp, N, M;
+  float dt, kappa;
+  int sde, drv, g;
+  float drv_p0, drv_p1, g_p0, g_p1;
+  const float* X;   // [N+1][M][dp]
+  const float* S;   // [N][M][dp]  sigma(X_n) dW_n
+  const float* U;   // [R]
+  const float* Z;   // [R][dp]
+  float* UB;        // [R]
+  float* ZB;        // [R][dp]
+  float* CB;        // [R] residual weights 2 r_n / M (2 e / M at n = N)
+  double* part;     // [blocks] fp64 loss partials
+  int* nf;          // non-finite flag of the reductions: cleared here, every call
+};
+
+__device__ __forceinline__ float wsum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Residuals are independent across rows given u and Z: one wave per row
+// (n, m), RPW consecutive rows per wave.  Row n < N: r_n = u_{n+1} - u_n -
+// phi dt - Z_n . s_n, its weight c_n = 2 r_n / M into CB (the seeds
+// dL/du_n collect c_{n-1} - c_n (1 + phi_y dt), formed by k_useeds),
+// dL/dZ_n = -c_n (phi_z dt + s_n).  Row N: e = u_N - g(X_N), CB = 2 e / M,
+// and the penalty's dL/dZ_N = 2 kappa (Z_N - grad g) / M.  Loss sums in
+// fp64, fixed order (rows of a wave, then the waves of a workgroup).
+constexpr int RES_RPW = 8;
+
+__global__ __launch_bounds__(256) void k_ures(ResArgs A) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ double sl[4];
+  double loss = 0.0;
+  const long long R = (long long)(A.N + 1) * A.M;
+  const float invM = 1.f / (float)A.M;
+  for (int q = 0; q < RES_RPW; ++q) {
+    const long long r = ((long long)blockIdx.x * 4 + wv) * RES_RPW + q;
+    if (r >= R) break;
+    const int n = (int)(r / A.M);
+    const float* x = A.X + r * A.dp;
+    const float* z = A.Z + r * A.dp;
+    float* zb = A.ZB + r * A.dp;
+    if (n < A.N) {
+      const float* s = A.S + r * A.dp;
+      float zs = 0.f, zq = 0.f;
+      for (int i = lane; i < A.d; i += 64) {
+        const float zi = z[i];
+        zs += zi * s[i];
+        zq += A.drv == 0 ? zi * x[i] : zi * zi;
+      }
+      zs = wsum(zs);
+      zq = wsum(zq);
+      const float un = A.U[r], un1 = A.U[r + A.M];
+      float phi;
+      switch (A.drv) {
+        case 0: phi = A.drv_p0 * (un - zq); break;          // BSB r (y - z.x)
+        case 1: phi = A.drv_p0 * zq; break;                 // HJB lam |z|^2
+        case 2: phi = un * un * un - un; break;             // Allen-Cahn y^3 - y
+        default: phi = A.drv_p0 * un + A.drv_p1; break;     // linear a y + b
+      }
+      const float res = un1 - un - phi * A.dt - zs;
+      loss += (double)res * (double)res;
+      const float c = 2.f * res * invM;
+      if (lane == 0) A.CB[r] = c;
+      for (int i = lane; i < A.d; i += 64) {
+        float pz = 0.f;
+        if (A.drv == 0) pz = -A.drv_p0 * x[i];
+        else if (A.drv == 1) pz = 2.f * A.drv_p0 * z[i];
+        zb[i] = -c * (pz * A.dt + s[i]);
+      }
+    } else {
+      float qx = 0.f, lin = 0.f;
+      for (int i = lane; i < A.d; i += 64) {
+        qx += x[i] * x[i];
+        lin += x[i];
+      }
+      qx = wsum(qx);
+      lin = wsum(lin);
+      float gv, gs;  // g(x) and grad g = gs x (linear g: the constant a)
+      switch (A.g) {
+        case 0: gv = qx; gs = 2.f; break;
+        case 1: gv = logf(0.5f * (1.f + qx)); gs = 2.f / (1.f + qx); break;
+        case 2: { const float den = A.g_p0 + A.g_p1 * qx; gv = 1.f / den; gs = -2.f * A.g_p1 / (den * den); break; }
+        default: gv = A.g_p0 * lin + A.g_p1; gs = 0.f; break;
+      }
+      const float e = A.U[r] - gv;
+      loss += (double)e * (double)e;
+      if (lane == 0) A.CB[r] = 2.f * e * invM;
+      float pen = 0.f;
+      for (int i = lane; i < A.d; i += 64) {
+        const float gi = A.g == 3 ? A.g_p0 : gs * x[i];
+        const float dz = z[i] - gi;
+        pen += dz * dz;
+        zb[i] = 2.f * A.kappa * dz * invM;
+      }
+      pen = wsum(pen);
+      loss += (double)A.kappa * (double)pen;
+    }
+  }
+  if (lane == 0) sl[wv] = loss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    A.part[blockIdx.x] = ((sl[0] + sl[1]) + sl[2]) + sl[3];
+    if (blockIdx.x == 0) A.nf[0] = 0;
+  }
+}
+
+// dL/du_n = c_{n-1} - c_n (1 + phi_y(u_n) dt) for n < N (c_{-1} = 0), and
+// c_{N-1} + 2 e / M at n = N (CB holds 2 e / M there).
+__global__ __launch_bounds__(256) void k_useeds(ResArgs A) {
+  const long long R = (long long)(A.N + 1) * A.M;
+  const long long r = blockIdx.x * 256LL + threadIdx.x;
+  if (r >= R) return;
+  const int n = (int)(r / A.M);
+  const float prev = n > 0 ? A.CB[r - A.M] : 0.f;
+  if (n == A.N) {
+    A.UB[r] = prev + A.CB[r];
+    return;
+  }
+  const float un = A.U[r];
+  float phiy;
+  switch (A.drv) {
+    case 0: phiy = A.drv_p0; break;
+    case 1: phiy = 0.f; break;
+    case 2: phiy = 3.f * un * un - 1.f; break;
+    default: phiy = A.drv_p0; break;
+  }
+  A.UB[r] = prev - A.CB[r] * (1.f + phiy * A.dt);
+}
+
+// ------------------------------------------------------------- column sums
+// part[slot][off + a * stride] = sum over the slot's rows r of
+//   mode 0: P[r][a]            (bias gradients)
+//   mode 1: t_r P[r][a]        (t column of W_0 / E_k)
+//   mode 2: P[r][a] + ub_r Q[r][a]  (w_o)
+//   mode 3: ub_r  (a = 0 only)      (b_o)
+struct ColJob {
+  int mode, cols;
+  const float* P; const float* Q;
+  long long off; int stride;
+};
+struct ColArgs {
+  long long R; long long ld; int mp; float dt;
+  const float* ub;
+  float* part; long long pstride;
+  int slots; long long chunk;  // rows per slot
+  ColJob job[40];
+  int njobs;
+};
+
+// grid: (column blocks of 256, slots, jobs)
+__global__ __launch_bounds__(256) void k_ucolsum(ColArgs C) {
+  const int jb = blockIdx.z;
+  if (jb >= C.njobs) return;
+  const ColJob J = C.job[jb];
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= J.cols) return;
+  const long long r0 = (long long)blockIdx.y * C.chunk;
+  const long long r1 = min(C.R, r0 + C.chunk);
+  float s = 0.f;
+  for (long long r = r0; r < r1; ++r) {
+    if (J.mode == 0) s += J.P[r * C.ld + a];
+    else if (J.mode == 1) s += (float)(r / C.mp) * C.dt * J.P[r * C.ld + a];
+    else if (J.mode == 2) s += J.P[r * C.ld + a] + C.ub[r] * J.Q[r * C.ld + a];
+    else s += C.ub[r];
+  }
+  C.part[(long long)blockIdx.y * C.pstride + J.off + (long long)a * J.stride] = s;
+}
+
+// ---------------------------------------------------------------- packing
+// Aligned copies of the weight blocks the GEMMs read: W0x [w][dp] (x
+// columns of W_0, zero padded) and w0t [w] (its t column); per block
+// A_k [w][wq] (or R_k for NAIS) and, for NAIS, E_kx [w][dp], e_kt [w].
+struct PackArgs {
+  const float* params;
+  int d, dp, w, wq, K, nais;
+  float* W0x; float* w0t;
+  float* Ak;  // [K][w][wq]
+  float* Ex;  // [K][w][dp]
+  float* et;  // [K][w]
+};
+
+__global__ __launch_bounds__(256) void k_upack(PackArgs P) {
+  const long long d1 = P.d + 1;
+  const long long blk = (long long)P.w * P.w + (P.nais ? (long long)P.w * d1 : 0) + P.w;
+  const long long off0 = (long long)P.w * d1 + P.w;
+  const long long n0 = (long long)P.w * P.dp;
+  const long long na = (long long)P.K * P.w * P.wq;
+  const long long ne = P.nais ? (long long)P.K * P.w * P.dp : 0;
+  const long long total = n0 + P.w + na + ne + (P.nais ? (long long)P.K * P.w : 0);
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+    if (e < n0) {
+      const long long a = e / P.dp, i = e % P.dp;
+      P.W0x[e] = i < P.d ? P.params[a * d1 + i] : 0.f;
+    } else if (e < n0 + P.w) {
+      const long long a = e - n0;
+      P.w0t[a] = P.params[a * d1 + P.d];
+    } else if (e < n0 + P.w + na) {
+      const long long q = e - n0 - P.w;
+      const long long k = q / ((long long)P.w * P.wq), rem = q % ((long long)P.w * P.wq);
+      const long long a = rem / P.wq, c = rem % P.wq;
+      P.Ak[q] = c < P.w ? P.params[off0 + k * blk + a * P.w + c] : 0.f;
+    } else if (e < n0 + P.w + na + ne) {
+      const long long q = e - n0 - P.w - na;
+      const long long k = q / ((long long)P.w * P.dp), rem = q % ((long long)P.w * P.dp);
+      const long long a = rem / P.dp, i = rem % P.dp;
+      P.Ex[q] = i < P.d ? P.params[off0 + k * blk + (long long)P.w * P.w + a * d1 + i] : 0.f;
+    } else {
+      const long long q = e - n0 - P.w - na - ne;
+      const long long k = q / P.w, a = q % P.w;
+      P.et[q] = P.params[off0 + k * blk + (long long)P.w * P.w + a * d1 + P.d];
+    }
+  }
+}
+
+// -------------------------------------------------------- reduce, finalize
+// grad[e] = sum over slots in order; the loss partials of the residual
+// kernel are summed by the last wave in fixed order.
+__global__ __launch_bounds__(256) void k_ureduce(long long P, long long pstride, const float* __restrict__ part,
+                                                 int slots, float* __restrict__ grad, int* __restrict__ nf) {
+  bool bad = false;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < P; e += (long long)gridDim.x * 256) {
+    float s = 0.f;
+    for (int k = 0; k < slots; ++k) s += part[(long long)k * pstride + e];
+    grad[e] = s;
+    bad |= !isfinite(s);
+  }
+  if (bad) nf[0] = 1;
+}
+
+__global__ __launch_bounds__(64) void k_ufinal(int M, const double* __restrict__ sp, int nb, double* __restrict__ loss,
+                                               int* __restrict__ nf, int* __restrict__ host_flag) {
+  double a = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 64) a += sp[k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+  if (threadIdx.x == 0) {
+    if (loss) loss[0] = a / (double)M;
+    const bool bad = nf[0] != 0 || !isfinite(a);
+    nf[0] = 0;
+    if (bad && host_flag) host_flag[0] = 1;
+  }
+}
+
+// R-bar_k = -R_k (A-bar_k + A-bar_k^T) (NAIS), one thread per element: the
+// value goes to slot 0 of R_k's partial rows, zeros to the other slots.
+__global__ __launch_bounds__(256) void k_unais_rgrad(int w, const float* __restrict__ R, const float* __restrict__ Ab,
+                                                     float* __restrict__ part, long long pstride, int slots) {
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= (long long)w * w) return;
+  const int q = (int)(e / w), c = (int)(e % w);
+  float s = 0.f;
+  for (int a = 0; a < w; ++a) s += R[(long long)q * w + a] * (Ab[(long long)a * w + c] + Ab[(long long)c * w + a]);
+  part[e] = -s;
+  for (int k = 1; k < slots; ++k) part[(long long)k * pstride + e] = 0.f;
+}
+
+// NAIS projection: |R^T R|_F per block from RtR [K][w][wq], then R scaled by
+// sqrt(c / |R^T R|_F) where that exceeds c.  One workgroup per block.
+__global__ __launch_bounds__(256) void k_unais_project(int w, int wq, const float* __restrict__ RtR, float* __restrict__ params,
+                                                       long long off0, long long blk, float c) {
+  const int k = blockIdx.x;
+  __shared__ double sh[256];
+  double s = 0.0;
+  const float* M = RtR + (long long)k * w * wq;
+  for (long long e = threadIdx.x; e < (long long)w * w; e += 256) {
+    const double v = M[(e / w) * wq + e % w];
+    s += v * v;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double f = sqrt(sh[0]);
+  if (f <= (double)c) return;
+  const float sc = (float)sqrt((double)c / f);
+  float* R = params + off0 + (long long)k * blk;
+  for (long long e = threadIdx.x; e < (long long)w * w; e += 256) R[e] *= sc;
+}
+
+}  // namespace un
+
+// ----------------------------------------------------------------- driver
+using namespace un;
+
+namespace {
+
+template <bool AKM, bool BKM, int EPI>
+hipError_t gemm(const UGemm& G0, const UEpi& E, int M_i, int N_j, int splits, hipStream_t s) {
+  UGemm G = G0;
+  const long long K = G.K;
+  splits = splits < 1 ? 1 : splits;
+  G.kchunk = ((K + splits - 1) / splits + BK - 1) / BK * BK;
+  if (G.kchunk < BK) G.kchunk = BK;
+  G.ts = (int)((K + G.kchunk - 1) / G.kchunk);
+  if (G.ts < 1) G.ts = 1;
+  // wider tiles when they still give every CU a few workgroups
+  const long long big = (long long)((M_i + 127) / 128) * ((N_j + 127) / 128) * G.ts;
+  if (big >= 1024) {
+    G.ti = (M_i + 127) / 128;
+    G.tj = (N_j + 127) / 128;
+    hipLaunchKernelGGL((k_ugemm<AKM, BKM, EPI, 4, 4>), dim3(G.ti * G.tj * G.ts), dim3(256), 0, s, G, E);
+  } else {
+    G.ti = (M_i + 63) / 64;
+    G.tj = (N_j + 63) / 64;
+    hipLaunchKernelGGL((k_ugemm<AKM, BKM, EPI, 2, 2>), dim3(G.ti * G.tj * G.ts), dim3(256), 0, s, G, E);
+  }
+  return hipGetLastError();
+}
+
+UEpi epi0(const Geo& g, long long ld) {
+  UEpi E{};
+  E.mp = g.M;
+  E.dt = g.dt;
+  E.c = g.uarch == 0 ? 0.f : 1.f;
+  E.eps = g.ueps;
+  E.ld = ld;
+  return E;
+}
+
+}  // namespace
+
+UnetLayout unet_layout(const Geo& g) {
+  UnetLayout L;
+  L.R = (long long)(g.N + 1) * g.M;
+  L.wq = (g.w + 3) / 4 * 4;
+  L.K = g.L;
+  const int K = g.L;
+  const long long d1 = g.d + 1;
+  L.blk = (long long)g.w * g.w + (g.uarch == 2 ? (long long)g.w * d1 : 0) + g.w;
+  L.off_W0 = 0;
+  L.off_b0 = (long long)g.w * d1;
+  L.off_blk0 = L.off_b0 + g.w;
+  L.off_wo = L.off_blk0 + (long long)K * L.blk;
+  L.off_bo = L.off_wo + g.w;
+  L.slots = 16;
+  const long long np4 = (g.nparams + 3) / 4 * 4;
+  L.off_abar = np4;
+  L.pstride = np4 + (g.uarch == 2 ? (long long)K * g.w * g.w : 0);
+  L.pstride = (L.pstride + 3) / 4 * 4;
+  return L;
+}
+
+hipError_t unet_forward_backward(const Geo& g, const UnetBufs& B, const float* params, float* grad, double* loss,
+                                 double* y0, int* nf, int* host_flag, bool want_grad, hipStream_t s) {
+  const UnetLayout L = unet_layout(g);
+  const int K = L.K, w = g.w, d = g.d, dp = g.dp;
+  const long long R = L.R, wq = L.wq;
+  const bool nais = g.uarch == 2;
+  const bool fc = g.uarch == 0;
+  hipError_t e;
+  auto Hk = [&](int k) { return B.H + (long long)k * R * wq; };
+  auto ALk = [&](int k) { return fc ? Hk(k) : B.AL + (long long)(k - 1) * R * wq; };  // k >= 1
+  auto HHk = [&](int k) { return B.HH + (long long)k * R * wq; };                     // k < K
+  auto Gk = [&](int k) { return B.G + (long long)k * R * wq; };
+  auto HHBk = [&](int k) { return B.HHB + (long long)k * R * wq; };
+  auto ALBk = [&](int k) { return B.ALB + (long long)(k - 1) * R * wq; };
+  auto ABk = [&](int k) { return B.ABAR + (long long)k * R * wq; };
+  auto Ak = [&](int k) { return B.Ak + (long long)(k - 1) * w * wq; };  // k >= 1
+  auto Exk = [&](int k) { return B.Ex + (long long)(k - 1) * w * dp; };
+  auto etk = [&](int k) { return B.et + (long long)(k - 1) * w; };
+  const float* bias0 = params + L.off_b0;
+  auto biask = [&](int k) { return params + L.off_blk0 + (long long)(k - 1) * L.blk + L.blk - w; };
+  const float* wo = params + L.off_wo;
+  const float* bo = params + L.off_bo;
+
+  // ---- pack the weights the GEMMs read
+  {
+    PackArgs P{params, d, dp, w, (int)wq, K, nais ? 1 : 0, B.W0x, B.w0t, nais ? B.Rk : B.Ak, B.Ex, B.et};
+    hipLaunchKernelGGL(k_upack, dim3(512), dim3(256), 0, s, P);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (nais) {  // A_k = -R_k^T R_k - eps I
+    for (int k = 1; k <= K; ++k) {
+      const float* Rk = B.Rk + (long long)(k - 1) * w * wq;
+      UGemm G{Rk, wq, w, Rk, wq, w, w, 0, 0, 0, 0};
+      UEpi E = epi0(g, wq);
+      E.rows = w; E.cols = w; E.out0 = const_cast<float*>(Ak(k));
+      if ((e = gemm<true, true, U_NAISA>(G, E, w, w, 1, s)) != hipSuccess) return e;
+    }
+  }
+  // ---- forward
+  {
+    UGemm G{B.X, dp, (int)R, B.W0x, dp, w, d, 0, 0, 0, 0};
+    UEpi E = epi0(g, wq);
+    E.rows = (int)R; E.cols = w; E.bias = bias0; E.wt = B.w0t; E.out0 = Hk(0);
+    if ((e = gemm<false, false, U_LIFT>(G, E, (int)R, w, 1, s)) != hipSuccess) return e;
+  }
+  for (int k = 1; k <= K; ++k) {
+    if (nais) {  // P = [x; t] E_k^T
+      UGemm G{B.X, dp, (int)R, Exk(k), dp, w, d, 0, 0, 0, 0};
+      UEpi E = epi0(g, wq);
+      E.rows = (int)R; E.cols = w; E.wt = etk(k); E.out0 = B.P;
+      if ((e = gemm<false, false, U_STORE>(G, E, (int)R, w, 1, s)) != hipSuccess) return e;
+    }
+    UGemm G{Hk(k - 1), wq, (int)R, Ak(k), wq, w, w, 0, 0, 0, 0};
+    UEpi E = epi0(g, wq);
+    E.rows = (int)R; E.cols = w; E.bias = biask(k); E.in0 = Hk(k - 1); E.in1 = nais ? B.P : nullptr;
+    E.out0 = Hk(k); E.out1 = fc ? nullptr : const_cast<float*>(ALk(k)); E.out2 = k == K ? Gk(K) : nullptr;
+    E.wo = wo;
+    if ((e = gemm<false, false, U_BLOCK>(G, E, (int)R, w, 1, s)) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_urowdot, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, s, R, w, wq, Hk(K), wo, bo, B.U, y0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // ---- Z = grad_x u
+  for (int k = K; k >= 1; --k) {
+    UGemm G{Gk(k), wq, (int)R, Ak(k), wq, w, w, 0, 0, 0, 0};
+    UEpi E = epi0(g, wq);
+    E.rows = (int)R; E.cols = w; E.wo = wo;
+    E.in0 = k == K ? nullptr : HHk(k);
+    E.in1 = k - 1 >= 1 ? ALk(k - 1) : Hk(0);
+    E.out0 = HHk(k - 1); E.out1 = Gk(k - 1);
+    if ((e = gemm<false, true, U_ZBACK>(G, E, (int)R, w, 1, s)) != hipSuccess) return e;
+  }
+  {
+    UGemm G{Gk(0), wq, (int)R, B.W0x, dp, d, w, 0, 0, 0, 0};
+    UEpi E = epi0(g, dp);
+    E.rows = (int)R; E.cols = d; E.out0 = B.Z;
+    if ((e = gemm<false, true, U_STORE>(G, E, (int)R, d, 1, s)) != hipSuccess) return e;
+  }
+  if (nais) {
+    for (int k = 1; k <= K; ++k) {  // Z += G_k E_kx
+      UGemm G{Gk(k), wq, (int)R, Exk(k), dp, d, w, 0, 0, 0, 0};
+      UEpi E = epi0(g, dp);
+      E.rows = (int)R; E.cols = d; E.out0 = B.Z; E.acc = 1;
+      if ((e = gemm<false, true, U_STORE>(G, E, (int)R, d, 1, s)) != hipSuccess) return e;
+    }
+  }
+  // ---- residuals, seeds, loss partials
+  {
+    ResArgs A{d, dp, g.N, g.M, g.dt, g.kappa, g.sde, g.drv, g.g, g.drv_p0, g.drv_p1, g.g_p0, g.g_p1,
+              B.X, B.S, B.U, B.Z, B.UB, B.ZB, B.CB, B.lpart, nf};
+    hipLaunchKernelGGL(k_ures, dim3((unsigned)((R + 4 * RES_RPW - 1) / (4 * RES_RPW))), dim3(256), 0, s, A);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (want_grad) {
+      hipLaunchKernelGGL(k_useeds, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, A);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  const int lblocks = (int)((R + 4 * RES_RPW - 1) / (4 * RES_RPW));
+  if (!want_grad) {
+    hipLaunchKernelGGL(k_ufinal, dim3(1), dim3(64), 0, s, g.M, B.lpart, lblocks, loss, nf, host_flag);
+    return hipGetLastError();
+  }
+  // ---- second-order sweep (forward order)
+  {
+    UGemm G{B.ZB, dp, (int)R, B.W0x, dp, w, d, 0, 0, 0, 0};
+    UEpi E = epi0(g, wq);
+    E.rows = (int)R; E.cols = w; E.in0 = Hk(0); E.in1 = HHk(0); E.out0 = HHBk(0); E.out1 = B.HB0;
+    if ((e = gemm<false, false, U_S0>(G, E, (int)R, w, 1, s)) != hipSuccess) return e;
+  }
+  for (int k = 1; k <= K; ++k) {
+    if (nais) {  // Q = ZB E_kx^T
+      UGemm G{B.ZB, dp, (int)R, Exk(k), dp, w, d, 0, 0, 0, 0};
+      UEpi E = epi0(g, wq);
+      E.rows = (int)R; E.cols = w; E.out0 = B.P;
+      if ((e = gemm<false, false, U_STORE>(G, E, (int)R, w, 1, s)) != hipSuccess) return e;
+    }
+    UGemm G{HHBk(k - 1), wq, (int)R, Ak(k), wq, w, w, 0, 0, 0, 0};
+    UEpi E = epi0(g, wq);
+    E.rows = (int)R; E.cols = w; E.wo = wo; E.ub = B.UB;
+    E.in0 = HHBk(k - 1); E.in1 = ALk(k); E.in2 = k == K ? nullptr : HHk(k); E.in3 = nais ? B.P : nullptr;
+    E.out0 = HHBk(k); E.out1 = ALBk(k); E.out2 = k == K ? ABk(K) : nullptr;
+    if ((e = gemm<false, false, U_SBLK>(G, E, (int)R, w, 1, s)) != hipSuccess) return e;
+  }
+  // ---- reverse sweep of the forward pass
+  for (int k = K; k >= 1; --k) {
+    UGemm G{ABk(k), wq, (int)R, Ak(k), wq, w, w, 0, 0, 0, 0};
+    UEpi E = epi0(g, wq);
+    E.rows = (int)R; E.cols = w; E.wo = wo; E.ub = B.UB;
+    E.in0 = k == K ? nullptr : B.HBAR;
+    E.in1 = k - 1 >= 1 ? ALk(k - 1) : Hk(0);
+    E.in2 = k - 1 >= 1 ? ALBk(k - 1) : B.HB0;
+    E.out0 = B.HBAR; E.out1 = ABk(k - 1);
+    if ((e = gemm<false, true, U_RBLK>(G, E, (int)R, w, 1, s)) != hipSuccess) return e;
+  }
+  // ---- weight gradients: every element receives L.slots partial sums (a
+  // two-term block half of them from each term), summed in slot order
+  const int half = L.slots / 2;
+  const long long pstride = L.pstride;
+  auto wgrad = [&](const float* Aop, long long lda, int arows, const float* Bop, long long ldb, int brows,
+                   long long pbase, int pld, int slot0, int nsl) -> hipError_t {
+    UGemm G{Aop, lda, arows, Bop, ldb, brows, (int)R, 0, 0, 0, 0};
+    G.kchunk = ((R + nsl - 1) / nsl + BK - 1) / BK * BK;
+    G.ts = nsl;  // splits past the rows reduce nothing and store zeros: every slot is written
+    G.ti = (arows + 63) / 64;
+    G.tj = (brows + 63) / 64;
+    UEpi E = epi0(g, 0);
+    E.rows = arows; E.cols = brows; E.part = B.part; E.pbase = pbase; E.pld = pld; E.pstride = pstride;
+    E.slot0 = slot0;
+    hipLaunchKernelGGL((k_ugemm<true, true, U_PART, 2, 2>), dim3(G.ti * G.tj * G.ts), dim3(256), 0, s, G, E);
+    return hipGetLastError();
+  };
+  // W_0 x columns: G_0^T ZB + ABAR_0^T X
+  if ((e = wgrad(Gk(0), wq, w, B.ZB, dp, d, L.off_W0, d + 1, 0, half)) != hipSuccess) return e;
+  if ((e = wgrad(ABk(0), wq, w, B.X, dp, d, L.off_W0, d + 1, half, half)) != hipSuccess) return e;
+  for (int k = 1; k <= K; ++k) {
+    const long long base = L.off_blk0 + (long long)(k - 1) * L.blk;
+    // dA_k = G_k^T HHB_{k-1} + ABAR_k^T H_{k-1}; NAIS: into the scratch part of
+    // the partial rows (R_k's gradient is formed from it below)
+    const long long abase = nais ? L.off_abar + (long long)(k - 1) * w * w : base;
+    if ((e = wgrad(Gk(k), wq, w, HHBk(k - 1), wq, w, abase, w, 0, half)) != hipSuccess) return e;
+    if ((e = wgrad(ABk(k), wq, w, Hk(k - 1), wq, w, abase, w, half, half)) != hipSuccess) return e;
+    if (nais) {  // dE_k x columns: G_k^T ZB + ABAR_k^T X
+      const long long ebase = base + (long long)w * w;
+      if ((e = wgrad(Gk(k), wq, w, B.ZB, dp, d, ebase, d + 1, 0, half)) != hipSuccess) return e;
+      if ((e = wgrad(ABk(k), wq, w, B.X, dp, d, ebase, d + 1, half, half)) != hipSuccess) return e;
+    }
+  }
+  // vector gradients by column sums over row ranges
+  {
+    ColArgs C{};
+    C.R = R; C.ld = wq; C.mp = g.M; C.dt = g.dt; C.ub = B.UB; C.part = B.part; C.pstride = pstride;
+    C.slots = L.slots; C.chunk = (R + L.slots - 1) / L.slots;
+    int nj = 0;
+    C.job[nj++] = ColJob{0, w, ABk(0), nullptr, L.off_b0, 1};
+    C.job[nj++] = ColJob{1, w, ABk(0), nullptr, L.off_W0 + d, d + 1};
+    for (int k = 1; k <= K; ++k) {
+      const long long base = L.off_blk0 + (long long)(k - 1) * L.blk;
+      C.job[nj++] = ColJob{0, w, ABk(k), nullptr, base + L.blk - w, 1};
+      if (nais) C.job[nj++] = ColJob{1, w, ABk(k), nullptr, base + (long long)w * w + d, d + 1};
+    }
+    C.job[nj++] = ColJob{2, w, HHBk(K), Hk(K), L.off_wo, 1};
+    C.job[nj++] = ColJob{3, 1, nullptr, nullptr, L.off_bo, 1};
+    C.njobs = nj;
+    hipLaunchKernelGGL(k_ucolsum, dim3((w + 255) / 256, L.slots, nj), dim3(256), 0, s, C);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (nais) {
+    // dA_k summed over the slots, then dR_k = -R_k (dA_k + dA_k^T) into slot 0
+    // of R_k's partial rows and zeros into the others
+    const long long na = (long long)K * w * w;
+    hipLaunchKernelGGL(k_ureduce, dim3(512), dim3(256), 0, s, na, pstride, B.part + L.off_abar, L.slots, B.Abar, nf);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int k = 1; k <= K; ++k) {
+      const long long base = L.off_blk0 + (long long)(k - 1) * L.blk;
+      hipLaunchKernelGGL(k_unais_rgrad, dim3((unsigned)(((long long)w * w + 255) / 256)), dim3(256), 0, s, w,
+                         params + base, B.Abar + (long long)(k - 1) * w * w, B.part + base, pstride, L.slots);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(k_ureduce, dim3(1024), dim3(256), 0, s, (long long)g.nparams, pstride, B.part, L.slots, grad, nf);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ufinal, dim3(1), dim3(64), 0, s, g.M, B.lpart, lblocks, loss, nf, host_flag);
+  return hipGetLastError();
+}
+
+hipError_t unet_nais_project(const Geo& g, const UnetBufs& B, float* params, float c, hipStream_t s) {
+  const UnetLayout L = unet_layout(g);
+  const int K = L.K, w = g.w;
+  const long long wq = L.wq;
+  hipError_t e;
+  PackArgs P{params, g.d, g.dp, w, (int)wq, K, 1, B.W0x, B.w0t, B.Rk, B.Ex, B.et};
+  hipLaunchKernelGGL(k_upack, dim3(512), dim3(256), 0, s, P);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int k = 1; k <= K; ++k) {  // R_k^T R_k into the A_k buffer
+    const float* Rk = B.Rk + (long long)(k - 1) * w * wq;
+    UGemm G{Rk, wq, w, Rk, wq, w, w, 0, 0, 0, 0};
+    UEpi E = epi0(g, wq);
+    E.rows = w; E.cols = w; E.out0 = B.Ak + (long long)(k - 1) * w * wq;
+    if ((e = gemm<true, true, U_STORE>(G, E, w, w, 1, s)) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_unais_project, dim3(K), dim3(256), 0, s, w, (int)wq, B.Ak, params, L.off_blk0, L.blk, c);
+  return hipGetLastError();
+}
+
+}  // namespace fbsde

@@ -95,3 +95,37 @@ def allen_cahn_batch(n: int = 32, seed: int = 2019):
     ds = rng.integers(20, 201, size=n)
     Ns = rng.choice([10, 20, 40], size=n)
     return [(int(d), int(N)) for d, N in zip(ds, Ns)]
+
+
+def unet_blocks(d: int, net: dict):
+    """(name, rows, cols) of the blocks of the u-network's flat layout
+    (arch "fc" | "res" | "nais", depth K blocks after the input layer)."""
+    w, K, arch = int(net["width"]), int(net.get("depth", 3)), net.get("arch", "fc")
+    out = [("W0", w, d + 1), ("b0", w, 1)]
+    for k in range(1, K + 1):
+        out.append((f"R{k}" if arch == "nais" else f"A{k}", w, w))
+        if arch == "nais":
+            out.append((f"E{k}", w, d + 1))
+        out.append((f"b{k}", w, 1))
+    out += [("wo", 1, w), ("bo", 1, 1)]
+    return out
+
+
+def init_unet_params(problem: dict, net: dict, seed: int = 0, out_scale: float = 1.0) -> np.ndarray:
+    """Glorot-uniform weight blocks, zero biases (the u-network of the
+    paper's own formulation); NAIS R_k at half the Glorot range."""
+    rng = np.random.default_rng(seed)
+    d = int(problem["d"])
+    parts = []
+    for name, r, c in unet_blocks(d, net):
+        if name.startswith("b"):
+            parts.append(np.zeros(r * c))
+            continue
+        fan = (r + c) if name != "wo" else (c + 1)
+        a = math.sqrt(6.0 / fan)
+        if name.startswith("R"):
+            a *= 0.5
+        if name == "wo":
+            a *= out_scale
+        parts.append(rng.uniform(-a, a, size=r * c))
+    return np.concatenate(parts)

@@ -177,6 +177,57 @@ class Plan:
         return self.get_config()
 
 
+class UPlan(Plan):
+    """The paper's own formulation (one network u(t, x) for every step,
+    Z = grad u, per-step residual loss): net = dict(kind="u_fc" | "u_res" |
+    "u_nais", width, depth = blocks after the input layer), fp32.  kappa is
+    the weight of the terminal-gradient penalty, eps the NAIS shift."""
+
+    def __init__(self, problem: dict, net: dict, N: int, M: int, kappa: float = 0.0, eps: float = 0.01,
+                 device: str | torch.device = "cuda"):
+        net = dict(net, prec="fp32")
+        super().__init__(problem, net, N, M, device=device)
+        B.check(self.lib.fbsde_plan_set_unet_loss(self._h, float(kappa), float(eps)))
+        self.kappa, self.eps = float(kappa), float(eps)
+
+    def forward_backward(self, params: torch.Tensor, seed: int, it: int, out: tuple | None = None,
+                         grad: bool = True):
+        """Returns (loss fp64 scalar, grad fp32 [n_params] or None, u(0, x0) fp64 scalar)."""
+        self._check_params(params)
+        if out is None:
+            loss = torch.empty((), dtype=torch.float64, device=self.device)
+            g = torch.empty(self.n_params, dtype=torch.float32, device=self.device) if grad else None
+            y0 = torch.empty((), dtype=torch.float64, device=self.device)
+        else:
+            loss, g, y0 = out
+        B.check(self.lib.fbsde_unet_forward_backward(self._h, _ptr(params), _ptr(g), _ptr(loss), _ptr(y0),
+                                                     seed, it, _ptr(self.ws), _stream()))
+        return loss, g, y0
+
+    def adam_step(self, params, grad, m, v, t: int, lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999,
+                  eps: float = 1e-8):
+        B.check(self.lib.fbsde_adam_step(self._h, _ptr(params), None, _ptr(grad), None, _ptr(m), _ptr(v), None,
+                                         None, int(t), float(lr), float(lr), float(b1), float(b2), float(eps),
+                                         _stream()))
+
+    def nais_project(self, params: torch.Tensor, c: float):
+        self._check_params(params)
+        B.check(self.lib.fbsde_unet_nais_project(self._h, _ptr(params), float(c), _ptr(self.ws), _stream()))
+
+    def states(self):
+        """(u [(N+1) M], Z [(N+1) M][d]) of the last call, row n M + m."""
+        R = (self.N + 1) * self.M
+        u = torch.empty(R, dtype=torch.float32, device=self.device)
+        z = torch.empty((R, int(self.problem["d"])), dtype=torch.float32, device=self.device)
+        B.check(self.lib.fbsde_unet_states(self._h, _ptr(self.ws), _ptr(u), _ptr(z), _stream()))
+        return u, z
+
+    def set_x0(self, x0):
+        import ctypes as C_
+        arr = (C_.c_double * int(self.problem["d"]))(*[float(v) for v in x0])
+        B.check(self.lib.fbsde_plan_set_x0(self._h, arr))
+
+
 class TrainState:
     """Parameters, y0 and Adam state of one instance, as device tensors."""
 

@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import inputs as I
-from .plan import Plan
+from .plan import Plan, UPlan
 
 
 @dataclasses.dataclass
@@ -167,3 +167,90 @@ def time_to_accuracy(h: History, target: float, rel: float = 0.01, hold: int = 1
     never)."""
     i = first_accurate_iteration(h, target, rel, hold, finest_N)
     return None if i is None else float(h.t[i])
+
+
+def train_unet(problem: dict, net: dict, M: int, schedule: list, *, lr: float = 1e-3, seed: int = 1,
+               init_seed: int = 0, params_init: np.ndarray | None = None, kappa: float = 0.0,
+               eps: float = 0.01, nais_c: float | None = None, device: str = "cuda", plans: dict | None = None,
+               warmup: int = 0, switch_rel: float | None = None, switch_window: int = 100) -> History:
+    """Adam on the paper's own formulation (one u-network, residual loss):
+    net = dict(kind="u_fc" | "u_res" | "u_nais", width, depth).  Y0 = u(0, x0)
+    is logged every iteration.  The network is shared by every step, so the
+    multilevel warm start carries it over unchanged; Adam moments restart at
+    every level.  NAIS: after every Adam step each R_k is projected onto
+    |R_k^T R_k|_F <= nais_c (default 1 - 2 eps).  Level switch as in train."""
+    plans = {} if plans is None else plans
+    arch = {"u_fc": "fc", "u_res": "res", "u_nais": "nais"}[net["kind"]]
+    if arch == "nais" and nais_c is None:
+        nais_c = 1.0 - 2.0 * eps
+
+    def plan_for(N):
+        if N not in plans:
+            plans[N] = UPlan(problem, net, N, M, kappa=kappa, eps=eps, device=device)
+        return plans[N]
+
+    P0 = plan_for(schedule[0].N)
+    if params_init is None:
+        params_init = I.init_unet_params(problem, dict(net, arch=arch), seed=init_seed)
+    params = torch.from_numpy(np.asarray(params_init, dtype=np.float32)).to(P0.device)
+
+    def run(P, st, k0, iters, ylog, llog, it0):
+        for k in range(k0, k0 + iters):
+            P.forward_backward(params, seed, it0 + k, out=(st.loss, st.grad, st.y))
+            P.adam_step(params, st.grad, st.m, st.v, k + 1, lr=lr)
+            if arch == "nais":
+                P.nais_project(params, nais_c)
+            if ylog is not None:
+                llog[k].copy_(st.loss, non_blocking=True)
+                ylog[k].copy_(st.y, non_blocking=True)
+
+    class _St:
+        def __init__(self, p):
+            self.m, self.v = torch.zeros_like(p), torch.zeros_like(p)
+            self.grad = torch.empty_like(p)
+            self.loss = torch.empty((), dtype=torch.float64, device=p.device)
+            self.y = torch.empty((), dtype=torch.float64, device=p.device)
+
+    if warmup > 0:
+        keep = params.clone()
+        run(P0, _St(params), 0, warmup, None, None, 0)
+        params.copy_(keep)
+    torch.cuda.synchronize()
+    Ns, ys, ls, ts, level_seconds, level_iters = [], [], [], [], [], []
+    t_start = time.perf_counter()
+    t_prev = 0.0
+    it0 = 0
+    last_y = float("nan")
+    for li, lv in enumerate(schedule):
+        P = plan_for(lv.N)
+        ylog = torch.empty(lv.iters, dtype=torch.float64, device=P.device)
+        llog = torch.empty(lv.iters, dtype=torch.float64, device=P.device)
+        st = _St(params)
+        if switch_rel is None or li == len(schedule) - 1:
+            run(P, st, 0, lv.iters, ylog, llog, it0)
+            done = lv.iters
+        else:
+            done = 0
+            while done < lv.iters:
+                k = min(switch_window, lv.iters - done)
+                run(P, st, done, k, ylog, llog, it0)
+                done += k
+                if done >= 2 * switch_window:
+                    a_, b_ = ylog[done - 1 - switch_window].item(), ylog[done - 1].item()
+                    if abs(b_ - a_) <= switch_rel * abs(b_):
+                        break
+        torch.cuda.synchronize()
+        t_now = time.perf_counter() - t_start
+        dt_level = t_now - t_prev
+        level_seconds.append(dt_level)
+        level_iters.append(done)
+        Ns.append(np.full(done, lv.N))
+        ys.append(ylog[:done].cpu().numpy())
+        ls.append(llog[:done].cpu().numpy())
+        ts.append(t_prev + dt_level * (np.arange(1, done + 1) / done))
+        t_prev = t_now
+        it0 += done
+        last_y = float(ys[-1][-1])
+    return History(N=np.concatenate(Ns), y0=np.concatenate(ys), loss=np.concatenate(ls),
+                   t=np.concatenate(ts), level_seconds=level_seconds, params=params, y0_final=last_y,
+                   level_iters=level_iters)

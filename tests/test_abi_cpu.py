@@ -70,6 +70,10 @@ def test_invalid_problem(lib, change, expect):
     (dict(width=4, depth=2), 4, 2 ** 31, B.ERR_INVALID),
     (dict(width=300, depth=2), 4, 8, B.ERR_UNSUPPORTED),
     (dict(width=4, depth=9), 4, 8, B.ERR_UNSUPPORTED),
+    (dict(kind="u_fc", width=8, depth=2, prec="bf16"), 4, 8, B.ERR_UNSUPPORTED),   # u-network: fp32 only
+    (dict(kind="u_res", width=8, depth=17), 4, 8, B.ERR_UNSUPPORTED),              # at most 16 blocks
+    (dict(kind="u_nais", width=8, depth=2), 2 ** 20, 2 ** 10, B.ERR_UNSUPPORTED),  # (N + 1) M >= 2^29 rows
+    (dict(kind="u_fc", width=8, depth=0), 4, 8, B.ERR_INVALID),
 ])
 def test_invalid_net_and_sizes(lib, net, N, M, expect):
     st, h = _create(lib, BASE, net, N, M)
@@ -85,3 +89,8 @@ def test_null_plan_calls(lib):
     assert lib.fbsde_prolong(None, None, None, None, None) == B.ERR_INVALID
     assert lib.fbsde_plan_set_checkpointing(None, 1, 0) == B.ERR_INVALID
     assert lib.fbsde_plan_status(None) == B.ERR_INVALID
+    assert lib.fbsde_unet_forward_backward(None, None, None, None, None, 0, 0, None, None) == B.ERR_INVALID
+    assert lib.fbsde_unet_nais_project(None, None, 1.0, None, None) == B.ERR_INVALID
+    assert lib.fbsde_unet_states(None, None, None, None, None) == B.ERR_INVALID
+    assert lib.fbsde_plan_set_unet_loss(None, 0.0, 0.01) == B.ERR_INVALID
+    assert lib.fbsde_plan_set_x0(None, None) == B.ERR_INVALID

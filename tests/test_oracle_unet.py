@@ -356,3 +356,25 @@ def test_nais_block_matrix_is_negative_definite():
     A = -R.T @ R - 0.05 * np.eye(w)
     np.testing.assert_allclose(Ah, A @ h0, rtol=1e-10, atol=1e-12)
     assert h0 @ Ah <= -0.05 * (h0 @ h0) + 1e-12
+
+
+def test_results_do_not_depend_on_the_thread_count():
+    """Path sums are formed per 64-path chunk and added in chunk order, so
+    one thread and all threads give bitwise the same loss and gradient."""
+    import os
+    prob = I.hjb(6)
+    net = dict(arch="res", width=8, depth=2)
+    p = _params(prob, net, seed=4, scale=0.3)
+    mlp = dict(kind="mlp", width=10, depth=2)
+    pm = I.init_params(prob, mlp, 4, seed=2)
+    try:
+        O.set_threads(1)
+        a = O.unet_loss_grad(prob, net, 4, 300, p, seed=1, kappa=0.5)
+        am = O.loss_grad(prob, mlp, 4, 300, pm, 0.5, seed=1)
+        O.set_threads(max(2, os.cpu_count() or 2))
+        b = O.unet_loss_grad(prob, net, 4, 300, p, seed=1, kappa=0.5)
+        bm = O.loss_grad(prob, mlp, 4, 300, pm, 0.5, seed=1)
+    finally:
+        O.set_threads(os.cpu_count() or 1)
+    assert a["loss"] == b["loss"] and np.array_equal(a["grad"], b["grad"])
+    assert am["loss"] == bm["loss"] and np.array_equal(am["grad"], bm["grad"]) and am["grad_y0"] == bm["grad_y0"]
