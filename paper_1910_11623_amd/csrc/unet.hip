@@ -660,7 +660,9 @@ UnetLayout unet_layout(const Geo& g) {
   L.off_blk0 = L.off_b0 + g.w;
   L.off_wo = L.off_blk0 + (long long)K * L.blk;
   L.off_bo = L.off_wo + g.w;
-  L.slots = 16;
+  // partial sums per parameter: each two-term weight gradient splits its rows
+  // over slots / 2 workgroup rows, enough to fill the chip at 16 output tiles
+  L.slots = L.R < 32768 ? 32 : 64;
   const long long np4 = (g.nparams + 3) / 4 * 4;
   L.off_abar = np4;
   L.pstride = np4 + (g.uarch == 2 ? (long long)K * g.w * g.w : 0);
