@@ -336,6 +336,25 @@ fbsde_status fbsde_unet_states(fbsde_plan *plan, const void *ws_dev, float *u_de
  * from a perturbed initial condition (Sec. 4, generalisation). */
 fbsde_status fbsde_plan_set_x0(fbsde_plan *plan, const double *x0_host);
 
+/* ---- allocation-free variant ------------------------------------------------
+ * For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): fbsde_forward_backward with the library's own static device
+ * scratch array of FBSDE_NOALLOC_SCRATCH_BYTES as workspace (each GPU the
+ * library runs on holds one, from the moment the library's code is loaded
+ * on it until the process ends).  Same arguments, results and errors as
+ * fbsde_forward_backward (bitwise the same results); the caller still
+ * passes params, y0, grad, grad_y0 and loss.  Allocates nothing.  Every call
+ * on one GPU uses the same array, so calls that overlap in time on one GPU
+ * (other streams, threads or plans) race; the array keeps the previous
+ * call's contents, which no call reads before writing.  Errors in addition:
+ * UNSUPPORTED if the plan's workspace exceeds the scratch (use
+ * fbsde_forward_backward), INVALID if the current device is not the plan's. */
+#define FBSDE_NOALLOC_SCRATCH_BYTES (64ull << 20)
+fbsde_status fbsde_forward_backward_noalloc(fbsde_plan *plan, const float *params_dev,
+                                            const double *y0_dev, float *grad_dev, double *grad_y0_dev,
+                                            double *loss_dev, uint64_t seed, uint64_t iter, void *stream);
+
 const char *fbsde_status_str(fbsde_status s);
 const char *fbsde_last_error(void);
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "fbsde_profile_enable", "fbsde_profile_read", "fbsde_plan_config", "fbsde_plan_get_config",
     "fbsde_plan_autotune", "fbsde_plan_set_checkpointing", "fbsde_plan_status", "fbsde_batch_create", "fbsde_batch_step", "fbsde_batch_destroy",
     "fbsde_plan_set_unet_loss", "fbsde_unet_forward_backward", "fbsde_unet_nais_project", "fbsde_unet_states",
-    "fbsde_plan_set_x0",
+    "fbsde_plan_set_x0", "fbsde_forward_backward_noalloc",
     "fbsde_status_str", "fbsde_last_error",
 ]
 PROF_NAMES = ["pack", "sde", "forward", "scan", "backward", "wgrad", "reduce", "adam"]
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
     L.fbsde_unet_nais_project.argtypes = [vp, vp, C.c_double, vp, vp]
     L.fbsde_unet_states.argtypes = [vp, vp, vp, vp, vp]
     L.fbsde_plan_set_x0.argtypes = [vp, C.POINTER(C.c_double)]
+    L.fbsde_forward_backward_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, u64, u64, vp]
     L.fbsde_status_str.argtypes = [C.c_int]
     L.fbsde_status_str.restype = C.c_char_p
     L.fbsde_last_error.argtypes = []

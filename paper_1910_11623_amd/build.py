@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfbsde.so")
-SOURCES = ["kernels.hip", "resnet.hip", "unet.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "resnet.hip", "unet.hip", "noalloc.hip", "api.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
          # keep hipcc from emitting packed-fp32 VALU ops

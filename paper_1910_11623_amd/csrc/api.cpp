@@ -424,6 +424,16 @@ fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double
 
 }  // namespace
 
+namespace fbsde {
+fbsde_status api_fail(fbsde_status s, const char* msg) { return fail(s, msg); }
+fbsde_status api_active_workspace(const fbsde_plan* plan, size_t* bytes, int* device) {
+  if (!plan || !bytes || !device) return fail(FBSDE_ERR_INVALID, "NULL argument");
+  *bytes = plan->ws.total;
+  *device = plan->device;
+  return FBSDE_OK;
+}
+}  // namespace fbsde
+
 extern "C" {
 
 const char* fbsde_status_str(fbsde_status s) {

@@ -4,7 +4,15 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/fbsde.h"
+
 namespace fbsde {
+
+// ABI helpers shared by the translation units that implement entry points:
+// set the thread-local error message and return the status; the bytes of
+// workspace the plan's current configuration uses and the plan's device.
+fbsde_status api_fail(fbsde_status s, const char* msg);
+fbsde_status api_active_workspace(const fbsde_plan* plan, size_t* bytes, int* device);
 
 // Plan geometry, passed to every kernel by value.
 struct Geo {
