@@ -94,54 +94,104 @@ struct UEpi {
   float* part; long long pbase, pstride; int pld, slot0;
 };
 
+__device__ __forceinline__ f32x4 ldv(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
+__device__ __forceinline__ void stv(float* p, f32x4 v) { *reinterpret_cast<f32x4*>(p) = v; }
+
+// Element q of four consecutive columns j..j+3 of row i (j a multiple of 4).
+// Full runs (j + 3 < cols) move every operand as one 16-byte access: row
+// strides and buffer offsets are multiples of 4 floats.  The ragged last run
+// goes element by element.
+template <int EPI>
+__device__ __forceinline__ void epi_elem(const UEpi& E, int i, int jj, long long o, float a, float& r0, float& r1,
+                                         float& r2, float i0, float i1, float i2, float i3) {
+  if constexpr (EPI == U_NAISA) {
+    r0 = -a - (i == jj ? E.eps : 0.f);
+  } else if constexpr (EPI == U_STORE) {
+    float x = a;
+    if (E.bias) x += E.bias[jj];
+    if (E.wt) x += (float)(i / E.mp) * E.dt * E.wt[jj];
+    r0 = E.acc ? i0 + x : x;
+  } else if constexpr (EPI == U_LIFT) {
+    r0 = fast_tanh(a + E.bias[jj] + (float)(i / E.mp) * E.dt * E.wt[jj]);
+  } else if constexpr (EPI == U_BLOCK) {
+    const float al = fast_tanh(a + E.bias[jj] + i1);
+    r1 = al;
+    r0 = E.c * i0 + al;
+    r2 = E.wo[jj] * (1.f - al * al);
+  } else if constexpr (EPI == U_ZBACK) {
+    const float hh = E.c * (E.in0 ? i0 : E.wo[jj]) + a;
+    r0 = hh;
+    r1 = hh * (1.f - i1 * i1);
+  } else if constexpr (EPI == U_S0) {
+    r0 = a * (1.f - i0 * i0);
+    r1 = a * i1 * (-2.f * i0);
+  } else if constexpr (EPI == U_SBLK) {
+    const float gb = a + i3;
+    r0 = E.c * i0 + gb * (1.f - i1 * i1);
+    const float alb = gb * (E.in2 ? i2 : E.wo[jj]) * (-2.f * i1);
+    r1 = alb;
+    r2 = (alb + E.ub[i] * E.wo[jj]) * (1.f - i1 * i1);
+  } else if constexpr (EPI == U_RBLK) {
+    const float hb = E.c * (E.in0 ? i0 : E.ub[i] * E.wo[jj]) + a;
+    r0 = hb;
+    r1 = (i2 + hb) * (1.f - i1 * i1);
+  }
+  (void)o;
+}
+
 template <int EPI>
 __device__ __forceinline__ void epi4(const UEpi& E, int i, int j, f32x4 v, int sp) {
-  if (i >= E.rows) return;
+  if (i >= E.rows || j >= E.cols) return;
+  if constexpr (EPI == U_PART) {
+    const long long p = (long long)(E.slot0 + sp) * E.pstride + E.pbase + (long long)i * E.pld + j;
+    if (j + 4 <= E.cols && (p & 3) == 0) {
+      stv(E.part + p, v);
+    } else {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int jj = j + q;
-    if (jj >= E.cols) return;
-    const float a = v[q];
-    const long long o = (long long)i * E.ld + jj;
-    if constexpr (EPI == U_PART) {
-      E.part[(long long)(E.slot0 + sp) * E.pstride + E.pbase + (long long)i * E.pld + jj] = a;
-    } else if constexpr (EPI == U_NAISA) {
-      E.out0[o] = -a - (i == jj ? E.eps : 0.f);
-    } else if constexpr (EPI == U_STORE) {
-      float x = a;
-      if (E.bias) x += E.bias[jj];
-      if (E.wt) x += (float)(i / E.mp) * E.dt * E.wt[jj];
-      E.out0[o] = E.acc ? E.out0[o] + x : x;
-    } else if constexpr (EPI == U_LIFT) {
-      E.out0[o] = fast_tanh(a + E.bias[jj] + (float)(i / E.mp) * E.dt * E.wt[jj]);
-    } else if constexpr (EPI == U_BLOCK) {
-      const float al = fast_tanh(a + E.bias[jj] + (E.in1 ? E.in1[o] : 0.f));
-      if (E.out1) E.out1[o] = al;
-      E.out0[o] = (E.c != 0.f ? E.c * E.in0[o] : 0.f) + al;
-      if (E.out2) E.out2[o] = E.wo[jj] * (1.f - al * al);
-    } else if constexpr (EPI == U_ZBACK) {
-      const float prev = E.in0 ? E.in0[o] : E.wo[jj];
-      const float hh = (E.c != 0.f ? E.c * prev : 0.f) + a;
-      E.out0[o] = hh;
-      const float dv = E.in1[o];
-      E.out1[o] = hh * (1.f - dv * dv);
-    } else if constexpr (EPI == U_S0) {
-      const float h0 = E.in0[o];
-      E.out0[o] = a * (1.f - h0 * h0);
-      E.out1[o] = a * E.in1[o] * (-2.f * h0);
-    } else if constexpr (EPI == U_SBLK) {
-      const float gb = a + (E.in3 ? E.in3[o] : 0.f);
-      const float al = E.in1[o];
-      E.out0[o] = (E.c != 0.f ? E.c * E.in0[o] : 0.f) + gb * (1.f - al * al);
-      const float alb = gb * (E.in2 ? E.in2[o] : E.wo[jj]) * (-2.f * al);
-      E.out1[o] = alb;
-      if (E.out2) E.out2[o] = (alb + E.ub[i] * E.wo[jj]) * (1.f - al * al);
-    } else if constexpr (EPI == U_RBLK) {
-      const float prev = E.in0 ? E.in0[o] : E.ub[i] * E.wo[jj];
-      const float hb = (E.c != 0.f ? E.c * prev : 0.f) + a;
-      E.out0[o] = hb;
-      const float dv = E.in1[o];
-      E.out1[o] = (E.in2[o] + hb) * (1.f - dv * dv);
+      for (int q = 0; q < 4; ++q)
+        if (j + q < E.cols) E.part[p + q] = v[q];
+    }
+    return;
+  } else {
+    const long long o = (long long)i * E.ld + j;
+    const f32x4 z4 = f32x4{0.f, 0.f, 0.f, 0.f};
+    // inputs this epilogue reads (in0 for U_STORE only when accumulating)
+    constexpr bool R0 = EPI == U_BLOCK || EPI == U_ZBACK || EPI == U_S0 || EPI == U_SBLK || EPI == U_RBLK ||
+                        EPI == U_STORE;
+    constexpr bool R1 = EPI == U_BLOCK || EPI == U_ZBACK || EPI == U_S0 || EPI == U_SBLK || EPI == U_RBLK;
+    constexpr bool R2 = EPI == U_SBLK || EPI == U_RBLK;
+    constexpr bool R3 = EPI == U_SBLK;
+    // the skip term c in0 is not read for fully connected blocks (c = 0)
+    const bool r0 = R0 && (EPI == U_STORE ? E.acc != 0 : E.in0 != nullptr) && (EPI == U_S0 || EPI == U_STORE || E.c != 0.f);
+    const bool r1 = R1 && E.in1;
+    const bool r2 = R2 && E.in2;
+    const bool r3 = R3 && E.in3;
+    const float* in0 = EPI == U_STORE ? E.out0 : E.in0;
+    if (j + 4 <= E.cols) {
+      const f32x4 a0 = r0 ? ldv(in0 + o) : z4, a1 = r1 ? ldv(E.in1 + o) : z4;
+      const f32x4 a2 = r2 ? ldv(E.in2 + o) : z4, a3 = r3 ? ldv(E.in3 + o) : z4;
+      f32x4 o0, o1, o2;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+        epi_elem<EPI>(E, i, j + q, o + q, v[q], x0, x1, x2, a0[q], a1[q], a2[q], a3[q]);
+        o0[q] = x0; o1[q] = x1; o2[q] = x2;
+      }
+      stv(E.out0 + o, o0);
+      if (E.out1) stv(E.out1 + o, o1);
+      if (E.out2) stv(E.out2 + o, o2);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (j + q >= E.cols) break;
+        const float a0 = r0 ? in0[o + q] : 0.f, a1 = r1 ? E.in1[o + q] : 0.f;
+        const float a2 = r2 ? E.in2[o + q] : 0.f, a3 = r3 ? E.in3[o + q] : 0.f;
+        float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+        epi_elem<EPI>(E, i, j + q, o + q, v[q], x0, x1, x2, a0, a1, a2, a3);
+        E.out0[o + q] = x0;
+        if (E.out1) E.out1[o + q] = x1;
+        if (E.out2) E.out2[o + q] = x2;
+      }
     }
   }
 }
@@ -473,23 +523,46 @@ struct ColArgs {
   int njobs;
 };
 
-// grid: (column blocks of 256, slots, jobs)
+// grid: (column blocks of 64, slots, jobs).  Thread (c, g) of a block adds
+// column c over rows r0 + g, r0 + g + 4, ... of the slot (eight loads in
+// flight), then the four row groups are added in order through LDS.
 __global__ __launch_bounds__(256) void k_ucolsum(ColArgs C) {
   const int jb = blockIdx.z;
-  if (jb >= C.njobs) return;
+  if (jb >= C.njobs) return;  // uniform
   const ColJob J = C.job[jb];
-  const int a = blockIdx.x * 256 + threadIdx.x;
-  if (a >= J.cols) return;
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int a = blockIdx.x * 64 + c;
   const long long r0 = (long long)blockIdx.y * C.chunk;
   const long long r1 = min(C.R, r0 + C.chunk);
+  __shared__ float sh[4][64];
   float s = 0.f;
-  for (long long r = r0; r < r1; ++r) {
-    if (J.mode == 0) s += J.P[r * C.ld + a];
-    else if (J.mode == 1) s += (float)(r / C.mp) * C.dt * J.P[r * C.ld + a];
-    else if (J.mode == 2) s += J.P[r * C.ld + a] + C.ub[r] * J.Q[r * C.ld + a];
-    else s += C.ub[r];
+  if (a < J.cols) {
+    long long r = r0 + g;
+    for (; r + 28 < r1; r += 32) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const long long rr = r + 4 * u;
+        if (J.mode == 0) v[u] = J.P[rr * C.ld + a];
+        else if (J.mode == 1) v[u] = (float)(rr / C.mp) * C.dt * J.P[rr * C.ld + a];
+        else if (J.mode == 2) v[u] = J.P[rr * C.ld + a] + C.ub[rr] * J.Q[rr * C.ld + a];
+        else v[u] = C.ub[rr];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; r < r1; r += 4) {
+      if (J.mode == 0) s += J.P[r * C.ld + a];
+      else if (J.mode == 1) s += (float)(r / C.mp) * C.dt * J.P[r * C.ld + a];
+      else if (J.mode == 2) s += J.P[r * C.ld + a] + C.ub[r] * J.Q[r * C.ld + a];
+      else s += C.ub[r];
+    }
   }
-  C.part[(long long)blockIdx.y * C.pstride + J.off + (long long)a * J.stride] = s;
+  sh[g][c] = s;
+  __syncthreads();
+  if (g == 0 && a < J.cols)
+    C.part[(long long)blockIdx.y * C.pstride + J.off + (long long)a * J.stride] =
+        ((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c];
 }
 
 // ---------------------------------------------------------------- packing
@@ -852,7 +925,7 @@ hipError_t unet_forward_backward(const Geo& g, const UnetBufs& B, const float* p
     C.job[nj++] = ColJob{2, w, HHBk(K), Hk(K), L.off_wo, 1};
     C.job[nj++] = ColJob{3, 1, nullptr, nullptr, L.off_bo, 1};
     C.njobs = nj;
-    hipLaunchKernelGGL(k_ucolsum, dim3((w + 255) / 256, L.slots, nj), dim3(256), 0, s, C);
+    hipLaunchKernelGGL(k_ucolsum, dim3((w + 63) / 64, L.slots, nj), dim3(256), 0, s, C);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (nais) {

@@ -254,3 +254,24 @@ def train_unet(problem: dict, net: dict, M: int, schedule: list, *, lr: float = 
     return History(N=np.concatenate(Ns), y0=np.concatenate(ys), loss=np.concatenate(ls),
                    t=np.concatenate(ts), level_seconds=level_seconds, params=params, y0_final=last_y,
                    level_iters=level_iters)
+
+
+def first_accurate_mean_iteration(h: History, target: float, rel: float = 0.01, window: int = 100,
+                                  hold: int = 500, finest_N: int | None = None) -> int | None:
+    """Index of the first iteration on the finest level at which the mean of
+    Y0 over the trailing `window` finest-level iterations is within `rel` of
+    `target` and stays so for the next `hold` iterations (None if never).
+    For noisy Y0 trajectories (the paper's formulation at M = 100 paths,
+    where Y0 = u(0, x0) moves with every Adam step)."""
+    finest_N = int(h.N.max()) if finest_N is None else finest_N
+    idx = np.nonzero(h.N == finest_N)[0]
+    if idx.size < window:
+        return None
+    y = h.y0[idx]
+    c = np.cumsum(np.concatenate([[0.0], y]))
+    mean = (c[window:] - c[:-window]) / window          # mean[k] = mean of y[k .. k + window)
+    ok = np.abs(mean / target - 1.0) <= rel
+    for k in range(len(ok) - hold):
+        if ok[k:k + hold + 1].all():
+            return int(idx[k + window - 1])
+    return None
