@@ -192,6 +192,60 @@ def measured_traffic(kernel: str, prec: str):
     return None if t is None else int(round(t["read_bytes"] + t["write_bytes"]))
 
 
+# Kernel-name prefix -> the roofline keys the bench uses
+_TRAFFIC_KEYS = {"k_pack": "pack", "k_sde": "sde", "k_forward": "forward", "k_scan": "scan",
+                 "k_backward": "backward", "k_wgrad": "wgrad", "k_reduce": "reduce", "k_finalize": "finalize",
+                 "k_adam": "adam"}
+
+
+def _counter_means(path: str, counter: str) -> dict:
+    """{kernel name: mean over its dispatches of `counter`} from a rocprofv3
+    --pmc CSV directory (values of one dispatch summed over dimensions)."""
+    import csv
+    import glob
+    per = {}
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    for fn in files:
+        for r in csv.DictReader(open(fn)):
+            if r.get("Counter_Name") != counter:
+                continue
+            key = (r["Kernel_Name"], r.get("Dispatch_Id", r.get("Correlation_Id")))
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    sums = {}
+    for (name, _), v in per.items():
+        t = sums.setdefault(name, [0.0, 0])
+        t[0] += v
+        t[1] += 1
+    return {k: v[0] / v[1] for k, v in sums.items()}
+
+
+def summarize_traffic(fetch32: str, write32: str, fetch16: str, write16: str, copyf: str, copyw: str) -> dict:
+    """HBM bytes per launch of the hot-path kernels from FETCH_SIZE and
+    WRITE_SIZE runs (KiB per dispatch), each scaled so that a plain copy of
+    known size reads and writes exactly its bytes; keyed by the bench's
+    kernel names and tagged with the hash of the kernel source."""
+    import hashlib
+    n = (1 << 30)
+    cf = max(_counter_means(copyf, "FETCH_SIZE").items(), key=lambda kv: kv[1])[1]
+    cw = max(_counter_means(copyw, "WRITE_SIZE").items(), key=lambda kv: kv[1])[1]
+    fscale, wscale = n / (cf * 1024.0), n / (cw * 1024.0)
+    src = "paper_1910_11623_amd/csrc/kernels.hip"
+    out = {"source": src, "source_sha256": hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest(),
+           "workload": f"BSB d={D} N={N} M={M} per-step MLP {W}x{DEPTH}", "fetch_scale": fscale,
+           "write_scale": wscale, "per_launch": {}}
+    for prec, fd, wd in (("fp32", fetch32, write32), ("bf16", fetch16, write16)):
+        fm, wm = _counter_means(fd, "FETCH_SIZE"), _counter_means(wd, "WRITE_SIZE")
+        for name, v in fm.items():
+            short = name.split("(")[0].replace("void ", "").split("<")[0].split("::")[-1]
+            key = _TRAFFIC_KEYS.get(short)
+            if key is None:
+                continue
+            out["per_launch"][f"{key}_{prec}"] = {"read_bytes": v * 1024.0 * fscale,
+                                                  "write_bytes": wm.get(name, 0.0) * 1024.0 * wscale,
+                                                  "kernel": name.split("(")[0].replace("void fbsde::", "")}
+    return out
+
+
 def roofline_entry(prec: str, kern_ms: dict):
     """Roofline of the dominant MFMA kernel (the longest of forward, reverse
     sweep and weight gradient): its algorithmic flops per launch over its
@@ -607,7 +661,7 @@ def paper_leg(steps: int = 100, tta: bool = True, archs=("u_fc", "u_res", "u_nai
     return out
 
 
-def generalisation_leg(iters: int = 4000, deltas=(0.0, 0.05, 0.1, 0.2, 0.4), N_: int = 32, M_: int = 100,
+def generalisation_leg(iters: int = 8000, deltas=(0.0, 0.05, 0.1, 0.2, 0.4), N_: int = 32, M_: int = 100,
                        n_dirs: int = 4):
     """Sec. 4 generalisation experiment: u-networks of the three block types
     (fully connected, residual, NAIS), trained at x0 with the same budget,
@@ -827,9 +881,19 @@ def main():
     ap.add_argument("--only", choices=["batch", "hjb", "resnet", "resnet_kept", "resnet_multilevel", "paper",
                                        "generalisation"],
                     help="run just one of the extra legs and print its JSON")
+    ap.add_argument("--summarize-traffic", nargs=6, metavar="DIR",
+                    help="rocprofv3 --pmc output dirs: FETCH_SIZE fp32, WRITE_SIZE fp32, FETCH_SIZE bf16, "
+                         "WRITE_SIZE bf16, FETCH_SIZE and WRITE_SIZE of --copy-calibration; writes "
+                         "profiles/bsb_d100_traffic.json")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        rec = summarize_traffic(*args.summarize_traffic)
+        with open(os.path.join(ROOT, "profiles", "bsb_d100_traffic.json"), "w") as fo:
+            json.dump(rec, fo, indent=1)
+        print(json.dumps(rec["per_launch"]), flush=True)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only; there is no multi-GPU path in this library.", file=sys.stderr)
