@@ -68,6 +68,9 @@ struct UGemm {
   int K;
   long long kchunk;  // reduction range of one split (multiple of BK)
   int ti, tj, ts;    // tiles over i, j and splits
+  // optional second term: C += A2 B2^T over the same k range (same strides);
+  // a split first reduces (a, b), then (a2, b2)
+  const float* a2; const float* b2;
 };
 
 enum {
@@ -92,6 +95,10 @@ struct UEpi {
   float* out0; float* out1; float* out2;
   long long ld;           // row stride of the row buffers touched by the epilogue
   float* part; long long pbase, pstride; int pld, slot0;
+  // U_PART: sums over the split's k range of the (last term's) A operand,
+  // plain into part[.. + cbase + i] and weighted by t_k = (k / mp) dt into
+  // part[.. + tbase + i * tstride] (either offset < 0: not formed)
+  long long cbase, tbase; int tstride;
 };
 
 __device__ __forceinline__ f32x4 ldv(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
@@ -263,24 +270,26 @@ __global__ __launch_bounds__(256) void k_ugemm(UGemm G, UEpi E) {
       boff[q] = (long long)min(j0 + 4 * c4, (int)G.ldb - 4);
     }
   }
+  const float* pa = G.a;
+  const float* pb = G.b;
   auto load = [&](int slab, f32x4 (&ra)[UA], f32x4 (&rb)[UB]) {
     const long long kt = ks + (long long)(slab < nk ? slab : 0) * BK;
 #pragma unroll
     for (int q = 0; q < UA; ++q) {
       if constexpr (!AKM) {
-        ra[q] = *reinterpret_cast<const f32x4*>(G.a + aoff[q] + kt);
+        ra[q] = *reinterpret_cast<const f32x4*>(pa + aoff[q] + kt);
       } else {
         const long long k = min(kt + akq[q], (long long)G.K - 1);
-        ra[q] = *reinterpret_cast<const f32x4*>(G.a + k * G.lda + aoff[q]);
+        ra[q] = *reinterpret_cast<const f32x4*>(pa + k * G.lda + aoff[q]);
       }
     }
 #pragma unroll
     for (int q = 0; q < UB; ++q) {
       if constexpr (!BKM) {
-        rb[q] = *reinterpret_cast<const f32x4*>(G.b + boff[q] + kt);
+        rb[q] = *reinterpret_cast<const f32x4*>(pb + boff[q] + kt);
       } else {
         const long long k = min(kt + bkq[q], (long long)G.K - 1);
-        rb[q] = *reinterpret_cast<const f32x4*>(G.b + k * G.ldb + boff[q]);
+        rb[q] = *reinterpret_cast<const f32x4*>(pb + k * G.ldb + boff[q]);
       }
     }
   };
@@ -315,7 +324,15 @@ __global__ __launch_bounds__(256) void k_ugemm(UGemm G, UEpi E) {
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  auto compute = [&](int buf) {
+  // column sums of A (bias and t-column gradients): the waves of the first
+  // j-tile column, last term only
+  const int nseg = G.a2 ? 2 : 1;
+  bool csum = false;
+  if constexpr (EPI == U_PART) csum = (E.cbase >= 0 || E.tbase >= 0) && jt == 0 && wj == 0;
+  float cs[TM], tsum[TM];
+#pragma unroll
+  for (int a = 0; a < TM; ++a) cs[a] = tsum[a] = 0.f;
+  auto compute = [&](int buf, long long kt, bool sums) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       float fa[TM], fb[TN];
@@ -328,20 +345,35 @@ __global__ __launch_bounds__(256) void k_ugemm(UGemm G, UEpi E) {
       for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[b], fa[a], acc[a][b], 0, 0, 0);
+      if constexpr (EPI == U_PART) {
+        if (sums) {  // wave-uniform
+          const float tk = (float)((kt + kr) / E.mp) * E.dt;
+#pragma unroll
+          for (int a = 0; a < TM; ++a) {
+            cs[a] += fa[a];
+            tsum[a] += tk * fa[a];
+          }
+        }
+      }
     }
   };
 
   f32x4 ra[UA], rb[UB];
-  if (nk > 0) {
-    load(0, ra, rb);
-    store(0, 0, ra, rb);
-  }
-  __syncthreads();
-  for (int s = 0; s < nk; ++s) {
-    load(s + 1, ra, rb);  // past the last slab: a harmless re-read of the first
-    compute(s & 1);
-    if (s + 1 < nk) store(s + 1, (s + 1) & 1, ra, rb);
+  for (int seg = 0; seg < nseg; ++seg) {
+    pa = seg ? G.a2 : G.a;
+    pb = seg ? G.b2 : G.b;
+    const bool sums = csum && seg == nseg - 1;
+    if (nk > 0) {
+      load(0, ra, rb);
+      store(0, 0, ra, rb);
+    }
     __syncthreads();
+    for (int s = 0; s < nk; ++s) {
+      load(s + 1, ra, rb);  // past the last slab: a harmless re-read of the first
+      compute(s & 1, ks + (long long)s * BK, sums);
+      if (s + 1 < nk) store(s + 1, (s + 1) & 1, ra, rb);
+      __syncthreads();
+    }
   }
   // lane: row i = .. + l16, columns j = .. + 4 (lane / 16) + 0..3
 #pragma unroll
@@ -349,6 +381,24 @@ __global__ __launch_bounds__(256) void k_ugemm(UGemm G, UEpi E) {
 #pragma unroll
     for (int b = 0; b < TN; ++b)
       epi4<EPI>(E, i0 + wi * 16 * TM + 16 * a + l16, j0 + wj * 16 * TN + 16 * b + 4 * g4, acc[a][b], sp);
+  if constexpr (EPI == U_PART) {
+    if (csum) {
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        float c = cs[a], t = tsum[a];
+        c += __shfl_xor(c, 16);
+        c += __shfl_xor(c, 32);
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        const int i = i0 + wi * 16 * TM + 16 * a + l16;
+        if (g4 == 0 && i < E.rows) {
+          const long long base = (long long)(E.slot0 + sp) * E.pstride;
+          if (E.cbase >= 0) E.part[base + E.cbase + i] = c;
+          if (E.tbase >= 0) E.part[base + E.tbase + (long long)i * E.tstride] = t;
+        }
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------- u = H_K w_o + b_o
@@ -710,6 +760,7 @@ hipError_t gemm(const UGemm& G0, const UEpi& E, int M_i, int N_j, int splits, hi
 
 UEpi epi0(const Geo& g, long long ld) {
   UEpi E{};
+  E.cbase = E.tbase = -1;
   E.mp = g.M;
   E.dt = g.dt;
   E.c = g.uarch == 0 ? 0.f : 1.f;
@@ -733,9 +784,9 @@ UnetLayout unet_layout(const Geo& g) {
   L.off_blk0 = L.off_b0 + g.w;
   L.off_wo = L.off_blk0 + (long long)K * L.blk;
   L.off_bo = L.off_wo + g.w;
-  // partial sums per parameter: each two-term weight gradient splits its rows
-  // over slots / 2 workgroup rows, enough to fill the chip at 16 output tiles
-  L.slots = L.R < 32768 ? 32 : 64;
+  // partial sums per parameter: one per row range of the weight-gradient
+  // GEMMs, enough ranges to give every CU two 128 x 128 tiles at w = 256
+  L.slots = L.R < 32768 ? 32 : 128;
   const long long np4 = (g.nparams + 3) / 4 * 4;
   L.off_abar = np4;
   L.pstride = np4 + (g.uarch == 2 ? (long long)K * g.w * g.w : 0);
@@ -876,52 +927,60 @@ hipError_t unet_forward_backward(const Geo& g, const UnetBufs& B, const float* p
     E.out0 = B.HBAR; E.out1 = ABk(k - 1);
     if ((e = gemm<false, true, U_RBLK>(G, E, (int)R, w, 1, s)) != hipSuccess) return e;
   }
-  // ---- weight gradients: every element receives L.slots partial sums (a
-  // two-term block half of them from each term), summed in slot order
-  const int half = L.slots / 2;
+  // ---- weight gradients: every element receives L.slots partial sums, one
+  // per row range, both terms of a block in one launch (the range's rows of
+  // the first term, then of the second); the column sums of the second
+  // term's A operand give the bias (and t-column) gradients of the block
   const long long pstride = L.pstride;
-  auto wgrad = [&](const float* Aop, long long lda, int arows, const float* Bop, long long ldb, int brows,
-                   long long pbase, int pld, int slot0, int nsl) -> hipError_t {
-    UGemm G{Aop, lda, arows, Bop, ldb, brows, (int)R, 0, 0, 0, 0};
+  auto wgrad = [&](const float* A1, const float* B1, const float* A2, const float* B2, long long lda, int arows,
+                   long long ldb, int brows, long long pbase, int pld, long long cbase, long long tbase,
+                   int tstride) -> hipError_t {
+    const int nsl = L.slots;
+    UGemm G{A1, lda, arows, B1, ldb, brows, (int)R, 0, 0, 0, 0, A2, B2};
     G.kchunk = ((R + nsl - 1) / nsl + BK - 1) / BK * BK;
     G.ts = nsl;  // splits past the rows reduce nothing and store zeros: every slot is written
-    G.ti = (arows + 63) / 64;
-    G.tj = (brows + 63) / 64;
     UEpi E = epi0(g, 0);
     E.rows = arows; E.cols = brows; E.part = B.part; E.pbase = pbase; E.pld = pld; E.pstride = pstride;
-    E.slot0 = slot0;
-    hipLaunchKernelGGL((k_ugemm<true, true, U_PART, 2, 2>), dim3(G.ti * G.tj * G.ts), dim3(256), 0, s, G, E);
+    E.slot0 = 0; E.cbase = cbase; E.tbase = tbase; E.tstride = tstride;
+    // 128 x 128 tiles (half the operand re-reads of 64 x 64) when they still
+    // give 512 workgroups
+    const long long t4 = (long long)((arows + 127) / 128) * ((brows + 127) / 128) * nsl;
+    if (t4 >= 512) {
+      G.ti = (arows + 127) / 128;
+      G.tj = (brows + 127) / 128;
+      hipLaunchKernelGGL((k_ugemm<true, true, U_PART, 4, 4>), dim3(G.ti * G.tj * G.ts), dim3(256), 0, s, G, E);
+    } else {
+      G.ti = (arows + 63) / 64;
+      G.tj = (brows + 63) / 64;
+      hipLaunchKernelGGL((k_ugemm<true, true, U_PART, 2, 2>), dim3(G.ti * G.tj * G.ts), dim3(256), 0, s, G, E);
+    }
     return hipGetLastError();
   };
-  // W_0 x columns: G_0^T ZB + ABAR_0^T X
-  if ((e = wgrad(Gk(0), wq, w, B.ZB, dp, d, L.off_W0, d + 1, 0, half)) != hipSuccess) return e;
-  if ((e = wgrad(ABk(0), wq, w, B.X, dp, d, L.off_W0, d + 1, half, half)) != hipSuccess) return e;
+  // W_0: x columns G_0^T ZB + ABAR_0^T X; b_0 and the t column from ABAR_0
+  if ((e = wgrad(Gk(0), B.ZB, ABk(0), B.X, wq, w, dp, d, L.off_W0, d + 1, L.off_b0, L.off_W0 + d, d + 1)) !=
+      hipSuccess)
+    return e;
   for (int k = 1; k <= K; ++k) {
     const long long base = L.off_blk0 + (long long)(k - 1) * L.blk;
-    // dA_k = G_k^T HHB_{k-1} + ABAR_k^T H_{k-1}; NAIS: into the scratch part of
-    // the partial rows (R_k's gradient is formed from it below)
+    // dA_k = G_k^T HHB_{k-1} + ABAR_k^T H_{k-1}, db_k from ABAR_k; NAIS: dA_k
+    // into the scratch part of the partial rows (R_k's gradient is formed
+    // from it below)
     const long long abase = nais ? L.off_abar + (long long)(k - 1) * w * w : base;
-    if ((e = wgrad(Gk(k), wq, w, HHBk(k - 1), wq, w, abase, w, 0, half)) != hipSuccess) return e;
-    if ((e = wgrad(ABk(k), wq, w, Hk(k - 1), wq, w, abase, w, half, half)) != hipSuccess) return e;
-    if (nais) {  // dE_k x columns: G_k^T ZB + ABAR_k^T X
+    if ((e = wgrad(Gk(k), HHBk(k - 1), ABk(k), Hk(k - 1), wq, w, wq, w, abase, w, base + L.blk - w, -1, 0)) !=
+        hipSuccess)
+      return e;
+    if (nais) {  // dE_k: x columns G_k^T ZB + ABAR_k^T X, t column from ABAR_k
       const long long ebase = base + (long long)w * w;
-      if ((e = wgrad(Gk(k), wq, w, B.ZB, dp, d, ebase, d + 1, 0, half)) != hipSuccess) return e;
-      if ((e = wgrad(ABk(k), wq, w, B.X, dp, d, ebase, d + 1, half, half)) != hipSuccess) return e;
+      if ((e = wgrad(Gk(k), B.ZB, ABk(k), B.X, wq, w, dp, d, ebase, d + 1, -1, ebase + d, d + 1)) != hipSuccess)
+        return e;
     }
   }
-  // vector gradients by column sums over row ranges
+  // w_o and b_o by column sums over row ranges
   {
     ColArgs C{};
     C.R = R; C.ld = wq; C.mp = g.M; C.dt = g.dt; C.ub = B.UB; C.part = B.part; C.pstride = pstride;
     C.slots = L.slots; C.chunk = (R + L.slots - 1) / L.slots;
     int nj = 0;
-    C.job[nj++] = ColJob{0, w, ABk(0), nullptr, L.off_b0, 1};
-    C.job[nj++] = ColJob{1, w, ABk(0), nullptr, L.off_W0 + d, d + 1};
-    for (int k = 1; k <= K; ++k) {
-      const long long base = L.off_blk0 + (long long)(k - 1) * L.blk;
-      C.job[nj++] = ColJob{0, w, ABk(k), nullptr, base + L.blk - w, 1};
-      if (nais) C.job[nj++] = ColJob{1, w, ABk(k), nullptr, base + (long long)w * w + d, d + 1};
-    }
     C.job[nj++] = ColJob{2, w, HHBk(K), Hk(K), L.off_wo, 1};
     C.job[nj++] = ColJob{3, 1, nullptr, nullptr, L.off_bo, 1};
     C.njobs = nj;
