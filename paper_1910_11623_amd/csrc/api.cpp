@@ -401,13 +401,20 @@ fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double
       return hip_fail(e, "reduce");
     return FBSDE_OK;
   }
-  {
+  if (fbsde::reverse_fused_fits(g)) {
+    // the reverse sweep and the weight gradient in one kernel (timed as the backward)
     ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
-    if ((e = fbsde::launch_backward(g, at<void>(ws, L.PB), at<float>(ws, L.V), at<float>(ws, L.LAM),
-                                    at<void>(ws, L.H), at<void>(ws, L.DZ), at<void>(ws, L.DH), s)) != hipSuccess)
-      return hip_fail(e, "backward");
-  }
-  {
+    if ((e = fbsde::launch_reverse(g, at<void>(ws, L.PB), at<float>(ws, L.X), at<float>(ws, L.V),
+                                   at<float>(ws, L.LAM), at<void>(ws, L.H), at<float>(ws, L.PART), L.splits,
+                                   L.chunk, s)) != hipSuccess)
+      return hip_fail(e, "reverse");
+  } else {
+    {
+      ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
+      if ((e = fbsde::launch_backward(g, at<void>(ws, L.PB), at<float>(ws, L.V), at<float>(ws, L.LAM),
+                                      at<void>(ws, L.H), at<void>(ws, L.DZ), at<void>(ws, L.DH), s)) != hipSuccess)
+        return hip_fail(e, "backward");
+    }
     ProfScope ps(plan, FBSDE_PROF_WGRAD, s);
     if ((e = fbsde::launch_wgrad(g, at<float>(ws, L.X), at<void>(ws, L.H), at<void>(ws, L.DZ),
                                  at<void>(ws, L.DH), at<float>(ws, L.PART), L.splits, L.chunk, s)) != hipSuccess)
@@ -506,7 +513,7 @@ fbsde_status fbsde_plan_create(const fbsde_problem* problem, const fbsde_net* ne
   g.M = (int)M;
   g.kind = unet ? 2 : resnet ? 1 : 0;
   g.L = net->depth;
-  g.lds = 1;
+  g.lds = 2;  // LDS staging, and the fused reverse kernel where it applies
   g.tpw = 0;
   g.uarch = unet ? net->kind - FBSDE_NET_U_FC : 0;
   g.kappa = 0.f;
@@ -933,7 +940,7 @@ fbsde_status fbsde_plan_config(fbsde_plan* plan, int32_t shape, int32_t lds, int
   const Geo keep_g = plan->geo;
   const WsLayout keep_w = plan->ws;
   if (plan->geo.kind == 0) set_tiles(plan->geo, plan->cand_ti[shape], plan->cand_tw[shape]);
-  plan->geo.lds = lds ? 1 : 0;
+  plan->geo.lds = lds <= 0 ? 0 : (lds >= 2 ? 2 : 1);
   plan->geo.tpw = tpw;
   plan->ws.splits = splits;
   make_layout(plan);
@@ -1018,7 +1025,7 @@ fbsde_status fbsde_plan_autotune(fbsde_plan* plan, const float* params, const do
     (void)hipEventElapsedTime(ms, e0, e1);
     return FBSDE_OK;
   };
-  int best[4] = {0, 1, 0, 0};  // shape, lds, tpw, splits
+  int best[4] = {0, 2, 0, 0};  // shape, lds, tpw, splits
   float best_ms = 1e30f;
   auto trial = [&](int sh, int l, int tp, int sp) -> fbsde_status {
     if (fbsde_plan_config(plan, sh, l, tp, sp) != FBSDE_OK) return FBSDE_OK;  // skip what does not fit
@@ -1032,18 +1039,16 @@ fbsde_status fbsde_plan_autotune(fbsde_plan* plan, const float* params, const do
     return FBSDE_OK;
   };
   fbsde_status r = FBSDE_OK;
-  // 1. register-tile shape and LDS staging
+  // 1. register-tile shape and LDS mode (2 = fused reverse where it applies, 1, 0)
   for (int sh = 0; sh < plan->ncand && r == FBSDE_OK; ++sh)
-    for (int l = 1; l >= 0 && r == FBSDE_OK; --l) r = trial(sh, l, 0, 0);
+    for (int l = 2; l >= 0 && r == FBSDE_OK; --l) r = trial(sh, l, 0, 0);
   // 2. tiles per wave of the LDS kernels
   if (r == FBSDE_OK && best[1]) {
-    Geo g = plan->geo;
-    fbsde_plan_config(plan, best[0], 1, 0, 0);
+    fbsde_plan_config(plan, best[0], best[1], 0, 0);
     const int a = fbsde::auto_tiles_per_wave(plan->geo);
-    (void)g;
     const int cand[3] = {a > 1 ? a / 2 : 0, a * 2 <= 64 ? a * 2 : 0, a > 2 ? a - 1 : 0};
     for (int c = 0; c < 3 && r == FBSDE_OK; ++c)
-      if (cand[c] > 0) r = trial(best[0], 1, cand[c], 0);
+      if (cand[c] > 0) r = trial(best[0], best[1], cand[c], 0);
   }
   // 3. weight-gradient path splits
   for (int sp : {4, 8, 16, 32}) {

@@ -37,7 +37,7 @@ struct Geo {
   long long packf_step;   // packed forward fragments per step (elements)
   long long packb_step;   // packed backward fragments per step (elements)
   long long pbias_step;   // padded fp32 biases per step: L * 16 tw + 16 ti
-  int lds;                // 1: step weights may be staged in LDS (when they fit)
+  int lds;                // 1: step weights may be staged in LDS (when they fit); 2: also the fused reverse kernel
   int tpw;                // 16-path tiles per wave of the LDS kernels (0: automatic)
   int kind;               // 0: per-step MLP, 1: shared residual network (L = blocks), 2: u-network
   int uarch;              // u-network blocks: 0 fully connected, 1 residual, 2 NAIS
@@ -151,6 +151,12 @@ hipError_t launch_backward(const Geo& g, const void* packB, const float* V, cons
                            const void* H, void* DZ, void* DH, hipStream_t s);
 hipError_t launch_wgrad(const Geo& g, const float* X, const void* H, const void* DZ, const void* DH,
                         float* part, int splits, long long chunk, hipStream_t s);
+// Reverse sweep and weight gradient in one kernel (fp32 per-step MLP with
+// g.lds == 2, depth <= 2, d + 1 <= 16 ti, w + 1 <= 16 tw, fitting LDS); the
+// same partials as launch_backward + launch_wgrad with the same splits.
+bool reverse_fused_fits(const Geo& g);
+hipError_t launch_reverse(const Geo& g, const void* packB, const float* X, const float* V, const float* LAM,
+                          const void* H, float* part, int splits, long long chunk, hipStream_t s);
 // The scan's partials are followed by an int flag: cleared by the scan, set
 // by the reduction on a non-finite gradient; the finalize step folds it (and
 // the loss, dL/dY0) into *host_flag (pinned host memory) and clears it.

@@ -979,6 +979,64 @@ __device__ __forceinline__ void wgrad_put(unsigned char* smem, int tid,
   }
 }
 
+// fp32 staging with the loads in flight across the MFMAs: the loads are
+// unconditional (rows and columns clamped into their buffers, a missing
+// input read from the delta buffer) and their values are consumed only when
+// wgrad_put_f32 writes them to LDS, which applies the path range, the row
+// extent, the bias column and the zero padding (the semantics of
+// wgrad_fetch).
+template <int T>
+__device__ __forceinline__ void wgrad_fetch_raw(const Job& J, int R0, int C0, long long pc, long long p1, int tid,
+                                                f32x4 (&v)[WgradStage<false, T>::NS]) {
+  constexpr int NV = WgradStage<false, T>::NV;
+#pragma unroll
+  for (int k = 0; k < WgradStage<false, T>::NS; ++k) {
+    const int s = min(tid + k * WG_THREADS, 2 * NV - 1);
+    const bool isA = s < NV;
+    const int q = isA ? s : s - NV;
+    const int kp = q / (4 * T), c4 = q % (4 * T);
+    const size_t p = (size_t)min(pc + kp, p1 - 1);
+    const float* src;
+    if (isA || J.B == nullptr) {
+      src = reinterpret_cast<const float*>(J.A) + p * J.sA + min(R0 + 4 * c4, J.sA - 4);
+    } else {
+      src = reinterpret_cast<const float*>(J.B) + p * J.sB + min(C0 + 4 * c4, J.sB - 4);
+    }
+    v[k] = ld4(src);
+  }
+}
+
+template <int T>
+__device__ __forceinline__ void wgrad_put_f32(const Job& J, int R0, int C0, long long pc, long long p1,
+                                              unsigned char* smem, int tid,
+                                              const f32x4 (&v)[WgradStage<false, T>::NS]) {
+  using L = WgradLds<false, T>;
+  constexpr int NV = WgradStage<false, T>::NV;
+#pragma unroll
+  for (int k = 0; k < WgradStage<false, T>::NS; ++k) {
+    const int s = tid + k * WG_THREADS;
+    if (s >= 2 * NV) continue;
+    const bool isA = s < NV;
+    const int q = isA ? s : s - NV;
+    const int kp = q / (4 * T), c4 = q % (4 * T);
+    const bool ok = pc + kp < p1;
+    f32x4 x = zero4();
+    if (isA) {
+      if (ok && R0 + 4 * c4 < J.rows) x = v[k];
+    } else if (ok) {
+      const int c = C0 + 4 * c4, stride = J.B ? J.sB : 0;
+      if (c < stride) x = v[k];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (c + e == J.cols) x[e] = 1.f;
+        else if (c + e > J.cols) x[e] = 0.f;
+      }
+    }
+    float* dst = reinterpret_cast<float*>(smem) + (isA ? 0 : L::KC * L::LDA) + kp * L::LDA + 4 * c4;
+    st4(dst, x);
+  }
+}
+
 // One wave's share of the T x T tile block: NR tile rows from rt0 times NC
 // tile columns from ct0 (NR = NC = 0: the wave only stages).
 template <bool BF, int T, int NR, int NC>
@@ -997,14 +1055,19 @@ __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, 
     for (int j = 0; j < NCA; ++j) acc[i][j] = zero4();
 
   typename StageSlot<BF>::type pre[WgradStage<BF, T>::NS];
-  if constexpr (wg_prefetch<BF>()) wgrad_fetch<BF, T>(J, R0, C0, p0, p1, tid, pre);
+  if constexpr (wg_prefetch<BF>()) wgrad_fetch_raw<T>(J, R0, C0, p0, p1, tid, pre);
   for (long long pc = p0; pc < p1; pc += L::KC) {
     __syncthreads();
-    if constexpr (!wg_prefetch<BF>()) wgrad_fetch<BF, T>(J, R0, C0, pc, p1, tid, pre);
-    wgrad_put<BF, T>(smem, tid, pre);
+    if constexpr (!wg_prefetch<BF>()) {
+      wgrad_fetch<BF, T>(J, R0, C0, pc, p1, tid, pre);
+      wgrad_put<BF, T>(smem, tid, pre);
+    } else {
+      wgrad_put_f32<T>(J, R0, C0, pc, p1, smem, tid, pre);
+    }
     __syncthreads();
     // the next chunk's loads are in flight during this chunk's MFMAs
-    if (wg_prefetch<BF>() && pc + L::KC < p1) wgrad_fetch<BF, T>(J, R0, C0, pc + L::KC, p1, tid, pre);
+    if constexpr (wg_prefetch<BF>())
+      if (pc + L::KC < p1) wgrad_fetch_raw<T>(J, R0, C0, pc + L::KC, p1, tid, pre);
     if constexpr (!MM) continue;
     // ---- MFMA over the chunk
     if constexpr (!BF) {
@@ -1086,6 +1149,253 @@ __global__ __launch_bounds__(WG_THREADS) void k_wgrad(Geo g, const float* __rest
     if (WG_CPW == 2 && ncol == 2) wgrad_tiles<BF, T, T, WG_CPW>(g, J, R0, C0, p0, p1, smem, out, 0, WG_CPW * wv);
     else if (ncol == 1) wgrad_tiles<BF, T, T, 1>(g, J, R0, C0, p0, p1, smem, out, 0, WG_CPW * wv);
     else wgrad_tiles<BF, T, 0, 0>(g, J, R0, C0, p0, p1, smem, out, 0, 0);
+  }
+}
+
+// ---------------------------------------------------- fused reverse kernel
+// fp32 reverse sweep and weight gradient of one step in one kernel, so the
+// deltas never leave the CU.  Workgroup = (path split, step n), 8 waves.  It
+// stages step n's transposed weights (the backward fragments) in LDS once and
+// walks the split's paths in rounds of 16.  A round stages [path][feature]
+// rows of zeta = lambda_{n+1} v_n and of the layer inputs x, h_1..h_L (with
+// the bias column of ones); waves 0..TW-1 then form delta_L, ..., delta_1, one
+// 16-feature output tile each (D registers back to LDS rows), and every wave
+// accumulates its share of the step's weight-gradient tiles in registers.
+// Tile ownership follows k_wgrad: with 7 x 7 tile blocks, waves 0..6 take
+// tile rows 0..5 of tile column wv and wave 7 takes tile row 6 of every
+// column; with T <= 4 tiles, wave wv < T takes tile column wv.  Step 0 has no
+// network: its workgroups sum zeta_0 (the z0 gradient).  Paths, 16-path
+// chunks, the path-to-MFMA-slot assignment and the per-tile accumulation
+// order are those of k_backward + k_wgrad with the same split count, so the
+// two forms give bitwise equal gradients.
+//
+// Staged rows are 16-byte-group swizzled (rv_at): rows 0..7 (and 8..15) take
+// distinct swizzles, so the 16-byte reads and writes of 8 lanes on 8
+// consecutive rows hit 8 distinct bank groups; rows 2k and 2k + 1 differ in
+// bit 2 of the swizzle, so the 4-byte operand reads of one column over rows
+// 4k + {0, 1} (lanes 0..31) fall in disjoint bank halves.
+constexpr int RV_WAVES = 8, RV_THREADS = 64 * RV_WAVES, RV_KC = 16;
+
+__host__ __device__ constexpr int rv_lda(int ti, int tw) { return (16 * (ti > tw ? ti : tw) + 31) / 32 * 32; }
+__host__ __device__ constexpr int rv_arrays(int L) { return 2 * L + 2; }
+__host__ __device__ constexpr int NRA_(int nr) { return nr > 0 ? nr : 1; }
+__host__ __device__ constexpr int NCA_(int nc) { return nc > 0 ? nc : 1; }
+
+__device__ __forceinline__ int rv_swz(int row) { return ((row & 1) << 2) | ((row >> 1) & 3); }
+template <int LDA>
+__device__ __forceinline__ int rv_at(int row, int col) {
+  return row * LDA + 4 * ((col >> 2) ^ rv_swz(row)) + (col & 3);
+}
+
+// Weight-gradient matrix m of step n: staged arrays 0 = zeta, l = delta_l
+// (l = 1..L), L + 1 = x (step 0: a column of ones), L + 1 + l = h_l.
+struct RvMat { int rows, cols, rt, ct, da, aa; long long base; };
+__device__ __forceinline__ RvMat rv_mat(const Geo& g, int n, int m) {
+  RvMat R;
+  const int d = g.d, w = g.w, L = g.L;
+  if (n == 0) {  // dz0 = sum over paths of zeta_0: rows d, bias column only
+    R.rows = d; R.cols = 0; R.base = 0; R.da = 0; R.aa = L + 1;
+  } else {
+    const long long step = d + (long long)(n - 1) * g.pstep;
+    const long long lw1 = (long long)w * d + w, lwh = (long long)w * w + w;
+    if (m == 0) {  // W_1 += delta_1 x^T
+      R.rows = w; R.cols = d; R.base = step; R.da = 1; R.aa = L + 1;
+    } else if (m < L) {  // W_{m+1} += delta_{m+1} h_m^T
+      R.rows = w; R.cols = w; R.base = step + lw1 + (long long)(m - 1) * lwh; R.da = m + 1; R.aa = L + 1 + m;
+    } else {  // W_o += zeta h_L^T
+      R.rows = d; R.cols = w; R.base = step + lw1 + (long long)(L - 1) * lwh; R.da = 0; R.aa = 2 * L + 1;
+    }
+  }
+  R.rt = (R.rows + 15) / 16;
+  R.ct = (R.cols + 16) / 16;  // + the bias column
+  return R;
+}
+
+// The whole round loop for one wave role: NR tile rows from R0 times NC tile
+// columns from C0 of every weight-gradient matrix (NR = NC = 0: no tiles).
+// Tiles past a matrix's extent multiply zero-padded staged columns and are
+// dropped at the scatter.
+template <int TI, int TW, int L, int NR, int NC>
+__device__ __forceinline__ void rv_body(const Geo& g, const void* __restrict__ packB, const float* __restrict__ X,
+                                        const float* __restrict__ V, const float* __restrict__ LAM,
+                                        const float* __restrict__ H, float* __restrict__ part, long long p0,
+                                        long long p1, unsigned char* wsm, int R0, int C0) {
+  constexpr int LDA = rv_lda(TI, TW), ASZ = RV_KC * LDA, NSL = L + 2;
+  static_assert(RV_KC * 4 * (TI > TW ? TI : TW) <= RV_THREADS, "one staging item per thread and array");
+  const int n = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c16 = lane & 15, grp = lane >> 4;
+  float* arr = reinterpret_cast<float*>(wsm + (size_t)g.packb_step * 4);
+  const size_t rowM = (size_t)g.M * g.dp, hM = (size_t)g.M * g.wp;
+  const int nmat = n == 0 ? 1 : L + 1;
+
+  // ---- staging: slot a of every thread serves input a (0: v, scaled to
+  // zeta; 1: x, or the column of ones at step 0; 1 + l: h_l); item tid is
+  // (row p, columns c..c+3) of the round (c = -1: no item)
+  int sp[NSL], sc[NSL], sofs[NSL];
+#pragma unroll
+  for (int a = 0; a < NSL; ++a) {
+    const int gq = a == 0 ? g.dp / 4 : (a == 1 ? (n == 0 ? 1 : (g.d + 4) / 4) : (g.w + 4) / 4);
+    const int p = tid / gq;
+    sp[a] = p < RV_KC ? p : 0;
+    sc[a] = p < RV_KC ? 4 * (tid - p * gq) : -1;
+    sofs[a] = (a == 0 ? 0 : L + a) * ASZ + rv_at<LDA>(sp[a], sc[a] < 0 ? 0 : sc[a]);
+  }
+  const float* Vn = V + n * rowM;
+  const float* Ln = LAM + (size_t)n * g.M;
+  const float* Xn = X + n * rowM;
+  // Raw loads only: every load is unconditional (row and column clamped into
+  // the buffer), so a round's loads are all in flight while the previous
+  // round computes; validity, the bias column and zero padding are applied
+  // when the values are written to LDS.
+  f32x4 sv[NSL];
+#pragma unroll
+  for (int a = 0; a < NSL; ++a) sv[a] = zero4();
+  float sl = 0.f;
+  auto fetch = [&](long long pc) {
+#pragma unroll
+    for (int a = 0; a < NSL; ++a) {
+      const size_t p = (size_t)min(pc + sp[a], p1 - 1);
+      if (a == 0) {
+        sv[a] = ld4(Vn + p * g.dp + max(sc[a], 0));
+        sl = Ln[p];
+      } else if (a == 1) {
+        if (n > 0) sv[a] = ld4(Xn + p * g.dp + min(max(sc[a], 0), g.dp - 4));
+      } else {
+        sv[a] = ld4(H + ((size_t)n * L + (a - 2)) * hM + p * g.wp + min(max(sc[a], 0), g.wp - 4));
+      }
+    }
+  };
+  // the staged value of slot a for round pc (the semantics of load_cols4)
+  auto staged = [&](int a, long long pc) -> f32x4 {
+    const bool ok = sc[a] >= 0 && pc + sp[a] < p1;
+    const int c = sc[a];
+    if (a == 0) return ok ? sl * sv[0] : zero4();
+    const int cols = a == 1 ? (n == 0 ? 0 : g.d) : g.w;
+    const int stride = a == 1 ? (n == 0 ? 0 : g.dp) : g.wp;
+    f32x4 v = c < stride ? sv[a] : zero4();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (c + e == cols) v[e] = 1.f;
+      else if (c + e > cols) v[e] = 0.f;
+    }
+    return ok ? v : zero4();
+  };
+
+  f32x4 acc[L + 1][NRA_(NR)][NCA_(NC)];
+#pragma unroll
+  for (int m = 0; m < L + 1; ++m)
+#pragma unroll
+    for (int i = 0; i < NRA_(NR); ++i)
+#pragma unroll
+      for (int j = 0; j < NCA_(NC); ++j) acc[m][i][j] = zero4();
+
+  fetch(p0);
+  if (n > 0) copy_to_lds(wsm, reinterpret_cast<const char*>(packB) + (size_t)(n - 1) * g.packb_step * 4,
+                         (size_t)g.packb_step * 4);
+  // columns no round writes stay zero
+  for (int e = tid; e < rv_arrays(L) * ASZ / 4; e += RV_THREADS) st4(arr + 4 * e, zero4());
+  const f32x4* W4 = reinterpret_cast<const f32x4*>(wsm);
+  for (long long pc = p0; pc < p1; pc += RV_KC) {
+    __syncthreads();  // weights and zero fill (first round), or the previous round's reads, are done
+#pragma unroll
+    for (int a = 0; a < NSL; ++a)
+      if (sc[a] >= 0) st4(arr + sofs[a], staged(a, pc));
+    __syncthreads();
+    if (pc + RV_KC < p1) fetch(pc + RV_KC);  // in flight during this round's MFMAs
+    if (n > 0) {
+      // delta_L = (W_o^T zeta) (1 - h_L^2), then delta_l = (W_{l+1}^T delta_{l+1}) (1 - h_l^2)
+#pragma unroll
+      for (int l = L; l >= 1; --l) {
+        if (wv < TW) {
+          const int kt = l == L ? TI : TW;
+          const f32x4* A = W4 + (l == L ? 0 : 64 * (TW * TI + (l - 1) * TW * TW));
+          const float* in = arr + (l == L ? 0 : (l + 1) * ASZ);
+          f32x4 a4 = zero4();
+#pragma unroll
+          for (int t = 0; t < (l == L ? TI : TW); ++t) {
+            const f32x4 a = A[(wv * kt + t) * 64 + lane];
+            const f32x4 b = ld4(in + rv_at<LDA>(c16, 16 * t + 4 * grp));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a4 = mfma_f32(a[r], b[r], a4);
+          }
+          const int o = rv_at<LDA>(c16, 16 * wv + 4 * grp);
+          const f32x4 h = ld4(arr + (L + 1 + l) * ASZ + o);
+          f32x4 dl;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dl[r] = a4[r] * (1.f - h[r] * h[r]);
+          st4(arr + l * ASZ + o, dl);
+        }
+        __syncthreads();
+      }
+    }
+    if constexpr (NR > 0 && NC > 0) {
+      // weight-gradient tiles: the k slot of MFMA kb is path 4 kb + (lane / 16)
+#pragma unroll
+      for (int m = 0; m < L + 1; ++m) {
+        if (m >= nmat) break;
+        // staged operands of matrix m: (delta_1, x), (delta_{m+1}, h_m), (zeta, h_L); step 0 (zeta_0, ones)
+        const float* As = arr + (m == L || n == 0 ? 0 : m + 1) * ASZ;
+        const float* Bs = arr + (m == 0 ? L + 1 : L + 1 + m) * ASZ;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          const int row = 4 * kb + grp;
+          float a[NR], b[NC];
+#pragma unroll
+          for (int i = 0; i < NR; ++i) a[i] = As[rv_at<LDA>(row, 16 * (R0 + i) + c16)];
+#pragma unroll
+          for (int j = 0; j < NC; ++j) b[j] = Bs[rv_at<LDA>(row, 16 * (C0 + j) + c16)];
+#pragma unroll
+          for (int i = 0; i < NR; ++i)
+#pragma unroll
+            for (int j = 0; j < NC; ++j) acc[m][i][j] = mfma_f32(a[i], b[j], acc[m][i][j]);
+        }
+      }
+    }
+  }
+  // ---- this split's partial sums, scattered to the flat layout
+  if constexpr (NR > 0 && NC > 0) {
+    float* out = part + (size_t)blockIdx.x * g.pstride;
+#pragma unroll
+    for (int m = 0; m < L + 1; ++m) {
+      if (m >= nmat) break;
+      const RvMat T = rv_mat(g, n, m);
+#pragma unroll
+      for (int i = 0; i < NR; ++i)
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (R0 + i) + 4 * grp + r, c = 16 * (C0 + j) + c16;
+            if (row < T.rows && c <= T.cols) {
+              const long long off = (c < T.cols) ? T.base + (long long)row * T.cols + c
+                                                 : T.base + (long long)T.rows * T.cols + row;
+              out[off] = acc[m][i][j][r];
+            }
+          }
+    }
+  }
+}
+
+template <int TI, int TW, int L>
+__global__ __launch_bounds__(RV_THREADS) void k_reverse(Geo g, const void* __restrict__ packB,
+                                                        const float* __restrict__ X, const float* __restrict__ V,
+                                                        const float* __restrict__ LAM, const void* __restrict__ Hv,
+                                                        float* __restrict__ part, long long chunk) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
+  const long long p0 = (long long)blockIdx.x * chunk;
+  const long long p1 = min((long long)g.M, p0 + chunk);
+  const float* H = reinterpret_cast<const float*>(Hv);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int T = TI > TW ? TI : TW;
+  if constexpr (T == 7) {
+    if (wv < 7) rv_body<TI, TW, L, 6, 1>(g, packB, X, V, LAM, H, part, p0, p1, wsm, 0, wv);
+    else rv_body<TI, TW, L, 1, 7>(g, packB, X, V, LAM, H, part, p0, p1, wsm, 6, 0);
+  } else {
+    static_assert(T <= RV_WAVES, "one tile column per wave");
+    if (wv < T) rv_body<TI, TW, L, T, 1>(g, packB, X, V, LAM, H, part, p0, p1, wsm, 0, wv);
+    else rv_body<TI, TW, L, 0, 0>(g, packB, X, V, LAM, H, part, p0, p1, wsm, 0, 0);
   }
 }
 
@@ -1502,6 +1812,49 @@ hipError_t launch_wgrad(const Geo& g, const float* X, const void* H, const void*
   }
   WG_CASE(1) WG_CASE(2) WG_CASE(4) WG_CASE(7) WG_CASE(8)
 #undef WG_CASE
+  return hipErrorInvalidValue;
+}
+
+// The fused reverse kernel serves fp32 per-step MLPs of depth 1 or 2 whose
+// bias columns fit the tiles (d + 1 <= 16 ti, w + 1 <= 16 tw) and whose
+// transposed weights plus staged rows fit in LDS.
+static bool rv_shape(int ti, int tw) {
+  return (ti == 1 && tw == 2) || (ti == 2 && tw == 2) || (ti == 4 && tw == 4) || (ti == 7 && tw == 7);
+}
+static size_t reverse_lds_bytes(const Geo& g) {
+  return (size_t)g.packb_step * 4 + (size_t)rv_arrays(g.L) * RV_KC * rv_lda(g.ti, g.tw) * 4;
+}
+bool reverse_fused_fits(const Geo& g) {
+  return !g.bf16 && g.kind == 0 && g.lds == 2 && g.L >= 1 && g.L <= 2 && rv_shape(g.ti, g.tw) &&
+         g.d + 1 <= 16 * g.ti && g.w + 1 <= 16 * g.tw && reverse_lds_bytes(g) <= kLdsLimit;
+}
+
+template <int TI, int TW, int L>
+static void rev_inst(const Geo& g, const void* packB, const float* X, const float* V, const float* LAM,
+                     const void* H, float* part, int splits, long long chunk, hipStream_t s) {
+  static bool attr = [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_reverse<TI, TW, L>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+    return true;
+  }();
+  (void)attr;
+  dim3 grid((unsigned)splits, (unsigned)g.N);
+  k_reverse<TI, TW, L><<<grid, RV_THREADS, reverse_lds_bytes(g), s>>>(g, packB, X, V, LAM, H, part, chunk);
+}
+
+hipError_t launch_reverse(const Geo& g, const void* packB, const float* X, const float* V, const float* LAM,
+                          const void* H, float* part, int splits, long long chunk, hipStream_t s) {
+  if (!reverse_fused_fits(g) || splits < 1 || chunk < RV_KC || chunk % RV_KC != 0 ||
+      (long long)splits * chunk < g.M || (long long)(splits - 1) * chunk >= g.M)
+    return hipErrorInvalidValue;
+#define RV_CASE(TI_, TW_)                                                                    \
+  if (g.ti == TI_ && g.tw == TW_) {                                                          \
+    if (g.L == 1) rev_inst<TI_, TW_, 1>(g, packB, X, V, LAM, H, part, splits, chunk, s);      \
+    else rev_inst<TI_, TW_, 2>(g, packB, X, V, LAM, H, part, splits, chunk, s);               \
+    return hipGetLastError();                                                                \
+  }
+  RV_CASE(1, 2) RV_CASE(2, 2) RV_CASE(4, 4) RV_CASE(7, 7)
+#undef RV_CASE
   return hipErrorInvalidValue;
 }
 

@@ -150,8 +150,11 @@ class Plan:
 
 
     # -------------------------------------------------------------- tuning
-    def config(self, shape: int = 0, lds: bool = True, tpw: int = 0, splits: int = 0):
-        B.check(self.lib.fbsde_plan_config(self._h, int(shape), int(bool(lds)), int(tpw), int(splits)))
+    def config(self, shape: int = 0, lds=2, tpw: int = 0, splits: int = 0):
+        """lds: 0 weights read from global memory, 1 staged in LDS, 2 staged in
+        LDS with the fused reverse kernel where it applies (True = 2, False = 0)."""
+        mode = (2 if lds else 0) if isinstance(lds, bool) else int(lds)
+        B.check(self.lib.fbsde_plan_config(self._h, int(shape), mode, int(tpw), int(splits)))
 
     def finite_since_last_check(self) -> bool:
         """Whether every loss and gradient since the last report was finite
@@ -165,7 +168,7 @@ class Plan:
     def get_config(self) -> dict:
         c = (C.c_int32 * 6)()
         B.check(self.lib.fbsde_plan_get_config(self._h, c))
-        return dict(shape=c[0], ti=c[1], tw=c[2], lds=bool(c[3]), tpw=c[4], splits=c[5])
+        return dict(shape=c[0], ti=c[1], tw=c[2], lds=int(c[3]), tpw=c[4], splits=c[5])
 
     def autotune(self, params: torch.Tensor, y0: torch.Tensor, reps: int = 3) -> dict:
         self._check_params(params)

@@ -54,6 +54,21 @@ def test_roofline_uses_the_matrix_peak_of_the_dtype():
     assert r["algorithmic_bytes"] == nbytes
 
 
+def test_roofline_of_the_fused_reverse_kernel():
+    """The fused reverse kernel is timed in the backward slot with no
+    weight-gradient launches: it is reported as "reverse" and carries the
+    flops of both the reverse sweep and the weight gradient."""
+    kern = {"forward": 0.10, "backward": 0.19, "wgrad": 0.0, "reduce": 0.01}
+    dom, r = bench.roofline_entry("fp32", kern)
+    assert dom == "reverse"
+    f = bench.kernel_flops("fp32", 100, 110, 2, 32, 4096)
+    assert f["reverse"] == f["backward"] + f["wgrad"]
+    assert r["achieved"] == pytest.approx(f["reverse"] / 0.19e-3 / 1e12, rel=1e-3)
+    # the separate pair is untouched
+    assert bench.reverse_kernels({"forward": 0.1, "backward": 0.08, "wgrad": 0.12}) == \
+        {"forward": 0.1, "backward": 0.08, "wgrad": 0.12}
+
+
 def test_step_quantiles():
     q = bench._quantiles([1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0, 8.0, 9.0, 10.0])
     assert q["n"] == 10 and q["median"] == 5.5 and q["p10"] == pytest.approx(1.9) and q["p90"] == pytest.approx(9.1)

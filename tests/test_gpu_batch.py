@@ -29,7 +29,7 @@ def test_tile_shapes_lds_and_tpw_are_bitwise_identical(prec):
     ref = _fb(plan, p32, y0)
     ncand = 2
     for shape in range(ncand):
-        for lds in (True, False):
+        for lds in (2, 1, 0):  # fused reverse kernel (where it applies), split kernels, global weights
             for tpw in (0, 1, 3):
                 try:
                     plan.config(shape=shape, lds=lds, tpw=tpw, splits=0)
