@@ -1399,6 +1399,273 @@ __global__ __launch_bounds__(RV_THREADS) void k_reverse(Geo g, const void* __res
   }
 }
 
+// ------------------------------------------- fused reverse kernel, bf16 form
+// The same scheme on the bf16 MFMA (16x16x32, fp32 accumulation) in rounds
+// of 32 paths, the MFMA's K for the weight gradient.  Staged operands are
+// bf16 in two layouts: P rows [path][feature] hold the reverse sweep's B
+// operands (zeta, delta_2..delta_L) and the activations its epilogues read
+// (h_l), F rows [feature][path] hold every weight-gradient operand (zeta,
+// deltas, x, h_l with the bias row of ones), 8 consecutive paths per lane.
+// Rounding points are those of the separate bf16 kernels: zeta and each
+// delta are rounded to bf16 once, x when it is staged; the path-to-slot
+// assignment (lane group g takes paths 8g..8g+7 of a 32-path chunk) is
+// theirs too, so the two forms agree bitwise.  A staging item is a pair of
+// paths times 4 features, consecutive lanes taking consecutive pairs: its F
+// writes are 4-byte words (both paths of one feature) that 16 lanes lay
+// side by side in one row; F rows are 80 bytes apart, so the 16-byte
+// fragment reads of 8 lanes on 8 consecutive rows land in 8 distinct bank
+// groups; P rows are 264 bytes apart (66 words), which spreads the 8-byte
+// runs of 16 lanes on consecutive rows over distinct banks.
+constexpr int RB_KC = 32, RB_LDF = RB_KC + 8;
+__host__ __device__ constexpr int rb_ldp(int ti, int tw) { return 16 * (ti > tw ? ti : tw) + 4; }
+__host__ __device__ constexpr size_t rb_array_bytes(int ti, int tw, int L) {
+  return (size_t)2 * L * RB_KC * rb_ldp(ti, tw) * 2 + (size_t)(2 * L + 2) * 16 * (ti > tw ? ti : tw) * RB_LDF * 2;
+}
+
+__device__ __forceinline__ uint2 bf4_bits(f32x4 v) {
+  return uint2{bf16_bits(v[0]) | (bf16_bits(v[1]) << 16), bf16_bits(v[2]) | (bf16_bits(v[3]) << 16)};
+}
+// four bf16 values of one path into column `col` of F rows row0..row0+3
+__device__ __forceinline__ void rb_fput(uint16_t* F, int row0, int col, uint2 b) {
+  F[(row0 + 0) * RB_LDF + col] = (uint16_t)(b.x & 0xffffu);
+  F[(row0 + 1) * RB_LDF + col] = (uint16_t)(b.x >> 16);
+  F[(row0 + 2) * RB_LDF + col] = (uint16_t)(b.y & 0xffffu);
+  F[(row0 + 3) * RB_LDF + col] = (uint16_t)(b.y >> 16);
+}
+// the same for two paths (columns col, col + 1: one 4-byte word per row; col even)
+__device__ __forceinline__ void rb_fput2(uint16_t* F, int row0, int col, uint2 b0, uint2 b1) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(F + row0 * RB_LDF + col);
+  constexpr int R = RB_LDF / 2;
+  w[0] = (b0.x & 0xffffu) | (b1.x << 16);
+  w[R] = (b0.x >> 16) | (b1.x & 0xffff0000u);
+  w[2 * R] = (b0.y & 0xffffu) | (b1.y << 16);
+  w[3 * R] = (b0.y >> 16) | (b1.y & 0xffff0000u);
+}
+// bias row `cols` of ones and zeros past it, on a run of 4 rows starting at c
+__device__ __forceinline__ uint2 rb_patch(uint2 b, int c, int cols) {
+  uint32_t e[4] = {b.x & 0xffffu, b.x >> 16, b.y & 0xffffu, b.y >> 16};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (c + i == cols) e[i] = 0x3f80u;
+    else if (c + i > cols) e[i] = 0u;
+  }
+  return uint2{e[0] | (e[1] << 16), e[2] | (e[3] << 16)};
+}
+
+// P arrays: 0 zeta, l - 1 delta_l (l = 2..L), L - 1 + l h_l.
+// F arrays: 0 zeta, l delta_l (l = 1..L), L + 1 x (step 0: ones), L + 1 + l h_l.
+template <int TI, int TW, int L, int NR, int NC>
+__device__ __forceinline__ void rb_body(const Geo& g, const void* __restrict__ packB, const float* __restrict__ X,
+                                        const float* __restrict__ V, const float* __restrict__ LAM,
+                                        const uint16_t* __restrict__ H, float* __restrict__ part, long long p0,
+                                        long long p1, unsigned char* wsm, int R0, int C0) {
+  constexpr int TM = TI > TW ? TI : TW;
+  constexpr int LDP = rb_ldp(TI, TW), PSZ = RB_KC * LDP, FSZ = 16 * TM * RB_LDF;
+  static_assert(RB_KC / 2 * 4 * TM <= RV_THREADS, "one staging item per thread and input");
+  const int n = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c16 = lane & 15, grp = lane >> 4;
+  uint16_t* Pa = reinterpret_cast<uint16_t*>(wsm + (size_t)g.packb_step * 2);
+  uint16_t* Fa = Pa + 2 * L * PSZ;
+  const size_t rowM = (size_t)g.M * g.dp, hM = (size_t)g.M * g.wp;
+  const int nmat = n == 0 ? 1 : L + 1;
+
+  // ---- staging items: input a (0 v, 1 x or ones, 1 + l h_l); item tid is
+  // paths 2 pp, 2 pp + 1 of the round times columns c..c+3 (c = -1: none)
+  constexpr int NA = L + 2;
+  int spp[NA], sc[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    const int gq = a == 0 ? g.dp / 4 : (a == 1 ? (n == 0 ? 1 : (g.d + 4) / 4) : (g.w + 4) / 4);
+    const int j = tid / (RB_KC / 2);
+    spp[a] = tid % (RB_KC / 2);
+    sc[a] = j < gq ? 4 * j : -1;
+  }
+  const float* Vn = V + n * rowM;
+  const float* Ln = LAM + (size_t)n * g.M;
+  const float* Xn = X + n * rowM;
+  f32x4 rv[2], rx[2];
+  uint2 rh[L][2];
+  float rl[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    rv[e] = zero4(); rx[e] = zero4(); rl[e] = 0.f;
+#pragma unroll
+    for (int l = 0; l < L; ++l) rh[l][e] = uint2{0u, 0u};
+  }
+  // raw loads, unconditional (rows and columns clamped into their buffers)
+  auto fetch = [&](long long pc) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const size_t p = (size_t)min(pc + 2 * spp[0] + e, p1 - 1);
+      rv[e] = ld4(Vn + p * g.dp + max(sc[0], 0));
+      rl[e] = Ln[p];
+      if (n > 0) {
+        rx[e] = ld4(Xn + p * g.dp + min(max(sc[1], 0), g.dp - 4));
+#pragma unroll
+        for (int l = 0; l < L; ++l)
+          rh[l][e] = *reinterpret_cast<const uint2*>(H + ((size_t)n * L + l) * hM + p * g.wp +
+                                                     min(max(sc[2 + l], 0), g.wp - 4));
+      }
+    }
+  };
+  // validity, rounding, the bias row and the padding; P and F writes
+  auto put = [&](long long pc) {
+    const int pp = spp[0];
+    const bool ok0 = pc + 2 * pp < p1, ok1 = pc + 2 * pp + 1 < p1;
+    {  // zeta = bf16(lambda v)
+      const int c = sc[0];
+      if (c >= 0) {
+        const uint2 b0 = ok0 ? bf4_bits(rl[0] * rv[0]) : uint2{0u, 0u};
+        const uint2 b1 = ok1 ? bf4_bits(rl[1] * rv[1]) : uint2{0u, 0u};
+        *reinterpret_cast<uint2*>(Pa + (2 * pp) * LDP + c) = b0;
+        *reinterpret_cast<uint2*>(Pa + (2 * pp + 1) * LDP + c) = b1;
+        rb_fput2(Fa, c, 2 * pp, b0, b1);
+      }
+    }
+    {  // x in bf16 (step 0: the column of ones)
+      const int c = sc[1];
+      if (c >= 0) {
+        const int cols = n == 0 ? 0 : g.d;
+        const bool have = n > 0 && c < g.dp;
+        const uint2 b0 = ok0 ? rb_patch(have ? bf4_bits(rx[0]) : uint2{0u, 0u}, c, cols) : uint2{0u, 0u};
+        const uint2 b1 = ok1 ? rb_patch(have ? bf4_bits(rx[1]) : uint2{0u, 0u}, c, cols) : uint2{0u, 0u};
+        rb_fput2(Fa + (L + 1) * FSZ, c, 2 * pp, b0, b1);
+      }
+    }
+    if (n > 0) {
+#pragma unroll
+      for (int l = 0; l < L; ++l) {  // h_{l+1}: P raw, F with the bias row
+        const int c = sc[2 + l];
+        if (c >= 0) {
+          const uint2 b0 = ok0 ? rh[l][0] : uint2{0u, 0u}, b1 = ok1 ? rh[l][1] : uint2{0u, 0u};
+          *reinterpret_cast<uint2*>(Pa + (L + l) * PSZ + (2 * pp) * LDP + c) = b0;
+          *reinterpret_cast<uint2*>(Pa + (L + l) * PSZ + (2 * pp + 1) * LDP + c) = b1;
+          rb_fput2(Fa + (L + 2 + l) * FSZ, c, 2 * pp, ok0 ? rb_patch(b0, c, g.w) : b0,
+                   ok1 ? rb_patch(b1, c, g.w) : b1);
+        }
+      }
+    }
+  };
+
+  f32x4 acc[L + 1][NRA_(NR)][NCA_(NC)];
+#pragma unroll
+  for (int m = 0; m < L + 1; ++m)
+#pragma unroll
+    for (int i = 0; i < NRA_(NR); ++i)
+#pragma unroll
+      for (int j = 0; j < NCA_(NC); ++j) acc[m][i][j] = zero4();
+
+  fetch(p0);
+  if (n > 0) copy_to_lds(wsm, reinterpret_cast<const char*>(packB) + (size_t)(n - 1) * g.packb_step * 2,
+                         (size_t)g.packb_step * 2);
+  // rows and columns no round writes stay zero
+  for (int e = tid; e < (int)(rb_array_bytes(TI, TW, L) / 16); e += RV_THREADS)
+    reinterpret_cast<uint4*>(Pa)[e] = uint4{0u, 0u, 0u, 0u};
+  const bf16x8* W8 = reinterpret_cast<const bf16x8*>(wsm);
+  for (long long pc = p0; pc < p1; pc += RB_KC) {
+    __syncthreads();  // weights and zero fill (first round), or the previous round's reads, are done
+    put(pc);
+    __syncthreads();
+    if (pc + RB_KC < p1) fetch(pc + RB_KC);  // in flight during this round's MFMAs
+    if (n > 0) {
+      // delta_L = bf16((W_o^T zeta) (1 - h_L^2)), delta_l = bf16((W_{l+1}^T delta_{l+1}) (1 - h_l^2))
+#pragma unroll
+      for (int l = L; l >= 1; --l) {
+        if (wv < TW) {
+          const int kt = l == L ? TI : TW;
+          const bf16x8* A = W8 + (l == L ? 0 : 32 * (TW * TI + (l - 1) * TW * TW));
+          const uint16_t* in = Pa + (l == L ? 0 : l) * PSZ;
+          f32x4 a4[2] = {zero4(), zero4()};
+#pragma unroll
+          for (int kb = 0; kb < (l == L ? TI : TW) / 2; ++kb) {
+            const bf16x8 a = A[(wv * (kt / 2) + kb) * 64 + lane];
+#pragma unroll
+            for (int pt = 0; pt < 2; ++pt) {
+              const uint16_t* r = in + (16 * pt + c16) * LDP + 32 * kb + 4 * grp;
+              const uint2 lo = *reinterpret_cast<const uint2*>(r), hi = *reinterpret_cast<const uint2*>(r + 16);
+              a4[pt] = mfma_bf16(a, __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y}), a4[pt]);
+            }
+          }
+#pragma unroll
+          for (int pt = 0; pt < 2; ++pt) {
+            const int row = 16 * pt + c16, col = 16 * wv + 4 * grp;
+            const uint2 hb = *reinterpret_cast<const uint2*>(Pa + (L - 1 + l) * PSZ + row * LDP + col);
+            const float h[4] = {__uint_as_float(hb.x << 16), __uint_as_float(hb.x & 0xffff0000u),
+                                __uint_as_float(hb.y << 16), __uint_as_float(hb.y & 0xffff0000u)};
+            f32x4 dl;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dl[r] = a4[pt][r] * (1.f - h[r] * h[r]);
+            const uint2 db = bf4_bits(dl);
+            if (l >= 2) *reinterpret_cast<uint2*>(Pa + (l - 1) * PSZ + row * LDP + col) = db;
+            rb_fput(Fa + l * FSZ, col, row, db);
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if constexpr (NR > 0 && NC > 0) {
+      // weight-gradient tiles, K = the round's 32 paths (lane group g: paths 8g..8g+7)
+#pragma unroll
+      for (int m = 0; m < L + 1; ++m) {
+        if (m >= nmat) break;
+        const uint16_t* As = Fa + (m == L || n == 0 ? 0 : m + 1) * FSZ;
+        const uint16_t* Bs = Fa + (m == 0 ? L + 1 : L + 1 + m) * FSZ;
+        bf16x8 a[NR], b[NC];
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+          a[i] = *reinterpret_cast<const bf16x8*>(As + (16 * (R0 + i) + c16) * RB_LDF + 8 * grp);
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+          b[j] = *reinterpret_cast<const bf16x8*>(Bs + (16 * (C0 + j) + c16) * RB_LDF + 8 * grp);
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+#pragma unroll
+          for (int j = 0; j < NC; ++j) acc[m][i][j] = mfma_bf16(a[i], b[j], acc[m][i][j]);
+      }
+    }
+  }
+  // ---- this split's partial sums, scattered to the flat layout
+  if constexpr (NR > 0 && NC > 0) {
+    float* out = part + (size_t)blockIdx.x * g.pstride;
+#pragma unroll
+    for (int m = 0; m < L + 1; ++m) {
+      if (m >= nmat) break;
+      const RvMat T = rv_mat(g, n, m);
+#pragma unroll
+      for (int i = 0; i < NR; ++i)
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (R0 + i) + 4 * grp + r, c = 16 * (C0 + j) + c16;
+            if (row < T.rows && c <= T.cols) {
+              const long long off = (c < T.cols) ? T.base + (long long)row * T.cols + c
+                                                 : T.base + (long long)T.rows * T.cols + row;
+              out[off] = acc[m][i][j][r];
+            }
+          }
+    }
+  }
+}
+
+template <int TI, int TW, int L>
+__global__ __launch_bounds__(RV_THREADS) void k_reverse_bf(Geo g, const void* __restrict__ packB,
+                                                           const float* __restrict__ X, const float* __restrict__ V,
+                                                           const float* __restrict__ LAM, const void* __restrict__ Hv,
+                                                           float* __restrict__ part, long long chunk) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
+  const long long p0 = (long long)blockIdx.x * chunk;
+  const long long p1 = min((long long)g.M, p0 + chunk);
+  const uint16_t* H = reinterpret_cast<const uint16_t*>(Hv);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int T = TI > TW ? TI : TW;
+  static_assert(T <= RV_WAVES, "one tile column per wave");
+  if (wv < T) rb_body<TI, TW, L, T, 1>(g, packB, X, V, LAM, H, part, p0, p1, wsm, 0, wv);
+  else rb_body<TI, TW, L, 0, 0>(g, packB, X, V, LAM, H, part, p0, p1, wsm, 0, 0);
+}
+
 // ------------------------------------------------------------ reduce kernel
 // grad[e] = sum over splits k (in order) of part[k * stride + e]; 4 elements
 // per thread when grad is 16-byte aligned (the partial copies always are).
@@ -1815,45 +2082,55 @@ hipError_t launch_wgrad(const Geo& g, const float* X, const void* H, const void*
   return hipErrorInvalidValue;
 }
 
-// The fused reverse kernel serves fp32 per-step MLPs of depth 1 or 2 whose
-// bias columns fit the tiles (d + 1 <= 16 ti, w + 1 <= 16 tw) and whose
-// transposed weights plus staged rows fit in LDS.
-static bool rv_shape(int ti, int tw) {
+// The fused reverse kernels serve per-step MLPs of depth 1 or 2 whose bias
+// columns fit the tiles (d + 1 <= 16 ti, w + 1 <= 16 tw) and whose
+// transposed weights plus staged rows fit in LDS: fp32 tile shapes (1, 2),
+// (2, 2), (4, 4), (7, 7); bf16 shapes (2, 2), (4, 4), (6, 6), (8, 8).
+static bool rv_shape(int bf, int ti, int tw) {
+  if (bf) return ti == tw && (ti == 2 || ti == 4 || ti == 6 || ti == 8);
   return (ti == 1 && tw == 2) || (ti == 2 && tw == 2) || (ti == 4 && tw == 4) || (ti == 7 && tw == 7);
 }
 static size_t reverse_lds_bytes(const Geo& g) {
+  if (g.bf16) return (size_t)g.packb_step * 2 + rb_array_bytes(g.ti, g.tw, g.L);
   return (size_t)g.packb_step * 4 + (size_t)rv_arrays(g.L) * RV_KC * rv_lda(g.ti, g.tw) * 4;
 }
 bool reverse_fused_fits(const Geo& g) {
-  return !g.bf16 && g.kind == 0 && g.lds == 2 && g.L >= 1 && g.L <= 2 && rv_shape(g.ti, g.tw) &&
+  return g.kind == 0 && g.lds == 2 && g.L >= 1 && g.L <= 2 && rv_shape(g.bf16, g.ti, g.tw) &&
          g.d + 1 <= 16 * g.ti && g.w + 1 <= 16 * g.tw && reverse_lds_bytes(g) <= kLdsLimit;
 }
 
-template <int TI, int TW, int L>
+template <bool BF, int TI, int TW, int L>
 static void rev_inst(const Geo& g, const void* packB, const float* X, const float* V, const float* LAM,
                      const void* H, float* part, int splits, long long chunk, hipStream_t s) {
-  static bool attr = [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_reverse<TI, TW, L>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+  const void* fn;
+  if constexpr (BF) fn = reinterpret_cast<const void*>(k_reverse_bf<TI, TW, L>);
+  else fn = reinterpret_cast<const void*>(k_reverse<TI, TW, L>);
+  static bool attr = [fn] {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
     return true;
   }();
   (void)attr;
   dim3 grid((unsigned)splits, (unsigned)g.N);
-  k_reverse<TI, TW, L><<<grid, RV_THREADS, reverse_lds_bytes(g), s>>>(g, packB, X, V, LAM, H, part, chunk);
+  if constexpr (BF)
+    k_reverse_bf<TI, TW, L><<<grid, RV_THREADS, reverse_lds_bytes(g), s>>>(g, packB, X, V, LAM, H, part, chunk);
+  else
+    k_reverse<TI, TW, L><<<grid, RV_THREADS, reverse_lds_bytes(g), s>>>(g, packB, X, V, LAM, H, part, chunk);
 }
 
 hipError_t launch_reverse(const Geo& g, const void* packB, const float* X, const float* V, const float* LAM,
                           const void* H, float* part, int splits, long long chunk, hipStream_t s) {
-  if (!reverse_fused_fits(g) || splits < 1 || chunk < RV_KC || chunk % RV_KC != 0 ||
+  const long long kc = g.bf16 ? RB_KC : RV_KC;
+  if (!reverse_fused_fits(g) || splits < 1 || chunk < kc || chunk % kc != 0 ||
       (long long)splits * chunk < g.M || (long long)(splits - 1) * chunk >= g.M)
     return hipErrorInvalidValue;
-#define RV_CASE(TI_, TW_)                                                                    \
-  if (g.ti == TI_ && g.tw == TW_) {                                                          \
-    if (g.L == 1) rev_inst<TI_, TW_, 1>(g, packB, X, V, LAM, H, part, splits, chunk, s);      \
-    else rev_inst<TI_, TW_, 2>(g, packB, X, V, LAM, H, part, splits, chunk, s);               \
-    return hipGetLastError();                                                                \
+#define RV_CASE(BF_, TI_, TW_)                                                                    \
+  if (g.bf16 == BF_ && g.ti == TI_ && g.tw == TW_) {                                              \
+    if (g.L == 1) rev_inst<BF_, TI_, TW_, 1>(g, packB, X, V, LAM, H, part, splits, chunk, s);      \
+    else rev_inst<BF_, TI_, TW_, 2>(g, packB, X, V, LAM, H, part, splits, chunk, s);               \
+    return hipGetLastError();                                                                     \
   }
-  RV_CASE(1, 2) RV_CASE(2, 2) RV_CASE(4, 4) RV_CASE(7, 7)
+  RV_CASE(0, 1, 2) RV_CASE(0, 2, 2) RV_CASE(0, 4, 4) RV_CASE(0, 7, 7)
+  RV_CASE(1, 2, 2) RV_CASE(1, 4, 4) RV_CASE(1, 6, 6) RV_CASE(1, 8, 8)
 #undef RV_CASE
   return hipErrorInvalidValue;
 }

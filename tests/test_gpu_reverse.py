@@ -25,18 +25,27 @@ def _run(plan, p32, y0, seed=5, it=2):
     return out, prof["wgrad"][1]
 
 
-# (problem, d, width, depth, N, M): every instantiated tile shape (fp32 (1, 2),
-# (2, 2), (4, 4), (7, 7)) at depth 1 and 2, ragged path counts (partial last
-# 16-path chunk, uneven splits)
+# (problem, d, width, depth, N, M, precision): every instantiated tile shape
+# (fp32 (1, 2), (2, 2), (4, 4), (7, 7); bf16 (2, 2), (4, 4), (6, 6), (8, 8)) at
+# depth 1 and 2, the bias column in the last tile column, ragged path counts
+# (partial last chunk, uneven splits)
 CASES = [
-    ("ac", 10, 20, 2, 5, 70),
-    ("bsb", 12, 30, 1, 4, 33),
-    ("bsb", 20, 24, 2, 6, 200),
-    ("hjb", 31, 31, 1, 3, 517),
-    ("hjb", 40, 50, 2, 6, 1100),
-    ("bsb", 63, 63, 1, 4, 300),
-    ("bsb", 100, 110, 2, 4, 1000),
-    ("ac", 111, 111, 1, 3, 1030),
+    ("ac", 10, 20, 2, 5, 70, "fp32"),
+    ("bsb", 12, 30, 1, 4, 33, "fp32"),
+    ("bsb", 20, 24, 2, 6, 200, "fp32"),
+    ("hjb", 31, 31, 1, 3, 517, "fp32"),
+    ("hjb", 40, 50, 2, 6, 1100, "fp32"),
+    ("bsb", 63, 63, 1, 4, 300, "fp32"),
+    ("bsb", 100, 110, 2, 4, 1000, "fp32"),
+    ("ac", 111, 111, 1, 3, 1030, "fp32"),
+    ("ac", 10, 20, 2, 5, 70, "bf16"),
+    ("bsb", 31, 17, 1, 4, 45, "bf16"),
+    ("hjb", 40, 50, 2, 6, 1100, "bf16"),
+    ("bsb", 63, 60, 1, 3, 300, "bf16"),
+    ("hjb", 90, 95, 2, 4, 513, "bf16"),
+    ("ac", 95, 80, 1, 3, 200, "bf16"),
+    ("bsb", 100, 110, 2, 4, 1000, "bf16"),
+    ("hjb", 127, 127, 1, 3, 777, "bf16"),
 ]
 
 
@@ -44,13 +53,13 @@ def _problem(name, d):
     return {"bsb": I.bsb, "hjb": I.hjb, "ac": I.allen_cahn}[name](d)
 
 
-@pytest.mark.parametrize("name,d,w,L,N,M", CASES)
-def test_fused_reverse_matches_split_kernels_bitwise(name, d, w, L, N, M):
+@pytest.mark.parametrize("name,d,w,L,N,M,prec", CASES)
+def test_fused_reverse_matches_split_kernels_bitwise(name, d, w, L, N, M, prec):
     prob = _problem(name, d)
-    net = dict(width=w, depth=L, prec="fp32")
+    net = dict(width=w, depth=L, prec=prec)
     p32, _, y0 = inputs(prob, net, N, seed=3, y0=1.5)
     plan = Plan(prob, net, N, M)
-    print(f"{name} d={d} w={w} L={L} N={N} M={M} config {plan.get_config()}", flush=True)
+    print(f"{name} d={d} w={w} L={L} N={N} M={M} {prec} config {plan.get_config()}", flush=True)
     fused, nw = _run(plan, p32, y0)
     assert nw == 0, "the default configuration should take the fused reverse kernel"
     plan.config(lds=1)
@@ -61,12 +70,13 @@ def test_fused_reverse_matches_split_kernels_bitwise(name, d, w, L, N, M):
     assert np.all(np.isfinite(fused[1]))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("splits", [1, 3, 32])
-def test_fused_reverse_split_counts(splits):
+def test_fused_reverse_split_counts(splits, prec):
     """Every split count the tuner may pick: same partial-buffer layout as the
     weight-gradient kernel, so the reduction sees identical partials."""
     prob = I.bsb(100)
-    net = dict(width=110, depth=2, prec="fp32")
+    net = dict(width=110, depth=2, prec=prec)
     p32, _, y0 = inputs(prob, net, 3, seed=1, y0=70.0)
     plan = Plan(prob, net, 3, 4096)
     plan.config(lds=2, splits=splits)
@@ -94,10 +104,12 @@ def test_fused_reverse_against_oracle():
     check_grad(prob, net, N, gg, ref["grad"], 1e-4)
 
 
-@pytest.mark.parametrize("L,prec,d,w", [(3, "fp32", 20, 30), (2, "bf16", 20, 30), (2, "fp32", 112, 60)])
+@pytest.mark.parametrize("L,prec,d,w", [(3, "fp32", 20, 30), (3, "bf16", 20, 30), (2, "fp32", 112, 60),
+                                        (2, "bf16", 128, 30), (2, "bf16", 140, 150)])
 def test_configurations_outside_the_fused_kernel_use_the_split_pair(L, prec, d, w):
-    """Depth 3, bf16, and a bias column past the tiles (d = 112 with 7 tiles)
-    keep the separate kernels even in LDS mode 2."""
+    """Depth 3, a bias column past the tiles (d = 112 on 7 fp32 tiles, d = 128
+    on 8 bf16 tiles) and shapes beyond 8 tiles keep the separate kernels even
+    in LDS mode 2."""
     prob = I.bsb(d)
     net = dict(width=w, depth=L, prec=prec)
     p32, _, y0 = inputs(prob, net, 3, seed=2)
