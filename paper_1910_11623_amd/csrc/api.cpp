@@ -148,8 +148,18 @@ void make_layout(fbsde_plan* P) {
     w.RVB = take(rows * (size_t)R.dq * 2 + slack);
   }
   // weight-gradient splits over paths (per-step MLP) or over chunk rows
-  // (residual network): preset by the caller, 0 = automatic
-  int splits = w.splits > 0 ? w.splits : (g.kind == 0 ? (int)((M + 511) / 512) : 16);
+  // (residual network): preset by the caller, 0 = automatic.  The per-step
+  // MLP takes one split per 512 paths, and at least enough that the
+  // (split, step) workgroups of the fused reverse kernel cover the CUs.
+  int splits = w.splits;
+  if (splits <= 0) {
+    if (g.kind == 0) {
+      const long long fill = (fbsde::device_cus() + (long long)N - 1) / (long long)N;
+      splits = (int)std::max<long long>((long long)((M + 511) / 512), std::min<long long>(fill, (long long)M / 32));
+    } else {
+      splits = 16;
+    }
+  }
   if (w.splits <= 0)
     if (const char* e = getenv("FBSDE_WGRAD_SPLITS")) splits = atoi(e);
   if (splits < 1) splits = 1;
@@ -190,17 +200,20 @@ bool rn_offsets_fit(int64_t M, int64_t chunk_steps, int64_t width, int64_t d) {
   return (rows + 32) * wide < 0x7fffffffLL && (ldt + 32) * wide < 0x7fffffffLL;
 }
 
-// Largest workspace over the candidate tile shapes and the largest split count
-// the tuner may pick, so that any tuned configuration fits the caller's buffer.
+// Largest workspace over the candidate tile shapes, at the largest split count
+// the tuner may pick and at the automatic one, so that any tuned
+// configuration fits the caller's buffer.
 size_t reserve_bytes(fbsde_plan* P) {
   const Geo keep_g = P->geo;
   const WsLayout keep_w = P->ws;
   size_t mx = 0;
   for (int c = 0; c < P->ncand; ++c) {
     if (P->geo.kind == 0) set_tiles(P->geo, P->cand_ti[c], P->cand_tw[c]);
-    P->ws.splits = kMaxTuneSplits;
-    make_layout(P);
-    mx = P->ws.total > mx ? P->ws.total : mx;
+    for (int sp : {kMaxTuneSplits, 0}) {  // the tuner's largest split count and the automatic one
+      P->ws.splits = sp;
+      make_layout(P);
+      mx = P->ws.total > mx ? P->ws.total : mx;
+    }
   }
   P->geo = keep_g;
   P->ws = keep_w;

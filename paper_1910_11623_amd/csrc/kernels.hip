@@ -1917,6 +1917,8 @@ static int num_cus() {
   return cus;
 }
 
+int device_cus() { return num_cus(); }
+
 static const size_t kLdsLimit = 160 * 1024;
 
 bool lds_fits(const Geo& g) {
