@@ -235,11 +235,17 @@ fbsde_status fbsde_profile_read(fbsde_plan *plan, double *ms_host, int64_t *coun
  * A plan keeps up to two candidate register-tile shapes (the cheapest
  * instantiated kernels that cover d and width); fbsde_workspace_size covers
  * every configuration below, so tuning never needs a larger workspace.
- * fbsde_plan_config selects: shape index, LDS staging of the step weights
- * (lds != 0), 16-path tiles per wave of the LDS kernels (tpw, 0 = automatic),
- * and the path splits of the weight-gradient reduction (0 = automatic, <= 32).
- * Results are identical across shapes, LDS modes and tpw; the split count
- * changes the fp32 summation order of the weight gradient only. */
+ * fbsde_plan_config selects: shape index; the LDS mode (lds = 0: step weights
+ * read from global memory; 1: staged in LDS; 2, the default: staged, and the
+ * reverse sweep and weight gradient of a step run as one kernel that keeps
+ * the deltas in LDS, where it applies (per-step MLP of depth 1 or 2 whose
+ * d + 1 and width + 1 fit the tile shape: fp32 shapes 1x2, 2x2, 4x4, 7x7,
+ * bf16 2x2, 4x4, 6x6, 8x8); other values are taken as 0 or 2); 16-path tiles
+ * per wave of the LDS kernels (tpw, 0 = automatic); and the path splits of
+ * the weight-gradient reduction (0 = automatic: one per 512 paths and at
+ * least CUs / N, at most 64; explicit values <= 32).  Results are identical
+ * across shapes, LDS modes and tpw; the split count changes the fp32
+ * summation order of the weight gradient only. */
 fbsde_status fbsde_plan_config(fbsde_plan *plan, int32_t shape, int32_t lds, int32_t tpw, int32_t splits);
 /* Reports (FBSDE_ERR_NONFINITE) and clears the plan's non-finite flag
  * without launching anything; synchronise the streams that ran the plan's
