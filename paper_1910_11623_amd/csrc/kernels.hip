@@ -541,6 +541,164 @@ __global__ __launch_bounds__(LDSW ? 64 * fwd_waves(TI, TW) : 256) void k_forward
   }
 }
 
+// ------------------------------------------------ layer-streamed forward
+// For step networks whose packed weights do not fit LDS at once (fp32 8 x 8,
+// bf16 12 x 12 .. 16 x 16 tiles): the workgroup stages one layer's fragments
+// at a time and runs that layer over all of its tiles, the tanh activations
+// going through H (which the reverse sweep reads anyway) from one layer to
+// the next.  Each step's weights cross from L2 into LDS once per workgroup,
+// instead of once per 16-path tile from L2 into registers.  Layer products,
+// rounding and epilogues are those of k_forward, so both give bitwise equal
+// results.
+constexpr int LS_WAVES = 8;
+
+template <bool BF>
+__device__ __forceinline__ void ls_stage(unsigned char* lds, const void* src, size_t bytes) {
+  __syncthreads();  // every wave is done with the previous layer's fragments
+  copy_to_lds(lds, src, bytes);
+  __syncthreads();
+}
+
+template <bool BF, int TI, int TW>
+__global__ __launch_bounds__(64 * LS_WAVES) void k_forward_ls(Geo g, const float* __restrict__ params,
+                                                              const void* __restrict__ packF,
+                                                              const float* __restrict__ pbias,
+                                                              const float* __restrict__ X, float* __restrict__ V,
+                                                              float* __restrict__ C, void* __restrict__ H, int tpw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
+  const int n = blockIdx.y;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = LS_WAVES;
+  const int col = lane & 15, grp = lane >> 4;
+  const size_t rowM = (size_t)g.M * g.dp, hM = (size_t)g.M * g.wp;
+  const size_t esz = BF ? 2 : 4;
+  const float* Xn = X + n * rowM;
+  float* Vn = V + n * rowM;
+  const TileRange tr = tile_range(g.M);
+  // c_n = Z.s + dt * (Z-part of phi), v_n = s + dt * phi_z (as k_forward)
+  auto epilogue = [&](int p, bool valid, const f32x4 (&Z)[TI]) {
+    float cz = 0.f, cx = 0.f;
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      if (valid && c0 < g.dp) {
+        float* vp = Vn + (size_t)p * g.dp + c0;
+        const f32x4 s = ld4(vp);
+        f32x4 v = s;
+        if (g.drv == DRV_BSB) {
+          const f32x4 x = ld4(Xn + (size_t)p * g.dp + c0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            cz += Z[t][r] * s[r];
+            cx += Z[t][r] * x[r];
+            v[r] = s[r] - g.drv_p0 * g.dt * x[r];
+          }
+        } else if (g.drv == DRV_HJB) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            cz += Z[t][r] * s[r];
+            cx += Z[t][r] * Z[t][r];
+            v[r] = s[r] + 2.f * g.drv_p0 * g.dt * Z[t][r];
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cz += Z[t][r] * s[r];
+        }
+        st4(vp, v);
+      }
+    }
+    float c = cz;
+    if (g.drv == DRV_BSB) c -= g.dt * g.drv_p0 * cx;
+    else if (g.drv == DRV_HJB) c += g.dt * g.drv_p0 * cx;
+    c += __shfl_xor(c, 16);
+    c += __shfl_xor(c, 32);
+    if (valid && grp == 0) C[(size_t)n * g.M + p] = c;
+  };
+  if (n == 0) {  // Z_0 = z0
+    for (int it = 0; it < tpw; ++it) {
+      const int tile = tr.t0 + it * nwv + wv;
+      if (tile >= tr.t1) break;
+      const int p = tile * 16 + col;
+      f32x4 Z[TI];
+#pragma unroll
+      for (int t = 0; t < TI; ++t) Z[t] = bias4(params, 16 * t + 4 * grp, g.d);
+      epilogue(p, p < g.M, Z);
+    }
+    return;
+  }
+  const char* F = reinterpret_cast<const char*>(packF) + (size_t)(n - 1) * g.packf_step * esz;
+  const float* bp = pbias + (size_t)(n - 1) * g.pbias_step;
+  // layer 1: x -> h_1
+  ls_stage<BF>(wsm, F, 256ULL * TW * TI * esz);
+  for (int it = 0; it < tpw; ++it) {
+    const int tile = tr.t0 + it * nwv + wv;
+    if (tile >= tr.t1) break;
+    const int p = tile * 16 + col;
+    const bool valid = p < g.M;
+    f32x4 xv[TI], acc[TW];
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      xv[t] = (valid && c0 < g.dp) ? ld4(Xn + (size_t)p * g.dp + c0) : zero4();
+    }
+    layer_mm<BF, TW, TI>(acc, xv, wsm, lane);
+#pragma unroll
+    for (int T = 0; T < TW; ++T) {
+      const f32x4 bb = ld4(bp + 16 * T + 4 * grp);
+      f32x4 h;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[r] = fast_tanh(acc[T][r] + bb[r]);
+      h = round4(h, BF);
+      if (valid) st_act(H, ((size_t)n * g.L) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h, BF);
+    }
+  }
+  size_t foff = 256ULL * TW * TI;
+  // hidden layers l = 2..L: h_{l-1} -> h_l (h_{l-1} read back from H)
+  for (int l = 2; l <= g.L; ++l) {
+    ls_stage<BF>(wsm, F + foff * esz, 256ULL * TW * TW * esz);
+    const float* bl = bp + (size_t)(l - 1) * 16 * TW;
+    for (int it = 0; it < tpw; ++it) {
+      const int tile = tr.t0 + it * nwv + wv;
+      if (tile >= tr.t1) break;
+      const int p = tile * 16 + col;
+      const bool valid = p < g.M;
+      f32x4 hin[TW], acc[TW];
+#pragma unroll
+      for (int T = 0; T < TW; ++T)
+        hin[T] = valid ? ld_act(H, ((size_t)n * g.L + (l - 2)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, BF)
+                       : zero4();
+      layer_mm<BF, TW, TW>(acc, hin, wsm, lane);
+#pragma unroll
+      for (int T = 0; T < TW; ++T) {
+        const f32x4 bb = ld4(bl + 16 * T + 4 * grp);
+        f32x4 h;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[r] = fast_tanh(acc[T][r] + bb[r]);
+        h = round4(h, BF);
+        if (valid) st_act(H, ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h, BF);
+      }
+    }
+    foff += 256ULL * TW * TW;
+  }
+  // output layer: Z = W_o h_L + b_o, then the c_n / v_n epilogue
+  ls_stage<BF>(wsm, F + foff * esz, 256ULL * TI * TW * esz);
+  const float* bo = bp + (size_t)g.L * 16 * TW;
+  for (int it = 0; it < tpw; ++it) {
+    const int tile = tr.t0 + it * nwv + wv;
+    if (tile >= tr.t1) break;
+    const int p = tile * 16 + col;
+    const bool valid = p < g.M;
+    f32x4 hin[TW], Z[TI];
+#pragma unroll
+    for (int T = 0; T < TW; ++T)
+      hin[T] = valid ? ld_act(H, ((size_t)n * g.L + (g.L - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, BF)
+                     : zero4();
+    layer_mm<BF, TI, TW>(Z, hin, wsm, lane);
+#pragma unroll
+    for (int t = 0; t < TI; ++t) Z[t] += ld4(bo + 16 * t + 4 * grp);
+    epilogue(p, valid, Z);
+  }
+}
+
 // -------------------------------------------------------------- scan kernel
 __device__ __forceinline__ float phi_y(const Geo& g, float y) {
   switch (g.drv) {
@@ -790,6 +948,85 @@ __global__ __launch_bounds__(LDSW ? 64 * bwd_waves(TI, TW) : 256) void k_backwar
     layer_mm<BF, TW, TW>(acc, dl, pkl + (size_t)(l - 1) * 256ULL * TW * TW * esz, lane);
     epilogue(l);
   }
+  }
+}
+
+// ----------------------------------------------- layer-streamed reverse sweep
+// The reverse sweep for step networks whose transposed weights do not fit
+// LDS at once: one layer's fragments at a time, run over all of the
+// workgroup's tiles; delta_{l+1} comes back from DH (which the weight
+// gradient reads anyway).  Products, rounding and epilogues are those of
+// k_backward, so both give bitwise equal results.
+template <bool BF, int TI, int TW>
+__global__ __launch_bounds__(64 * LS_WAVES) void k_backward_ls(Geo g, const void* __restrict__ packB,
+                                                               const float* __restrict__ V,
+                                                               const float* __restrict__ LAM,
+                                                               const void* __restrict__ H, void* __restrict__ DZ,
+                                                               void* __restrict__ DH, int tpw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
+  const int n = blockIdx.y;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = LS_WAVES;
+  const int col = lane & 15, grp = lane >> 4;
+  const size_t rowM = (size_t)g.M * g.dp, hM = (size_t)g.M * g.wp;
+  const size_t esz = BF ? 2 : 4;
+  const float* Vn = V + n * rowM;
+  const TileRange tr = tile_range(g.M);
+  const char* Bk = reinterpret_cast<const char*>(packB) + (size_t)(n > 0 ? n - 1 : 0) * g.packb_step * esz;
+  // layer L: zeta = lambda_{n+1} v_n (stored in DZ), delta_L = (W_o^T zeta) (1 - h_L^2)
+  if (n > 0) ls_stage<BF>(wsm, Bk, 256ULL * TW * TI * esz);
+  for (int it = 0; it < tpw; ++it) {
+    const int tile = tr.t0 + it * nwv + wv;
+    if (tile >= tr.t1) break;
+    const int p = tile * 16 + col;
+    const bool valid = p < g.M;
+    const float lam = valid ? LAM[(size_t)n * g.M + p] : 0.f;
+    f32x4 zeta[TI];
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c0 = 16 * t + 4 * grp;
+      const f32x4 v = (valid && c0 < g.dp) ? ld4(Vn + (size_t)p * g.dp + c0) : zero4();
+      zeta[t] = round4(lam * v, BF);
+      if (valid) st_act(DZ, ((size_t)n * g.M + p) * g.zp + 16 * t + 4 * grp, zeta[t], BF);
+    }
+    if (n == 0) continue;
+    f32x4 acc[TW];
+    layer_mm<BF, TW, TI>(acc, zeta, wsm, lane);
+#pragma unroll
+    for (int T = 0; T < TW; ++T) {
+      const size_t idx = ((size_t)n * g.L + (g.L - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
+      const f32x4 h = valid ? ld_act(H, idx, BF) : zero4();
+      f32x4 dl;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dl[r] = acc[T][r] * (1.f - h[r] * h[r]);
+      dl = round4(dl, BF);
+      if (valid) st_act(DH, idx, dl, BF);
+    }
+  }
+  if (n == 0) return;
+  // delta_l = (W_{l+1}^T delta_{l+1}) (1 - h_l^2), l = L-1..1
+  for (int l = g.L - 1; l >= 1; --l) {
+    ls_stage<BF>(wsm, Bk + (256ULL * TW * TI + (size_t)(l - 1) * 256ULL * TW * TW) * esz, 256ULL * TW * TW * esz);
+    for (int it = 0; it < tpw; ++it) {
+      const int tile = tr.t0 + it * nwv + wv;
+      if (tile >= tr.t1) break;
+      const int p = tile * 16 + col;
+      const bool valid = p < g.M;
+      f32x4 din[TW], acc[TW];
+#pragma unroll
+      for (int T = 0; T < TW; ++T)
+        din[T] = valid ? ld_act(DH, ((size_t)n * g.L + l) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, BF) : zero4();
+      layer_mm<BF, TW, TW>(acc, din, wsm, lane);
+#pragma unroll
+      for (int T = 0; T < TW; ++T) {
+        const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
+        const f32x4 h = valid ? ld_act(H, idx, BF) : zero4();
+        f32x4 dl;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dl[r] = acc[T][r] * (1.f - h[r] * h[r]);
+        dl = round4(dl, BF);
+        if (valid) st_act(DH, idx, dl, BF);
+      }
+    }
   }
 }
 
@@ -1927,6 +2164,11 @@ bool lds_fits(const Geo& g) {
          (size_t)g.packb_step * esz <= kLdsLimit;
 }
 
+// LDS bytes of the largest single layer (the layer-streamed kernels stage one at a time)
+static constexpr size_t ls_layer_bytes(bool bf, int ti, int tw) {
+  return 256ull * (size_t)tw * (size_t)(ti > tw ? ti : tw) * (bf ? 2 : 4);
+}
+
 int auto_tiles_per_wave(const Geo& g) { return tiles_per_wave(g, fwd_waves(g.ti, g.tw), num_cus()); }
 
 template <bool BF, int TI, int TW>
@@ -1944,6 +2186,17 @@ static void fwd_inst(const Geo& g, const float* params, const void* packF, const
     const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, NW, num_cus());
     dim3 grid((unsigned)(((g.M + 15) / 16 + NW * tpw - 1) / (NW * tpw)), g.N);
     k_forward<BF, TI, TW, true><<<grid, 64 * NW, bytes, s>>>(g, params, packF, pbias, X, V, C, H, tpw);
+  } else if (g.lds && ls_layer_bytes(BF, TI, TW) <= kLdsLimit && g.N > 1) {
+    static bool attr = [] {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_forward_ls<BF, TI, TW>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+      return true;
+    }();
+    (void)attr;
+    const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, LS_WAVES, num_cus());
+    dim3 grid((unsigned)(((g.M + 15) / 16 + LS_WAVES * tpw - 1) / (LS_WAVES * tpw)), g.N);
+    k_forward_ls<BF, TI, TW><<<grid, 64 * LS_WAVES, ls_layer_bytes(BF, TI, TW), s>>>(g, params, packF, pbias, X, V, C,
+                                                                                     H, tpw);
   } else {
     dim3 grid((g.M + 63) / 64, g.N);
     k_forward<BF, TI, TW, false><<<grid, 256, 0, s>>>(g, params, packF, pbias, X, V, C, H, 1);
@@ -1964,6 +2217,17 @@ static void bwd_inst(const Geo& g, const void* packB, const float* V, const floa
     const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, NW, num_cus());
     dim3 grid((unsigned)(((g.M + 15) / 16 + NW * tpw - 1) / (NW * tpw)), g.N);
     k_backward<BF, TI, TW, true><<<grid, 64 * NW, bytes, s>>>(g, packB, V, LAM, H, DZ, DH, tpw);
+  } else if (g.lds && ls_layer_bytes(BF, TI, TW) <= kLdsLimit && g.N > 1) {
+    static bool attr = [] {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_backward_ls<BF, TI, TW>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+      return true;
+    }();
+    (void)attr;
+    const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, LS_WAVES, num_cus());
+    dim3 grid((unsigned)(((g.M + 15) / 16 + LS_WAVES * tpw - 1) / (LS_WAVES * tpw)), g.N);
+    k_backward_ls<BF, TI, TW><<<grid, 64 * LS_WAVES, ls_layer_bytes(BF, TI, TW), s>>>(g, packB, V, LAM, H, DZ, DH,
+                                                                                      tpw);
   } else {
     dim3 grid((g.M + 63) / 64, g.N);
     k_backward<BF, TI, TW, false><<<grid, 256, 0, s>>>(g, packB, V, LAM, H, DZ, DH, 1);

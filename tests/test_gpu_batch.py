@@ -146,3 +146,45 @@ def test_batch_step_reports_a_nonfinite_instance():
     batch.step()
     torch.cuda.synchronize()
     assert int(batch.iter.item()) == 3
+
+
+@pytest.mark.parametrize("prec,d,w,L,N,M", [
+    ("bf16", 150, 160, 2, 3, 300),   # 10 x 10 tiles: the whole step fits LDS
+    ("bf16", 170, 180, 2, 4, 200),   # 12 x 12: layer-streamed
+    ("bf16", 188, 198, 2, 3, 150),   # 14 x 14: layer-streamed
+    ("bf16", 230, 240, 1, 3, 100),   # 16 x 16, depth 1: layer-streamed
+    ("fp32", 120, 125, 2, 3, 150),   # fp32 8 x 8: layer-streamed
+])
+def test_layer_streamed_kernels_are_bitwise_identical(prec, d, w, L, N, M):
+    """Step networks whose weights do not fit LDS at once run one layer at a
+    time through LDS (lds modes 1 and 2); the global-fragment kernels (lds 0)
+    give the same bits."""
+    prob = I.allen_cahn(d)
+    net = dict(width=w, depth=L, prec=prec)
+    p32, _, y0 = inputs(prob, net, N, seed=5, y0=0.3)
+    plan = Plan(prob, net, N, M)
+    print(f"d={d} w={w} L={L} {prec} config {plan.get_config()}", flush=True)
+    ref = _fb(plan, p32, y0)
+    assert np.all(np.isfinite(ref[1]))
+    for lds in (1, 0):
+        plan.config(lds=lds)
+        got = _fb(plan, p32, y0)
+        assert got[0] == ref[0] and got[2] == ref[2], lds
+        assert np.array_equal(got[1], ref[1]), lds
+
+
+def test_layer_streamed_against_oracle():
+    """A 14 x 14 bf16 step network (layer-streamed forward and reverse sweep)
+    against the oracle's bf16 emulation, every block normwise and
+    elementwise."""
+    prob = I.allen_cahn(190)
+    net = dict(width=200, depth=2, prec="bf16")
+    N, M = 3, 96
+    p32, p64, y0 = inputs(prob, net, N, seed=8, y0=0.3)
+    plan = Plan(prob, net, N, M)
+    assert plan.get_config()["ti"] == 14
+    lg, gg, gy = run_gpu(plan, p32, y0, 4, 1)
+    emu = O.loss_grad(prob, oracle_net(net), N, M, p64, y0, seed=4, it=1)
+    assert abs(lg - emu["loss"]) <= 1e-3 * abs(emu["loss"]), (lg, emu["loss"])
+    assert abs(gy - emu["grad_y0"]) <= 1e-3 * abs(emu["grad_y0"]) + 1e-12
+    check_grad(prob, net, N, gg, emu["grad"], 1e-2)
