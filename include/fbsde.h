@@ -240,7 +240,9 @@ fbsde_status fbsde_profile_read(fbsde_plan *plan, double *ms_host, int64_t *coun
  * reverse sweep and weight gradient of a step run as one kernel that keeps
  * the deltas in LDS, where it applies (per-step MLP of depth 1 or 2 whose
  * d + 1 and width + 1 fit the tile shape: fp32 shapes 1x2, 2x2, 4x4, 7x7,
- * bf16 2x2, 4x4, 6x6, 8x8); other values are taken as 0 or 2); 16-path tiles
+ * bf16 2x2, 4x4, 6x6, 8x8) and, in fp32, where its splits x N workgroups
+ * fit one wave over the device's CUs (beyond that the separate kernels are
+ * faster); other values are taken as 0 or 2); 16-path tiles
  * per wave of the LDS kernels (tpw, 0 = automatic); and the path splits of
  * the weight-gradient reduction (0 = automatic: one per 512 paths and at
  * least CUs / N, at most 64; explicit values <= 32).  Results are identical

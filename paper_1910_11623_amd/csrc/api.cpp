@@ -414,7 +414,7 @@ fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double
       return hip_fail(e, "reduce");
     return FBSDE_OK;
   }
-  if (fbsde::reverse_fused_fits(g)) {
+  if (fbsde::reverse_fused_preferred(g, L.splits)) {
     // the reverse sweep and the weight gradient in one kernel (timed as the backward)
     ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
     if ((e = fbsde::launch_reverse(g, at<void>(ws, L.PB), at<float>(ws, L.X), at<float>(ws, L.V),

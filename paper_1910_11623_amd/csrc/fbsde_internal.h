@@ -155,6 +155,8 @@ hipError_t launch_wgrad(const Geo& g, const float* X, const void* H, const void*
 // g.lds == 2, depth <= 2, d + 1 <= 16 ti, w + 1 <= 16 tw, fitting LDS); the
 // same partials as launch_backward + launch_wgrad with the same splits.
 bool reverse_fused_fits(const Geo& g);
+// reverse_fused_fits and, for fp32, splits x N within one wave of workgroups over the CUs
+bool reverse_fused_preferred(const Geo& g, int splits);
 // compute units of the current device (256 if the query fails)
 int device_cus();
 hipError_t launch_reverse(const Geo& g, const void* packB, const float* X, const float* V, const float* LAM,

@@ -2365,6 +2365,15 @@ bool reverse_fused_fits(const Geo& g) {
          g.d + 1 <= 16 * g.ti && g.w + 1 <= 16 * g.tw && reverse_lds_bytes(g) <= kLdsLimit;
 }
 
+// Whether the fused kernel is the faster form: bf16 always (it moves half the
+// bytes of the separate pair); fp32 when its (split, step) workgroups fit one
+// wave over the CUs -- beyond that the pair's larger grids keep more of the
+// chip busy (BSB d = 100: fused 188 vs 197 us at M = 4096, 381 vs 369 us at
+// M = 8192, 2.96 vs 2.69 ms at M = 65536).
+bool reverse_fused_preferred(const Geo& g, int splits) {
+  return reverse_fused_fits(g) && (g.bf16 || (long long)splits * g.N <= num_cus());
+}
+
 template <bool BF, int TI, int TW, int L>
 static void rev_inst(const Geo& g, const void* packB, const float* X, const float* V, const float* LAM,
                      const void* H, float* part, int splits, long long chunk, hipStream_t s) {
