@@ -222,7 +222,10 @@ fbsde_status fbsde_terminal_states(fbsde_plan *plan, const void *ws_dev, float *
  * creates the event pool (host/driver allocation; not a hot call), 0
  * destroys it.  fbsde_profile_read waits for the recorded events and returns,
  * per kernel id (FBSDE_PROF_*), the summed milliseconds and launch counts
- * since the last read (n entries are written; n <= FBSDE_PROF_NUM). */
+ * since the last read (n entries are written; n <= FBSDE_PROF_NUM).  For
+ * the per-step MLP the packing of the step weights runs in the SDE's launch
+ * (FBSDE_PROF_SDE), and the fused reverse kernel, where it runs, is timed as
+ * FBSDE_PROF_BACKWARD with no FBSDE_PROF_WGRAD launches. */
 enum {
   FBSDE_PROF_PACK = 0, FBSDE_PROF_SDE = 1, FBSDE_PROF_FORWARD = 2, FBSDE_PROF_SCAN = 3,
   FBSDE_PROF_BACKWARD = 4, FBSDE_PROF_WGRAD = 5, FBSDE_PROF_REDUCE = 6, FBSDE_PROF_ADAM = 7,

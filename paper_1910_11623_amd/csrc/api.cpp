@@ -370,15 +370,12 @@ fbsde_status run_forward(fbsde_plan* P, const float* params, const double* y0, u
     return FBSDE_OK;
   }
   {
-    ProfScope ps(P, FBSDE_PROF_PACK, s);
-    if ((e = fbsde::launch_pack(g, params, at<void>(ws, L.PF), at<void>(ws, L.PB), at<float>(ws, L.PBIAS), s)) != hipSuccess)
-      return hip_fail(e, "pack");
-  }
-  {
+    // the step weights' packing and the SDE in one launch (timed as the SDE)
     ProfScope ps(P, FBSDE_PROF_SDE, s);
-    if ((e = fbsde::launch_sde(g, P->x0_dev, seed, iter, iter_dev, at<float>(ws, L.X), at<float>(ws, L.V),
-                               at<float>(ws, L.QN), at<float>(ws, L.LN), s)) != hipSuccess)
-      return hip_fail(e, "sde");
+    if ((e = fbsde::launch_pack_sde(g, params, at<void>(ws, L.PF), at<void>(ws, L.PB), at<float>(ws, L.PBIAS),
+                                    P->x0_dev, seed, iter, iter_dev, at<float>(ws, L.X), at<float>(ws, L.V),
+                                    at<float>(ws, L.QN), at<float>(ws, L.LN), s)) != hipSuccess)
+      return hip_fail(e, "pack and sde");
   }
   {
     ProfScope ps(P, FBSDE_PROF_FORWARD, s);

@@ -139,8 +139,10 @@ struct WsLayout {
 };
 
 // launchers (kernels.hip); all return hipError_t of the launch
-hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* packB, float* pbias,
-                       hipStream_t s);
+// launch_pack and launch_sde in one launch (independent work, one grid)
+hipError_t launch_pack_sde(const Geo& g, const float* params, void* packF, void* packB, float* pbias,
+                           const float* x0, uint64_t seed, uint64_t iter, const uint64_t* iter_dev, float* X,
+                           float* V, float* QN, float* LN, hipStream_t s);
 hipError_t launch_sde(const Geo& g, const float* x0, uint64_t seed, uint64_t iter, const uint64_t* iter_dev,
                       float* X, float* V, float* QN, float* LN, hipStream_t s);
 hipError_t launch_forward(const Geo& g, const float* params, const void* packF, const float* pbias,

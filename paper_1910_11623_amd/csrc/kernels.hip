@@ -204,22 +204,22 @@ __device__ __forceinline__ void pack_group(const float* W, int rows, int cols, b
   }
 }
 
+// Block bx of gx packing step n's fragments.
 template <bool BF>
-__global__ __launch_bounds__(256) void k_pack(Geo g, const float* __restrict__ params,
-                                              void* __restrict__ packF, void* __restrict__ packB,
-                                              float* __restrict__ pbias) {
+__device__ __forceinline__ void pack_block(const Geo& g, const float* __restrict__ params, void* __restrict__ packF,
+                                           void* __restrict__ packB, float* __restrict__ pbias, int bx, int gx,
+                                           int n) {
   constexpr int G = BF ? 8 : 4;          // elements per packed group
   constexpr int ESZ = BF ? 2 : 4;
   const int pf = (int)g.packf_step / G, pb = (int)g.packb_step / G;  // groups (every block is whole groups)
   const int nb = (int)g.pbias_step;
   const int per = pf + pb + nb;
-  const int n = 1 + (int)blockIdx.y;
   const float* base = params + g.d + (long long)(n - 1) * g.pstep;
   const int lw1 = g.w * g.d + g.w, lwh = g.w * g.w + g.w;
   const int sz_in = 256 * g.tw * g.ti, sz_h = 256 * g.tw * g.tw, sz_o = 256 * g.ti * g.tw;
   char* F = reinterpret_cast<char*>(packF) + (size_t)(n - 1) * g.packf_step * ESZ;
   char* Bk = reinterpret_cast<char*>(packB) + (size_t)(n - 1) * g.packb_step * ESZ;
-  for (int q = blockIdx.x * 256 + threadIdx.x; q < per; q += gridDim.x * 256) {
+  for (int q = bx * 256 + threadIdx.x; q < per; q += gx * 256) {
     if (q >= pf + pb) {  // biases, zero padded: b_1..b_L (16 tw each), b_o (16 ti)
       const int qb = q - pf - pb;
       const int hb = 16 * g.tw;
@@ -270,17 +270,18 @@ __global__ __launch_bounds__(256) void k_pack(Geo g, const float* __restrict__ p
 // threads.
 __device__ __forceinline__ int sde_threads_per_path(int dp) { return min(dp / 4, 256); }
 
-__global__ __launch_bounds__(256) void k_sde(Geo g, const float* __restrict__ x0, uint64_t seed,
-                                             uint64_t iter_imm, const uint64_t* __restrict__ iter_dev,
-                                             float* __restrict__ X, float* __restrict__ V,
-                                             float* __restrict__ QN, float* __restrict__ LN) {
+// Block bx of the SDE grid.
+__device__ __forceinline__ void sde_block(const Geo& g, const float* __restrict__ x0, uint64_t seed,
+                                          uint64_t iter_imm, const uint64_t* __restrict__ iter_dev,
+                                          float* __restrict__ X, float* __restrict__ V, float* __restrict__ QN,
+                                          float* __restrict__ LN, int bx) {
   const uint64_t iter = iter_dev ? iter_dev[0] : iter_imm;
   __shared__ float sq[256], sl[256];
   const int G = g.dp / 4;
   const int T = sde_threads_per_path(g.dp);
   const int ppb = 256 / T;
   const int lp = threadIdx.x / T, j0 = threadIdx.x % T;
-  const int m = blockIdx.x * ppb + lp;
+  const int m = bx * ppb + lp;
   const bool active = lp < ppb && m < g.M;
   float q = 0.f, lin = 0.f;
   if (active) {
@@ -314,6 +315,33 @@ __global__ __launch_bounds__(256) void k_sde(Geo g, const float* __restrict__ x0
     for (int k = 0; k < T; ++k) { a += sq[threadIdx.x + k]; b += sl[threadIdx.x + k]; }
     QN[m] = a;
     LN[m] = b;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sde(Geo g, const float* __restrict__ x0, uint64_t seed,
+                                             uint64_t iter_imm, const uint64_t* __restrict__ iter_dev,
+                                             float* __restrict__ X, float* __restrict__ V,
+                                             float* __restrict__ QN, float* __restrict__ LN) {
+  sde_block(g, x0, seed, iter_imm, iter_dev, X, V, QN, LN, blockIdx.x);
+}
+
+// The per-iteration packing of the step weights and the SDE are independent:
+// one launch runs both.  Blocks [0, sde_blocks) simulate (each runs a long
+// serial chain over the steps, so they are dispatched first), the rest pack
+// (pack_gx per step) on the CU slots the SDE leaves free.
+template <bool BF>
+__global__ __launch_bounds__(256) void k_pack_sde(Geo g, const float* __restrict__ params, void* __restrict__ packF,
+                                                  void* __restrict__ packB, float* __restrict__ pbias, int pack_gx,
+                                                  int sde_blocks, const float* __restrict__ x0, uint64_t seed,
+                                                  uint64_t iter_imm, const uint64_t* __restrict__ iter_dev,
+                                                  float* __restrict__ X, float* __restrict__ V,
+                                                  float* __restrict__ QN, float* __restrict__ LN) {
+  const int b = blockIdx.x;
+  if (b < sde_blocks) {
+    sde_block(g, x0, seed, iter_imm, iter_dev, X, V, QN, LN, b);
+  } else {
+    const int q = b - sde_blocks;
+    pack_block<BF>(g, params, packF, packB, pbias, q % pack_gx, pack_gx, 1 + q / pack_gx);
   }
 }
 
@@ -2103,14 +2131,23 @@ static inline unsigned grid1(long long n, long long cap = 65536) {
 }
 
 
-hipError_t launch_pack(const Geo& g, const float* params, void* packF, void* packB, float* pbias,
-                       hipStream_t s) {
-  if (g.N < 2) return hipSuccess;
+hipError_t launch_pack_sde(const Geo& g, const float* params, void* packF, void* packB, float* pbias,
+                           const float* x0, uint64_t seed, uint64_t iter, const uint64_t* iter_dev, float* X,
+                           float* V, float* QN, float* LN, hipStream_t s) {
   const int G = g.bf16 ? 8 : 4;
   const long long per = (g.packf_step + g.packb_step) / G + g.pbias_step;
-  dim3 grid(grid1(per, 1024), (unsigned)(g.N - 1));
-  if (g.bf16) k_pack<true><<<grid, 256, 0, s>>>(g, params, packF, packB, pbias);
-  else k_pack<false><<<grid, 256, 0, s>>>(g, params, packF, packB, pbias);
+  const int pack_gx = (int)grid1(per, 1024);
+  const int pack_blocks = g.N >= 2 ? pack_gx * (g.N - 1) : 0;
+  const int T = g.dp / 4 < 256 ? g.dp / 4 : 256;  // threads per path, as in sde_block
+  const int ppb = 256 / T;
+  const int sde_blocks = (int)((g.M + ppb - 1) / ppb);
+  const unsigned blocks = (unsigned)(pack_blocks + sde_blocks);
+  if (g.bf16)
+    k_pack_sde<true><<<blocks, 256, 0, s>>>(g, params, packF, packB, pbias, pack_gx, sde_blocks, x0, seed, iter,
+                                            iter_dev, X, V, QN, LN);
+  else
+    k_pack_sde<false><<<blocks, 256, 0, s>>>(g, params, packF, packB, pbias, pack_gx, sde_blocks, x0, seed, iter,
+                                             iter_dev, X, V, QN, LN);
   return hipGetLastError();
 }
 
