@@ -196,7 +196,7 @@ def measured_traffic(kernel: str, prec: str):
 # Kernel-name prefix -> the roofline keys the bench uses
 _TRAFFIC_KEYS = {"k_pack": "pack", "k_pack_sde": "sde", "k_sde": "sde", "k_forward": "forward", "k_scan": "scan",
                  "k_backward": "backward", "k_wgrad": "wgrad", "k_reverse": "reverse", "k_reverse_bf": "reverse",
-                 "k_reduce": "reduce", "k_finalize": "finalize", "k_adam": "adam"}
+                 "k_reduce": "reduce", "k_adam": "adam"}
 
 
 def reverse_kernels(kern_ms: dict) -> dict:

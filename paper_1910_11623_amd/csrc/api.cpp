@@ -172,7 +172,7 @@ void make_layout(fbsde_plan* P) {
   // (the u-network keeps its partial sums in its own buffer)
   w.PART = take(g.kind == 2 ? 0 : (size_t)splits * (size_t)g.pstride * 4);
   w.scan_blocks = (int)((M + 63) / 64);  // one wave per scan workgroup
-  w.RED = take((size_t)w.scan_blocks * 2 * 8 + 64);
+  w.RED = take((size_t)w.scan_blocks * 2 * 8);
   w.total = off;
 }
 

@@ -1935,9 +1935,10 @@ __global__ __launch_bounds__(RV_THREADS) void k_reverse_bf(Geo g, const void* __
 // grad[e] = sum over splits k (in order) of part[k * stride + e]; 4 elements
 // per thread when grad is 16-byte aligned (the partial copies always are).
 // fp64 loss and dY0 from the scan's per-block partials (one wave; strided
-// per-lane sums, then a fixed xor butterfly, so the result is deterministic)
+// per-lane sums, then a fixed xor butterfly, so the result is deterministic).
+// A non-finite loss or dY0 raises the host flag.
 __device__ __forceinline__ void finalize_wave(int M, const double* __restrict__ sp, int nb, double* loss,
-                                              double* gy0, int* nf, int* host_flag) {
+                                              double* gy0, int* host_flag) {
   double a = 0.0, b = 0.0;
   // each lane adds partials k, k + 64, k + 128, ... in that order; the loads
   // of eight of them are issued before their adds (missing ones add 0)
@@ -1960,18 +1961,26 @@ __device__ __forceinline__ void finalize_wave(int M, const double* __restrict__ 
   if (threadIdx.x == 0) {
     if (loss) loss[0] = a / (double)M;
     if (gy0) gy0[0] = b;
-    const bool bad = nf[0] != 0 || !isfinite(a) || (gy0 != nullptr && !isfinite(b));
-    nf[0] = 0;
+    const bool bad = !isfinite(a) || (gy0 != nullptr && !isfinite(b));
     if (bad && host_flag) host_flag[0] = 1;
   }
 }
 
-// grad[e] = sum over splits k (in order) of part[k * stride + e]; 4 elements
-// per thread, any non-finite sum raises the device flag
+// grad[e] = sum over splits k (in order) of part[k * stride + e], 4 elements
+// per thread over the first nred workgroups; a non-finite sum raises the host
+// flag.  Workgroup nred (the last one) finalizes the loss and dY0 from the
+// scan's partials, which the reduction does not touch, so both run in one
+// launch.
 __global__ __launch_bounds__(256) void k_reduce(long long P, long long stride, const float* __restrict__ part,
-                                                int splits, float* __restrict__ grad, int* __restrict__ nf) {
+                                                int splits, float* __restrict__ grad, int nred, int M,
+                                                const double* __restrict__ sp, int nb, double* __restrict__ loss,
+                                                double* __restrict__ gy0, int* __restrict__ host_flag) {
+  if ((int)blockIdx.x == nred) {
+    if (threadIdx.x < 64) finalize_wave(M, sp, nb, loss, gy0, host_flag);
+    return;
+  }
   bool bad = false;
-  const long long t0 = blockIdx.x * 256LL + threadIdx.x, step = (long long)gridDim.x * 256;
+  const long long t0 = blockIdx.x * 256LL + threadIdx.x, step = (long long)nred * 256;
   const long long P4 = (reinterpret_cast<uintptr_t>(grad) & 15) == 0 ? P / 4 : 0;
   for (long long e4 = t0; e4 < P4; e4 += step) {
     f32x4 s = zero4();
@@ -1985,15 +1994,12 @@ __global__ __launch_bounds__(256) void k_reduce(long long P, long long stride, c
     grad[e] = s;
     bad |= !isfinite(s);
   }
-  if (bad) nf[0] = 1;  // every writer stores the same value
+  if (bad && host_flag) host_flag[0] = 1;  // every writer stores the same value
 }
 
-// Fixed-order fp64 totals of the scan partials; folds the loss, dL/dY0 and
-// the gradient flag `nf` into the plan's host flag, then clears `nf`.
 __global__ __launch_bounds__(64) void k_finalize(int M, const double* __restrict__ sp, int nb,
-                                                 double* __restrict__ loss, double* __restrict__ gy0,
-                                                 int* __restrict__ nf, int* __restrict__ host_flag) {
-  finalize_wave(M, sp, nb, loss, gy0, nf, host_flag);
+                                                 double* __restrict__ loss, int* __restrict__ host_flag) {
+  finalize_wave(M, sp, nb, loss, nullptr, host_flag);
 }
 
 // -------------------------------------------------------------- Adam kernel
@@ -2447,25 +2453,17 @@ hipError_t launch_reverse(const Geo& g, const void* packB, const float* X, const
   return hipErrorInvalidValue;
 }
 
-// the non-finite flag lives right after the scan's fp64 partials
-static int* nf_flag(double* scan_part, int scan_blocks) {
-  return reinterpret_cast<int*>(scan_part + 2 * (size_t)scan_blocks);
-}
-
 hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* grad, double* scan_part,
                          int scan_blocks, double* loss, double* grad_y0, int* host_flag, hipStream_t s) {
-  int* nf = nf_flag(scan_part, scan_blocks);
-  k_reduce<<<grid1((g.nparams + 3) / 4, 4096), 256, 0, s>>>(g.nparams, g.pstride, part, splits, grad, nf);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  k_finalize<<<1, 64, 0, s>>>(g.M, scan_part, scan_blocks, loss, grad_y0, nf, host_flag);
+  const unsigned nred = grid1((g.nparams + 3) / 4, 4096);
+  k_reduce<<<nred + 1, 256, 0, s>>>(g.nparams, g.pstride, part, splits, grad, (int)nred, g.M, scan_part,
+                                    scan_blocks, loss, grad_y0, host_flag);
   return hipGetLastError();
 }
 
 hipError_t launch_loss_only(const Geo& g, double* scan_part, int scan_blocks, double* loss, int* host_flag,
                             hipStream_t s) {
-  k_finalize<<<1, 64, 0, s>>>(g.M, scan_part, scan_blocks, loss, nullptr, nf_flag(scan_part, scan_blocks),
-                               host_flag);
+  k_finalize<<<1, 64, 0, s>>>(g.M, scan_part, scan_blocks, loss, host_flag);
   return hipGetLastError();
 }
 

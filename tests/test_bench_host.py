@@ -76,11 +76,11 @@ def test_step_quantiles():
 
 def test_traffic_lookup_requires_the_profiled_source(tmp_path, monkeypatch):
     rec = json.load(open(os.path.join(ROOT, "profiles", "bsb_d100_traffic.json")))
-    t = bench.measured_traffic("wgrad", "fp32")
+    t = bench.measured_traffic("reverse", "fp32")
     src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     import hashlib
     if hashlib.sha256(src).hexdigest() == rec["source_sha256"]:
-        per = rec["per_launch"]["wgrad_fp32"]
+        per = rec["per_launch"]["reverse_fp32"]
         assert t == int(round(per["read_bytes"] + per["write_bytes"]))
     else:
         assert t is None
