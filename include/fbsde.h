@@ -263,9 +263,9 @@ fbsde_status fbsde_plan_status(fbsde_plan *plan);
  * chunks of whole steps of about chunk_rows rows (0: 262144; at least one
  * step).  recompute != 0 (the default): only X_n and v_n live across the
  * passes and the reverse sweep recomputes each chunk's activations.
- * recompute == 0: the forward pass keeps every chunk's bf16 activations and
- * their transposed copies, so the reverse sweep skips the recompute; the
- * workspace grows by about N M (B (3 w) + 2 w + d) bf16 elements.  Call
+ * recompute == 0: the forward pass keeps every chunk's bf16 activations
+ * (h_0..h_B, a_1..a_B, [x; t]), so the reverse sweep skips the recompute;
+ * the workspace grows by about N M ((2 B + 1) w + d) bf16 elements.  Call
  * before fbsde_workspace_size (it changes the workspace).  Results are
  * bitwise identical for every mode and chunk size except for the fp32
  * summation order of the weight gradients, which follows the chunks.

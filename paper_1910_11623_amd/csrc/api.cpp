@@ -139,12 +139,7 @@ void make_layout(fbsde_plan* P) {
     w.RD32 = take(rows * wd * 4);
     w.RGB = take(2 * rows * wd * 2 + slack);
     w.RZ = take(rows * (size_t)R.dq * 4);
-    const size_t ldt = (size_t)R.ldt;
-    w.RHT = take(kept * (g.L + 1) * wd * ldt * 2 + slack);
-    w.RGT = take(2 * wd * ldt * 2 + slack);
-    w.RZT = take((size_t)g.d * ldt * 2 + slack);
-    w.RXT = take(kept * (g.d + 1) * ldt * 2 + slack);
-    w.RXB = take(rows * (size_t)R.dq * 2 + slack);
+    w.RXB = take(kept * rows * (size_t)R.ldx * 2 + slack);
     w.RVB = take(rows * (size_t)R.dq * 2 + slack);
   }
   // weight-gradient splits over paths (per-step MLP) or over chunk rows
@@ -195,9 +190,9 @@ int rn_chunk_steps(int64_t N, int64_t M, int64_t rows) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(N, rows / std::max<int64_t>(1, M)));
 }
 bool rn_offsets_fit(int64_t M, int64_t chunk_steps, int64_t width, int64_t d) {
-  const int64_t rows = chunk_steps * M, ldt = (rows + 7) / 8 * 8, dq = (d + 7) / 8 * 8;
-  const int64_t wide = std::max<int64_t>(std::max<int64_t>(width, dq), d + 1);
-  return (rows + 32) * wide < 0x7fffffffLL && (ldt + 32) * wide < 0x7fffffffLL;
+  const int64_t rows = chunk_steps * M, ldx = (d + 1 + 7) / 8 * 8;
+  const int64_t wide = std::max<int64_t>(width, ldx);
+  return (rows + 32) * wide < 0x7fffffffLL;
 }
 
 // Largest workspace over the candidate tile shapes, at the largest split count
@@ -246,10 +241,6 @@ fbsde::ResnetBufs resnet_bufs(const fbsde_plan* P, void* ws) {
   R.d32 = at<float>(ws, L.RD32);
   R.gb = at<uint16_t>(ws, L.RGB);
   R.z = at<float>(ws, L.RZ);
-  R.ht = at<uint16_t>(ws, L.RHT);
-  R.gt = at<uint16_t>(ws, L.RGT);
-  R.zt = at<uint16_t>(ws, L.RZT);
-  R.xt = at<uint16_t>(ws, L.RXT);
   R.xb = at<uint16_t>(ws, L.RXB);
   R.vb = at<uint16_t>(ws, L.RVB);
   return R;

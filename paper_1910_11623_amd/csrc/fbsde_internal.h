@@ -50,10 +50,10 @@ struct Geo {
 // Shared residual network: packed weights and the per-chunk activation buffers.
 struct ResnetLayout {
   int dq;                 // d rounded up to 8
+  int ldx;                // row stride of bf16 [x; t]: d + 1 rounded up to 8
   long long pk_elems;     // bf16 packed weights (forward + transposed)
   long long pf_elems;     // fp32 time column and biases
   long long rows;         // rows per chunk = rn_chunk * M
-  long long ldt;          // row stride of the transposed copies: rows rounded up to 8
   int nchunks;            // row chunks per pass
   int kept;               // chunks whose activations have their own copy (1, or nchunks if stored)
 };
@@ -66,11 +66,7 @@ struct ResnetBufs {
   float* d32;             // [rows][w] fp32 delta
   uint16_t* gb;           // [2][rows][w] bf16 pre-activation gradients (ping-pong)
   float* z;               // [rows][dq] fp32 network output
-  uint16_t* ht;           // [kept][B+1][w][ldt] bf16 h_k^T
-  uint16_t* gt;           // [2][w][ldt] bf16 g^T (ping-pong)
-  uint16_t* zt;           // [d][ldt] bf16 zeta^T
-  uint16_t* xt;           // [kept][d+1][ldt] bf16 [x; t]^T
-  uint16_t* xb;           // [rows][dq] bf16 x
+  uint16_t* xb;           // [kept][rows][ldx] bf16 [x; t]
   uint16_t* vb;           // [rows][dq] bf16 zeta = lambda v
 };
 ResnetLayout resnet_layout(const Geo& g);
@@ -130,7 +126,7 @@ hipError_t unet_nais_project(const Geo& g, const UnetBufs& B, float* params, flo
 // Offsets (bytes) of the sub-buffers of one workspace.
 struct WsLayout {
   size_t X, V, C, Y, LAM, QN, LN, H, DZ, DH, PF, PB, PBIAS, PART, RED, total;
-  size_t RPK, RPF, RH32, RHB, RAB, RD32, RGB, RZ, RHT, RGT, RZT, RXT, RXB, RVB;  // residual-network buffers
+  size_t RPK, RPF, RH32, RHB, RAB, RD32, RGB, RZ, RXB, RVB;  // residual-network buffers
   size_t UU, UZ, UUB, UZB, UH, UAL, UHH, UG, UHHB, UHB0, UALB, UHBAR, UABAR, UW0X, UW0T, UAK, URK, UEX, UET, UP,
       UABARW, UPART, ULP, UCB;  // u-network buffers
   int scan_blocks;

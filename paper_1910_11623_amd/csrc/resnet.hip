@@ -101,7 +101,6 @@ struct Epi {
   float* h32; long long ldh;      // fp32 residual stream / delta [i][j]
   uint16_t* ob; long long ldb;    // bf16 output [i][j] (hb or gb)
   uint16_t* ab; long long lda;    // bf16 activation, out (EPI_TANH_RES, optional) or in (EPI_BWD_*)
-  uint16_t* ot; long long ldt;    // optional bf16 transposed copy [j][i] of the ob values
   float* out32; long long ldo;    // EPI_STORE
   float* part; long long base; int wcols;  // EPI_ACC: W[rows][wcols] at base, then the bias b[rows]
 };
@@ -110,119 +109,186 @@ __device__ __forceinline__ uint2 pack4(float a, float b, float c, float d) {
   return uint2{bfbits(a) | (bfbits(b) << 16), bfbits(c) | (bfbits(d) << 16)};
 }
 
-// Four consecutive columns j..j+3 of row i (j a multiple of 4).  With a
-// transposed copy requested, its bf16 values go to the wave's LDS block
-// `tl` at [jl + e][il] (row stride tld) and are written out afterwards.
-template <int EPI>
-__device__ __forceinline__ void epilogue4(const Epi& E, int i, int j, f32x4 acc, uint16_t* tl, int il, int jl,
-                                          int tld) {
-  if (i >= E.rows) return;
-  const bool full = j + 4 <= E.cols;
+// Epilogue of a wave's (16 TM) x (16 TN) tile: lane l holds, for each MFMA
+// tile (a, b), row i = i0w + 16 a + l % 16 and columns j = j0w + 16 b +
+// 4 (l / 16) + 0..3.  Everything a row block a reads from memory (residual
+// stream or delta, activations, weight-gradient partials) is loaded one block
+// ahead, so that its latency overlaps the arithmetic and stores of block
+// a - 1 instead of being waited for once per 4 columns; biases are loaded
+// once.  The residual-stream epilogues (EPI_TANH_*, EPI_BWD_*) have cols = w,
+// a multiple of 8, so a run of 4 columns is either wholly valid or wholly
+// past cols.  Loads of rows past `rows` and of columns past `cols` read a
+// clamped valid element; nothing is stored for them.
+template <int EPI, int TM, int TN>
+__device__ __forceinline__ void epilogue_tile(const Epi& E, const f32x4 (&acc)[TM][TN], int i0w, int j0w, int lane) {
+  const int jl = 4 * (lane >> 4);
   if constexpr (EPI == EPI_ACC) {
-    float* p = E.part + E.base + (long long)i * E.wcols + j;
+    // partial[i][j] += acc: 4 TN scalar read-modify-writes per row block
+    float pv[2][TN][4];
+    auto ld = [&](int a, float (&v)[TN][4]) {
+      const int i = min(i0w + 16 * a + (lane & 15), E.rows - 1);
+      const float* p = E.part + E.base + (long long)i * E.wcols;
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (j + e < E.cols) p[e] += acc[e];
-    return;
+      for (int b = 0; b < TN; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[b][e] = p[min(j0w + 16 * b + jl + e, E.cols - 1)];
+    };
+    ld(0, pv[0]);
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      if (a + 1 < TM) ld(a + 1, pv[(a + 1) & 1]);
+      const int i = i0w + 16 * a + (lane & 15);
+      if (i < E.rows) {
+        float* p = E.part + E.base + (long long)i * E.wcols;
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int j = j0w + 16 * b + jl + e;
+            if (j < E.cols) p[j] = pv[a & 1][b][e] + acc[a][b][e];
+          }
+      }
+    }
+  } else if constexpr (EPI == EPI_STORE) {
+    float bz[TN][4];
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bz[b][e] = E.bias ? E.bias[min(j0w + 16 * b + jl + e, E.cols - 1)] : 0.f;
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int i = i0w + 16 * a + (lane & 15);
+      if (i >= E.rows) continue;
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int j = j0w + 16 * b + jl;
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = acc[a][b][e] + bz[b][e];
+        float* o = E.out32 + (long long)i * E.ldo + j;
+        if (j + 4 <= E.cols) {
+          *reinterpret_cast<f32x4*>(o) = f32x4{v[0], v[1], v[2], v[3]};
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (j + e < E.cols) o[e] = v[e];
+        }
+      }
+    }
   } else {
-    float v[4];
-    if constexpr (EPI == EPI_STORE) {
+    constexpr bool HIN = (EPI == EPI_TANH_RES || EPI == EPI_BWD_RES);   // reads the stream / delta
+    constexpr bool AIN = (EPI == EPI_BWD_FIRST || EPI == EPI_BWD_RES);  // reads the activation
+    constexpr bool BIAS = (EPI == EPI_TANH_IN || EPI == EPI_TANH_RES);
+    f32x4 bz[TN], wz[TN];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = acc[e] + ((E.bias && j + e < E.cols) ? E.bias[j + e] : 0.f);
-      float* o = E.out32 + (long long)i * E.ldo + j;
-      if (full) {
-        *reinterpret_cast<f32x4*>(o) = f32x4{v[0], v[1], v[2], v[3]};
-      } else {
+    for (int b = 0; b < TN; ++b) {
+      const int jc = min(j0w + 16 * b + jl, E.cols - 4);
+      if constexpr (BIAS) bz[b] = *reinterpret_cast<const f32x4*>(E.bias + jc);
+      if constexpr (EPI == EPI_TANH_IN) wz[b] = *reinterpret_cast<const f32x4*>(E.wt + jc);
+    }
+    f32x4 hv[2][TN];
+    uint2 av[2][TN];
+    auto ld = [&](int a, f32x4 (&h)[TN], uint2 (&v)[TN]) {
+      const int i = min(i0w + 16 * a + (lane & 15), E.rows - 1);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (j + e < E.cols) o[e] = v[e];
+      for (int b = 0; b < TN; ++b) {
+        const int jc = min(j0w + 16 * b + jl, E.cols - 4);
+        if constexpr (HIN) h[b] = *reinterpret_cast<const f32x4*>(E.h32 + (long long)i * E.ldh + jc);
+        if constexpr (AIN) v[b] = *reinterpret_cast<const uint2*>(E.ab + (long long)i * E.lda + jc);
       }
-      return;
-    } else {
-      const long long ph = (long long)i * E.ldh + j;
-      float hv[4] = {0.f, 0.f, 0.f, 0.f}, av[4] = {0.f, 0.f, 0.f, 0.f};
-      if (full) {
-        if constexpr (EPI == EPI_TANH_RES || EPI == EPI_BWD_RES) {
-          const f32x4 h = *reinterpret_cast<const f32x4*>(E.h32 + ph);
-          hv[0] = h[0]; hv[1] = h[1]; hv[2] = h[2]; hv[3] = h[3];
-        }
-        if constexpr (EPI == EPI_BWD_FIRST || EPI == EPI_BWD_RES) {
-          const uint2 u = *reinterpret_cast<const uint2*>(E.ab + (long long)i * E.lda + j);
-          av[0] = __uint_as_float(u.x << 16); av[1] = __uint_as_float(u.x & 0xffff0000u);
-          av[2] = __uint_as_float(u.y << 16); av[3] = __uint_as_float(u.y & 0xffff0000u);
-        }
-      } else {
+    };
+    ld(0, hv[0], av[0]);
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      if (a + 1 < TM) ld(a + 1, hv[(a + 1) & 1], av[(a + 1) & 1]);
+      const int i = i0w + 16 * a + (lane & 15);
+      float t = 0.f;
+      if constexpr (EPI == EPI_TANH_IN) t = rbf((float)(E.n0 + i / E.mp) * E.dt);
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int j = j0w + 16 * b + jl;
+        const f32x4 h = hv[a & 1][b];
+        const uint2 u = av[a & 1][b];
+        const float avf[4] = {__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                              __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u)};
+        float hout[4], gout[4], aout[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          if (j + e >= E.cols) continue;
-          if constexpr (EPI == EPI_TANH_RES || EPI == EPI_BWD_RES) hv[e] = E.h32[ph + e];
-          if constexpr (EPI == EPI_BWD_FIRST || EPI == EPI_BWD_RES) av[e] = bf2f(E.ab[(long long)i * E.lda + j + e]);
+          if constexpr (EPI == EPI_TANH_IN) {
+            const float x = fast_tanh(acc[a][b][e] + bz[b][e] + t * wz[b][e]);
+            hout[e] = x; gout[e] = x;
+          } else if constexpr (EPI == EPI_TANH_RES) {
+            const float x = fast_tanh(acc[a][b][e] + bz[b][e]);
+            aout[e] = x;
+            hout[e] = h[e] + x; gout[e] = hout[e];
+          } else {  // EPI_BWD_FIRST / EPI_BWD_RES
+            const float dl = HIN ? h[e] + acc[a][b][e] : acc[a][b][e];
+            hout[e] = dl;
+            gout[e] = dl * (1.f - avf[e] * avf[e]);
+          }
         }
-      }
-      float hout[4], gout[4], aout[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int jj = full ? j + e : min(j + e, E.cols - 1);  // clamp: values past cols are never stored
-        if constexpr (EPI == EPI_TANH_IN) {
-          const float t = rbf((float)(E.n0 + i / E.mp) * E.dt);
-          const float a = fast_tanh(acc[e] + E.bias[jj] + t * E.wt[jj]);
-          hout[e] = a; gout[e] = a;
-        } else if constexpr (EPI == EPI_TANH_RES) {
-          const float a = fast_tanh(acc[e] + E.bias[jj]);
-          aout[e] = a;
-          hout[e] = hv[e] + a; gout[e] = hout[e];
-        } else {  // EPI_BWD_FIRST / EPI_BWD_RES
-          const float dl = (EPI == EPI_BWD_RES) ? hv[e] + acc[e] : acc[e];
-          hout[e] = dl;
-          gout[e] = dl * (1.f - av[e] * av[e]);
-        }
-      }
-      uint16_t* ob = E.ob + (long long)i * E.ldb + j;
-      if (full) {
-        *reinterpret_cast<f32x4*>(E.h32 + ph) = f32x4{hout[0], hout[1], hout[2], hout[3]};
-        *reinterpret_cast<uint2*>(ob) = pack4(gout[0], gout[1], gout[2], gout[3]);
-        if constexpr (EPI == EPI_TANH_RES)
-          if (E.ab) *reinterpret_cast<uint2*>(E.ab + (long long)i * E.lda + j) = pack4(aout[0], aout[1], aout[2], aout[3]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (j + e >= E.cols) continue;
-          E.h32[ph + e] = hout[e];
-          ob[e] = (uint16_t)bfbits(gout[e]);
+        if (i < E.rows && j < E.cols) {
+          *reinterpret_cast<f32x4*>(E.h32 + (long long)i * E.ldh + j) = f32x4{hout[0], hout[1], hout[2], hout[3]};
+          *reinterpret_cast<uint2*>(E.ob + (long long)i * E.ldb + j) = pack4(gout[0], gout[1], gout[2], gout[3]);
           if constexpr (EPI == EPI_TANH_RES)
-            if (E.ab) E.ab[(long long)i * E.lda + j + e] = (uint16_t)bfbits(aout[e]);
+            if (E.ab) *reinterpret_cast<uint2*>(E.ab + (long long)i * E.lda + j) = pack4(aout[0], aout[1], aout[2], aout[3]);
         }
-      }
-      if (tl) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) tl[(jl + e) * tld + il] = (uint16_t)bfbits(gout[e]);
       }
     }
   }
 }
 
 // ------------------------------------------------------------------ GEMM
-// Workgroup tile (32 TM) x (32 TN): 4 waves in 2 x 2, each (16 TM) x (16 TN)
+// Workgroup tile (32 TM) x (16 TN WJ): 2 x WJ waves, each (16 TM) x (16 TN)
 // as TM x TN MFMA 16x16x32 tiles.  The reduction is staged BK at a time in
-// two LDS buffers (64-byte rows, swizzled: conflict-free 16-byte writes and reads): the
-// global loads of slab s + 1 are in flight while slab s is multiplied.  The MFMA takes the B fragment as its
-// first operand, so every lane ends up holding four consecutive output
-// columns of one row (vector epilogue stores).  Tiles are ordered so that
-// the j-tiles of one (split, i-tile) are dispatched to the same XCD and
-// share the A slab in its L2.
-template <int EPI, int TM, int TN, int WJ>
+// two LDS buffers: the global loads of slab s + 2 are in flight while slab s
+// is multiplied.  The MFMA takes the B fragment as its first operand, so
+// every lane ends up holding four consecutive output columns of one row
+// (vector epilogue stores).  Tiles are ordered so that the j-tiles of one
+// (split, i-tile) are dispatched to the same XCD and share the A slab in its
+// L2.
+//
+// Operand forms.  KT = false: A[i][k] and B[j][k] are k-contiguous (row i of
+// A is a run of the reduction index); slab rows of 64 bytes, swizzled.
+// KT = true (the weight gradients, whose reduction runs over the rows of a
+// chunk): A[k][i] and B[k][j] are the row-major activations themselves, and
+// the slab keeps that [k][i] layout; the MFMA fragments (8 consecutive k of
+// one i per lane) come from two transposed LDS reads (ds_read_b64_tr_b16):
+// within each 16-lane group, lanes 4e..4e+3 point at slab row 8g + 4h + e,
+// columns 4q..4q+3 (q = lane % 4), and lane j of the group receives column j
+// of those four rows.
+#ifndef RN_KT_SWZ
+#define RN_KT_SWZ 1
+#endif
+// [k][i] slab rows: unpadded with the 16-element blocks of row k XOR-swizzled
+// by kt_swz(k), or padded by KT_PAD elements
+constexpr int KT_PAD = RN_KT_SWZ ? 0 : 16;
+__device__ __forceinline__ int kt_swz(int k) { return RN_KT_SWZ ? 16 * ((k & 3) | (((k >> 3) & 1) << 2)) : 0; }
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4s lds_v4s;
+__device__ __forceinline__ u32x4 tr_frag(const uint16_t* slab, int ld, int col0, int lane) {
+  const int g = lane >> 4, j = lane & 15;
+  const int k = 8 * g + (j >> 2);  // rows k and k + 4 share their swizzle
+  uint16_t* p = const_cast<uint16_t*>(slab) + k * ld + (col0 ^ kt_swz(k)) + 4 * (j & 3);
+  const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)p);
+  const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(p + 4 * ld));
+  const uint2 l = __builtin_bit_cast(uint2, lo), h = __builtin_bit_cast(uint2, hi);
+  return u32x4{l.x, l.y, h.x, h.y};
+}
+
+template <int EPI, int TM, int TN, int WJ, bool KT>
 __global__ __launch_bounds__(128 * WJ) __attribute__((amdgpu_waves_per_eu(RN_WPE))) void k_gemm(Gm G, Epi E) {
+  static_assert(!KT || EPI == EPI_ACC, "k-major operands are the weight-gradient form");
   constexpr int WI = 2, NT = 64 * WI * WJ;  // waves along i and j, threads
   constexpr int BM = 16 * TM * WI, BN = 16 * TN * WJ;
   constexpr int UA = BM * 4 / NT, UB = BN * 4 / NT;  // 16-byte staging units per thread
-  // LDS: the double-buffered A and B slabs; after the main loop the same
-  // memory holds each wave's (16 TN) x (16 TM) bf16 block of a transposed
-  // copy (272-byte rows for TM = 8: 16-byte aligned, conflict-free)
-  constexpr int TLD = 16 * TM + 8;
-  constexpr int STAGE = 2 * (BM + BN) * LDK, TBLK = 16 * TN * TLD;
-  __shared__ __attribute__((aligned(16))) uint16_t smem[STAGE > WI * WJ * TBLK ? STAGE : WI * WJ * TBLK];
-  uint16_t (*sA)[BM * LDK] = reinterpret_cast<uint16_t (*)[BM * LDK]>(smem);
-  uint16_t (*sB)[BN * LDK] = reinterpret_cast<uint16_t (*)[BN * LDK]>(smem + 2 * BM * LDK);
+  // slab row strides (elements) and sizes of the double-buffered A and B slabs
+  constexpr int LA = KT ? BM + KT_PAD : LDK, LB = KT ? BN + KT_PAD : LDK;
+  constexpr int SA = KT ? BK * LA : BM * LDK, SB = KT ? BK * LB : BN * LDK;
+  __shared__ __attribute__((aligned(16))) uint16_t smem[2 * (SA + SB)];
+  uint16_t (*sA)[SA] = reinterpret_cast<uint16_t (*)[SA]>(smem);
+  uint16_t (*sB)[SB] = reinterpret_cast<uint16_t (*)[SB]>(smem + 2 * SA);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int wi = wv / WJ, wj = wv % WJ;
@@ -241,38 +307,82 @@ __global__ __launch_bounds__(128 * WJ) __attribute__((amdgpu_waves_per_eu(RN_WPE
   Epi Ez = E;
   if constexpr (EPI == EPI_ACC) Ez.part = E.part + (long long)sp * G.pstride;
 
-  // Staging unit u = tid + NT q: row u / 4, k offset 8 (u % 4).  Loads are
-  // unconditional so that the wait before each LDS write counts exactly the
-  // loads it needs: rows past the operand clamp to its last row (they only
-  // feed outputs that are never stored) and slabs past the split's end
-  // re-read its first slab.  Only the split's last slab can hold k >= ke;
-  // its runs are masked at the LDS write.  A run of 8 starting below
-  // round_up(K, 32) lies inside the operand's allocation: every row stride
-  // is a multiple of 8 and every buffer carries 64 bytes of slack.
+  // Staging unit u = tid + NT q.  Loads are unconditional so that the wait
+  // before each LDS write counts exactly the loads it needs, and slabs past
+  // the split's end re-read its first slab.
+  // KT = false: row u / 4, k offset 8 (u % 4); rows past the operand clamp to
+  // its last row (they only feed outputs that are never stored).  Only the
+  // split's last slab can hold k >= ke; its runs are masked at the LDS write.
+  // A run of 8 starting below round_up(K, 32) lies inside the operand's
+  // allocation: every row stride is a multiple of 8 and every buffer carries
+  // 64 bytes of slack.
+  // KT = true: slab row (k) u / (BM / 8), columns 8 (u % (BM / 8)) .. + 7; a
+  // run past the operand's columns is moved back inside its row (it only
+  // feeds outputs that are never stored), rows k >= ke read row K - 1 and are
+  // stored as zeros.
   int aoff[UA], boff[UB];
 #pragma unroll
   for (int q = 0; q < UA; ++q) {
-    const int u = tid + NT * q, r = min(i0 + (u >> 2), G.arows - 1);
-    aoff[q] = r * (int)G.lda + (u & 3) * 8;
+    const int u = tid + NT * q;
+    if constexpr (KT) {
+      aoff[q] = min(i0 + 8 * (u % (BM / 8)), (int)G.lda - 8);
+    } else {
+      const int r = min(i0 + (u >> 2), G.arows - 1);
+      aoff[q] = r * (int)G.lda + (u & 3) * 8;
+    }
   }
 #pragma unroll
   for (int q = 0; q < UB; ++q) {
-    const int u = tid + NT * q, r = min(j0 + (u >> 2), G.brows - 1);
-    boff[q] = r * (int)G.ldb + (u & 3) * 8;
+    const int u = tid + NT * q;
+    if constexpr (KT) {
+      boff[q] = min(j0 + 8 * (u % (BN / 8)), (int)G.ldb - 8);
+    } else {
+      const int r = min(j0 + (u >> 2), G.brows - 1);
+      boff[q] = r * (int)G.ldb + (u & 3) * 8;
+    }
   }
-  const int kofs = (tid & 3) * 8;  // this thread's k offset inside a slab (same for every unit)
+  const int kofs = (tid & 3) * 8;  // KT = false: this thread's k offset inside a slab (same for every unit)
   auto load = [&](int slab, uint4 (&ra)[UA], uint4 (&rb)[UB]) {
     const long long kt = (slab < nk) ? ks + (long long)slab * BK : ks;
-    const uint16_t* pa = G.a + kt;
-    const uint16_t* pb = G.b + kt;
+    if constexpr (KT) {
 #pragma unroll
-    for (int q = 0; q < UA; ++q) ra[q] = *reinterpret_cast<const uint4*>(pa + aoff[q]);
+      for (int q = 0; q < UA; ++q) {
+        const int r = (int)min(kt + (tid + NT * q) / (BM / 8), (long long)G.K - 1);
+        ra[q] = *reinterpret_cast<const uint4*>(G.a + r * (int)G.lda + aoff[q]);
+      }
 #pragma unroll
-    for (int q = 0; q < UB; ++q) rb[q] = *reinterpret_cast<const uint4*>(pb + boff[q]);
+      for (int q = 0; q < UB; ++q) {
+        const int r = (int)min(kt + (tid + NT * q) / (BN / 8), (long long)G.K - 1);
+        rb[q] = *reinterpret_cast<const uint4*>(G.b + r * (int)G.ldb + boff[q]);
+      }
+    } else {
+      const uint16_t* pa = G.a + kt;
+      const uint16_t* pb = G.b + kt;
+#pragma unroll
+      for (int q = 0; q < UA; ++q) ra[q] = *reinterpret_cast<const uint4*>(pa + aoff[q]);
+#pragma unroll
+      for (int q = 0; q < UB; ++q) rb[q] = *reinterpret_cast<const uint4*>(pb + boff[q]);
+    }
   };
   auto store = [&](int slab, int buf, const uint4 (&ra)[UA], const uint4 (&rb)[UB]) {
     const long long kt = ks + (long long)slab * BK;
-    if (kt + BK <= ke) {  // uniform: a full slab
+    if constexpr (KT) {
+      const bool full = kt + BK <= ke;  // uniform
+#pragma unroll
+      for (int q = 0; q < UA; ++q) {
+        const int u = tid + NT * q, kr = u / (BM / 8);
+        const bool ok = full || kt + kr < ke;
+        *reinterpret_cast<uint4*>(&sA[buf][kr * LA + ((8 * (u % (BM / 8))) ^ kt_swz(kr))]) =
+            ok ? ra[q] : uint4{0u, 0u, 0u, 0u};
+      }
+#pragma unroll
+      for (int q = 0; q < UB; ++q) {
+        const int u = tid + NT * q, kr = u / (BN / 8);
+        const bool ok = full || kt + kr < ke;
+        *reinterpret_cast<uint4*>(&sB[buf][kr * LB + ((8 * (u % (BN / 8))) ^ kt_swz(kr))]) =
+            ok ? rb[q] : uint4{0u, 0u, 0u, 0u};
+      }
+    } else if (kt + BK <= ke) {  // uniform: a full slab
 #pragma unroll
       for (int q = 0; q < UA; ++q) {
         const int u = tid + NT * q;
@@ -318,13 +428,25 @@ __global__ __launch_bounds__(128 * WJ) __attribute__((amdgpu_waves_per_eu(RN_WPE
     bf16x8 fa[TM], fb[TN];
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
-      const uint4 u = *reinterpret_cast<const uint4*>(&sA[buf][slab_off(wi * 16 * TM + 16 * a + (lane & 15), lane >> 4)]);
-      fa[a] = __builtin_bit_cast(bf16x8, u32x4{u.x, u.y, u.z, u.w});
+      u32x4 u;
+      if constexpr (KT) {
+        u = tr_frag(sA[buf], LA, wi * 16 * TM + 16 * a, lane);
+      } else {
+        const uint4 v = *reinterpret_cast<const uint4*>(&sA[buf][slab_off(wi * 16 * TM + 16 * a + (lane & 15), lane >> 4)]);
+        u = u32x4{v.x, v.y, v.z, v.w};
+      }
+      fa[a] = __builtin_bit_cast(bf16x8, u);
     }
 #pragma unroll
     for (int b = 0; b < TN; ++b) {
-      const uint4 u = *reinterpret_cast<const uint4*>(&sB[buf][slab_off(wj * 16 * TN + 16 * b + (lane & 15), lane >> 4)]);
-      fb[b] = __builtin_bit_cast(bf16x8, u32x4{u.x, u.y, u.z, u.w});
+      u32x4 u;
+      if constexpr (KT) {
+        u = tr_frag(sB[buf], LB, wj * 16 * TN + 16 * b, lane);
+      } else {
+        const uint4 v = *reinterpret_cast<const uint4*>(&sB[buf][slab_off(wj * 16 * TN + 16 * b + (lane & 15), lane >> 4)]);
+        u = u32x4{v.x, v.y, v.z, v.w};
+      }
+      fb[b] = __builtin_bit_cast(bf16x8, u);
     }
 #pragma unroll
     for (int a = 0; a < TM; ++a)
@@ -380,43 +502,7 @@ __global__ __launch_bounds__(128 * WJ) __attribute__((amdgpu_waves_per_eu(RN_WPE
   }
 #endif
   // lane: row i = 16a + lane % 16, columns j = 16b + 4 (lane / 16) + 0..3
-  const int i0w = i0 + wi * 16 * TM, j0w = j0 + wj * 16 * TN;
-  uint16_t* tl = nullptr;
-  if constexpr (EPI != EPI_ACC && EPI != EPI_STORE)
-    if (E.ot) tl = smem + wv * TBLK;  // LDS is free: the loop ended with a barrier
-#pragma unroll
-  for (int a = 0; a < TM; ++a) {
-    const int il = 16 * a + (lane & 15);
-#pragma unroll
-    for (int b = 0; b < TN; ++b) {
-      const int jl = 16 * b + 4 * (lane >> 4);
-      epilogue4<EPI>(Ez, i0w + il, j0w + jl, acc[a][b], tl, il, jl, TLD);
-    }
-  }
-  if constexpr (EPI != EPI_ACC && EPI != EPI_STORE) {
-    if (E.ot) {  // uniform: the wave's block, transposed rows of 16 TM bf16 written as 16-byte runs
-      __syncthreads();
-      constexpr int CPR = 2 * TM, RPI = 64 / CPR;  // 16-byte chunks per row, rows per pass
-      const int c = lane % CPR;
-#pragma unroll
-      for (int pass = 0; pass < 16 * TN / RPI; ++pass) {
-        const int jl = pass * RPI + lane / CPR;
-        const int j = j0w + jl, i = i0w + 8 * c;
-        const uint4 v = *reinterpret_cast<const uint4*>(tl + jl * TLD + 8 * c);
-        if (j < E.cols) {
-          uint16_t* o = E.ot + (long long)j * E.ldt + i;
-          if (i + 8 <= E.rows) {
-            *reinterpret_cast<uint4*>(o) = v;
-          } else {
-            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-              if (i + e < E.rows) o[e] = (uint16_t)(w4[e >> 1] >> (16 * (e & 1)));
-          }
-        }
-      }
-    }
-  }
+  epilogue_tile<EPI, TM, TN>(Ez, acc, i0 + wi * 16 * TM, j0 + wj * 16 * TN, lane);
   if constexpr (EPI == EPI_ACC) {
     if (rowsum) {
 #pragma unroll
@@ -432,58 +518,28 @@ __global__ __launch_bounds__(128 * WJ) __attribute__((amdgpu_waves_per_eu(RN_WPE
 }
 
 // ------------------------------------------------------------- convert
-// v = src[r][c] * scale[r] (scale optional) for r < rows, c < cols:
-// rowm[r][c] = bf16(v) (if rowm) and tr[c][r] = bf16(v) (if tr); with
-// trow >= 0 also tr[trow][r] = bf16(t of row r).  64 x 64 tiles: each thread
-// reads float4 runs of src rows and writes 4-element bf16 runs of rowm; the
-// transpose goes through LDS and leaves as 4-element runs of tr rows.  The
-// src row stride is a multiple of 4; columns in [cols, stride) of rowm may
-// receive whatever src holds there (readers stop at cols).
+// rowm[r][c] = bf16(src[r][c] * scale[r]) (scale optional) for r < rows,
+// c < cols; with tcol >= 0 also rowm[r][tcol] = bf16(t of row r), t = (n0 +
+// r / mp) dt (the time input of the network, next to x).  Columns between
+// cols and the next multiple of 4 are written as zeros.  Each thread converts
+// float4 runs of one row and stores 4-element bf16 runs; the src row stride
+// is a multiple of 4.
 __global__ __launch_bounds__(256) void k_convert(const float* __restrict__ src, long long lds, int rows, int cols,
                                                  const float* __restrict__ scale, uint16_t* __restrict__ rowm,
-                                                 long long ldr, uint16_t* __restrict__ tr, long long ldt, int trow,
-                                                 int n0, int mp, float dt) {
-  __shared__ float tile[64][65];
-  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-  const int t = threadIdx.x;
-  {
-    const int cg = t & 15, rg = t >> 4;
-    const int c = c0 + 4 * cg;
+                                                 long long ldr, int tcol, int n0, int mp, float dt) {
+  const int c4 = (cols + 3) / 4;                                  // runs per row
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= (long long)rows * c4) return;
+  const int r = (int)(e / c4), c = 4 * (int)(e % c4);
+  f32x4 v = *reinterpret_cast<const f32x4*>(src + (long long)r * lds + c);
+  if (scale) v = v * scale[r];
+  float o[4] = {v[0], v[1], v[2], v[3]};
+  const float t = rbf((float)(n0 + r / mp) * dt);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int rl = rg + 16 * q, r = r0 + rl;
-      f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (r < rows && c < cols) {
-        v = *reinterpret_cast<const f32x4*>(src + (long long)r * lds + c);
-        if (scale) v = v * scale[r];
-        if (rowm) *reinterpret_cast<uint2*>(rowm + (long long)r * ldr + c) = pack4(v[0], v[1], v[2], v[3]);
-      }
-      tile[rl][4 * cg] = v[0]; tile[rl][4 * cg + 1] = v[1]; tile[rl][4 * cg + 2] = v[2]; tile[rl][4 * cg + 3] = v[3];
-    }
-  }
-  if (!tr) return;
-  __syncthreads();
-  {
-    const int rg = t & 15, cg = t >> 4;
-    const int r = r0 + 4 * rg;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int cl = cg + 16 * q, c = c0 + cl;
-      if (c >= cols || r >= rows) continue;
-      const float a0 = tile[4 * rg][cl], a1 = tile[4 * rg + 1][cl], a2 = tile[4 * rg + 2][cl], a3 = tile[4 * rg + 3][cl];
-      uint16_t* o = tr + (long long)c * ldt + r;
-      if (r + 4 <= rows) {
-        *reinterpret_cast<uint2*>(o) = pack4(a0, a1, a2, a3);
-      } else {
-        const float av[4] = {a0, a1, a2, a3};
-        for (int e = 0; e < 4 && r + e < rows; ++e) o[e] = (uint16_t)bfbits(av[e]);
-      }
-    }
-  }
-  if (trow >= 0 && blockIdx.x == 0 && t < 64) {
-    const int r = r0 + t;
-    if (r < rows) tr[(long long)trow * ldt + r] = (uint16_t)bfbits((float)(n0 + r / mp) * dt);
-  }
+  for (int q = 0; q < 4; ++q)
+    if (c + q >= cols) o[q] = (c + q == tcol) ? t : 0.f;
+  *reinterpret_cast<uint2*>(rowm + (long long)r * ldr + c) = pack4(o[0], o[1], o[2], o[3]);
+  if (tcol >= 0 && (cols & 3) == 0 && c + 4 == cols) rowm[(long long)r * ldr + tcol] = (uint16_t)bfbits(t);
 }
 
 // ------------------------------------------------------ row epilogue
@@ -581,8 +637,9 @@ static unsigned grid1(long long n, long long cap = 65536) {
   return (unsigned)b;
 }
 
-// Launch with TM x TN wave tiles; `splits` > 1 splits the reduction (EPI_ACC only).
-template <int EPI, int TM, int TN, int WJ = RN_WJ>
+// Launch with TM x TN wave tiles; `splits` > 1 splits the reduction (EPI_ACC
+// only); KT: k-major operands (EPI_ACC only).
+template <int EPI, int TM, int TN, bool KT = false, int WJ = RN_WJ>
 static hipError_t gemm(Gm G, const Epi& E, int Mrows, int Ncols, int splits, hipStream_t s) {
   constexpr int BM = 32 * TM, BN = 16 * TN * WJ;
   G.kchunk = G.K;
@@ -594,7 +651,7 @@ static hipError_t gemm(Gm G, const Epi& E, int Mrows, int Ncols, int splits, hip
   G.tj = (Ncols + BN - 1) / BN;
   const long long nt = (long long)G.ti * G.tj * G.ts;
   if (nt <= 0) return hipSuccess;
-  k_gemm<EPI, TM, TN, WJ><<<(unsigned)nt, 128 * WJ, 0, s>>>(G, E);
+  k_gemm<EPI, TM, TN, WJ, KT><<<(unsigned)nt, 128 * WJ, 0, s>>>(G, E);
   return hipGetLastError();
 }
 
@@ -621,8 +678,8 @@ ResnetLayout resnet_layout(const Geo& g) {
   L.dq = (int)dq;
   L.pk_elems = w * dq + B * w * w + d * w + B * w * w + w * dq;
   L.pf_elems = 2 * w + B * w + d;
+  L.ldx = (int)((d + 1 + 7) / 8 * 8);
   L.rows = (long long)g.rn_chunk * g.M;
-  L.ldt = (L.rows + 7) / 8 * 8;
   L.nchunks = (g.N + g.rn_chunk - 1) / g.rn_chunk;
   L.kept = g.rn_store ? L.nchunks : 1;
   return L;
@@ -650,32 +707,31 @@ hipError_t resnet_pack(const Geo& g, const float* params, uint16_t* pk, float* p
 }
 
 static hipError_t convert(const float* src, long long lds, int rows, int cols, const float* scale, uint16_t* rowm,
-                          long long ldr, uint16_t* tr, long long ldt, int trow, int n0, int mp, float dt,
-                          hipStream_t s) {
-  dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
-  k_convert<<<grid, 256, 0, s>>>(src, lds, rows, cols, scale, rowm, ldr, tr, ldt, trow, n0, mp, dt);
+                          long long ldr, int tcol, int n0, int mp, float dt, hipStream_t s) {
+  const long long n = (long long)rows * ((cols + 3) / 4);
+  if (n <= 0) return hipSuccess;
+  k_convert<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, lds, rows, cols, scale, rowm, ldr, tcol, n0, mp, dt);
   return hipGetLastError();
 }
 
 // Forward of the rows of steps [n0, n0 + ns).  With `recompute` (reverse
-// sweep) it also keeps a_1..a_B and the transposed bf16 copies h_k^T and
-// [x; t]^T that the weight gradients read; with `with_output` it forms Z.
+// sweep) it also keeps a_1..a_B and the time column of [x; t] that the
+// weight gradients read; with `with_output` it forms Z.
 static hipError_t chunk_forward(const Geo& g, const ResnetLayout& L, const ResnetBufs& R, int n0, int ns,
                                 const float* X, bool with_output, bool recompute, hipStream_t s) {
   const int rows = ns * g.M, w = g.w, d = g.d, B = g.L;
   const float* wt = R.pf;
   const float* bin = R.pf + w;
   hipError_t e;
-  // bf16 x (and, for the reverse sweep, [x; t]^T)
-  if ((e = convert(X + (size_t)n0 * g.M * g.dp, g.dp, rows, d, nullptr, R.xb, L.dq, recompute ? R.xt : nullptr,
-                   L.ldt, d, n0, g.M, g.dt, s)) != hipSuccess)
+  // bf16 [x; t] (the GEMM below reads the first d columns)
+  if ((e = convert(X + (size_t)n0 * g.M * g.dp, g.dp, rows, d, nullptr, R.xb, L.ldx, recompute ? d : -1, n0, g.M,
+                   g.dt, s)) != hipSuccess)
     return e;
   {  // h0 = tanh(W_in [x; t] + b_in)
-    Gm G = gm(R.xb, L.dq, rows, pk_win(g, L, R.pk), L.dq, w, d);
+    Gm G = gm(R.xb, L.ldx, rows, pk_win(g, L, R.pk), L.dq, w, d);
     Epi E = epi0(rows, w);
     E.bias = bin; E.wt = wt; E.n0 = n0; E.mp = g.M; E.dt = g.dt;
     E.h32 = R.h32; E.ldh = w; E.ob = R.hb; E.ldb = w;
-    if (recompute) E.ot = R.ht, E.ldt = L.ldt;
     if ((e = gemm<EPI_TANH_IN, RN_TM, RN_TN>(G, E, rows, w, 1, s)) != hipSuccess) return e;
   }
   for (int k = 1; k <= B; ++k) {  // a_k = tanh(W_k h_{k-1} + b_k), h_k = h_{k-1} + a_k
@@ -684,10 +740,7 @@ static hipError_t chunk_forward(const Geo& g, const ResnetLayout& L, const Resne
     E.bias = R.pf + 2 * w + (size_t)(k - 1) * w;
     E.h32 = R.h32; E.ldh = w;
     E.ob = R.hb + (size_t)k * L.rows * w; E.ldb = w;
-    if (recompute) {
-      E.ab = R.ab + (size_t)(k - 1) * L.rows * w; E.lda = w;
-      E.ot = R.ht + (size_t)k * w * L.ldt; E.ldt = L.ldt;
-    }
+    if (recompute) E.ab = R.ab + (size_t)(k - 1) * L.rows * w, E.lda = w;
     if ((e = gemm<EPI_TANH_RES, RN_TM, RN_TN>(G, E, rows, w, 1, s)) != hipSuccess) return e;
   }
   if (with_output) {  // Z = W_o h_B + b_o
@@ -705,11 +758,10 @@ static hipError_t chunk_forward(const Geo& g, const ResnetLayout& L, const Resne
 static ResnetBufs chunk_view(const Geo& g, const ResnetLayout& L, const ResnetBufs& R, int c) {
   ResnetBufs V = R;
   if (L.kept > 1) {
-    const size_t w = (size_t)g.w, rows = (size_t)L.rows, ldt = (size_t)L.ldt;
+    const size_t w = (size_t)g.w, rows = (size_t)L.rows;
     V.hb += (size_t)c * (g.L + 1) * rows * w;
     V.ab += (size_t)c * g.L * rows * w;
-    V.ht += (size_t)c * (g.L + 1) * w * ldt;
-    V.xt += (size_t)c * (g.d + 1) * ldt;
+    V.xb += (size_t)c * rows * L.ldx;
   }
   return V;
 }
@@ -720,7 +772,7 @@ hipError_t resnet_forward(const Geo& g, const ResnetBufs& R, const float* X, flo
   for (int n0 = 0; n0 < g.N; n0 += g.rn_chunk) {
     const int ns = min(g.rn_chunk, g.N - n0);
     // when activations are kept, the forward pass also writes what the
-    // reverse sweep reads (a_k, h_k^T, [x; t]^T) into the chunk's own copy
+    // reverse sweep reads (a_k, [x; t]) into the chunk's own copy
     const ResnetBufs Rc = chunk_view(g, L, R, n0 / g.rn_chunk);
     if ((e = chunk_forward(g, L, Rc, n0, ns, X, true, g.rn_store != 0, s)) != hipSuccess) return e;
     const int rows = ns * g.M;
@@ -731,11 +783,11 @@ hipError_t resnet_forward(const Geo& g, const ResnetBufs& R, const float* X, flo
 }
 
 // Reverse sweep of every chunk (recomputing its activations unless the
-// forward pass kept them).  Weight
-// gradients are products over the chunk's rows of transposed bf16 copies
-// (g_k^T, h_k^T, zeta^T, [x; t]^T) and accumulate over chunks into `splits`
-// partial buffers of the flat parameter layout, one per reduction split of
-// each GEMM (fixed order: deterministic).
+// forward pass kept them).  Weight gradients are products over the chunk's
+// rows of the row-major bf16 activations read k-major (g_k, h_k, zeta,
+// [x; t]) and accumulate over chunks into `splits` partial buffers of the
+// flat parameter layout, one per reduction split of each GEMM (fixed order:
+// deterministic).
 hipError_t resnet_backward(const Geo& g, const ResnetBufs& R0, const float* X, const float* V, const float* LAM,
                            float* part, int splits, hipStream_t s) {
   const ResnetLayout L = resnet_layout(g);
@@ -753,37 +805,36 @@ hipError_t resnet_backward(const Geo& g, const ResnetBufs& R0, const float* X, c
       if ((e = chunk_forward(g, L, R, n0, ns, X, false, true, s)) != hipSuccess) return e;
     const float* Vc = V + (size_t)n0 * g.M * g.dp;
     const float* lam = LAM + (size_t)n0 * g.M;  // lambda_{n+1} of every row
-    // zeta = lambda v in bf16, row-major and transposed
-    if ((e = convert(Vc, g.dp, rows, d, lam, R.vb, L.dq, R.zt, L.ldt, -1, 0, 1, 0.f, s)) != hipSuccess) return e;
+    // zeta = lambda v in bf16
+    if ((e = convert(Vc, g.dp, rows, d, lam, R.vb, L.dq, -1, 0, 1, 0.f, s)) != hipSuccess) return e;
     int cur = 0;
     uint16_t* gb[2] = {R.gb, R.gb + (size_t)L.rows * w};
-    uint16_t* gt[2] = {R.gt, R.gt + (size_t)w * L.ldt};
     {  // delta_B = W_o^T zeta, zeta = lambda v;  g_B = delta_B (1 - a_B^2)
       Gm G = gm(R.vb, L.dq, rows, pk_wot(g, L, R.pk), L.dq, w, d);
       Epi E = epi0(rows, w);
-      E.h32 = R.d32; E.ldh = w; E.ob = gb[cur]; E.ldb = w; E.ot = gt[cur]; E.ldt = L.ldt;
+      E.h32 = R.d32; E.ldh = w; E.ob = gb[cur]; E.ldb = w;
       E.ab = R.ab + (size_t)(B - 1) * L.rows * w; E.lda = w;
       if ((e = gemm<EPI_BWD_FIRST, RN_TM, RN_TN>(G, E, rows, w, 1, s)) != hipSuccess) return e;
     }
     {  // dW_o += zeta^T h_B, db_o += sum zeta
-      Gm G = gm(R.zt, L.ldt, d, R.ht + (size_t)B * w * L.ldt, L.ldt, w, rows);
+      Gm G = gm(R.vb, L.dq, d, R.hb + (size_t)B * L.rows * w, w, w, rows);
       G.pstride = g.pstride;
       Epi E = epi0(d, w);
       E.part = part; E.base = offo; E.wcols = w;
-      if ((e = gemm<EPI_ACC, RN_TM, RN_TN>(G, E, d, w, splits, s)) != hipSuccess) return e;
+      if ((e = gemm<EPI_ACC, RN_TM, RN_TN, true>(G, E, d, w, splits, s)) != hipSuccess) return e;
     }
     for (int k = B; k >= 1; --k) {
       {  // dW_k += g_k^T h_{k-1}, db_k += sum g_k
-        Gm G = gm(gt[cur], L.ldt, w, R.ht + (size_t)(k - 1) * w * L.ldt, L.ldt, w, rows);
+        Gm G = gm(gb[cur], w, w, R.hb + (size_t)(k - 1) * L.rows * w, w, w, rows);
         G.pstride = g.pstride;
         Epi E = epi0(w, w);
         E.part = part; E.base = offk + (long long)(k - 1) * ((long long)w * w + w); E.wcols = w;
-        if ((e = gemm<EPI_ACC, RN_TM, RN_TN>(G, E, w, w, splits, s)) != hipSuccess) return e;
+        if ((e = gemm<EPI_ACC, RN_TM, RN_TN, true>(G, E, w, w, splits, s)) != hipSuccess) return e;
       }
       {  // delta_{k-1} = delta_k + W_k^T g_k;  g_{k-1} = delta_{k-1} (1 - a_{k-1}^2), a_0 := h_0
         Gm G = gm(gb[cur], w, rows, pk_wkt(g, L, R.pk, k), w, w, w);
         Epi E = epi0(rows, w);
-        E.h32 = R.d32; E.ldh = w; E.ob = gb[cur ^ 1]; E.ldb = w; E.ot = gt[cur ^ 1]; E.ldt = L.ldt;
+        E.h32 = R.d32; E.ldh = w; E.ob = gb[cur ^ 1]; E.ldb = w;
         E.ab = (k >= 2) ? R.ab + (size_t)(k - 2) * L.rows * w : R.hb;
         E.lda = w;
         if ((e = gemm<EPI_BWD_RES, RN_TM, RN_TN>(G, E, rows, w, 1, s)) != hipSuccess) return e;
@@ -791,11 +842,11 @@ hipError_t resnet_backward(const Geo& g, const ResnetBufs& R0, const float* X, c
       }
     }
     {  // dW_in += g_0^T [x; t], db_in += sum g_0
-      Gm G = gm(gt[cur], L.ldt, w, R.xt, L.ldt, d + 1, rows);
+      Gm G = gm(gb[cur], w, w, R.xb, L.ldx, d + 1, rows);
       G.pstride = g.pstride;
       Epi E = epi0(w, d + 1);
       E.part = part; E.base = 0; E.wcols = d + 1;
-      if ((e = gemm<EPI_ACC, RN_TM, RN_TN>(G, E, w, d + 1, splits, s)) != hipSuccess) return e;
+      if ((e = gemm<EPI_ACC, RN_TM, RN_TN, true>(G, E, w, d + 1, splits, s)) != hipSuccess) return e;
     }
   }
   return hipSuccess;
