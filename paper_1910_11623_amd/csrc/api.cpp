@@ -138,7 +138,7 @@ void make_layout(fbsde_plan* P) {
     w.RAB = take(kept * g.L * rows * wd * 2 + slack);
     w.RD32 = take(rows * wd * 4);
     w.RGB = take(2 * rows * wd * 2 + slack);
-    w.RZ = take(rows * (size_t)R.dq * 4);
+    w.RRP = take((size_t)R.ntj * 2 * rows * 4);
     w.RXB = take(kept * rows * (size_t)R.ldx * 2 + slack);
     w.RVB = take(rows * (size_t)R.dq * 2 + slack);
   }
@@ -240,7 +240,7 @@ fbsde::ResnetBufs resnet_bufs(const fbsde_plan* P, void* ws) {
   R.ab = at<uint16_t>(ws, L.RAB);
   R.d32 = at<float>(ws, L.RD32);
   R.gb = at<uint16_t>(ws, L.RGB);
-  R.z = at<float>(ws, L.RZ);
+  R.rp = at<float>(ws, L.RRP);
   R.xb = at<uint16_t>(ws, L.RXB);
   R.vb = at<uint16_t>(ws, L.RVB);
   return R;

@@ -54,6 +54,7 @@ struct ResnetLayout {
   long long pk_elems;     // bf16 packed weights (forward + transposed)
   long long pf_elems;     // fp32 time column and biases
   long long rows;         // rows per chunk = rn_chunk * M
+  int ntj;                // column tiles of the output GEMM (its per-row partial sums)
   int nchunks;            // row chunks per pass
   int kept;               // chunks whose activations have their own copy (1, or nchunks if stored)
 };
@@ -65,7 +66,7 @@ struct ResnetBufs {
   uint16_t* ab;           // [kept][B][rows][w] bf16 a_1..a_B
   float* d32;             // [rows][w] fp32 delta
   uint16_t* gb;           // [2][rows][w] bf16 pre-activation gradients (ping-pong)
-  float* z;               // [rows][dq] fp32 network output
+  float* rp;              // [ntj][2][rows] fp32 per-tile row sums of the output GEMM
   uint16_t* xb;           // [kept][rows][ldx] bf16 [x; t]
   uint16_t* vb;           // [rows][dq] bf16 zeta = lambda v
 };
@@ -126,7 +127,7 @@ hipError_t unet_nais_project(const Geo& g, const UnetBufs& B, float* params, flo
 // Offsets (bytes) of the sub-buffers of one workspace.
 struct WsLayout {
   size_t X, V, C, Y, LAM, QN, LN, H, DZ, DH, PF, PB, PBIAS, PART, RED, total;
-  size_t RPK, RPF, RH32, RHB, RAB, RD32, RGB, RZ, RXB, RVB;  // residual-network buffers
+  size_t RPK, RPF, RH32, RHB, RAB, RD32, RGB, RRP, RXB, RVB;  // residual-network buffers
   size_t UU, UZ, UUB, UZB, UH, UAL, UHH, UG, UHHB, UHB0, UALB, UHBAR, UABAR, UW0X, UW0T, UAK, URK, UEX, UET, UP,
       UABARW, UPART, ULP, UCB;  // u-network buffers
   int scan_blocks;

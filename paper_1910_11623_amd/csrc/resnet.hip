@@ -85,7 +85,7 @@ struct Gm {
 };
 
 // ------------------------------------------------------------- epilogues
-enum { EPI_STORE = 0,      // out32[i][j] = acc + bias[j]
+enum { EPI_ROW = 0,        // Z = acc + bias[j] consumed at once: v (in place of s) and per-row partial sums
        EPI_TANH_IN = 1,    // h0 = tanh(acc + bias[j] + t(i) w_t[j]): h32, hb (+ hT)
        EPI_TANH_RES = 2,   // a = tanh(acc + bias[j]), h += a: h32 (in place), hb (+ ab, hT)
        EPI_BWD_FIRST = 3,  // delta = acc, g = delta (1 - a^2): d32, gb, gT
@@ -101,8 +101,11 @@ struct Epi {
   float* h32; long long ldh;      // fp32 residual stream / delta [i][j]
   uint16_t* ob; long long ldb;    // bf16 output [i][j] (hb or gb)
   uint16_t* ab; long long lda;    // bf16 activation, out (EPI_TANH_RES, optional) or in (EPI_BWD_*)
-  float* out32; long long ldo;    // EPI_STORE
   float* part; long long base; int wcols;  // EPI_ACC: W[rows][wcols] at base, then the bias b[rows]
+  // EPI_ROW: row i of the chunk is row i of sv (s_n in, v_n out) and of x (row stride ldv); its two
+  // partial sums over the tile's columns go to rp[(j-tile) * 2 * rows + {0, rows} + i]
+  float* sv; const float* x; long long ldv; float* rp;
+  int drv; float p0;
 };
 
 __device__ __forceinline__ uint2 pack4(float a, float b, float c, float d) {
@@ -120,7 +123,8 @@ __device__ __forceinline__ uint2 pack4(float a, float b, float c, float d) {
 // past cols.  Loads of rows past `rows` and of columns past `cols` read a
 // clamped valid element; nothing is stored for them.
 template <int EPI, int TM, int TN>
-__device__ __forceinline__ void epilogue_tile(const Epi& E, const f32x4 (&acc)[TM][TN], int i0w, int j0w, int lane) {
+__device__ __forceinline__ void epilogue_tile(const Epi& E, const f32x4 (&acc)[TM][TN], int i0w, int j0w, int lane,
+                                              float* red) {
   const int jl = 4 * (lane >> 4);
   if constexpr (EPI == EPI_ACC) {
     // partial[i][j] += acc: 4 TN scalar read-modify-writes per row block
@@ -149,30 +153,59 @@ __device__ __forceinline__ void epilogue_tile(const Epi& E, const f32x4 (&acc)[T
           }
       }
     }
-  } else if constexpr (EPI == EPI_STORE) {
+  } else if constexpr (EPI == EPI_ROW) {
+    // Z = acc + b_o, then per (row, column) of the chunk the driver's Z-dependent terms: v = s + dt phi_z
+    // and the row sums of z s and of z x (BSB: phi = r (y - z.x)) or z z (HJB: phi = lam |z|^2).  The
+    // wave's sums over its 16 columns of each row go to `red` (LDS) for the workgroup's reduction.
     float bz[TN][4];
 #pragma unroll
     for (int b = 0; b < TN; ++b)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) bz[b][e] = E.bias ? E.bias[min(j0w + 16 * b + jl + e, E.cols - 1)] : 0.f;
+      for (int e = 0; e < 4; ++e) bz[b][e] = E.bias[min(j0w + 16 * b + jl + e, E.cols - 1)];
+    f32x4 sv[2][TN], xv[2][TN];
+    auto ld = [&](int a, f32x4 (&sr)[TN], f32x4 (&xr)[TN]) {
+      const int i = min(i0w + 16 * a + (lane & 15), E.rows - 1);
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int jc = min(j0w + 16 * b + jl, (int)E.ldv - 4);
+        sr[b] = *reinterpret_cast<const f32x4*>(E.sv + (long long)i * E.ldv + jc);
+        xr[b] = *reinterpret_cast<const f32x4*>(E.x + (long long)i * E.ldv + jc);
+      }
+    };
+    ld(0, sv[0], xv[0]);
+    const float hz = E.p0 * E.dt, hz2 = 2.f * E.p0 * E.dt;
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
+      if (a + 1 < TM) ld(a + 1, sv[(a + 1) & 1], xv[(a + 1) & 1]);
       const int i = i0w + 16 * a + (lane & 15);
-      if (i >= E.rows) continue;
+      float cz = 0.f, cx = 0.f;
 #pragma unroll
       for (int b = 0; b < TN; ++b) {
         const int j = j0w + 16 * b + jl;
+        const f32x4 sr = sv[a & 1][b], xr = xv[a & 1][b];
         float v[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = acc[a][b][e] + bz[b][e];
-        float* o = E.out32 + (long long)i * E.ldo + j;
-        if (j + 4 <= E.cols) {
-          *reinterpret_cast<f32x4*>(o) = f32x4{v[0], v[1], v[2], v[3]};
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (j + e < E.cols) o[e] = v[e];
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = j + e < E.cols;
+          const float z = acc[a][b][e] + bz[b][e];
+          v[e] = sr[e];
+          if (E.drv == 0) v[e] = sr[e] - hz * xr[e];
+          else if (E.drv == 1) v[e] = sr[e] + hz2 * z;
+          if (!ok) v[e] = sr[e];
+          cz += ok ? z * sr[e] : 0.f;
+          cx += ok ? (E.drv == 1 ? z * z : z * xr[e]) : 0.f;
         }
+        if (i < E.rows && j < E.cols)
+          *reinterpret_cast<f32x4*>(E.sv + (long long)i * E.ldv + j) = f32x4{v[0], v[1], v[2], v[3]};
+      }
+      // the 4 lanes of row i (lane % 16) sum their columns; lane < 16 keeps the wave's row sums
+      cz += __shfl_xor(cz, 16);
+      cx += __shfl_xor(cx, 16);
+      cz += __shfl_xor(cz, 32);
+      cx += __shfl_xor(cx, 32);
+      if (lane < 16) {
+        red[2 * (16 * a + lane)] = cz;
+        red[2 * (16 * a + lane) + 1] = cx;
       }
     }
   } else {
@@ -502,7 +535,24 @@ __global__ __launch_bounds__(128 * WJ) __attribute__((amdgpu_waves_per_eu(RN_WPE
   }
 #endif
   // lane: row i = 16a + lane % 16, columns j = 16b + 4 (lane / 16) + 0..3
-  epilogue_tile<EPI, TM, TN>(Ez, acc, i0 + wi * 16 * TM, j0 + wj * 16 * TN, lane);
+  // EPI_ROW: the LDS (free after the loop's last barrier) holds each wave's row sums [wj][row][2]
+  static_assert(EPI != EPI_ROW || 2 * WJ * BM * 4 <= (int)sizeof(smem), "row sums must fit the staging LDS");
+  float* red = reinterpret_cast<float*>(smem) + 2 * (wj * BM + wi * 16 * TM);
+  epilogue_tile<EPI, TM, TN>(Ez, acc, i0 + wi * 16 * TM, j0 + wj * 16 * TN, lane, red);
+  if constexpr (EPI == EPI_ROW) {
+    __syncthreads();
+    if (tid < BM && i0 + tid < E.rows) {  // the workgroup's sums over its BN columns, waves in order
+      const float* r = reinterpret_cast<const float*>(smem) + 2 * tid;
+      float cz = 0.f, cx = 0.f;
+#pragma unroll
+      for (int q = 0; q < WJ; ++q) {
+        cz += r[2 * q * BM];
+        cx += r[2 * q * BM + 1];
+      }
+      E.rp[(long long)jt * 2 * E.rows + i0 + tid] = cz;
+      E.rp[(long long)jt * 2 * E.rows + E.rows + i0 + tid] = cx;
+    }
+  }
   if constexpr (EPI == EPI_ACC) {
     if (rowsum) {
 #pragma unroll
@@ -542,38 +592,23 @@ __global__ __launch_bounds__(256) void k_convert(const float* __restrict__ src, 
   if (tcol >= 0 && (cols & 3) == 0 && c + 4 == cols) rowm[(long long)r * ldr + tcol] = (uint16_t)bfbits(t);
 }
 
-// ------------------------------------------------------ row epilogue
-// Per row r = (n, m) of a chunk: c_n = Z.s + dt (Z-part of phi), v_n = s + dt phi_z,
-// with one wave per row (lanes stride over the d columns, fixed-order reduction).
-__global__ __launch_bounds__(256) void k_row_epilogue(Geo g, int n0, int rows, const float* __restrict__ Z,
-                                                      long long ldz, const float* __restrict__ X,
-                                                      float* __restrict__ V, float* __restrict__ C) {
-  const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+// ------------------------------------------------------ row sums
+// c_n of row r of a chunk from the output GEMM's per-tile partial sums (in
+// j-tile order): c = sum z.s - dt r sum z.x (BSB), sum z.s + dt lam sum z.z
+// (HJB), sum z.s otherwise; C is indexed by the chunk's first row.
+__global__ __launch_bounds__(256) void k_csum(Geo g, int rows, int ntj, const float* __restrict__ rp,
+                                              float* __restrict__ C) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= rows) return;
-  const int n = n0 + r / g.M, m = r % g.M;
-  const size_t row = ((size_t)n * g.M + m) * g.dp;
   float cz = 0.f, cx = 0.f;
-  for (int i = lane; i < g.d; i += 64) {
-    const float z = Z[(long long)r * ldz + i];
-    const float s = V[row + i];
-    const float x = X[row + i];
-    cz += z * s;
-    float v = s;
-    if (g.drv == 0) {  // BSB: phi = r (y - z.x)
-      cx += z * x;
-      v = s - g.drv_p0 * g.dt * x;
-    } else if (g.drv == 1) {  // HJB: phi = lam |z|^2
-      cx += z * z;
-      v = s + 2.f * g.drv_p0 * g.dt * z;
-    }
-    V[row + i] = v;
+  for (int q = 0; q < ntj; ++q) {
+    cz += rp[(long long)q * 2 * rows + r];
+    cx += rp[(long long)q * 2 * rows + rows + r];
   }
   float c = cz;
   if (g.drv == 0) c -= g.dt * g.drv_p0 * cx;
   else if (g.drv == 1) c += g.dt * g.drv_p0 * cx;
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  if (lane == 0) C[(size_t)n * g.M + m] = c;
+  C[r] = c;
 }
 
 // ------------------------------------------------------------ packing
@@ -680,6 +715,7 @@ ResnetLayout resnet_layout(const Geo& g) {
   L.pf_elems = 2 * w + B * w + d;
   L.ldx = (int)((d + 1 + 7) / 8 * 8);
   L.rows = (long long)g.rn_chunk * g.M;
+  L.ntj = (int)((d + 16 * RN_TN * RN_WJ - 1) / (16 * RN_TN * RN_WJ));
   L.nchunks = (g.N + g.rn_chunk - 1) / g.rn_chunk;
   L.kept = g.rn_store ? L.nchunks : 1;
   return L;
@@ -716,9 +752,11 @@ static hipError_t convert(const float* src, long long lds, int rows, int cols, c
 
 // Forward of the rows of steps [n0, n0 + ns).  With `recompute` (reverse
 // sweep) it also keeps a_1..a_B and the time column of [x; t] that the
-// weight gradients read; with `with_output` it forms Z.
+// weight gradients read; with `with_output` it forms Z and from it v_n
+// (over s_n in V) and c_n (C).
 static hipError_t chunk_forward(const Geo& g, const ResnetLayout& L, const ResnetBufs& R, int n0, int ns,
-                                const float* X, bool with_output, bool recompute, hipStream_t s) {
+                                const float* X, float* V, float* C, bool with_output, bool recompute,
+                                hipStream_t s) {
   const int rows = ns * g.M, w = g.w, d = g.d, B = g.L;
   const float* wt = R.pf;
   const float* bin = R.pf + w;
@@ -743,12 +781,16 @@ static hipError_t chunk_forward(const Geo& g, const ResnetLayout& L, const Resne
     if (recompute) E.ab = R.ab + (size_t)(k - 1) * L.rows * w, E.lda = w;
     if ((e = gemm<EPI_TANH_RES, RN_TM, RN_TN>(G, E, rows, w, 1, s)) != hipSuccess) return e;
   }
-  if (with_output) {  // Z = W_o h_B + b_o
+  if (with_output) {  // Z = W_o h_B + b_o, consumed at once: v_n (over s_n in V) and c_n (C)
+    const size_t r0 = (size_t)n0 * g.M;
     Gm G = gm(R.hb + (size_t)B * L.rows * w, w, rows, pk_wo(g, L, R.pk), w, d, w);
     Epi E = epi0(rows, d);
     E.bias = R.pf + 2 * w + (size_t)B * w;
-    E.out32 = R.z; E.ldo = L.dq;
-    if ((e = gemm<EPI_STORE, RN_TM, RN_TN>(G, E, rows, d, 1, s)) != hipSuccess) return e;
+    E.sv = V + r0 * g.dp; E.x = X + r0 * g.dp; E.ldv = g.dp; E.rp = R.rp;
+    E.drv = g.drv; E.p0 = g.drv_p0; E.dt = g.dt;
+    if ((e = gemm<EPI_ROW, RN_TM, RN_TN>(G, E, rows, d, 1, s)) != hipSuccess) return e;
+    k_csum<<<(unsigned)((rows + 255) / 256), 256, 0, s>>>(g, rows, L.ntj, R.rp, C + r0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -774,10 +816,7 @@ hipError_t resnet_forward(const Geo& g, const ResnetBufs& R, const float* X, flo
     // when activations are kept, the forward pass also writes what the
     // reverse sweep reads (a_k, [x; t]) into the chunk's own copy
     const ResnetBufs Rc = chunk_view(g, L, R, n0 / g.rn_chunk);
-    if ((e = chunk_forward(g, L, Rc, n0, ns, X, true, g.rn_store != 0, s)) != hipSuccess) return e;
-    const int rows = ns * g.M;
-    k_row_epilogue<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(g, n0, rows, R.z, L.dq, X, V, C);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = chunk_forward(g, L, Rc, n0, ns, X, V, C, true, g.rn_store != 0, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -802,7 +841,7 @@ hipError_t resnet_backward(const Geo& g, const ResnetBufs& R0, const float* X, c
     const int rows = ns * g.M;
     const ResnetBufs R = chunk_view(g, L, R0, n0 / g.rn_chunk);
     if (!g.rn_store)  // checkpointed: recompute the chunk's activations
-      if ((e = chunk_forward(g, L, R, n0, ns, X, false, true, s)) != hipSuccess) return e;
+      if ((e = chunk_forward(g, L, R, n0, ns, X, nullptr, nullptr, false, true, s)) != hipSuccess) return e;
     const float* Vc = V + (size_t)n0 * g.M * g.dp;
     const float* lam = LAM + (size_t)n0 * g.M;  // lambda_{n+1} of every row
     // zeta = lambda v in bf16
