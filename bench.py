@@ -101,10 +101,9 @@ def time_library(prec: str, steps: int, warmup: int, min_samples: int = 100):
            torch.empty((), dtype=torch.float64, device="cuda"))
     k_next = [0]
 
-    def step():
+    def step():  # forward + reverse sweep + Adam (fbsde_train_step: the reduction applies the update)
         k = k_next[0]
-        plan.forward_backward(params, y0, 1, k, out=out)
-        plan.adam_step(params, y0, out[1], out[2], m, v, my, vy, k + 1, lr=1e-3, lr_y0=1e-2)
+        plan.train_step(params, y0, out[1], out[2], out[0], m, v, my, vy, 1, k, k + 1, lr=1e-3, lr_y0=1e-2)
         k_next[0] = k + 1
 
     for _ in range(warmup):
@@ -196,7 +195,7 @@ def measured_traffic(kernel: str, prec: str):
 # Kernel-name prefix -> the roofline keys the bench uses
 _TRAFFIC_KEYS = {"k_pack": "pack", "k_pack_sde": "sde", "k_sde": "sde", "k_forward": "forward", "k_scan": "scan",
                  "k_backward": "backward", "k_wgrad": "wgrad", "k_reverse": "reverse", "k_reverse_bf": "reverse",
-                 "k_reduce": "reduce", "k_adam": "adam"}
+                 "k_reduce": "reduce", "k_reduce_adam": "reduce", "k_adam": "adam"}
 
 
 def reverse_kernels(kern_ms: dict) -> dict:

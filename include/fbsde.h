@@ -20,7 +20,8 @@
  *     named *_host are host memory.  `stream` is a hipStream_t (NULL = the
  *     null stream); hot calls are asynchronous on it.
  *   - Hot calls (fbsde_forward, fbsde_forward_backward, fbsde_adam_step,
- *     fbsde_prolong, fbsde_sample_normals, fbsde_terminal_mean) allocate
+ *     fbsde_train_step, fbsde_prolong, fbsde_sample_normals,
+ *     fbsde_terminal_mean) allocate
  *     nothing: all scratch lives in the caller's workspace of
  *     fbsde_workspace_size bytes (256-byte aligned).  One workspace must not
  *     be used by two calls that overlap in time.
@@ -31,7 +32,8 @@
  *     (in the reductions of fbsde_forward / fbsde_forward_backward) and
  *     raises a flag in pinned host memory owned by the plan.  The next hot
  *     call on that plan (fbsde_forward, fbsde_forward_backward,
- *     fbsde_adam_step, or fbsde_batch_step of a batch that holds it) returns
+ *     fbsde_adam_step, fbsde_train_step, or fbsde_batch_step of a batch that
+ *     holds it) returns
  *     FBSDE_ERR_NONFINITE without launching anything and clears the flag; no
  *     call synchronises to check it, so the report arrives once the
  *     offending work has completed.
@@ -194,6 +196,23 @@ fbsde_status fbsde_adam_step(fbsde_plan *plan, float *params_dev, double *y0_dev
                              const float *grad_dev, const double *grad_y0_dev, float *m_dev,
                              float *v_dev, double *m_y0_dev, double *v_y0_dev, int64_t t, double lr,
                              double lr_y0, double beta1, double beta2, double eps, void *stream);
+
+/* One training iteration (Sec. 2.2 loss, trained with Adam as in Sec. 4):
+ * fbsde_forward_backward of iteration `iter` followed by fbsde_adam_step
+ * with step count t, giving the same bits in every output (loss, gradients,
+ * parameters, y0 and the moments), with the gradient reduction and the Adam
+ * update in one launch.  grad_dev and grad_y0_dev still receive the
+ * gradients.  Unlike fbsde_adam_step after a separate fbsde_forward_backward,
+ * the update is applied even when this iteration's loss or gradient is
+ * non-finite (the device cannot stop it); the next hot call on the plan
+ * reports FBSDE_ERR_NONFINITE, as for fbsde_batch_step.  Every pointer is
+ * required.  Errors: INVALID (NULL buffer, t < 1, hyper-parameters out of
+ * range), UNSUPPORTED (u-network plans). */
+fbsde_status fbsde_train_step(fbsde_plan *plan, float *params_dev, double *y0_dev, float *grad_dev,
+                              double *grad_y0_dev, double *loss_dev, float *m_dev, float *v_dev,
+                              double *m_y0_dev, double *v_y0_dev, int64_t t, double lr, double lr_y0,
+                              double beta1, double beta2, double eps, uint64_t seed, uint64_t iter,
+                              void *ws_dev, void *stream);
 
 /* Multilevel warm start (Sec. 3.2): copy the parameters of a plan with Nc
  * steps into a plan with Nf = 2 Nc steps of the same problem and network.

@@ -22,7 +22,7 @@ PREC = {"fp32": 0, "bf16": 1}
 
 EXPORTS = [
     "fbsde_plan_create", "fbsde_plan_destroy", "fbsde_param_count", "fbsde_param_layout", "fbsde_workspace_size",
-    "fbsde_forward", "fbsde_forward_backward", "fbsde_adam_step", "fbsde_prolong",
+    "fbsde_forward", "fbsde_forward_backward", "fbsde_adam_step", "fbsde_train_step", "fbsde_prolong",
     "fbsde_sample_normals", "fbsde_terminal_mean", "fbsde_terminal_states",
     "fbsde_profile_enable", "fbsde_profile_read", "fbsde_plan_config", "fbsde_plan_get_config",
     "fbsde_plan_autotune", "fbsde_plan_set_checkpointing", "fbsde_plan_status", "fbsde_batch_create", "fbsde_batch_step", "fbsde_batch_destroy",
@@ -84,6 +84,8 @@ def load(path: str = LIB_PATH):
     L.fbsde_forward_backward.argtypes = [vp, vp, vp, vp, vp, vp, u64, u64, vp, vp]
     L.fbsde_adam_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, C.c_double, C.c_double,
                                   C.c_double, C.c_double, C.c_double, vp]
+    L.fbsde_train_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, C.c_double, C.c_double,
+                                   C.c_double, C.c_double, C.c_double, u64, u64, vp, vp]
     L.fbsde_prolong.argtypes = [vp, vp, vp, vp, vp]
     L.fbsde_sample_normals.argtypes = [vp, u64, u64, vp, vp]
     L.fbsde_terminal_mean.argtypes = [vp, u64, u64, vp, vp, vp]

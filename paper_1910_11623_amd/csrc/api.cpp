@@ -385,7 +385,22 @@ fbsde_status run_forward(fbsde_plan* P, const float* params, const double* y0, u
   return FBSDE_OK;
 }
 
-fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double* loss, void* ws, hipStream_t s) {
+// Sum of the split partials into grad, loss and dL/dY0 (and the Adam step
+// when `adam` is given).
+hipError_t reduce_tail(fbsde_plan* plan, float* grad, double* grad_y0, double* loss, void* ws, hipStream_t s,
+                       const fbsde::AdamArgs* adam) {
+  const WsLayout& L = plan->ws;
+  if (adam)
+    return fbsde::launch_reduce_adam(plan->geo, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
+                                     L.scan_blocks, loss, grad_y0, plan->nf_host, *adam, s);
+  return fbsde::launch_reduce(plan->geo, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
+                              L.scan_blocks, loss, grad_y0, plan->nf_host, s);
+}
+
+// The reverse sweep and the gradient reduction; with `adam` the reduction
+// also applies the Adam step (one launch).
+fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double* loss, void* ws, hipStream_t s,
+                          const fbsde::AdamArgs* adam = nullptr) {
   const Geo& g = plan->geo;
   const WsLayout& L = plan->ws;
   hipError_t e;
@@ -397,9 +412,7 @@ fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double
         return hip_fail(e, "backward");
     }
     ProfScope ps(plan, FBSDE_PROF_REDUCE, s);
-    if ((e = fbsde::launch_reduce(g, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
-                                  L.scan_blocks, loss, grad_y0, plan->nf_host, s)) != hipSuccess)
-      return hip_fail(e, "reduce");
+    if ((e = reduce_tail(plan, grad, grad_y0, loss, ws, s, adam)) != hipSuccess) return hip_fail(e, "reduce");
     return FBSDE_OK;
   }
   if (fbsde::reverse_fused_preferred(g, L.splits)) {
@@ -423,9 +436,7 @@ fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double
   }
   {
     ProfScope ps(plan, FBSDE_PROF_REDUCE, s);
-    if ((e = fbsde::launch_reduce(g, at<float>(ws, L.PART), L.splits, grad, at<double>(ws, L.RED),
-                                  L.scan_blocks, loss, grad_y0, plan->nf_host, s)) != hipSuccess)
-      return hip_fail(e, "reduce");
+    if ((e = reduce_tail(plan, grad, grad_y0, loss, ws, s, adam)) != hipSuccess) return hip_fail(e, "reduce");
   }
   return FBSDE_OK;
 }
@@ -739,6 +750,25 @@ fbsde_status fbsde_adam_step(fbsde_plan* plan, float* params, double* y0, const 
                                     (double)t, nullptr, lr_y0, b1, b2, eps, reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "adam");
   return FBSDE_OK;
+}
+
+fbsde_status fbsde_train_step(fbsde_plan* plan, float* params, double* y0, float* grad, double* grad_y0,
+                              double* loss, float* m, float* v, double* m_y0, double* v_y0, int64_t t, double lr,
+                              double lr_y0, double b1, double b2, double eps, uint64_t seed, uint64_t iter, void* ws,
+                              void* stream) {
+  fbsde_status st = check_hot(plan, ws);
+  if (st != FBSDE_OK) return st;
+  if (plan->geo.kind == 2) return fail(FBSDE_ERR_UNSUPPORTED, "u-network plans use fbsde_unet_forward_backward");
+  if (!params || !y0 || !grad || !grad_y0 || !loss || !m || !v || !m_y0 || !v_y0)
+    return fail(FBSDE_ERR_INVALID, "every buffer must be non-NULL");
+  if (t < 1) return fail(FBSDE_ERR_INVALID, "Adam step count must be >= 1");
+  if (!(lr >= 0) || !(lr_y0 >= 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+    return fail(FBSDE_ERR_INVALID, "Adam hyper-parameters out of range");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  st = run_forward(plan, params, y0, seed, iter, nullptr, ws, s);
+  if (st != FBSDE_OK) return st;
+  const fbsde::AdamArgs a = {params, m, v, y0, m_y0, v_y0, lr, (double)t, nullptr, lr_y0, b1, b2, eps};
+  return run_backward(plan, grad, grad_y0, loss, ws, s, &a);
 }
 
 fbsde_status fbsde_plan_set_unet_loss(fbsde_plan* plan, double kappa, double eps) {
@@ -1095,13 +1125,10 @@ void batch_free(fbsde_batch* b) {
 fbsde_status batch_item_step(fbsde_batch* b, const fbsde_batch_item& it, hipStream_t s) {
   fbsde_status st = run_forward(it.plan, it.params_dev, it.y0_dev, it.seed, 0, b->iter_dev, it.ws_dev, s);
   if (st != FBSDE_OK) return st;
-  st = run_backward(it.plan, it.grad_dev, it.grad_y0_dev, it.loss_dev, it.ws_dev, s);
-  if (st != FBSDE_OK) return st;
-  hipError_t e = fbsde::launch_adam(it.plan->geo.nparams, it.params_dev, it.grad_dev, it.m_dev, it.v_dev,
-                                    it.y0_dev, it.grad_y0_dev, it.m_y0_dev, it.v_y0_dev, (float)b->lr, 1.0,
-                                    b->iter_dev, b->lr_y0, b->b1, b->b2, b->eps, s);
-  if (e != hipSuccess) return hip_fail(e, "adam");
-  return FBSDE_OK;
+  // the reduction applies Adam (step iter_dev[0] + 1) in the same launch
+  const fbsde::AdamArgs a = {it.params_dev, it.m_dev, it.v_dev, it.y0_dev, it.m_y0_dev, it.v_y0_dev,
+                             b->lr, 1.0, b->iter_dev, b->lr_y0, b->b1, b->b2, b->eps};
+  return run_backward(it.plan, it.grad_dev, it.grad_y0_dev, it.loss_dev, it.ws_dev, s, &a);
 }
 
 }  // namespace

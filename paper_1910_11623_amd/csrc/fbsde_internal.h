@@ -165,6 +165,19 @@ hipError_t launch_reverse(const Geo& g, const void* packB, const float* X, const
 // the loss, dL/dY0) into *host_flag (pinned host memory) and clears it.
 hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* grad, double* scan_part,
                          int scan_blocks, double* loss, double* grad_y0, int* host_flag, hipStream_t s);
+// Adam state and hyper-parameters of one step (y0, my0, vy0 may be null
+// together: no scalar y0 to train).
+struct AdamArgs {
+  float *p, *m, *v;
+  double *y0, *my0, *vy0;
+  double lr, t;
+  const uint64_t* t_dev;  // step read on the device (t_dev[0] + 1) when non-null
+  double lr_y0, b1, b2, eps;
+};
+// launch_reduce followed by Adam on params and y0, in one launch
+hipError_t launch_reduce_adam(const Geo& g, const float* part, int splits, float* grad, double* scan_part,
+                              int scan_blocks, double* loss, double* grad_y0, int* host_flag, const AdamArgs& a,
+                              hipStream_t s);
 hipError_t launch_loss_only(const Geo& g, double* scan_part, int scan_blocks, double* loss, int* host_flag,
                             hipStream_t s);
 hipError_t launch_adam(long long n, float* p, const float* gr, float* m, float* v, double* y0,

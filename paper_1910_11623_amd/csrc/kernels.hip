@@ -850,8 +850,6 @@ __global__ __launch_bounds__(64) void k_scan(Geo g, const double* __restrict__ y
   if (threadIdx.x == 0) {
     part[2 * blockIdx.x] = a;
     part[2 * blockIdx.x + 1] = b;
-    // the non-finite flag after the partials starts every iteration clear
-    if (blockIdx.x == 0) reinterpret_cast<int*>(part + 2 * gridDim.x)[0] = 0;
   }
 }
 
@@ -2005,6 +2003,33 @@ __global__ __launch_bounds__(64) void k_finalize(int M, const double* __restrict
 // -------------------------------------------------------------- Adam kernel
 // Adam step t (bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t).  With t_dev
 // non-null, t = t_dev[0] + 1 is read on the device (graph replays).
+// Adam arithmetic shared by k_adam and the fused reduction + Adam kernel, so
+// that both give the same bits: bias corrections c1 = 1 - b1^t and
+// c2 = 1 - b2^t (t = t_dev[0] + 1 on the device for graph replays), the
+// fp32 parameter update and the fp64 update of y0.
+__device__ __forceinline__ void adam_corr(double t_imm, const uint64_t* t_dev, double b1d, double b2d, double* corr) {
+  const double t = t_dev ? (double)(t_dev[0] + 1) : t_imm;
+  corr[0] = 1.0 - pow(b1d, t);
+  corr[1] = 1.0 - pow(b2d, t);
+}
+// The moment updates are written as explicit fused multiply-adds: left to
+// the compiler, which product it fuses can differ between two kernels that
+// inline the same expression.
+__device__ __forceinline__ float adam_upd(float pi, float gi, float& mi, float& vi, float lr, float b1, float b2,
+                                          float eps, float c1, float c2) {
+  mi = fmaf(b1, mi, (1.f - b1) * gi);
+  vi = fmaf(b2, vi, ((1.f - b2) * gi) * gi);
+  return pi - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+__device__ __forceinline__ void adam_y0(double gi, double* y0, double* my0, double* vy0, double lr_y0, double b1d,
+                                        double b2d, double epsd, double c1d, double c2d) {
+  const double mi = fma(b1d, my0[0], (1.0 - b1d) * gi);
+  const double vi = fma(b2d, vy0[0], ((1.0 - b2d) * gi) * gi);
+  my0[0] = mi;
+  vy0[0] = vi;
+  y0[0] -= lr_y0 * (mi / c1d) / (sqrt(vi / c2d) + epsd);
+}
+
 __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p, const float* __restrict__ gr,
                                               float* __restrict__ m, float* __restrict__ v,
                                               double* __restrict__ y0, const double* __restrict__ gy0,
@@ -2029,19 +2054,11 @@ __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p
   // bias corrections: one evaluation per workgroup, shared through LDS (the
   // same device code for an immediate step count and a device-side counter)
   __shared__ double corr[2];
-  if (threadIdx.x == 0) {
-    const double t = t_dev ? (double)(t_dev[0] + 1) : t_imm;
-    corr[0] = 1.0 - pow(b1d, t);
-    corr[1] = 1.0 - pow(b2d, t);
-  }
+  if (threadIdx.x == 0) adam_corr(t_imm, t_dev, b1d, b2d, corr);
   __syncthreads();
   const double c1d = corr[0], c2d = corr[1];
   const float c1 = (float)c1d, c2 = (float)c2d;
-  auto upd = [&](float pi, float gi, float& mi, float& vi) {
-    mi = b1 * mi + (1.f - b1) * gi;
-    vi = b2 * vi + (1.f - b2) * gi * gi;
-    return pi - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-  };
+  auto upd = [&](float pi, float gi, float& mi, float& vi) { return adam_upd(pi, gi, mi, vi, lr, b1, b2, eps, c1, c2); };
   for (long long i = i0; i < n4; i += (long long)gridDim.x * 256) {
     if (i != i0) {
       P4 = reinterpret_cast<const f32x4*>(p)[i];
@@ -2066,14 +2083,79 @@ __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p
     m[i] = mi;
     v[i] = vi;
   }
-  if (i0 == 0 && y0) {
-    const double gi = gy0[0];
-    const double mi = b1d * my0[0] + (1.0 - b1d) * gi;
-    const double vi = b2d * vy0[0] + (1.0 - b2d) * gi * gi;
-    my0[0] = mi;
-    vy0[0] = vi;
-    y0[0] -= lr_y0 * (mi / c1d) / (sqrt(vi / c2d) + epsd);
+  if (i0 == 0 && y0) adam_y0(gy0[0], y0, my0, vy0, lr_y0, b1d, b2d, epsd, c1d, c2d);
+}
+
+// One training step's tail in one launch: workgroups [0, nred) sum the
+// split partials of 4 elements per thread into grad (as k_reduce) and apply
+// Adam to those elements at once (as k_adam); workgroup nred forms the loss
+// and dY0 (as k_reduce's last workgroup) and applies Adam to y0.  Non-finite
+// sums raise the host flag; the update is applied regardless.
+__global__ __launch_bounds__(256) void k_reduce_adam(long long P, long long stride, const float* __restrict__ part,
+                                                     int splits, float* __restrict__ grad, int nred, int M,
+                                                     const double* __restrict__ sp, int nb, double* __restrict__ loss,
+                                                     double* __restrict__ gy0, int* __restrict__ host_flag,
+                                                     float* __restrict__ p, float* __restrict__ m,
+                                                     float* __restrict__ v, double* __restrict__ y0,
+                                                     double* __restrict__ my0, double* __restrict__ vy0, float lr,
+                                                     double t_imm, const uint64_t* __restrict__ t_dev, double lr_y0,
+                                                     double b1d, double b2d, double epsd) {
+  __shared__ double corr[2];
+  if ((int)blockIdx.x == nred) {
+    if (threadIdx.x == 0) adam_corr(t_imm, t_dev, b1d, b2d, corr);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      finalize_wave(M, sp, nb, loss, gy0, host_flag);
+      if (threadIdx.x == 0 && y0) adam_y0(gy0[0], y0, my0, vy0, lr_y0, b1d, b2d, epsd, corr[0], corr[1]);
+    }
+    return;
   }
+  bool bad = false;
+  const long long t0 = blockIdx.x * 256LL + threadIdx.x, step = (long long)nred * 256;
+  const bool vec = ((reinterpret_cast<uintptr_t>(grad) | reinterpret_cast<uintptr_t>(p) |
+                     reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v)) & 15) == 0;
+  const long long P4 = vec ? P / 4 : 0;
+  // the first element's sum is formed before the bias corrections are known,
+  // so the partial loads overlap the workgroup's pow evaluations
+  auto sum4 = [&](long long e4) {
+    f32x4 s = zero4();
+    for (int k = 0; k < splits; ++k) s += ld4(part + (size_t)k * stride + 4 * e4);
+    return s;
+  };
+  f32x4 s0 = zero4();
+  if (t0 < P4) s0 = sum4(t0);
+  if (threadIdx.x == 0) adam_corr(t_imm, t_dev, b1d, b2d, corr);
+  __syncthreads();
+  const double c1d = corr[0], c2d = corr[1];
+  const float b1 = (float)b1d, b2 = (float)b2d, eps = (float)epsd, c1 = (float)c1d, c2 = (float)c2d;
+  for (long long e4 = t0; e4 < P4; e4 += step) {
+    const f32x4 s = e4 == t0 ? s0 : sum4(e4);
+    st4(grad + 4 * e4, s);
+    bad |= !(isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2]) && isfinite(s[3]));
+    f32x4 P4v = reinterpret_cast<const f32x4*>(p)[e4], M4 = reinterpret_cast<const f32x4*>(m)[e4],
+          V4 = reinterpret_cast<const f32x4*>(v)[e4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float mi = M4[r], vi = V4[r];
+      P4v[r] = adam_upd(P4v[r], s[r], mi, vi, lr, b1, b2, eps, c1, c2);
+      M4[r] = mi;
+      V4[r] = vi;
+    }
+    reinterpret_cast<f32x4*>(m)[e4] = M4;
+    reinterpret_cast<f32x4*>(v)[e4] = V4;
+    reinterpret_cast<f32x4*>(p)[e4] = P4v;
+  }
+  for (long long e = 4 * P4 + t0; e < P; e += step) {
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part[(size_t)k * stride + e];
+    grad[e] = s;
+    bad |= !isfinite(s);
+    float mi = m[e], vi = v[e];
+    p[e] = adam_upd(p[e], s, mi, vi, lr, b1, b2, eps, c1, c2);
+    m[e] = mi;
+    v[e] = vi;
+  }
+  if (bad && host_flag) host_flag[0] = 1;  // every writer stores the same value
 }
 
 __global__ void k_count(uint64_t* __restrict__ c) {
@@ -2458,6 +2540,16 @@ hipError_t launch_reduce(const Geo& g, const float* part, int splits, float* gra
   const unsigned nred = grid1((g.nparams + 3) / 4, 4096);
   k_reduce<<<nred + 1, 256, 0, s>>>(g.nparams, g.pstride, part, splits, grad, (int)nred, g.M, scan_part,
                                     scan_blocks, loss, grad_y0, host_flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_adam(const Geo& g, const float* part, int splits, float* grad, double* scan_part,
+                              int scan_blocks, double* loss, double* grad_y0, int* host_flag, const AdamArgs& a,
+                              hipStream_t s) {
+  const unsigned nred = grid1((g.nparams + 3) / 4, 4096);
+  k_reduce_adam<<<nred + 1, 256, 0, s>>>(g.nparams, g.pstride, part, splits, grad, (int)nred, g.M, scan_part,
+                                         scan_blocks, loss, grad_y0, host_flag, a.p, a.m, a.v, a.y0, a.my0, a.vy0,
+                                         (float)a.lr, a.t, a.t_dev, a.lr_y0, a.b1, a.b2, a.eps);
   return hipGetLastError();
 }
 

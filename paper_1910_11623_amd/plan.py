@@ -113,6 +113,17 @@ class Plan:
                                          float(lr if lr_y0 is None else lr_y0), float(b1), float(b2),
                                          float(eps), _stream()))
 
+    def train_step(self, params, y0, grad, gy0, loss, m, v, my0, vy0, seed: int, it: int, t: int,
+                   lr: float = 1e-3, lr_y0: float | None = None, b1: float = 0.9, b2: float = 0.999,
+                   eps: float = 1e-8):
+        """forward_backward of iteration `it` then adam_step with step count t,
+        the reduction and the update in one launch (same bits)."""
+        self._check_params(params)
+        B.check(self.lib.fbsde_train_step(self._h, _ptr(params), _ptr(y0), _ptr(grad), _ptr(gy0), _ptr(loss),
+                                          _ptr(m), _ptr(v), _ptr(my0), _ptr(vy0), int(t), float(lr),
+                                          float(lr if lr_y0 is None else lr_y0), float(b1), float(b2),
+                                          float(eps), seed, it, _ptr(self.ws), _stream()))
+
     def prolong_to(self, fine: "Plan", params: torch.Tensor) -> torch.Tensor:
         self._check_params(params)
         out = torch.empty(fine.n_params, dtype=torch.float32, device=self.device)
@@ -252,6 +263,11 @@ class TrainState:
         self.plan.forward_backward(self.params, self.y0, seed, it, out=(self.loss, self.grad, self.gy0))
         self.plan.adam_step(self.params, self.y0, self.grad, self.gy0, self.m, self.v, self.my0, self.vy0,
                             it + 1, lr=lr, lr_y0=lr_y0, b1=b1, b2=b2, eps=eps)
+
+    def fused_step(self, seed: int, it: int, lr=1e-3, lr_y0=1e-2, b1=0.9, b2=0.999, eps=1e-8):
+        """eager_step as one library call (fbsde_train_step): the same bits."""
+        self.plan.train_step(self.params, self.y0, self.grad, self.gy0, self.loss, self.m, self.v, self.my0,
+                             self.vy0, seed, it, it + 1, lr=lr, lr_y0=lr_y0, b1=b1, b2=b2, eps=eps)
 
 
 class Batch:

@@ -139,8 +139,9 @@ def _run_iters(P: Plan, params, y0, st: _AdamState, k0, iters, lr, lr_y0, seed, 
     """Iterations k0 .. k0 + iters - 1 of a level (Adam step count k + 1),
     updating params and y0 in place."""
     for k in range(k0, k0 + iters):
-        P.forward_backward(params, y0, seed, it0 + k, out=(st.loss, st.grad, st.gy))
-        P.adam_step(params, y0, st.grad, st.gy, st.m, st.v, st.my, st.vy, k + 1, lr=lr, lr_y0=lr_y0)
+        # forward_backward + adam_step as one call (same bits)
+        P.train_step(params, y0, st.grad, st.gy, st.loss, st.m, st.v, st.my, st.vy, seed, it0 + k, k + 1, lr=lr,
+                     lr_y0=lr_y0)
         if llog is not None:
             llog[k].copy_(st.loss, non_blocking=True)
             ylog[k].copy_(y0, non_blocking=True)
