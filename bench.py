@@ -776,7 +776,7 @@ def batch_leg(steps: int = 20):
 
     def eager():
         for s, seed in zip(states, seeds):
-            s.eager_step(seed, it[0], lr=LR_AC)
+            s.fused_step(seed, it[0], lr=LR_AC)
         it[0] += 1
 
     def all_finite():
@@ -822,12 +822,12 @@ def hjb_leg(steps: int = 20):
         plan = Plan(prob, net, 20, 65536)
         s = TrainState(plan, I.init_params(prob, net, 20, seed=0), 4.6)
         for k in range(3):
-            s.eager_step(1, k)
+            s.fused_step(1, k)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for k in range(steps):
-            s.eager_step(1, 3 + k)
+            s.fused_step(1, 3 + k)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
@@ -850,18 +850,18 @@ def resnet_leg(steps: int = 3, recompute: bool = True):
     net = dict(kind="resnet", width=w, depth=B, prec="bf16")
     plan = Plan(prob, net, Nr, Mr, recompute=recompute)
     s = TrainState(plan, I.init_params(prob, net, Nr, seed=0, out_scale=0.1), 760.0)
-    s.eager_step(1, 0)
+    s.fused_step(1, 0)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for k in range(steps):
-        s.eager_step(1, 1 + k)
+        s.fused_step(1, 1 + k)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     plan.profile(True)
     for k in range(steps):
-        s.eager_step(1, 10 + k)
+        s.fused_step(1, 10 + k)
     torch.cuda.synchronize()
     prof = plan.profile_read()
     plan.profile(False)

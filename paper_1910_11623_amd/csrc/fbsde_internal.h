@@ -136,7 +136,7 @@ struct WsLayout {
 };
 
 // launchers (kernels.hip); all return hipError_t of the launch
-// launch_pack and launch_sde in one launch (independent work, one grid)
+// the per-iteration weight packing and the SDE in one launch (independent work, one grid)
 hipError_t launch_pack_sde(const Geo& g, const float* params, void* packF, void* packB, float* pbias,
                            const float* x0, uint64_t seed, uint64_t iter, const uint64_t* iter_dev, float* X,
                            float* V, float* QN, float* LN, hipStream_t s);
