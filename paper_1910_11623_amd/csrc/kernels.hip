@@ -774,44 +774,49 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // One wave per workgroup: the paths' serial recursions leave the SIMDs idle,
 // so spreading the waves over as many CUs as possible shortens the latency
-// chain each CU's memory pipeline serves.
+// chain each CU's memory pipeline serves.  NR > 0: time grids of at most NR
+// steps keep c_n and Y_n in registers (NR is the smallest of 16, 32, 64 that
+// holds N: the unrolled loops and loads stop there, 13 -> 10 us at N = 32);
+// NR = 0: longer grids stream them.
+template <int NR>
 __global__ __launch_bounds__(64) void k_scan(Geo g, const double* __restrict__ y0,
                                              const float* __restrict__ C, const float* __restrict__ QN,
                                              const float* __restrict__ LN, float* __restrict__ Y,
                                              float* __restrict__ LAM, double* __restrict__ part) {
   const int m = blockIdx.x * 64 + threadIdx.x;
   double l2 = 0.0, lam0 = 0.0;
-  constexpr int NR = 64;  // time grids up to NR steps keep c_n and Y_n in registers
-  if (m < g.M && g.N <= NR) {
-    // every c_n load is issued up front (indices clamped, so unconditional),
-    // Y_n stays in registers for the reverse recursion: two memory latencies
-    // per path instead of one per batch of steps in each direction
-    float cv[NR], yv[NR + 1];
-    const float qn = QN[m], ln = LN[m];  // terminal inputs, fetched with the c_n
+  if constexpr (NR > 0) {
+    if (m < g.M) {
+      // every c_n load is issued up front (indices clamped, so unconditional),
+      // Y_n stays in registers for the reverse recursion: two memory latencies
+      // per path instead of one per batch of steps in each direction
+      float cv[NR], yv[NR + 1];
+      const float qn = QN[m], ln = LN[m];  // terminal inputs, fetched with the c_n
 #pragma unroll
-    for (int n = 0; n < NR; ++n) cv[n] = C[(size_t)min(n, g.N - 1) * g.M + m];
-    float y = (float)y0[0];
-    yv[0] = y;
-    Y[m] = y;
+      for (int n = 0; n < NR; ++n) cv[n] = C[(size_t)min(n, g.N - 1) * g.M + m];
+      float y = (float)y0[0];
+      yv[0] = y;
+      Y[m] = y;
 #pragma unroll
-    for (int n = 0; n < NR; ++n) {
-      if (n < g.N) {
-        y = y + g.dt * phi_y(g, y) + cv[n];
-        yv[n + 1] = y;
-        Y[(size_t)(n + 1) * g.M + m] = y;
+      for (int n = 0; n < NR; ++n) {
+        if (n < g.N) {
+          y = y + g.dt * phi_y(g, y) + cv[n];
+          yv[n + 1] = y;
+          Y[(size_t)(n + 1) * g.M + m] = y;
+        }
       }
-    }
-    const float e = y - terminal_g(g, qn, ln);
-    l2 = (double)e * (double)e;
-    float lam = 2.f * e / (float)g.M;
+      const float e = y - terminal_g(g, qn, ln);
+      l2 = (double)e * (double)e;
+      float lam = 2.f * e / (float)g.M;
 #pragma unroll
-    for (int n = NR - 1; n >= 0; --n) {
-      if (n < g.N) {
-        LAM[(size_t)n * g.M + m] = lam;
-        lam = lam * (1.f + g.dt * phi_yy(g, yv[n]));
+      for (int n = NR - 1; n >= 0; --n) {
+        if (n < g.N) {
+          LAM[(size_t)n * g.M + m] = lam;
+          lam = lam * (1.f + g.dt * phi_yy(g, yv[n]));
+        }
       }
+      lam0 = (double)lam;
     }
-    lam0 = (double)lam;
   } else if (m < g.M) {
     // both recursions are serial in n; the loads they need are not, so
     // they are issued SB steps at a time ahead of the arithmetic
@@ -2432,7 +2437,10 @@ hipError_t launch_forward(const Geo& g, const float* params, const void* packF, 
 
 hipError_t launch_scan(const Geo& g, const double* y0, const float* C, const float* QN, const float* LN,
                        float* Y, float* LAM, double* part, int blocks, hipStream_t s) {
-  k_scan<<<blocks, 64, 0, s>>>(g, y0, C, QN, LN, Y, LAM, part);
+  if (g.N <= 16) k_scan<16><<<blocks, 64, 0, s>>>(g, y0, C, QN, LN, Y, LAM, part);
+  else if (g.N <= 32) k_scan<32><<<blocks, 64, 0, s>>>(g, y0, C, QN, LN, Y, LAM, part);
+  else if (g.N <= 64) k_scan<64><<<blocks, 64, 0, s>>>(g, y0, C, QN, LN, Y, LAM, part);
+  else k_scan<0><<<blocks, 64, 0, s>>>(g, y0, C, QN, LN, Y, LAM, part);
   return hipGetLastError();
 }
 

@@ -66,6 +66,9 @@ FP32_CASES = [
     ("hjb", 3, 5, 2, 3, 100003),   # 1563 one-wave scan workgroups (ragged), 64 gradient splits
     ("ac", 130, 140, 2, 3, 40),    # d, w above 128: 16-tile kernels
     ("hjb", 256, 256, 2, 3, 21),   # largest per-step shape: d = w = 256 (16 x 16 tiles, no padding)
+    ("bsb", 5, 8, 2, 40, 50),      # 33 <= N <= 64: the scan's 64-step register form
+    ("hjb", 8, 12, 1, 70, 64),     # N > 64: the scan streams c_n and Y_n (HJB: the Y recursion is
+    ("hjb", 8, 12, 1, 130, 40),    # stable; Allen-Cahn's y^3 drift amplifies fp32 rounding at long grids)
 ]
 
 
