@@ -2450,11 +2450,19 @@ hipError_t launch_backward(const Geo& g, const void* packB, const float* V, cons
   return hipGetLastError();
 }
 
+// Output tiles per side of a weight-gradient workgroup's block.  Past 8
+// tiles a matrix spans several blocks, whose tile loops always run the full
+// block: 7 or 8, whichever covers the (rows x cols + 1) matrix with fewer
+// tile slots (d = 188, w = 198: 4 blocks of 7 x 7 instead of 4 of 8 x 8).
+// Each tile's accumulation order does not depend on the block, so neither
+// do the results.
 int wgrad_block_tiles(const Geo& g) {
   const int rmax = g.d > g.w ? g.d : g.w;
   const int cmax = (g.d > g.w ? g.d : g.w) + 1;
   const int t = ((rmax > cmax ? rmax : cmax) + 15) / 16;
-  return t <= 1 ? 1 : (t <= 2 ? 2 : (t <= 4 ? 4 : (t <= 7 ? 7 : 8)));
+  if (t <= 8) return t <= 1 ? 1 : (t <= 2 ? 2 : (t <= 4 ? 4 : (t <= 7 ? 7 : 8)));
+  auto slots = [&](int T) { return ((rmax + 16 * T - 1) / (16 * T)) * ((cmax + 16 * T - 1) / (16 * T)) * T * T; };
+  return slots(7) < slots(8) ? 7 : 8;
 }
 
 template <bool BF, int T>
