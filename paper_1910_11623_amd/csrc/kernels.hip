@@ -1138,9 +1138,30 @@ template <bool BF, int T>
 struct WgradLds {
   static constexpr int KC = wg_kc<BF>();
   static constexpr int LDA = 16 * T + ((T % 2 == 0) ? 16 : 0);  // fp32 row stride (floats), == 16 mod 32
-  static constexpr int LDT = KC + 4;                             // bf16 transposed row stride (elements)
-  static constexpr size_t BYTES = BF ? 2ull * 16 * T * LDT * 2 : 2ull * KC * LDA * 4;
+  static constexpr int LDB = 128;                                // bf16 [path][feature] row (T <= 8 tiles)
+  static constexpr size_t BYTES = BF ? 2ull * KC * LDB * 2 : 2ull * KC * LDA * 4;
+  static_assert(!BF || T <= 8, "bf16 rows hold at most 8 tiles");
 };
+
+// bf16 staging keeps each path's features as one LDS row; the MFMA fragment
+// (8 consecutive paths of one feature per lane) comes from two transposed
+// reads (ds_read_b64_tr_b16): in each 16-lane group, lanes 4e..4e+3 point at
+// row 8g + 4h + e, columns 4q..4q+3 of the tile (q = lane % 4), and lane j
+// receives column j of those four rows.  The 16-feature blocks of row k are
+// XOR-swizzled by (k mod 4) + 4 (floor(k / 8) mod 2), which rows k and k + 4
+// share, so the 8 rows one read instruction touches per 32 lanes fall into
+// distinct banks.
+__device__ __forceinline__ int wg_swz(int k) { return ((k & 3) | (((k >> 3) & 1) << 2)) * 16; }
+typedef short wg_v4s __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) wg_v4s wg_lds_v4s;
+__device__ __forceinline__ bf16x8 wg_frag(const uint16_t* rows, int col0, int lane) {
+  const int g = lane >> 4, j = lane & 15, k = 8 * g + (j >> 2);
+  uint16_t* p = const_cast<uint16_t*>(rows) + k * 128 + (col0 ^ wg_swz(k)) + 4 * (j & 3);
+  const wg_v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((wg_lds_v4s*)p);
+  const wg_v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((wg_lds_v4s*)(p + 4 * 128));
+  const uint2 l = __builtin_bit_cast(uint2, lo), h = __builtin_bit_cast(uint2, hi);
+  return __builtin_bit_cast(bf16x8, u32x4{l.x, l.y, h.x, h.y});
+}
 
 // 4 consecutive fp32 input columns c..c+3 of one path, with the bias column
 // of ones at `cols` and zeros beyond (src row holds `stride` valid entries)
@@ -1234,15 +1255,10 @@ __device__ __forceinline__ void wgrad_put(unsigned char* smem, int tid,
       float* dst = reinterpret_cast<float*>(smem) + (isA ? 0 : L::KC * L::LDA) + kp * L::LDA + 4 * c4;
       st4(dst, v[k]);
     } else {
-      // the 8-path group of a row is XOR-swizzled by bits 4-5 of the row, so
-      // that a wave's 2-byte transposing writes (rows 4 apart) spread over
-      // twice as many LDS banks; fragment reads stay 16 contiguous bytes
-      const int kps = kp ^ (8 * ((c4 >> 2) & 3));  // rows 4c4..4c4+3: (row >> 4) & 3
-      uint16_t* dst = reinterpret_cast<uint16_t*>(smem) + (isA ? 0 : 16 * T * L::LDT) + 4 * c4 * L::LDT + kps;
-      dst[0] = (uint16_t)(v[k].x & 0xffffu);
-      dst[L::LDT] = (uint16_t)(v[k].x >> 16);
-      dst[2 * L::LDT] = (uint16_t)(v[k].y & 0xffffu);
-      dst[3 * L::LDT] = (uint16_t)(v[k].y >> 16);
+      // features 4 c4 .. 4 c4 + 3 of path kp, one 8-byte write into its row
+      uint16_t* dst = reinterpret_cast<uint16_t*>(smem) + (isA ? 0 : L::KC * L::LDB) + kp * L::LDB +
+                      ((16 * (c4 >> 2)) ^ wg_swz(kp)) + 4 * (c4 & 3);
+      *reinterpret_cast<uint2*>(dst) = v[k];
     }
   }
 }
@@ -1356,20 +1372,12 @@ __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, 
       }
     } else {
       const uint16_t* As = reinterpret_cast<const uint16_t*>(smem);
-      const uint16_t* Bs = As + 16 * T * L::LDT;
+      const uint16_t* Bs = As + L::KC * L::LDB;
       bf16x8 a[NRA], b[NCA];
 #pragma unroll
-      for (int i = 0; i < NR; ++i) {
-        const uint16_t* src = As + (16 * (rt0 + i) + c16) * L::LDT + 8 * (grp ^ ((rt0 + i) & 3));
-        const uint2 lo = *reinterpret_cast<const uint2*>(src), hi = *reinterpret_cast<const uint2*>(src + 4);
-        a[i] = __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y});
-      }
+      for (int i = 0; i < NR; ++i) a[i] = wg_frag(As, 16 * (rt0 + i), lane);
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const uint16_t* src = Bs + (16 * (ct0 + j) + c16) * L::LDT + 8 * (grp ^ ((ct0 + j) & 3));
-        const uint2 lo = *reinterpret_cast<const uint2*>(src), hi = *reinterpret_cast<const uint2*>(src + 4);
-        b[j] = __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y});
-      }
+      for (int j = 0; j < NC; ++j) b[j] = wg_frag(Bs, 16 * (ct0 + j), lane);
 #pragma unroll
       for (int i = 0; i < NR; ++i)
 #pragma unroll
@@ -1393,7 +1401,8 @@ __device__ __forceinline__ void wgrad_tiles(const Geo& g, const Job& J, int R0, 
 }
 
 template <bool BF, int T>
-__global__ __launch_bounds__(WG_THREADS) void k_wgrad(Geo g, const float* __restrict__ X, const void* __restrict__ H,
+__global__ __launch_bounds__(WG_THREADS) __attribute__((amdgpu_waves_per_eu(BF ? 6 : 1))) void k_wgrad(
+    Geo g, const float* __restrict__ X, const void* __restrict__ H,
                                                const void* __restrict__ DZ, const void* __restrict__ DH,
                                                float* __restrict__ part, long long chunk) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[WgradLds<BF, T>::BYTES];
