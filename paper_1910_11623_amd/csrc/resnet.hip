@@ -313,6 +313,8 @@ __device__ __forceinline__ u32x4 tr_frag(const uint16_t* slab, int ld, int col0,
 template <int EPI, int TM, int TN, int WJ, bool KT>
 __global__ __launch_bounds__(128 * WJ) __attribute__((amdgpu_waves_per_eu(RN_WPE))) void k_gemm(Gm G, Epi E) {
   static_assert(!KT || EPI == EPI_ACC, "k-major operands are the weight-gradient form");
+  static_assert(!KT || !RN_KT_SWZ || (16 * TM * 2 >= 128 && 16 * TN * WJ >= 128),
+                "the [k][i] slab swizzle permutes 8 blocks of 16 columns");
   constexpr int WI = 2, NT = 64 * WI * WJ;  // waves along i and j, threads
   constexpr int BM = 16 * TM * WI, BN = 16 * TN * WJ;
   constexpr int UA = BM * 4 / NT, UB = BN * 4 / NT;  // 16-byte staging units per thread
