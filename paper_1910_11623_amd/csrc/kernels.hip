@@ -1983,6 +1983,39 @@ __device__ __forceinline__ void finalize_wave(int M, const double* __restrict__ 
 // flag.  Workgroup nred (the last one) finalizes the loss and dY0 from the
 // scan's partials, which the reduction does not touch, so both run in one
 // launch.
+// Sum over the split partials of one float4 group (or one element), in split
+// order from zero.  The loads go out eight at a time, so a thread waits for
+// one memory latency per eight splits instead of one per split; the
+// additions keep their order, so the sum is the same bits.
+constexpr int RED_BATCH = 8;
+__device__ __forceinline__ f32x4 sum_splits4(const float* __restrict__ part, long long stride, int splits,
+                                             long long e4) {
+  f32x4 s = zero4();
+  for (int k0 = 0; k0 < splits; k0 += RED_BATCH) {
+    f32x4 t[RED_BATCH];
+#pragma unroll
+    for (int q = 0; q < RED_BATCH; ++q)
+      t[q] = k0 + q < splits ? ld4(part + (size_t)(k0 + q) * stride + 4 * e4) : zero4();
+#pragma unroll
+    for (int q = 0; q < RED_BATCH; ++q)
+      if (k0 + q < splits) s += t[q];
+  }
+  return s;
+}
+__device__ __forceinline__ float sum_splits1(const float* __restrict__ part, long long stride, int splits,
+                                             long long e) {
+  float s = 0.f;
+  for (int k0 = 0; k0 < splits; k0 += RED_BATCH) {
+    float t[RED_BATCH];
+#pragma unroll
+    for (int q = 0; q < RED_BATCH; ++q) t[q] = k0 + q < splits ? part[(size_t)(k0 + q) * stride + e] : 0.f;
+#pragma unroll
+    for (int q = 0; q < RED_BATCH; ++q)
+      if (k0 + q < splits) s += t[q];
+  }
+  return s;
+}
+
 __global__ __launch_bounds__(256) void k_reduce(long long P, long long stride, const float* __restrict__ part,
                                                 int splits, float* __restrict__ grad, int nred, int M,
                                                 const double* __restrict__ sp, int nb, double* __restrict__ loss,
@@ -1995,14 +2028,12 @@ __global__ __launch_bounds__(256) void k_reduce(long long P, long long stride, c
   const long long t0 = blockIdx.x * 256LL + threadIdx.x, step = (long long)nred * 256;
   const long long P4 = (reinterpret_cast<uintptr_t>(grad) & 15) == 0 ? P / 4 : 0;
   for (long long e4 = t0; e4 < P4; e4 += step) {
-    f32x4 s = zero4();
-    for (int k = 0; k < splits; ++k) s += ld4(part + (size_t)k * stride + 4 * e4);
+    const f32x4 s = sum_splits4(part, stride, splits, e4);
     st4(grad + 4 * e4, s);
     bad |= !(isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2]) && isfinite(s[3]));
   }
   for (long long e = 4 * P4 + t0; e < P; e += step) {
-    float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part[(size_t)k * stride + e];
+    const float s = sum_splits1(part, stride, splits, e);
     grad[e] = s;
     bad |= !isfinite(s);
   }
@@ -2131,19 +2162,14 @@ __global__ __launch_bounds__(256) void k_reduce_adam(long long P, long long stri
   const long long P4 = vec ? P / 4 : 0;
   // the first element's sum is formed before the bias corrections are known,
   // so the partial loads overlap the workgroup's pow evaluations
-  auto sum4 = [&](long long e4) {
-    f32x4 s = zero4();
-    for (int k = 0; k < splits; ++k) s += ld4(part + (size_t)k * stride + 4 * e4);
-    return s;
-  };
   f32x4 s0 = zero4();
-  if (t0 < P4) s0 = sum4(t0);
+  if (t0 < P4) s0 = sum_splits4(part, stride, splits, t0);
   if (threadIdx.x == 0) adam_corr(t_imm, t_dev, b1d, b2d, corr);
   __syncthreads();
   const double c1d = corr[0], c2d = corr[1];
   const float b1 = (float)b1d, b2 = (float)b2d, eps = (float)epsd, c1 = (float)c1d, c2 = (float)c2d;
   for (long long e4 = t0; e4 < P4; e4 += step) {
-    const f32x4 s = e4 == t0 ? s0 : sum4(e4);
+    const f32x4 s = e4 == t0 ? s0 : sum_splits4(part, stride, splits, e4);
     st4(grad + 4 * e4, s);
     bad |= !(isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2]) && isfinite(s[3]));
     f32x4 P4v = reinterpret_cast<const f32x4*>(p)[e4], M4 = reinterpret_cast<const f32x4*>(m)[e4],
@@ -2160,8 +2186,7 @@ __global__ __launch_bounds__(256) void k_reduce_adam(long long P, long long stri
     reinterpret_cast<f32x4*>(p)[e4] = P4v;
   }
   for (long long e = 4 * P4 + t0; e < P; e += step) {
-    float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part[(size_t)k * stride + e];
+    const float s = sum_splits1(part, stride, splits, e);
     grad[e] = s;
     bad |= !isfinite(s);
     float mi = m[e], vi = v[e];
