@@ -288,10 +288,21 @@ fbsde_status fbsde_plan_status(fbsde_plan *plan);
  * before fbsde_workspace_size (it changes the workspace).  Results are
  * bitwise identical for every mode and chunk size except for the fp32
  * summation order of the weight gradients, which follows the chunks.
+ * Per-step MLP (the per-step networks of Sec. 2.2 trained through the
+ * unrolled chain of eq. (disc equations)): recompute == 0 (the default)
+ * keeps every step's tanh activations between the passes; recompute != 0
+ * keeps only those of one chunk of whole steps (about chunk_rows rows, as
+ * above), which the forward pass writes chunk by chunk and the reverse pass
+ * recomputes from X_n, chunk by chunk, before each chunk's reverse sweep:
+ * the activation buffers shrink from N to (chunk steps) x M x L x width
+ * elements, for one more forward product per step.  Its results are
+ * bitwise identical to keeping the activations (the same kernels and
+ * arithmetic recompute them, and every step's weight gradient has its own
+ * partial sums).
  * Errors: INVALID (negative chunk_rows, or a mode that needs more workspace
- * than an earlier fbsde_workspace_size reported); UNSUPPORTED (a chunk too large for
- * 32-bit element offsets; the per-step MLP, which always keeps its
- * activations, with recompute != 0). */
+ * than an earlier fbsde_workspace_size reported); UNSUPPORTED (a shared-net
+ * chunk too large for 32-bit element offsets; u-network plans with
+ * recompute != 0). */
 fbsde_status fbsde_plan_set_checkpointing(fbsde_plan *plan, int32_t recompute, int64_t chunk_rows);
 /* cfg_host[6] = {shape, ti, tw, lds, tpw (resolved), splits} of the current configuration */
 fbsde_status fbsde_plan_get_config(const fbsde_plan *plan, int32_t *cfg_host);

@@ -118,9 +118,11 @@ void make_layout(fbsde_plan* P) {
     w.UCB = tk(R);
     w.ULP = take(((R + 31) / 32) * 8 + 64);  // one fp64 partial per 32-row residual workgroup, then the flag
   } else if (g.kind == 0) {
-    w.H = take(N * g.L * M * g.wp * esz);
-    w.DZ = take(N * M * g.zp * esz);
-    w.DH = take(N * g.L * M * g.wp * esz);
+    // activations of every step, or of one recompute chunk of steps
+    const size_t NA = g.rn_chunk > 0 ? (size_t)g.rn_chunk : N;
+    w.H = take(NA * g.L * M * g.wp * esz);
+    w.DZ = take(NA * M * g.zp * esz);
+    w.DH = take(NA * g.L * M * g.wp * esz);
     w.PF = take((N > 1 ? N - 1 : 0) * (size_t)g.packf_step * esz);
     w.PB = take((N > 1 ? N - 1 : 0) * (size_t)g.packb_step * esz);
     w.PBIAS = take((N > 1 ? N - 1 : 0) * (size_t)g.pbias_step * 4);
@@ -369,11 +371,18 @@ fbsde_status run_forward(fbsde_plan* P, const float* params, const double* y0, u
       return hip_fail(e, "pack and sde");
   }
   {
+    // with checkpointing the activations of each chunk of steps are written
+    // over the previous chunk's (the reverse pass recomputes them)
     ProfScope ps(P, FBSDE_PROF_FORWARD, s);
-    if ((e = fbsde::launch_forward(g, params, at<void>(ws, L.PF), at<float>(ws, L.PBIAS), at<float>(ws, L.X),
-                                   at<float>(ws, L.V),
-                                   at<float>(ws, L.C), at<void>(ws, L.H), s)) != hipSuccess)
-      return hip_fail(e, "forward");
+    const int cs = g.rn_chunk > 0 ? g.rn_chunk : g.N;
+    for (int n0 = 0; n0 < g.N; n0 += cs) {
+      Geo gc = g;
+      gc.n0 = n0;
+      gc.ns = std::min(cs, g.N - n0);
+      if ((e = fbsde::launch_forward(gc, params, at<void>(ws, L.PF), at<float>(ws, L.PBIAS), at<float>(ws, L.X),
+                                     at<float>(ws, L.V), at<float>(ws, L.C), at<void>(ws, L.H), s)) != hipSuccess)
+        return hip_fail(e, "forward");
+    }
   }
   {
     ProfScope ps(P, FBSDE_PROF_SCAN, s);
@@ -415,24 +424,44 @@ fbsde_status run_backward(fbsde_plan* plan, float* grad, double* grad_y0, double
     if ((e = reduce_tail(plan, grad, grad_y0, loss, ws, s, adam)) != hipSuccess) return hip_fail(e, "reduce");
     return FBSDE_OK;
   }
-  if (fbsde::reverse_fused_preferred(g, L.splits)) {
-    // the reverse sweep and the weight gradient in one kernel (timed as the backward)
-    ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
-    if ((e = fbsde::launch_reverse(g, at<void>(ws, L.PB), at<float>(ws, L.X), at<float>(ws, L.V),
-                                   at<float>(ws, L.LAM), at<void>(ws, L.H), at<float>(ws, L.PART), L.splits,
-                                   L.chunk, s)) != hipSuccess)
-      return hip_fail(e, "reverse");
-  } else {
-    {
-      ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
-      if ((e = fbsde::launch_backward(g, at<void>(ws, L.PB), at<float>(ws, L.V), at<float>(ws, L.LAM),
-                                      at<void>(ws, L.H), at<void>(ws, L.DZ), at<void>(ws, L.DH), s)) != hipSuccess)
-        return hip_fail(e, "backward");
+  // Checkpointing: chunks of steps, last first; each chunk's activations are
+  // recomputed from X_n (same kernel and arithmetic as the forward pass, so
+  // the same bits) just before its reverse sweep.  Every step's weight
+  // gradient has its own partial slots, so the chunk order does not matter.
+  const bool fused = fbsde::reverse_fused_preferred(g, L.splits);
+  const int cs = g.rn_chunk > 0 ? g.rn_chunk : g.N;
+  for (int n0 = (g.N - 1) / cs * cs; n0 >= 0; n0 -= cs) {
+    Geo gc = g;
+    gc.n0 = n0;
+    gc.ns = std::min(cs, g.N - n0);
+    if (g.rn_chunk > 0) {
+      ProfScope ps(plan, FBSDE_PROF_FORWARD, s);
+      gc.recomp = 1;  // step 0 has no network, so the parameters themselves are not read
+      if ((e = fbsde::launch_forward(gc, nullptr, at<void>(ws, L.PF), at<float>(ws, L.PBIAS), at<float>(ws, L.X),
+                                     at<float>(ws, L.V), at<float>(ws, L.C), at<void>(ws, L.H), s)) != hipSuccess)
+        return hip_fail(e, "recompute");
+      gc.recomp = 0;
     }
-    ProfScope ps(plan, FBSDE_PROF_WGRAD, s);
-    if ((e = fbsde::launch_wgrad(g, at<float>(ws, L.X), at<void>(ws, L.H), at<void>(ws, L.DZ),
-                                 at<void>(ws, L.DH), at<float>(ws, L.PART), L.splits, L.chunk, s)) != hipSuccess)
-      return hip_fail(e, "wgrad");
+    if (fused) {
+      // the reverse sweep and the weight gradient in one kernel (timed as the backward)
+      ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
+      if ((e = fbsde::launch_reverse(gc, at<void>(ws, L.PB), at<float>(ws, L.X), at<float>(ws, L.V),
+                                     at<float>(ws, L.LAM), at<void>(ws, L.H), at<float>(ws, L.PART), L.splits,
+                                     L.chunk, s)) != hipSuccess)
+        return hip_fail(e, "reverse");
+    } else {
+      {
+        ProfScope ps(plan, FBSDE_PROF_BACKWARD, s);
+        if ((e = fbsde::launch_backward(gc, at<void>(ws, L.PB), at<float>(ws, L.V), at<float>(ws, L.LAM),
+                                        at<void>(ws, L.H), at<void>(ws, L.DZ), at<void>(ws, L.DH), s)) !=
+            hipSuccess)
+          return hip_fail(e, "backward");
+      }
+      ProfScope ps(plan, FBSDE_PROF_WGRAD, s);
+      if ((e = fbsde::launch_wgrad(gc, at<float>(ws, L.X), at<void>(ws, L.H), at<void>(ws, L.DZ),
+                                   at<void>(ws, L.DH), at<float>(ws, L.PART), L.splits, L.chunk, s)) != hipSuccess)
+        return hip_fail(e, "wgrad");
+    }
   }
   {
     ProfScope ps(plan, FBSDE_PROF_REDUCE, s);
@@ -991,18 +1020,22 @@ fbsde_status fbsde_plan_status(fbsde_plan* plan) {
 fbsde_status fbsde_plan_set_checkpointing(fbsde_plan* plan, int32_t recompute, int64_t chunk_rows) {
   if (!plan) return fail(FBSDE_ERR_INVALID, "plan is NULL");
   if (chunk_rows < 0) return fail(FBSDE_ERR_INVALID, "chunk_rows must be >= 0");
-  if (plan->geo.kind != 1) {
-    if (recompute) return fail(FBSDE_ERR_UNSUPPORTED, "only the shared residual Z-network recomputes activations");
+  if (plan->geo.kind == 2) {
+    if (recompute) return fail(FBSDE_ERR_UNSUPPORTED, "the u-network does not recompute activations");
     return FBSDE_OK;
   }
   const int steps = rn_chunk_steps(plan->N, plan->M, chunk_rows > 0 ? chunk_rows : kDefaultChunkRows);
-  if (!rn_offsets_fit(plan->M, steps, plan->geo.w, plan->geo.d))
+  if (plan->geo.kind == 1 && !rn_offsets_fit(plan->M, steps, plan->geo.w, plan->geo.d))
     return fail(FBSDE_ERR_UNSUPPORTED, "chunk too large for 32-bit element offsets");
   const Geo keep_g = plan->geo;
   const WsLayout keep_w = plan->ws;
   const size_t keep_r = plan->reserve;
-  plan->geo.rn_chunk = steps;
-  plan->geo.rn_store = recompute ? 0 : 1;
+  if (plan->geo.kind == 1) {
+    plan->geo.rn_chunk = steps;
+    plan->geo.rn_store = recompute ? 0 : 1;
+  } else {
+    plan->geo.rn_chunk = recompute ? steps : 0;  // per-step MLP: 0 keeps every step's activations
+  }
   make_layout(plan);
   size_t r = reserve_bytes(plan);
   if (r < plan->ws.total) r = plan->ws.total;

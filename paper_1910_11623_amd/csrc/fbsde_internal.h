@@ -43,9 +43,18 @@ struct Geo {
   int uarch;              // u-network blocks: 0 fully connected, 1 residual, 2 NAIS
   float kappa;            // u-network: weight of the terminal-gradient penalty
   float ueps;             // u-network NAIS: A_k = -R_k^T R_k - ueps I
-  int rn_chunk;           // residual network: time steps per row chunk
+  int rn_chunk;           // residual network: time steps per row chunk; per-step MLP: time steps
+                          // per recompute chunk (0: every step's activations are kept)
   int rn_store;           // residual network: 1 = keep every chunk's activations (no recompute)
+  // per-step MLP launches over a range of steps: blockIdx.y (or the weight
+  // gradient's job) counts from step n0, over ns steps (0: all N); the
+  // activation buffers H, DZ, DH hold steps n0 .. n0 + ns - 1 from their row 0
+  int n0, ns;
+  int recomp;             // forward launch that only recomputes the activations (no Z, c_n, v_n)
 };
+
+// steps covered by one per-step-MLP launch
+inline int launch_steps(const Geo& g) { return g.ns > 0 ? g.ns : g.N; }
 
 // Shared residual network: packed weights and the per-chunk activation buffers.
 struct ResnetLayout {

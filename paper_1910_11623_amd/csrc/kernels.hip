@@ -149,6 +149,11 @@ __device__ __forceinline__ f32x4 normals4(uint64_t seed, uint64_t iter, int j, i
   return f32x4{a0, a1, a2, a3};
 }
 
+// Row block of step n in the activation buffers (H, DZ, DH) of a per-step
+// MLP launch: they hold the launch's steps n0 .. n0 + ns - 1 (all N steps
+// unless activations are recomputed in chunks of steps).
+__device__ __forceinline__ size_t act_step(const Geo& g, int n) { return (size_t)(n - g.n0); }
+
 // -------------------------------------------------------------- pack kernel
 // Packed A-fragment of a (R x K) matrix A with 16-row tiles T and K tiles t:
 //   fp32: elem ((T*Ti + t)*64 + lane)*4 + r   <- A[16T + lane%16][16t + 4(lane/16) + r]
@@ -436,7 +441,10 @@ __device__ __forceinline__ void stage_weights(unsigned char* dst, const void* sr
 // CU): 3 per SIMD for shapes up to 8 x 8 tiles (<= 170 VGPRs), else 2.
 constexpr int fwd_waves(int ti, int tw) { return (ti <= 8 && tw <= 8) ? 12 : 8; }
 
-template <bool BF, int TI, int TW, bool LDSW>
+// RC: recompute launch (activations only).  A compile-time switch: as a
+// run-time test inside the tile loop it cost the ordinary forward its
+// register budget (spills; bf16 51 -> 70 us at d = 100).
+template <bool BF, int TI, int TW, bool LDSW, bool RC = false>
 __global__ __launch_bounds__(LDSW ? 64 * fwd_waves(TI, TW) : 256) void k_forward(Geo g, const float* __restrict__ params,
                                                                const void* __restrict__ packF,
                                                                const float* __restrict__ pbias,
@@ -444,7 +452,8 @@ __global__ __launch_bounds__(LDSW ? 64 * fwd_waves(TI, TW) : 256) void k_forward
                                                                float* __restrict__ V, float* __restrict__ C,
                                                                void* __restrict__ H, int tpw) {
   extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
-  const int n = blockIdx.y;
+  const int n = g.n0 + (int)blockIdx.y;
+  if (RC && n == 0) return;  // step 0 has no network
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const size_t rowM = (size_t)g.M * g.dp;
@@ -505,7 +514,7 @@ __global__ __launch_bounds__(LDSW ? 64 * fwd_waves(TI, TW) : 256) void k_forward
       for (int r = 0; r < 4; ++r) h[T][r] = fast_tanh(acc[T][r] + bb[r]);
       h[T] = round4(h[T], BF);
       if (valid)
-        st_act(H, ((size_t)n * g.L) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h[T], BF);
+        st_act(H, (act_step(g, n) * g.L) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h[T], BF);
     }
     const char* pkl = pk + 256ULL * TW * TI * esz;
     for (int l = 2; l <= g.L; ++l) {
@@ -518,10 +527,11 @@ __global__ __launch_bounds__(LDSW ? 64 * fwd_waves(TI, TW) : 256) void k_forward
         for (int r = 0; r < 4; ++r) h[T][r] = fast_tanh(acc[T][r] + bb[r]);
         h[T] = round4(h[T], BF);
         if (valid)
-          st_act(H, ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h[T], BF);
+          st_act(H, (act_step(g, n) * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h[T], BF);
       }
       pkl += 256ULL * TW * TW * esz;
     }
+    if constexpr (RC) continue;  // the activations were all that was asked for
     layer_mm<BF, TI, TW>(Z, h, pkl, lane);
     const float* bo = bp + (size_t)g.L * 16 * TW;
 #pragma unroll
@@ -594,7 +604,7 @@ __global__ __launch_bounds__(64 * LS_WAVES) void k_forward_ls(Geo g, const float
                                                               const float* __restrict__ X, float* __restrict__ V,
                                                               float* __restrict__ C, void* __restrict__ H, int tpw) {
   extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
-  const int n = blockIdx.y;
+  const int n = g.n0 + (int)blockIdx.y;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = LS_WAVES;
   const int col = lane & 15, grp = lane >> 4;
   const size_t rowM = (size_t)g.M * g.dp, hM = (size_t)g.M * g.wp;
@@ -642,6 +652,7 @@ __global__ __launch_bounds__(64 * LS_WAVES) void k_forward_ls(Geo g, const float
     if (valid && grp == 0) C[(size_t)n * g.M + p] = c;
   };
   if (n == 0) {  // Z_0 = z0
+    if (g.recomp) return;
     for (int it = 0; it < tpw; ++it) {
       const int tile = tr.t0 + it * nwv + wv;
       if (tile >= tr.t1) break;
@@ -676,7 +687,7 @@ __global__ __launch_bounds__(64 * LS_WAVES) void k_forward_ls(Geo g, const float
 #pragma unroll
       for (int r = 0; r < 4; ++r) h[r] = fast_tanh(acc[T][r] + bb[r]);
       h = round4(h, BF);
-      if (valid) st_act(H, ((size_t)n * g.L) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h, BF);
+      if (valid) st_act(H, (act_step(g, n) * g.L) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h, BF);
     }
   }
   size_t foff = 256ULL * TW * TI;
@@ -692,7 +703,7 @@ __global__ __launch_bounds__(64 * LS_WAVES) void k_forward_ls(Geo g, const float
       f32x4 hin[TW], acc[TW];
 #pragma unroll
       for (int T = 0; T < TW; ++T)
-        hin[T] = valid ? ld_act(H, ((size_t)n * g.L + (l - 2)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, BF)
+        hin[T] = valid ? ld_act(H, (act_step(g, n) * g.L + (l - 2)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, BF)
                        : zero4();
       layer_mm<BF, TW, TW>(acc, hin, wsm, lane);
 #pragma unroll
@@ -702,11 +713,12 @@ __global__ __launch_bounds__(64 * LS_WAVES) void k_forward_ls(Geo g, const float
 #pragma unroll
         for (int r = 0; r < 4; ++r) h[r] = fast_tanh(acc[T][r] + bb[r]);
         h = round4(h, BF);
-        if (valid) st_act(H, ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h, BF);
+        if (valid) st_act(H, (act_step(g, n) * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, h, BF);
       }
     }
     foff += 256ULL * TW * TW;
   }
+  if (g.recomp) return;  // the activations were all that was asked for
   // output layer: Z = W_o h_L + b_o, then the c_n / v_n epilogue
   ls_stage<BF>(wsm, F + foff * esz, 256ULL * TI * TW * esz);
   const float* bo = bp + (size_t)g.L * 16 * TW;
@@ -718,7 +730,7 @@ __global__ __launch_bounds__(64 * LS_WAVES) void k_forward_ls(Geo g, const float
     f32x4 hin[TW], Z[TI];
 #pragma unroll
     for (int T = 0; T < TW; ++T)
-      hin[T] = valid ? ld_act(H, ((size_t)n * g.L + (g.L - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, BF)
+      hin[T] = valid ? ld_act(H, (act_step(g, n) * g.L + (g.L - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, BF)
                      : zero4();
     layer_mm<BF, TI, TW>(Z, hin, wsm, lane);
 #pragma unroll
@@ -872,7 +884,7 @@ __global__ __launch_bounds__(LDSW ? 64 * bwd_waves(TI, TW) : 256) void k_backwar
                                                                 void* __restrict__ DZ, void* __restrict__ DH,
                                                                 int tpw) {
   extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
-  const int n = blockIdx.y;
+  const int n = g.n0 + (int)blockIdx.y;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const size_t rowM = (size_t)g.M * g.dp;
@@ -904,7 +916,7 @@ __global__ __launch_bounds__(LDSW ? 64 * bwd_waves(TI, TW) : 256) void k_backwar
   auto load_h = [&](int pp, bool ok, int li) {
 #pragma unroll
     for (int T = 0; T < TW; ++T) {
-      const size_t idx = ((size_t)n * g.L + li) * hM + (size_t)pp * g.wp + 16 * T + 4 * grp;
+      const size_t idx = (act_step(g, n) * g.L + li) * hM + (size_t)pp * g.wp + 16 * T + 4 * grp;
       hv[T] = ok ? ld_act(H, idx, BF) : zero4();
     }
   };
@@ -947,7 +959,7 @@ __global__ __launch_bounds__(LDSW ? 64 * bwd_waves(TI, TW) : 256) void k_backwar
   }
 #pragma unroll
   for (int t = 0; t < TI; ++t)
-    if (valid) st_act(DZ, ((size_t)n * g.M + p) * g.zp + 16 * t + 4 * grp, zeta[t], BF);
+    if (valid) st_act(DZ, (act_step(g, n) * g.M + p) * g.zp + 16 * t + 4 * grp, zeta[t], BF);
   if (n == 0) continue;
   f32x4 dl[TW], acc[TW];
   // delta_l = (acc) * (1 - h^2) for layer l, then the next epilogue's loads,
@@ -966,7 +978,7 @@ __global__ __launch_bounds__(LDSW ? 64 * bwd_waves(TI, TW) : 256) void k_backwar
     }
 #pragma unroll
     for (int T = 0; T < TW; ++T) {
-      const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
+      const size_t idx = (act_step(g, n) * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
       if (valid) st_act(DH, idx, dl[T], BF);
     }
   };
@@ -995,7 +1007,7 @@ __global__ __launch_bounds__(64 * LS_WAVES) void k_backward_ls(Geo g, const void
                                                                const void* __restrict__ H, void* __restrict__ DZ,
                                                                void* __restrict__ DH, int tpw) {
   extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
-  const int n = blockIdx.y;
+  const int n = g.n0 + (int)blockIdx.y;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = LS_WAVES;
   const int col = lane & 15, grp = lane >> 4;
   const size_t rowM = (size_t)g.M * g.dp, hM = (size_t)g.M * g.wp;
@@ -1017,14 +1029,14 @@ __global__ __launch_bounds__(64 * LS_WAVES) void k_backward_ls(Geo g, const void
       const int c0 = 16 * t + 4 * grp;
       const f32x4 v = (valid && c0 < g.dp) ? ld4(Vn + (size_t)p * g.dp + c0) : zero4();
       zeta[t] = round4(lam * v, BF);
-      if (valid) st_act(DZ, ((size_t)n * g.M + p) * g.zp + 16 * t + 4 * grp, zeta[t], BF);
+      if (valid) st_act(DZ, (act_step(g, n) * g.M + p) * g.zp + 16 * t + 4 * grp, zeta[t], BF);
     }
     if (n == 0) continue;
     f32x4 acc[TW];
     layer_mm<BF, TW, TI>(acc, zeta, wsm, lane);
 #pragma unroll
     for (int T = 0; T < TW; ++T) {
-      const size_t idx = ((size_t)n * g.L + (g.L - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
+      const size_t idx = (act_step(g, n) * g.L + (g.L - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
       const f32x4 h = valid ? ld_act(H, idx, BF) : zero4();
       f32x4 dl;
 #pragma unroll
@@ -1045,11 +1057,11 @@ __global__ __launch_bounds__(64 * LS_WAVES) void k_backward_ls(Geo g, const void
       f32x4 din[TW], acc[TW];
 #pragma unroll
       for (int T = 0; T < TW; ++T)
-        din[T] = valid ? ld_act(DH, ((size_t)n * g.L + l) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, BF) : zero4();
+        din[T] = valid ? ld_act(DH, (act_step(g, n) * g.L + l) * hM + (size_t)p * g.wp + 16 * T + 4 * grp, BF) : zero4();
       layer_mm<BF, TW, TW>(acc, din, wsm, lane);
 #pragma unroll
       for (int T = 0; T < TW; ++T) {
-        const size_t idx = ((size_t)n * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
+        const size_t idx = (act_step(g, n) * g.L + (l - 1)) * hM + (size_t)p * g.wp + 16 * T + 4 * grp;
         const f32x4 h = valid ? ld_act(H, idx, BF) : zero4();
         f32x4 dl;
 #pragma unroll
@@ -1064,6 +1076,8 @@ __global__ __launch_bounds__(64 * LS_WAVES) void k_backward_ls(Geo g, const void
 // ------------------------------------------------------------- wgrad kernel
 // Job 0: dz0 = sum_m zeta_0 (a d x 0 "matrix" with only its bias column).
 // Job 1 + (n-1)(L+1) + (l-1), l = 1..L+1: dW_l of step n (bias as column cols).
+// A launch over steps n0 .. n0 + ns - 1 numbers its jobs the same way from
+// its first step (job 0 is step 0's only when n0 = 0).
 struct Job {
   int rows, cols;
   long long base;          // flat offset of W_l (b_l follows at base + rows*cols)
@@ -1076,13 +1090,14 @@ __device__ __forceinline__ Job job_info(const Geo& g, int job, const float* X, c
                                         const void* DZ, const void* DH) {
   Job J;
   const size_t esz = g.bf16 ? 2 : 4;
-  if (job == 0) {
+  if (g.n0 == 0 && job == 0) {
     J.rows = g.d; J.cols = 0; J.base = 0;
     J.A = DZ; J.sA = g.zp; J.B = nullptr; J.sB = 0; J.Bf32 = false;
     return J;
   }
-  const int jj = job - 1;
-  const int n = 1 + jj / (g.L + 1), l = 1 + jj % (g.L + 1);
+  // jobs of the launch's steps with a network, from max(n0, 1)
+  const int jj = job - (g.n0 == 0 ? 1 : 0);
+  const int n = (g.n0 > 1 ? g.n0 : 1) + jj / (g.L + 1), l = 1 + jj % (g.L + 1);
   const size_t hM = (size_t)g.M * g.wp;
   const long long step = g.d + (long long)(n - 1) * g.pstep;
   const long long lw1 = (long long)g.w * g.d + g.w, lwh = (long long)g.w * g.w + g.w;
@@ -1090,14 +1105,14 @@ __device__ __forceinline__ Job job_info(const Geo& g, int job, const float* X, c
   J.cols = (l == 1) ? g.d : g.w;
   J.base = step + (l == 1 ? 0 : lw1 + (long long)(l - 2) * lwh);
   if (l == g.L + 1) {
-    J.A = reinterpret_cast<const char*>(DZ) + (size_t)n * g.M * g.zp * esz; J.sA = g.zp;
+    J.A = reinterpret_cast<const char*>(DZ) + act_step(g, n) * g.M * g.zp * esz; J.sA = g.zp;
   } else {
-    J.A = reinterpret_cast<const char*>(DH) + ((size_t)n * g.L + (l - 1)) * hM * esz; J.sA = g.wp;
+    J.A = reinterpret_cast<const char*>(DH) + (act_step(g, n) * g.L + (l - 1)) * hM * esz; J.sA = g.wp;
   }
   if (l == 1) {
     J.B = X + (size_t)n * g.M * g.dp; J.sB = g.dp; J.Bf32 = true;
   } else {
-    J.B = reinterpret_cast<const char*>(H) + ((size_t)n * g.L + (l - 2)) * hM * esz; J.sB = g.wp;
+    J.B = reinterpret_cast<const char*>(H) + (act_step(g, n) * g.L + (l - 2)) * hM * esz; J.sB = g.wp;
     J.Bf32 = false;
   }
   return J;
@@ -1499,7 +1514,7 @@ __device__ __forceinline__ void rv_body(const Geo& g, const void* __restrict__ p
                                         long long p1, unsigned char* wsm, int R0, int C0) {
   constexpr int LDA = rv_lda(TI, TW), ASZ = RV_KC * LDA, NSL = L + 2;
   static_assert(RV_KC * 4 * (TI > TW ? TI : TW) <= RV_THREADS, "one staging item per thread and array");
-  const int n = blockIdx.y;
+  const int n = g.n0 + (int)blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c16 = lane & 15, grp = lane >> 4;
@@ -1540,7 +1555,7 @@ __device__ __forceinline__ void rv_body(const Geo& g, const void* __restrict__ p
       } else if (a == 1) {
         if (n > 0) sv[a] = ld4(Xn + p * g.dp + min(max(sc[a], 0), g.dp - 4));
       } else {
-        sv[a] = ld4(H + ((size_t)n * L + (a - 2)) * hM + p * g.wp + min(max(sc[a], 0), g.wp - 4));
+        sv[a] = ld4(H + (act_step(g, n) * L + (a - 2)) * hM + p * g.wp + min(max(sc[a], 0), g.wp - 4));
       }
     }
   };
@@ -1739,7 +1754,7 @@ __device__ __forceinline__ void rb_body(const Geo& g, const void* __restrict__ p
   constexpr int TM = TI > TW ? TI : TW;
   constexpr int LDP = rb_ldp(TI, TW), PSZ = RB_KC * LDP, FSZ = 16 * TM * RB_LDF;
   static_assert(RB_KC / 2 * 4 * TM <= RV_THREADS, "one staging item per thread and input");
-  const int n = blockIdx.y;
+  const int n = g.n0 + (int)blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c16 = lane & 15, grp = lane >> 4;
@@ -1782,7 +1797,7 @@ __device__ __forceinline__ void rb_body(const Geo& g, const void* __restrict__ p
         rx[e] = ld4(Xn + p * g.dp + min(max(sc[1], 0), g.dp - 4));
 #pragma unroll
         for (int l = 0; l < L; ++l)
-          rh[l][e] = *reinterpret_cast<const uint2*>(H + ((size_t)n * L + l) * hM + p * g.wp +
+          rh[l][e] = *reinterpret_cast<const uint2*>(H + (act_step(g, n) * L + l) * hM + p * g.wp +
                                                      min(max(sc[2 + l], 0), g.wp - 4));
       }
     }
@@ -2343,13 +2358,18 @@ static void fwd_inst(const Geo& g, const float* params, const void* packF, const
     static bool attr = [] {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_forward<BF, TI, TW, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_forward<BF, TI, TW, true, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
       return true;
     }();
     (void)attr;
     constexpr int NW = fwd_waves(TI, TW);
     const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, NW, num_cus());
-    dim3 grid((unsigned)(((g.M + 15) / 16 + NW * tpw - 1) / (NW * tpw)), g.N);
-    k_forward<BF, TI, TW, true><<<grid, 64 * NW, bytes, s>>>(g, params, packF, pbias, X, V, C, H, tpw);
+    dim3 grid((unsigned)(((g.M + 15) / 16 + NW * tpw - 1) / (NW * tpw)), launch_steps(g));
+    if (g.recomp)
+      k_forward<BF, TI, TW, true, true><<<grid, 64 * NW, bytes, s>>>(g, params, packF, pbias, X, V, C, H, tpw);
+    else
+      k_forward<BF, TI, TW, true><<<grid, 64 * NW, bytes, s>>>(g, params, packF, pbias, X, V, C, H, tpw);
   } else if (g.lds && ls_layer_bytes(BF, TI, TW) <= kLdsLimit && g.N > 1) {
     static bool attr = [] {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_forward_ls<BF, TI, TW>),
@@ -2358,12 +2378,15 @@ static void fwd_inst(const Geo& g, const float* params, const void* packF, const
     }();
     (void)attr;
     const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, LS_WAVES, num_cus());
-    dim3 grid((unsigned)(((g.M + 15) / 16 + LS_WAVES * tpw - 1) / (LS_WAVES * tpw)), g.N);
+    dim3 grid((unsigned)(((g.M + 15) / 16 + LS_WAVES * tpw - 1) / (LS_WAVES * tpw)), launch_steps(g));
     k_forward_ls<BF, TI, TW><<<grid, 64 * LS_WAVES, ls_layer_bytes(BF, TI, TW), s>>>(g, params, packF, pbias, X, V, C,
                                                                                      H, tpw);
   } else {
-    dim3 grid((g.M + 63) / 64, g.N);
-    k_forward<BF, TI, TW, false><<<grid, 256, 0, s>>>(g, params, packF, pbias, X, V, C, H, 1);
+    dim3 grid((g.M + 63) / 64, launch_steps(g));
+    if (g.recomp)
+      k_forward<BF, TI, TW, false, true><<<grid, 256, 0, s>>>(g, params, packF, pbias, X, V, C, H, 1);
+    else
+      k_forward<BF, TI, TW, false><<<grid, 256, 0, s>>>(g, params, packF, pbias, X, V, C, H, 1);
   }
 }
 template <bool BF, int TI, int TW>
@@ -2379,7 +2402,7 @@ static void bwd_inst(const Geo& g, const void* packB, const float* V, const floa
     (void)attr;
     constexpr int NW = bwd_waves(TI, TW);
     const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, NW, num_cus());
-    dim3 grid((unsigned)(((g.M + 15) / 16 + NW * tpw - 1) / (NW * tpw)), g.N);
+    dim3 grid((unsigned)(((g.M + 15) / 16 + NW * tpw - 1) / (NW * tpw)), launch_steps(g));
     k_backward<BF, TI, TW, true><<<grid, 64 * NW, bytes, s>>>(g, packB, V, LAM, H, DZ, DH, tpw);
   } else if (g.lds && ls_layer_bytes(BF, TI, TW) <= kLdsLimit && g.N > 1) {
     static bool attr = [] {
@@ -2389,11 +2412,11 @@ static void bwd_inst(const Geo& g, const void* packB, const float* V, const floa
     }();
     (void)attr;
     const int tpw = g.tpw > 0 ? g.tpw : tiles_per_wave(g, LS_WAVES, num_cus());
-    dim3 grid((unsigned)(((g.M + 15) / 16 + LS_WAVES * tpw - 1) / (LS_WAVES * tpw)), g.N);
+    dim3 grid((unsigned)(((g.M + 15) / 16 + LS_WAVES * tpw - 1) / (LS_WAVES * tpw)), launch_steps(g));
     k_backward_ls<BF, TI, TW><<<grid, 64 * LS_WAVES, ls_layer_bytes(BF, TI, TW), s>>>(g, packB, V, LAM, H, DZ, DH,
                                                                                       tpw);
   } else {
-    dim3 grid((g.M + 63) / 64, g.N);
+    dim3 grid((g.M + 63) / 64, launch_steps(g));
     k_backward<BF, TI, TW, false><<<grid, 256, 0, s>>>(g, packB, V, LAM, H, DZ, DH, 1);
   }
 }
@@ -2504,7 +2527,8 @@ static void wgrad_inst(const Geo& g, const float* X, const void* H, const void* 
                        int splits, long long chunk, hipStream_t s) {
   const int rmax = g.d > g.w ? g.d : g.w, cmax = rmax + 1;
   const unsigned groups = (unsigned)(((rmax + 16 * T - 1) / (16 * T)) * ((cmax + 16 * T - 1) / (16 * T)));
-  const unsigned jobs = 1u + (unsigned)(g.N - 1) * (unsigned)(g.L + 1);
+  const int n1 = g.n0 + launch_steps(g), nf = g.n0 > 1 ? g.n0 : 1;  // steps with a network: nf .. n1 - 1
+  const unsigned jobs = (g.n0 == 0 ? 1u : 0u) + (unsigned)(n1 > nf ? n1 - nf : 0) * (unsigned)(g.L + 1);
   dim3 grid(jobs, groups, splits);
   k_wgrad<BF, T><<<grid, WG_THREADS, 0, s>>>(g, X, H, DZ, DH, part, chunk);
 }
@@ -2560,7 +2584,7 @@ static void rev_inst(const Geo& g, const void* packB, const float* X, const floa
     return true;
   }();
   (void)attr;
-  dim3 grid((unsigned)splits, (unsigned)g.N);
+  dim3 grid((unsigned)splits, (unsigned)launch_steps(g));
   if constexpr (BF)
     k_reverse_bf<TI, TW, L><<<grid, RV_THREADS, reverse_lds_bytes(g), s>>>(g, packB, X, V, LAM, H, part, chunk);
   else

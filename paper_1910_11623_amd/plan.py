@@ -25,11 +25,14 @@ class Plan:
     """One (problem, network, N, M) configuration of the hot path."""
 
     def __init__(self, problem: dict, net: dict, N: int, M: int, device: str | torch.device = "cuda",
-                 recompute: bool = True, chunk_rows: int = 0):
-        """Shared residual network only: `recompute` False keeps every
-        chunk's activations from the forward pass (larger workspace, no
-        recompute in the reverse sweep); `chunk_rows` sets the rows per chunk
-        of whole steps (0: the library's default)."""
+                 recompute: bool | None = None, chunk_rows: int = 0):
+        """Activation checkpointing (fbsde_plan_set_checkpointing).  Shared
+        residual network: `recompute` (default True) recomputes each chunk's
+        activations in the reverse sweep, False keeps them all (larger
+        workspace).  Per-step MLP: `recompute` (default False) True keeps one
+        chunk's activations and recomputes the rest (same bits).
+        `chunk_rows` sets the rows per chunk of whole steps (0: the
+        library's default)."""
         self.lib = B.load()
         self.problem, self.net, self.N, self.M = problem, dict(net), int(N), int(M)
         dev = torch.device(device)
@@ -46,8 +49,9 @@ class Plan:
             n = C.c_int64()
             B.check(self.lib.fbsde_param_count(self._h, C.byref(n)))
             self.n_params = int(n.value)
-            self.recompute = bool(recompute) if self.net.get("kind") == "resnet" else False
-            if self.net.get("kind") == "resnet":
+            kind = self.net.get("kind")
+            self.recompute = (recompute is None or bool(recompute)) if kind == "resnet" else bool(recompute)
+            if kind == "resnet" or (kind == "mlp" and self.recompute):
                 B.check(self.lib.fbsde_plan_set_checkpointing(self._h, int(self.recompute), int(chunk_rows)))
             sz = C.c_size_t()
             B.check(self.lib.fbsde_workspace_size(self._h, C.byref(sz)))

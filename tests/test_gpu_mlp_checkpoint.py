@@ -1,0 +1,89 @@
+"""GPU: activation checkpointing of the per-step MLP.  With recompute on,
+the forward pass keeps only one chunk of steps' activations and the reverse
+pass recomputes each chunk's from X_n with the same kernels before its
+reverse sweep, so loss, dL/dY0 and the gradient must equal those of the plan
+that keeps every step's activations bit for bit, for every reverse-kernel
+form (fused, separate pair, layer-streamed, global-fragment) and for chunk
+counts that do and do not divide N."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1910_11623_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1910_11623_amd.plan import Plan, TrainState
+
+# (problem, d, net, N, M, lds mode, steps per chunk)
+CASES = [
+    ("bsb", 20, dict(kind="mlp", width=30, depth=2, prec="fp32"), 6, 300, 2, 2),   # fused fp32, 3 chunks
+    ("bsb", 20, dict(kind="mlp", width=30, depth=2, prec="fp32"), 6, 300, 2, 4),   # ragged: 4 + 2 steps
+    ("hjb", 12, dict(kind="mlp", width=24, depth=2, prec="fp32"), 5, 130, 1, 1),   # separate pair, 1 step
+    ("ac", 10, dict(kind="mlp", width=20, depth=2, prec="fp32"), 4, 77, 0, 3),     # weights from global memory
+    ("hjb", 7, dict(kind="mlp", width=9, depth=3, prec="fp32"), 4, 33, 2, 2),      # depth 3: the pair
+    ("bsb", 24, dict(kind="mlp", width=40, depth=2, prec="bf16"), 5, 200, 2, 2),   # fused bf16
+    ("hjb", 150, dict(kind="mlp", width=160, depth=2, prec="bf16"), 4, 90, 2, 3),  # layer-streamed bf16
+    ("bsb", 6, dict(kind="mlp", width=8, depth=1, prec="fp32"), 1, 40, 2, 1),      # N = 1: step 0 only
+]
+
+
+def _prob(name, d):
+    return {"bsb": I.bsb, "hjb": I.hjb, "ac": I.allen_cahn}[name](d)
+
+
+@pytest.mark.parametrize("name,d,net,N,M,lds,cs", CASES)
+def test_checkpointed_gradient_is_bitwise_equal(name, d, net, N, M, lds, cs):
+    prob = _prob(name, d)
+    keep = Plan(prob, net, N, M)
+    ck = Plan(prob, net, N, M, recompute=True, chunk_rows=cs * M)
+    for p in (keep, ck):
+        p.config(lds=lds)
+    print(f"{name} d={d} N={N} M={M} {net} lds={lds} chunk={cs} steps; workspace {keep.ws_bytes} -> "
+          f"{ck.ws_bytes} bytes", flush=True)
+    if cs < N:
+        assert ck.ws_bytes < keep.ws_bytes
+    params = torch.from_numpy(I.init_params(prob, net, N, seed=7, out_scale=0.3).astype(np.float32)).cuda()
+    y0 = torch.tensor(10.0 if name == "bsb" else 0.6, dtype=torch.float64, device="cuda")
+    for it in (0, 3):
+        la, ga, ya = keep.forward_backward(params, y0, 5, it)
+        lb, gb, yb = ck.forward_backward(params, y0, 5, it)
+        torch.cuda.synchronize()
+        assert np.isfinite(la.item())
+        assert la.item() == lb.item() and ya.item() == yb.item()
+        assert torch.equal(ga, gb)
+    # the forward-only loss is unchanged by the chunked forward pass
+    assert keep.forward(params, y0, 5, 3).item() == ck.forward(params, y0, 5, 3).item()
+
+
+def test_checkpointed_training_steps_bitwise():
+    """Fused training steps (reduction + Adam) over several iterations."""
+    prob = I.bsb(30)
+    net = dict(kind="mlp", width=40, depth=2, prec="bf16")
+    N, M = 8, 256
+    keep = Plan(prob, net, N, M)
+    ck = Plan(prob, net, N, M, recompute=True, chunk_rows=3 * M)
+    p = I.init_params(prob, net, N, seed=2, out_scale=0.3)
+    a, b = TrainState(keep, p, 20.0), TrainState(ck, p, 20.0)
+    for k in range(4):
+        a.fused_step(11, k, lr=3e-3, lr_y0=0.05)
+        b.fused_step(11, k, lr=3e-3, lr_y0=0.05)
+    torch.cuda.synchronize()
+    for f in ("params", "y0", "grad", "gy0", "loss", "m", "v"):
+        assert torch.equal(getattr(a, f), getattr(b, f)), f
+
+
+def test_checkpointing_after_workspace_query_is_refused_if_larger():
+    """Switching back to kept activations needs more workspace than the
+    checkpointed plan reported: refused, and the plan keeps working."""
+    from paper_1910_11623_amd import binding as B
+    prob = I.bsb(10)
+    net = dict(kind="mlp", width=20, depth=2, prec="fp32")
+    ck = Plan(prob, net, 8, 64, recompute=True, chunk_rows=64)
+    with pytest.raises(B.FbsdeError):
+        B.check(ck.lib.fbsde_plan_set_checkpointing(ck._h, 0, 0))
+    params = torch.from_numpy(I.init_params(prob, net, 8, seed=1).astype(np.float32)).cuda()
+    y0 = torch.tensor(5.0, dtype=torch.float64, device="cuda")
+    loss, _, _ = ck.forward_backward(params, y0, 1, 0)
+    assert np.isfinite(loss.item())
