@@ -2316,7 +2316,7 @@ static int tiles_per_wave(const Geo& g, int waves, int cus) {
   for (int t = 1; t <= 64; ++t) {
     const long long gx = (tiles + (long long)waves * t - 1) / ((long long)waves * t);
     const long long per_wg = (tiles + gx - 1) / gx;
-    const long long wgs = gx * g.N;
+    const long long wgs = gx * launch_steps(g);  // a launch over a chunk of steps has fewer rows of workgroups
     const long long span = ((wgs + cus - 1) / cus) * (16LL * ((per_wg + 3) / 4) + waves);
     if (best_span < 0 || span < best_span) { best_span = span; best = t; }
   }
