@@ -835,6 +835,42 @@ def hjb_leg(steps: int = 20):
     return out
 
 
+def mlp_checkpoint_leg(steps: int = 20, chunk_steps: int = 8):
+    """HJB d=100, N=20, M=65536, width 110x2, fp32 and bf16: training steps
+    with activation checkpointing (chunks of `chunk_steps` steps, recomputed
+    in the reverse pass) against every step's activations kept: ms per step,
+    workspace, and whether the trained parameters are the same bits."""
+    import torch
+    from paper_1910_11623_amd import inputs as I
+    from paper_1910_11623_amd.plan import Plan, TrainState
+
+    N, Mh = 20, 65536
+    out = {"chunk_steps": chunk_steps}
+    for prec in ("fp32", "bf16"):
+        prob = I.hjb(100)
+        net = dict(kind="mlp", width=110, depth=2, prec=prec)
+        res = {}
+        for ck in (False, True):
+            plan = Plan(prob, net, N, Mh, recompute=ck, chunk_rows=chunk_steps * Mh if ck else 0)
+            s = TrainState(plan, I.init_params(prob, net, N, seed=0), 4.6)
+            for k in range(3):
+                s.fused_step(1, k)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for k in range(steps):
+                s.fused_step(1, 3 + k)
+            e1.record()
+            torch.cuda.synchronize()
+            res[ck] = (e0.elapsed_time(e1) / steps, plan.ws_bytes / 2**30, s.params.clone())
+            del plan, s
+        out[prec] = {"kept_ms_per_step": round(res[False][0], 4), "kept_workspace_gib": round(res[False][1], 3),
+                     "checkpointed_ms_per_step": round(res[True][0], 4),
+                     "checkpointed_workspace_gib": round(res[True][1], 3),
+                     "same_bits": bool(torch.equal(res[False][2], res[True][2]))}
+    return out
+
+
 def resnet_leg(steps: int = 3, recompute: bool = True):
     """BSB d=1000, N=64, M=16384, shared residual network (width 1024,
     4 blocks, t as input), bf16 MFMA; the reverse sweep recomputes each row
@@ -892,8 +928,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the batched Allen-Cahn and HJB legs")
     ap.add_argument("--prec", choices=["fp32", "bf16", "both"], default="both",
                     help="which library precision(s) to time")
-    ap.add_argument("--only", choices=["batch", "hjb", "resnet", "resnet_kept", "resnet_multilevel", "paper",
-                                       "generalisation"],
+    ap.add_argument("--only", choices=["batch", "hjb", "mlp_checkpoint", "resnet", "resnet_kept",
+                                       "resnet_multilevel", "paper", "generalisation"],
                     help="run just one of the extra legs and print its JSON")
     ap.add_argument("--summarize-traffic", nargs=6, metavar="DIR",
                     help="rocprofv3 --pmc output dirs: FETCH_SIZE fp32, WRITE_SIZE fp32, FETCH_SIZE bf16, "
@@ -930,7 +966,7 @@ def main():
         leg = {"batch": batch_leg, "hjb": hjb_leg, "resnet": resnet_leg,
                "resnet_kept": lambda: resnet_leg(recompute=False),
                "resnet_multilevel": resnet_multilevel_leg, "paper": lambda: paper_leg(tta=not args.no_tta),
-               "generalisation": generalisation_leg}[args.only]
+               "generalisation": generalisation_leg, "mlp_checkpoint": mlp_checkpoint_leg}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return
     if args.prec == "bf16":
@@ -962,6 +998,8 @@ def main():
             f"{extra['batched_allen_cahn_32']['graph_ms']} ms, tuned graph {extra['batched_allen_cahn_32']['graph_tuned_ms']} ms")
         extra["hjb_d100_M65536"] = hjb_leg()
         log(f"HJB d=100 M=65536: {extra['hjb_d100_M65536']}")
+        extra["mlp_checkpoint_hjb_d100"] = mlp_checkpoint_leg()
+        log(f"per-step MLP checkpointing, HJB d=100 M=65536: {extra['mlp_checkpoint_hjb_d100']}")
         extra["resnet_bsb_d1000"] = resnet_leg(recompute=True)
         log(f"ResNet BSB d=1000 (recompute): {extra['resnet_bsb_d1000']}")
         extra["resnet_bsb_d1000_kept"] = resnet_leg(recompute=False)
