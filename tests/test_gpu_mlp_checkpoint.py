@@ -87,3 +87,25 @@ def test_checkpointing_after_workspace_query_is_refused_if_larger():
     y0 = torch.tensor(5.0, dtype=torch.float64, device="cuda")
     loss, _, _ = ck.forward_backward(params, y0, 1, 0)
     assert np.isfinite(loss.item())
+
+
+def test_autograd_function_with_checkpointing():
+    """The adjoint behind torch.autograd with a checkpointed plan: the same
+    gradients as with kept activations."""
+    from paper_1910_11623_amd.plan import FBSDELoss
+    prob = I.hjb(16)
+    net = dict(kind="mlp", width=24, depth=2, prec="fp32")
+    N, M = 6, 96
+    keep = Plan(prob, net, N, M)
+    ck = Plan(prob, net, N, M, recompute=True, chunk_rows=2 * M)
+    p0 = torch.from_numpy(I.init_params(prob, net, N, seed=4, out_scale=0.3).astype(np.float32)).cuda()
+    grads = []
+    for plan in (keep, ck):
+        params = p0.clone().requires_grad_(True)
+        y = torch.tensor(0.5, dtype=torch.float64, device="cuda", requires_grad=True)
+        loss = FBSDELoss.apply(params, y, plan, 2, 1)
+        (3.0 * loss).backward()
+        grads.append((loss.detach(), params.grad, y.grad))
+    assert torch.equal(grads[0][0], grads[1][0])
+    assert torch.equal(grads[0][1], grads[1][1])
+    assert torch.equal(grads[0][2], grads[1][2])
