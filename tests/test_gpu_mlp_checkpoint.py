@@ -109,3 +109,31 @@ def test_autograd_function_with_checkpointing():
     assert torch.equal(grads[0][0], grads[1][0])
     assert torch.equal(grads[0][1], grads[1][1])
     assert torch.equal(grads[0][2], grads[1][2])
+
+
+def test_checkpointed_plans_in_a_batch_graph():
+    """Checkpointed instances captured in one hipGraph (their chunk loops
+    included): every replay gives the bits of kept-activation eager steps."""
+    from paper_1910_11623_amd.plan import Batch
+    shapes = [(20, 10), (57, 6)]
+    M = 300
+    eager, graph, seeds = [], [], []
+    for k, (d, N) in enumerate(shapes):
+        prob = I.allen_cahn(d)
+        net = dict(kind="mlp", width=d + 10, depth=2, prec="bf16")
+        p = I.init_params(prob, net, N, seed=k, out_scale=0.05)
+        eager.append(TrainState(Plan(prob, net, N, M), p, 0.3))
+        graph.append(TrainState(Plan(prob, net, N, M, recompute=True, chunk_rows=4 * M), p, 0.3))
+        seeds.append(21 + k)
+    batch = Batch(graph, seeds)
+    for k in range(3):
+        for s, seed in zip(eager, seeds):
+            s.eager_step(seed, k)
+        junk = torch.randn(1 << 16, device="cuda").sum()  # unrelated eager work between replays
+        batch.step()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for a, b in zip(eager, graph):
+            assert torch.equal(a.params, b.params), k
+            assert torch.equal(a.y0, b.y0), k
+            assert torch.equal(a.loss, b.loss), k
