@@ -390,7 +390,8 @@ fbsde_status fbsde_plan_set_x0(fbsde_plan *plan, const double *x0_host);
  * (other streams, threads or plans) race; the array keeps the previous
  * call's contents, which no call reads before writing.  Errors in addition:
  * UNSUPPORTED if the plan's workspace exceeds the scratch (use
- * fbsde_forward_backward), INVALID if the current device is not the plan's. */
+ * fbsde_forward_backward, or shrink it with fbsde_plan_set_checkpointing),
+ * INVALID if the current device is not the plan's. */
 #define FBSDE_NOALLOC_SCRATCH_BYTES (64ull << 20)
 fbsde_status fbsde_forward_backward_noalloc(fbsde_plan *plan, const float *params_dev,
                                             const double *y0_dev, float *grad_dev, double *grad_y0_dev,
